@@ -1,0 +1,217 @@
+"""ctypes wrapper around oracle.c, the serial FP64 reference (test infrastructure).
+
+Only tests/, the smoke check and the CPU-baseline leg of the benchmark use this
+module.  It is independent of the HIP library: it shares no source with it and
+never imports the product package.
+
+Layouts (all host numpy arrays, C order):
+  ijkl      int32 [n, 4]   oct coordinates (i, j, k) and level l
+  u         float64 [8n, 5] conserved state per cell, cell = 8*oct + ix + 2iy + 4iz,
+            variables (rho, rho u, rho v, rho w, E)
+  nbr27     int32 [n, 27]  neighbour list, entry (dx+1) + 3(dy+1) + 9(dz+1)
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+OUTSIDE = -(2 ** 31)
+PERIODIC, OUTFLOW = 0, 1
+OK, EUNGRADED = 0, 4
+
+
+def build(force=True):
+    """Compile oracle.c with gcc: serial, -O2, no FMA contraction, no fast-math."""
+    if not force and os.path.exists(_LIB_PATH):
+        return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+           "-o", tmp, _SRC, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        i64, i32, f64, u32 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_uint32
+        L.orc_hilbert.restype = ctypes.c_uint64
+        L.orc_hilbert.argtypes = [ctypes.c_int, u32, u32, u32]
+        L.orc_key.restype = ctypes.c_uint64
+        L.orc_key.argtypes = [i32, i32, i32, i32]
+        L.orc_keys.restype = None
+        L.orc_keys.argtypes = [i64, P, P]
+        L.orc_tree_order.restype = None
+        L.orc_tree_order.argtypes = [i64, P, P]
+        L.orc_neighbours.restype = ctypes.c_int
+        L.orc_neighbours.argtypes = [i64, P, ctypes.c_int, P, P, P, P]
+        L.orc_prim.restype = None
+        L.orc_prim.argtypes = [P, f64, P]
+        L.orc_minmod.restype = f64
+        L.orc_minmod.argtypes = [f64, f64]
+        L.orc_predict.restype = None
+        L.orc_predict.argtypes = [P, P, f64, f64, P]
+        L.orc_hllc.restype = None
+        L.orc_hllc.argtypes = [P, P, ctypes.c_int, f64, P]
+        L.orc_cfl_dt.restype = f64
+        L.orc_cfl_dt.argtypes = [i64, P, P, P, f64, f64]
+        L.orc_hydro_octs.restype = None
+        L.orc_hydro_octs.argtypes = [i64, P, P, P, i64, i64, P, P, P, f64, f64]
+        L.orc_step.restype = f64
+        L.orc_step.argtypes = [i64, P, P, P, P, P, f64, f64]
+        L.orc_step_fixed.restype = f64
+        L.orc_step_fixed.argtypes = [i64, P, P, P, P, P, f64, f64]
+        L.orc_run.restype = None
+        L.orc_run.argtypes = [i64, P, P, P, P, P, f64, f64, i64, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def hilbert(b, i, j, k):
+    """H_b(i, j, k) on the order-20 curve coarsened to 2^b cubes per side."""
+    return int(lib().orc_hilbert(int(b), int(i), int(j), int(k)))
+
+
+def key(i, j, k, l):
+    return int(lib().orc_key(int(i), int(j), int(k), int(l)))
+
+
+def keys(ijkl):
+    ijkl = _c(ijkl, np.int32).reshape(-1, 4)
+    out = np.empty(len(ijkl), dtype=np.uint64)
+    lib().orc_keys(len(ijkl), _p(ijkl), _p(out))
+    return out
+
+
+def tree_order(ijkl):
+    """perm such that ijkl[perm] is in key order (level, then Hilbert)."""
+    ijkl = _c(ijkl, np.int32).reshape(-1, 4)
+    perm = np.empty(len(ijkl), dtype=np.int64)
+    lib().orc_tree_order(len(ijkl), _p(ijkl), _p(perm))
+    return perm
+
+
+def neighbours(ijkl, bc):
+    """(status, bad_oct, nbr27[n,27], father_cell[n], son_mask[n]) for key-ordered octs."""
+    ijkl = _c(ijkl, np.int32).reshape(-1, 4)
+    n = len(ijkl)
+    nbr = np.zeros((n, 27), dtype=np.int32)
+    fc = np.zeros(n, dtype=np.int32)
+    sm = np.zeros(n, dtype=np.uint8)
+    bad = np.zeros(1, dtype=np.int64)
+    st = lib().orc_neighbours(n, _p(ijkl), int(bc), _p(nbr), _p(fc), _p(sm), _p(bad))
+    return st, int(bad[0]), nbr, fc, sm
+
+
+def prim(U, gamma):
+    U = _c(U, np.float64)
+    W = np.empty(5)
+    lib().orc_prim(_p(U), float(gamma), _p(W))
+    return W
+
+
+def minmod(a, b):
+    return lib().orc_minmod(float(a), float(b))
+
+
+def predict(W, dW, h, gamma):
+    """Hancock half step W' from W[5], slopes dW[3,5] and h = dt/(2dx)."""
+    W = _c(W, np.float64)
+    dW = _c(dW, np.float64).reshape(3, 5)
+    Wp = np.empty(5)
+    lib().orc_predict(_p(W), _p(dW), float(h), float(gamma), _p(Wp))
+    return Wp
+
+
+def hllc(WL, WR, axis, gamma):
+    WL = _c(WL, np.float64)
+    WR = _c(WR, np.float64)
+    F = np.empty(5)
+    lib().orc_hllc(_p(WL), _p(WR), int(axis), float(gamma), _p(F))
+    return F
+
+
+def cfl_dt(ijkl, son_mask, u, gamma, cfl):
+    ijkl = _c(ijkl, np.int32)
+    sm = _c(son_mask, np.uint8)
+    u = _c(u, np.float64)
+    return lib().orc_cfl_dt(len(sm), _p(ijkl), _p(sm), _p(u), float(gamma), float(cfl))
+
+
+def hydro_octs(ijkl, nbr27, son_mask, ob, oe, uold, unew, corr, dt, gamma):
+    """Hydro update of octs [ob, oe) into unew / corr (arrays modified in place)."""
+    ijkl = _c(ijkl, np.int32)
+    nbr27 = _c(nbr27, np.int32)
+    sm = _c(son_mask, np.uint8)
+    assert uold.dtype == np.float64 and uold.flags.c_contiguous
+    assert unew.dtype == np.float64 and unew.flags.c_contiguous
+    assert corr.dtype == np.float64 and corr.flags.c_contiguous
+    lib().orc_hydro_octs(len(sm), _p(ijkl), _p(nbr27), _p(sm), int(ob), int(oe), _p(uold), _p(unew),
+                         _p(corr), float(dt), float(gamma))
+
+
+class Tree:
+    """A key-ordered tree with the oracle's own neighbour lists."""
+
+    def __init__(self, ijkl, bc):
+        ijkl = _c(ijkl, np.int32).reshape(-1, 4)
+        self.perm = tree_order(ijkl)
+        self.ijkl = np.ascontiguousarray(ijkl[self.perm])
+        self.bc = bc
+        self.keys = keys(self.ijkl)
+        st, bad, self.nbr27, self.father_cell, self.son_mask = neighbours(self.ijkl, bc)
+        if st != OK:
+            raise ValueError("tree is not graded (oct %d)" % bad)
+        self.n = len(self.ijkl)
+        lv = self.ijkl[:, 3]
+        self.lmin, self.lmax = int(lv.min()), int(lv.max())
+        self.level_begin = {l: int(np.searchsorted(lv, l, side="left")) for l in range(self.lmin, self.lmax + 2)}
+
+    def permute_cells(self, u_input_order):
+        """Reorder a per-cell array given in input oct order into key order."""
+        u = np.asarray(u_input_order).reshape(-1, 8, 5)
+        return np.ascontiguousarray(u[self.perm].reshape(-1, 5))
+
+    def cfl_dt(self, u, gamma, cfl):
+        return cfl_dt(self.ijkl, self.son_mask, u, gamma, cfl)
+
+    def step(self, u, gamma, cfl):
+        """One global-dt step, in place; returns dt."""
+        assert u.dtype == np.float64 and u.flags.c_contiguous and u.shape == (8 * self.n, 5)
+        return lib().orc_step(self.n, _p(self.ijkl), _p(self.nbr27), _p(self.father_cell), _p(self.son_mask),
+                              _p(u), float(gamma), float(cfl))
+
+    def step_fixed(self, u, gamma, dt):
+        """One step with the given dt, in place."""
+        assert u.dtype == np.float64 and u.flags.c_contiguous and u.shape == (8 * self.n, 5)
+        return lib().orc_step_fixed(self.n, _p(self.ijkl), _p(self.nbr27), _p(self.father_cell),
+                                    _p(self.son_mask), _p(u), float(gamma), float(dt))
+
+    def run(self, u, gamma, cfl, nsteps):
+        """nsteps steps in place; returns the array of dts."""
+        assert u.dtype == np.float64 and u.flags.c_contiguous and u.shape == (8 * self.n, 5)
+        dts = np.zeros(nsteps)
+        lib().orc_run(self.n, _p(self.ijkl), _p(self.nbr27), _p(self.father_cell), _p(self.son_mask),
+                      _p(u), float(gamma), float(cfl), int(nsteps), _p(dts))
+        return dts

@@ -1,0 +1,276 @@
+/*
+ * rg.h -- C ABI of the MI355X (gfx950) library for the per-level
+ * hydrodynamics update on a cell-by-cell oct tree, after RAMSES-GPU
+ * (Teyssier et al., arXiv 2607.20704).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Pointers named d_* are device memory owned by the caller; pointers named
+ *   h_* are host memory read (or written) during the call only.  The library
+ *   allocates no device memory in any call below except rg_sort_keys'
+ *   caller-sized workspace use and rg_batch_create (which owns only its
+ *   graph and a small device table, released by rg_batch_destroy).
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *   work is enqueued asynchronously on it; nothing synchronises unless the
+ *   description says so.
+ * - Every call returns an rg_status.  Calls never abort, throw or print.  On
+ *   an argument error nothing is enqueued and the outputs are untouched.
+ *   rg_last_error_detail() returns a thread-local text for the last failure.
+ * - Errors found on the device (duplicate key, ungraded tree, full table)
+ *   are recorded in the hash workspace header and reported by rg_check().
+ * - Results are deterministic: identical inputs give identical bits.  There
+ *   are no floating-point atomics on the update path.
+ *
+ * Tree and state layout
+ * ---------------------
+ * - Level l (1 <= l <= RG_MAX_LEVEL) of the unit box has 2^l cells and
+ *   2^(l-1) octs per side; an oct is the 2x2x2 cell block (i,j,k,l) (Sec. 2).
+ * - Octs are stored in ascending key order: by level, then along a 3-D
+ *   Hilbert curve (Sec. 2.2 and Fig. 1).  Key of oct (i,j,k,l):
+ *       K = 2^(3(l-1)) + H_(l-1)(i,j,k)
+ *   where H_b is Skilling's Hilbert index (AIP Conf. Proc. 707, 2004)
+ *   evaluated at order 20 on (i,j,k) * 2^(20-b) and shifted right by
+ *   3(20-b).  The parent key is K >> 3; no key is zero.
+ * - Cell c of oct o has global id 8*o + c, c = ix + 2*iy + 4*iz.
+ * - State: double U[8*n_oct][5], variables (rho, rho*u, rho*v, rho*w, E),
+ *   ideal gas.  Floors rho >= RG_RHO_MIN and p >= RG_P_MIN are applied to
+ *   primitive variables.
+ * - Neighbour list (Sec. 2.1, 2.3; the 27-entry list of Sec. 5):
+ *   int32 nbr27[n_oct][27], entry (dx+1) + 3(dy+1) + 9(dz+1) for the oct
+ *   offset (dx,dy,dz) in {-1,0,1}^3 (entry 13 is the oct itself):
+ *       e >= 0         same-level oct index
+ *       e <= -1        the missing oct is covered by coarse leaf cell -1-e
+ *       RG_NBR_OUTSIDE outside the domain (outflow boundaries)
+ * - father_cell[o]: global id of the level-(l-1) cell that oct o refines,
+ *   -1 on the coarsest level.  son_mask[o]: bit c set iff cell c of oct o has
+ *   a child oct (32-bit word per oct, low 8 bits used).
+ */
+#ifndef RG_H
+#define RG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RG_ABI_VERSION 1
+#define RG_MAX_LEVEL 21
+#define RG_NBR_OUTSIDE INT32_MIN
+#define RG_RHO_MIN 1e-10
+#define RG_P_MIN 1e-20
+
+typedef enum rg_status {
+    RG_OK = 0,
+    RG_EINVAL = 1,       /* bad argument: null/misaligned pointer, size, level, enum */
+    RG_EFULL = 2,        /* hash workspace too small for the keys */
+    RG_EDUPKEY = 3,      /* a key was inserted twice */
+    RG_EUNGRADED = 4,    /* a missing neighbour has no coarse cell under it */
+    RG_ENONFINITE = 5,   /* reserved: non-finite state detected */
+    RG_EHIP = 6,         /* a HIP runtime call failed (text in the detail) */
+    RG_ENOTSUP = 7       /* unsupported device or configuration */
+} rg_status;
+
+enum { RG_BC_PERIODIC = 0, RG_BC_OUTFLOW = 1 };
+
+/* Precision forms of the hydro update:
+ *   RG_FP64  every step in double precision.
+ *   RG_MIXED primitive variables (including pressure) computed in double
+ *            from the double state, then rounded to float; slopes,
+ *            predictor, face states and HLLC in float; each face flux is
+ *            widened to double, scaled by dt/dx and accumulated in double,
+ *            the same value entering both neighbours (so mass, momentum and
+ *            energy are conserved to double rounding).  dt stays double. */
+enum { RG_FP64 = 0, RG_MIXED = 1 };
+
+const char *rg_status_string(int status);
+
+/* Copies the thread-local detail of the last failed call (NUL-terminated,
+ * truncated to len) and returns its full length. */
+size_t rg_last_error_detail(char *buf, size_t len);
+
+/* Library ABI version (RG_ABI_VERSION). */
+int rg_abi_version(void);
+
+/* ---------------------------------------------------------------------- */
+/* Keys and order (Sec. 2.1 key tuple; Sec. 2.2 level sort + Hilbert sort) */
+/* ---------------------------------------------------------------------- */
+
+/* Keys of n octs: d_ijkl is int32[n][4] = (i, j, k, l) with 1 <= l <= 21 and
+ * 0 <= i,j,k < 2^(l-1); d_keys is uint64[n].  Out-of-range input gives key 0,
+ * which rg_hash_build rejects (RG_EINVAL via rg_check). */
+rg_status rg_encode_keys(const int32_t *d_ijkl, int64_t n, uint64_t *d_keys, void *stream);
+
+/* Host evaluation of the same key function the kernels use (testing aid):
+ * returns K for (i,j,k,l), 0 if out of range. */
+uint64_t rg_key_host(int32_t i, int32_t j, int32_t k, int32_t l);
+
+/* Host inverse of rg_key_host for a valid key: writes (i,j,k,l) to h_ijkl[4]. */
+void rg_key_coords_host(uint64_t key, int32_t *h_ijkl);
+
+/* Inverse of rg_encode_keys: d_ijkl[n][4] from valid keys. */
+rg_status rg_decode_keys(const uint64_t *d_keys, int64_t n, int32_t *d_ijkl, void *stream);
+
+/* Device workspace needed by rg_sort_keys for n keys. */
+size_t rg_sort_workspace_bytes(int64_t n);
+
+/* Sorts n keys ascending (LSD radix sort over the 64-bit keys) into
+ * d_keys_out and writes d_perm[r] = input position of the r-th key
+ * (int32).  d_ws must hold rg_sort_workspace_bytes(n) bytes. */
+rg_status rg_sort_keys(const uint64_t *d_keys_in, int64_t n, uint64_t *d_keys_out, int32_t *d_perm,
+                       void *d_ws, size_t ws_bytes, void *stream);
+
+/* First oct of every level in sorted keys: d_level_begin is
+ * int64[RG_MAX_LEVEL + 2]; octs of level l are [begin[l], begin[l+1]). */
+rg_status rg_level_ranges(const uint64_t *d_sorted_keys, int64_t n, int64_t *d_level_begin, void *stream);
+
+/* Gathers per-oct rows: d_out[r] = d_in[d_perm[r]] for rows of `row_doubles`
+ * doubles (40 for a cell state of one oct).  Used to put the state in key
+ * order. */
+rg_status rg_permute_rows(const double *d_in, const int32_t *d_perm, int64_t n_rows, int row_doubles,
+                          double *d_out, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Hash table (Sec. 2.1: fnv64 hash with linear probing; Sec. 6: CAS insert) */
+/* ---------------------------------------------------------------------- */
+
+/* Workspace for n keys: a 256-byte header, then capacity = the power of two
+ * >= 2n (load factor <= 1/2) slots of uint64 keys and int32 values. */
+size_t rg_hash_workspace_bytes(int64_t n_keys);
+
+/* Clears the table and inserts (d_keys[i], i) for i < n: slot = FNV-1a-64
+ * over the 8 little-endian key bytes, masked by capacity - 1, then linear
+ * probing; a 64-bit compare-and-swap claims the slot.  Keys must be
+ * non-zero and unique; violations are flagged in the header (rg_check).
+ * Slot positions depend on insertion order; only lookups are defined. */
+rg_status rg_hash_build(const uint64_t *d_keys, int64_t n, void *d_ws, size_t ws_bytes, void *stream);
+
+/* The paper's hash_get: d_idx[i] = index of key d_q[i], or -1 if absent. */
+rg_status rg_hash_lookup(const void *d_ws, const uint64_t *d_q, int64_t m, int32_t *d_idx, void *stream);
+
+/* Synchronises `stream` and returns the first device-side error recorded in
+ * the workspace since the last rg_hash_build (RG_OK if none); *h_bad_index
+ * receives the offending key or oct index (or -1). */
+rg_status rg_check(const void *d_ws, int64_t *h_bad_index, void *stream);
+
+/* FNV-1a-64 of the 8 little-endian bytes of `key`, computed on the host with
+ * the same code the kernels use (offered for testing against the published
+ * FNV definition). */
+uint64_t rg_fnv1a64(uint64_t key);
+
+/* ---------------------------------------------------------------------- */
+/* Neighbour lists (Sec. 2.1 hash_get; Sec. 2.3 ghost zones; Sec. 5 nbor)   */
+/* ---------------------------------------------------------------------- */
+
+/* For n key-ordered octs whose keys are in the hash table d_ws: writes
+ * nbr27[n][27], father_cell[n] and son_mask[n] (layout above).  Each oct's
+ * coordinates come from decoding its key; each neighbour is found by
+ * encoding its key and probing the table, then, if absent, probing its
+ * father key (K >> 3) for the coarse cell underneath.  `lmin` is the
+ * coarsest level present.  A missing neighbour without coarse cell, or an
+ * oct above lmin without father, sets RG_EUNGRADED in the workspace
+ * (rg_check).  bc is RG_BC_PERIODIC or RG_BC_OUTFLOW. */
+rg_status rg_build_neighbours(void *d_ws, const uint64_t *d_keys, int64_t n, int lmin, int bc,
+                              int32_t *d_nbr27, int32_t *d_father_cell, uint32_t *d_son_mask, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Hydro update (Sec. 3: MUSCL-Hancock + HLLC, uold -> unew)              */
+/* ---------------------------------------------------------------------- */
+
+/* Kernel choice; zero-initialised means "library default". */
+typedef struct rg_tuning {
+    int32_t octs_per_group;   /* octs handled by one workgroup (1..16, 0 = default) */
+    int32_t threads;          /* workgroup size: 64, 128, 192 or 256 (0 = default) */
+    int32_t reserved[6];
+} rg_tuning;
+
+/* Bytes of the coarse-fine correction buffer for octs [corr_base, n_oct):
+ * 30 doubles (6 sides x 5 variables) per oct. */
+size_t rg_corr_workspace_bytes(int64_t n_octs);
+
+/* One level's update (Sec. 3): for the octs [oct_begin, oct_end) of one
+ * level, with cell size dx and the time step *d_dt (device scalar):
+ *   - gathers the 6x6x6 stencil of each oct: same-level neighbours give
+ *     their cells, a missing neighbour gives its coarse cell to all 8
+ *     positions (injection), outside positions copy the nearest cell in the
+ *     domain (zero gradient);
+ *   - primitive variables, minmod slopes of primitives along x, y, z, the
+ *     Hancock half step W' = W - dt/(2dx) sum_d A_d(W) dW_d, face states
+ *     W' -/+ dW_d/2 (floored);
+ *   - HLLC flux (Davis speeds, side-symmetric star state) on the 36 faces of
+ *     the oct's cells, G = F dt/dx, set to zero on a face touching a split
+ *     cell;
+ *   - unew = ((uold + (Gx- - Gx+)) + (Gy- - Gy+)) + (Gz- - Gz+) for the
+ *     oct's 8 cells;
+ *   - for each side bordering a coarse cell, writes the flux owed to it,
+ *     +/- (1/8) ((G00 + G10) + (G01 + G11)), into
+ *     d_corr[30 * (o - corr_base) + 5 * side + var] (side = 2 * axis +
+ *     high); d_corr may be NULL only if no oct in the range has a coarse
+ *     neighbour.
+ * uold and unew must not overlap.  form is RG_FP64 or RG_MIXED; tune may be
+ * NULL. */
+rg_status rg_hydro_step_level(double dx, const double *d_dt, double gamma,
+                              const double *d_uold, double *d_unew,
+                              const int32_t *d_nbr27, const uint32_t *d_son_mask,
+                              int64_t oct_begin, int64_t oct_end,
+                              double *d_corr, int64_t corr_base,
+                              int form, const rg_tuning *tune, void *stream);
+
+/* Adds the fluxes recorded by rg_hydro_step_level for octs [oct_begin,
+ * oct_end) to the coarse cells they border: for side = 0..5 in turn, every
+ * oct whose neighbour across that side is coarse cell C does
+ * unew[C] += d_corr[30 * (o - corr_base) + 5 * side + v].  One launch per
+ * side; within a side no two octs share a target, so no atomics are used. */
+rg_status rg_apply_coarse_corrections(double *d_unew, const double *d_corr, int64_t corr_base,
+                                      const int32_t *d_nbr27, int64_t oct_begin, int64_t oct_end, void *stream);
+
+/* Upload (Table 1 "hydro - upload"): for octs [oct_begin, oct_end) of one
+ * level, u[father_cell[o]] = 0.125 * (((c0+c1)+(c2+c3))+((c4+c5)+(c6+c7))). */
+rg_status rg_restrict_level(double *d_u, const int32_t *d_father_cell, int64_t oct_begin, int64_t oct_end,
+                            void *stream);
+
+/* CFL time step (Table 1 "compute dt"): *d_dt = cfl * min over leaf cells of
+ * dx_l / (|u| + |v| + |w| + 3 c), c = sqrt(gamma p / rho), dx_l = 2^-l.
+ * h_level_begin[l] (host, int64[RG_MAX_LEVEL + 2]) gives the level ranges;
+ * the minimum is taken with a 64-bit atomicMin on the bits of positive
+ * doubles, so the result is exact and order independent. */
+rg_status rg_cfl_dt(const double *d_u, const uint32_t *d_son_mask, const int64_t *h_level_begin,
+                    int lmin, int lmax, double gamma, double cfl, double *d_dt, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Whole step on one tree                                                 */
+/* ---------------------------------------------------------------------- */
+
+typedef struct rg_tree {
+    int64_t n_oct;
+    int32_t lmin, lmax;                       /* levels present */
+    int32_t bc;                               /* RG_BC_* */
+    int32_t pad0;
+    int64_t level_begin[RG_MAX_LEVEL + 2];    /* host copy of the level ranges */
+    const uint64_t *d_keys;                   /* sorted keys [n_oct] */
+    void *d_hash_ws;                          /* rg_hash_workspace_bytes(n_oct) */
+    size_t hash_ws_bytes;
+    int32_t *d_nbr27;                         /* [n_oct][27] */
+    int32_t *d_father_cell;                   /* [n_oct] */
+    uint32_t *d_son_mask;                     /* [n_oct] */
+    double *d_corr;                           /* 30 doubles per oct of levels > lmin; NULL if lmin == lmax */
+} rg_tree;
+
+#define RG_STEP_REBUILD 1u    /* rebuild the hash table and neighbour lists first */
+
+/* One step with a global time step (no subcycling):
+ *   [if RG_STEP_REBUILD] hash build + neighbour lists;
+ *   dt = rg_cfl_dt(uold) into *d_dt;
+ *   every level: rg_hydro_step_level(uold -> unew);
+ *   rg_apply_coarse_corrections over all levels above lmin;
+ *   rg_restrict_level from lmax down to lmin + 1 on unew.
+ * The caller swaps uold and unew afterwards. */
+rg_status rg_step(const rg_tree *t, const double *d_uold, double *d_unew, double gamma, double cfl, int form,
+                  unsigned flags, double *d_dt, const rg_tuning *tune, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RG_H */

@@ -1,0 +1,97 @@
+"""ctypes loader for librg.so, the gfx950 library declared in include/rg.h.
+
+Argument marshalling only: every computation runs in the library's kernels.
+Loading fails loudly when the library is missing; there is no fallback.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librg.so")
+
+RG_OK, RG_EINVAL, RG_EFULL, RG_EDUPKEY, RG_EUNGRADED, RG_ENONFINITE, RG_EHIP, RG_ENOTSUP = range(8)
+RG_BC_PERIODIC, RG_BC_OUTFLOW = 0, 1
+RG_FP64, RG_MIXED = 0, 1
+RG_MAX_LEVEL = 21
+RG_NBR_OUTSIDE = -(2 ** 31)
+RG_STEP_REBUILD = 1
+
+# every symbol include/rg.h declares, with (restype, argtypes)
+P = ctypes.c_void_p
+i32, i64, u32, u64, f64, sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double,
+                               ctypes.c_size_t)
+st = ctypes.c_int
+
+
+class RgTuning(ctypes.Structure):
+    _fields_ = [("octs_per_group", i32), ("threads", i32), ("reserved", i32 * 6)]
+
+
+class RgTree(ctypes.Structure):
+    _fields_ = [("n_oct", i64), ("lmin", i32), ("lmax", i32), ("bc", i32), ("pad0", i32),
+                ("level_begin", i64 * (RG_MAX_LEVEL + 2)),
+                ("d_keys", P), ("d_hash_ws", P), ("hash_ws_bytes", sz),
+                ("d_nbr27", P), ("d_father_cell", P), ("d_son_mask", P), ("d_corr", P)]
+
+
+SIGNATURES = {
+    "rg_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "rg_last_error_detail": (sz, [ctypes.c_char_p, sz]),
+    "rg_abi_version": (ctypes.c_int, []),
+    "rg_encode_keys": (st, [P, i64, P, P]),
+    "rg_key_host": (u64, [i32, i32, i32, i32]),
+    "rg_key_coords_host": (None, [u64, P]),
+    "rg_decode_keys": (st, [P, i64, P, P]),
+    "rg_sort_workspace_bytes": (sz, [i64]),
+    "rg_sort_keys": (st, [P, i64, P, P, P, sz, P]),
+    "rg_level_ranges": (st, [P, i64, P, P]),
+    "rg_permute_rows": (st, [P, P, i64, ctypes.c_int, P, P]),
+    "rg_hash_workspace_bytes": (sz, [i64]),
+    "rg_hash_build": (st, [P, i64, P, sz, P]),
+    "rg_hash_lookup": (st, [P, P, i64, P, P]),
+    "rg_check": (st, [P, ctypes.POINTER(i64), P]),
+    "rg_fnv1a64": (u64, [u64]),
+    "rg_build_neighbours": (st, [P, P, i64, ctypes.c_int, ctypes.c_int, P, P, P, P]),
+    "rg_corr_workspace_bytes": (sz, [i64]),
+    "rg_hydro_step_level": (st, [f64, P, f64, P, P, P, P, i64, i64, P, i64, ctypes.c_int,
+                                 ctypes.POINTER(RgTuning), P]),
+    "rg_apply_coarse_corrections": (st, [P, P, i64, P, i64, i64, P]),
+    "rg_restrict_level": (st, [P, P, i64, i64, P]),
+    "rg_cfl_dt": (st, [P, P, P, ctypes.c_int, ctypes.c_int, f64, f64, P, P]),
+    "rg_step": (st, [ctypes.POINTER(RgTree), P, P, f64, f64, ctypes.c_int, ctypes.c_uint, P,
+                     ctypes.POINTER(RgTuning), P]),
+}
+
+_lib = None
+
+
+class RgError(RuntimeError):
+    def __init__(self, status, detail):
+        super().__init__(detail or "status %d" % status)
+        self.status = status
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("librg.so is not built (%s); run `python -m paper_2607_20704_amd.build`" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def detail():
+    buf = ctypes.create_string_buffer(1024)
+    lib().rg_last_error_detail(buf, len(buf))
+    return buf.value.decode(errors="replace")
+
+
+def check(status):
+    if status != RG_OK:
+        raise RgError(status, detail())
+    return status

@@ -1,0 +1,228 @@
+"""Thin Python binding of include/rg.h over PyTorch device tensors.
+
+Functions carry the C names without the ``rg_`` prefix and take torch tensors
+on the current HIP device; they marshal pointers, sizes and the current
+stream and raise RgError on a non-OK status.  PyTorch supplies device memory
+and streams only: every step of the computation runs in librg.so's kernels.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import (RG_BC_OUTFLOW, RG_BC_PERIODIC, RG_FP64, RG_MAX_LEVEL, RG_MIXED, RG_NBR_OUTSIDE,  # noqa: F401
+                   RG_STEP_REBUILD, RgError, RgTree, RgTuning, check)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _tuning(tune):
+    if tune is None:
+        return None
+    t = RgTuning()
+    t.octs_per_group, t.threads = int(tune[0]), int(tune[1])
+    return ctypes.byref(t)
+
+
+def _u8(n):
+    return torch.empty(int(n), dtype=torch.uint8, device="cuda")
+
+
+# ---------------------------------------------------------------- keys, order
+
+def encode_keys(ijkl):
+    keys = torch.empty(ijkl.shape[0], dtype=torch.uint64, device="cuda")
+    check(L.lib().rg_encode_keys(_ptr(ijkl), ijkl.shape[0], _ptr(keys), _stream()))
+    return keys
+
+
+def decode_keys(keys):
+    ijkl = torch.empty((keys.shape[0], 4), dtype=torch.int32, device="cuda")
+    check(L.lib().rg_decode_keys(_ptr(keys), keys.shape[0], _ptr(ijkl), _stream()))
+    return ijkl
+
+
+def key_host(i, j, k, l):
+    return int(L.lib().rg_key_host(int(i), int(j), int(k), int(l)))
+
+
+def key_coords_host(key):
+    out = (ctypes.c_int32 * 4)()
+    L.lib().rg_key_coords_host(ctypes.c_uint64(int(key)), out)
+    return tuple(out)
+
+
+def fnv1a64(key):
+    return int(L.lib().rg_fnv1a64(ctypes.c_uint64(int(key))))
+
+
+def sort_keys(keys):
+    n = keys.shape[0]
+    ws_bytes = L.lib().rg_sort_workspace_bytes(n)
+    ws = _u8(ws_bytes)
+    out = torch.empty_like(keys)
+    perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    check(L.lib().rg_sort_keys(_ptr(keys), n, _ptr(out), _ptr(perm), _ptr(ws), ws_bytes, _stream()))
+    return out, perm
+
+
+def level_ranges(sorted_keys):
+    begin = torch.empty(RG_MAX_LEVEL + 2, dtype=torch.int64, device="cuda")
+    check(L.lib().rg_level_ranges(_ptr(sorted_keys), sorted_keys.shape[0], _ptr(begin), _stream()))
+    return begin
+
+
+def permute_rows(x, perm):
+    out = torch.empty_like(x)
+    rows = perm.shape[0]
+    check(L.lib().rg_permute_rows(_ptr(x), _ptr(perm), rows, x.numel() // max(rows, 1), _ptr(out), _stream()))
+    return out
+
+
+# ---------------------------------------------------------------- hash table
+
+def hash_workspace_bytes(n):
+    return int(L.lib().rg_hash_workspace_bytes(int(n)))
+
+
+def hash_build(keys, ws=None):
+    n = keys.shape[0]
+    nb = hash_workspace_bytes(n)
+    if ws is None:
+        ws = _u8(nb)
+    check(L.lib().rg_hash_build(_ptr(keys), n, _ptr(ws), ws.numel(), _stream()))
+    return ws
+
+
+def hash_lookup(ws, q):
+    out = torch.empty(q.shape[0], dtype=torch.int32, device="cuda")
+    check(L.lib().rg_hash_lookup(_ptr(ws), _ptr(q), q.shape[0], _ptr(out), _stream()))
+    return out
+
+
+def check_ws(ws):
+    """(status, bad_index) of the device-side flags; synchronises."""
+    bad = ctypes.c_int64(-1)
+    st = L.lib().rg_check(_ptr(ws), ctypes.byref(bad), _stream())
+    return st, bad.value
+
+
+# ---------------------------------------------------------------- neighbours
+
+def build_neighbours(ws, keys, lmin, bc, nbr27=None, father_cell=None, son_mask=None):
+    n = keys.shape[0]
+    nbr27 = nbr27 if nbr27 is not None else torch.empty((n, 27), dtype=torch.int32, device="cuda")
+    father_cell = father_cell if father_cell is not None else torch.empty(n, dtype=torch.int32, device="cuda")
+    son_mask = son_mask if son_mask is not None else torch.empty(n, dtype=torch.int32, device="cuda")
+    check(L.lib().rg_build_neighbours(_ptr(ws), _ptr(keys), n, int(lmin), int(bc), _ptr(nbr27), _ptr(father_cell),
+                                      _ptr(son_mask), _stream()))
+    return nbr27, father_cell, son_mask
+
+
+# ---------------------------------------------------------------- hydro
+
+def hydro_step_level(dx, dt, gamma, uold, unew, nbr27, son_mask, oct_begin, oct_end, corr=None, corr_base=0,
+                     form=RG_FP64, tune=None):
+    check(L.lib().rg_hydro_step_level(float(dx), _ptr(dt), float(gamma), _ptr(uold), _ptr(unew), _ptr(nbr27),
+                                      _ptr(son_mask), int(oct_begin), int(oct_end), _ptr(corr), int(corr_base),
+                                      int(form), _tuning(tune), _stream()))
+
+
+def apply_coarse_corrections(unew, corr, corr_base, nbr27, oct_begin, oct_end):
+    check(L.lib().rg_apply_coarse_corrections(_ptr(unew), _ptr(corr), int(corr_base), _ptr(nbr27), int(oct_begin),
+                                              int(oct_end), _stream()))
+
+
+def restrict_level(u, father_cell, oct_begin, oct_end):
+    check(L.lib().rg_restrict_level(_ptr(u), _ptr(father_cell), int(oct_begin), int(oct_end), _stream()))
+
+
+def cfl_dt(u, son_mask, level_begin, lmin, lmax, gamma, cfl, dt=None):
+    dt = dt if dt is not None else torch.empty(1, dtype=torch.float64, device="cuda")
+    lb = np.ascontiguousarray(level_begin, dtype=np.int64)
+    check(L.lib().rg_cfl_dt(_ptr(u), _ptr(son_mask), lb.ctypes.data_as(ctypes.c_void_p), int(lmin), int(lmax),
+                            float(gamma), float(cfl), _ptr(dt), _stream()))
+    return dt
+
+
+# ---------------------------------------------------------------- whole tree
+
+class DeviceTree:
+    """A tree resident on the device: sorted keys, hash table, neighbour
+    lists and the coarse-fine correction buffer, built from oct coordinates
+    by the library (encode, radix sort, level ranges, hash, neighbours)."""
+
+    def __init__(self, ijkl, bc):
+        ijkl_d = torch.as_tensor(np.ascontiguousarray(ijkl, dtype=np.int32)).to("cuda")
+        self.bc = int(bc)
+        self.n = int(ijkl_d.shape[0])
+        keys_in = encode_keys(ijkl_d)
+        self.keys, self.perm = sort_keys(keys_in)
+        begin = level_ranges(self.keys).cpu().numpy()
+        self.level_begin = begin
+        present = [l for l in range(1, RG_MAX_LEVEL + 1) if begin[l + 1] > begin[l]]
+        self.lmin, self.lmax = min(present), max(present)
+        self.hash_ws = torch.empty(hash_workspace_bytes(self.n), dtype=torch.uint8, device="cuda")
+        self.nbr27 = torch.empty((self.n, 27), dtype=torch.int32, device="cuda")
+        self.father_cell = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        self.son_mask = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        self.corr_base = int(begin[self.lmin + 1])
+        nfine = self.n - self.corr_base
+        self.corr = torch.empty(max(nfine, 1) * 30, dtype=torch.float64, device="cuda") if nfine > 0 else None
+        self.rebuild()
+        st, bad = check_ws(self.hash_ws)
+        if st != L.RG_OK:
+            raise RgError(st, "tree build failed (%s) at index %d" % (L.lib().rg_status_string(st).decode(), bad))
+        self._desc = self._descriptor()
+
+    def rebuild(self):
+        hash_build(self.keys, self.hash_ws)
+        build_neighbours(self.hash_ws, self.keys, self.lmin, self.bc, self.nbr27, self.father_cell, self.son_mask)
+
+    def _descriptor(self):
+        t = RgTree()
+        t.n_oct, t.lmin, t.lmax, t.bc = self.n, self.lmin, self.lmax, self.bc
+        for l in range(RG_MAX_LEVEL + 2):
+            t.level_begin[l] = int(self.level_begin[l])
+        t.d_keys = self.keys.data_ptr()
+        t.d_hash_ws = self.hash_ws.data_ptr()
+        t.hash_ws_bytes = self.hash_ws.numel()
+        t.d_nbr27 = self.nbr27.data_ptr()
+        t.d_father_cell = self.father_cell.data_ptr()
+        t.d_son_mask = self.son_mask.data_ptr()
+        t.d_corr = self.corr.data_ptr() if self.corr is not None else None
+        return t
+
+    def to_key_order(self, u_input_order):
+        """Device copy of a per-cell state given in input oct order, in key order."""
+        u = torch.as_tensor(np.ascontiguousarray(u_input_order, dtype=np.float64)).to("cuda")
+        return permute_rows(u, self.perm)
+
+    def step(self, uold, unew, gamma, cfl, form=RG_FP64, rebuild=False, dt=None, tune=None):
+        dt = dt if dt is not None else torch.empty(1, dtype=torch.float64, device="cuda")
+        flags = RG_STEP_REBUILD if rebuild else 0
+        check(L.lib().rg_step(ctypes.byref(self._desc), _ptr(uold), _ptr(unew), float(gamma), float(cfl), int(form),
+                              flags, _ptr(dt), _tuning(tune), _stream()))
+        return dt
+
+    def run(self, u, gamma, cfl, nsteps, form=RG_FP64, rebuild=False, tune=None):
+        """nsteps steps; returns (state, dts) with the state in key order."""
+        a, b = u.clone(), torch.empty_like(u)
+        dts = torch.empty(nsteps, dtype=torch.float64, device="cuda")
+        for s in range(nsteps):
+            self.step(a, b, gamma, cfl, form, rebuild, dts[s:s + 1], tune)
+            a, b = b, a
+        return a, dts

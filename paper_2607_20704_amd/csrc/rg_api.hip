@@ -1,0 +1,103 @@
+// rg_api.hip -- status strings, error detail and the whole-step driver.
+//
+// rg_step follows the order of the per-step phases in the paper's Table 1
+// (compute dt, set unew, godunov, set uold, upload) with a global time step:
+// optional hash + neighbour rebuild (Sec. 2.1, 2.3), CFL dt, every level's
+// hydro update from uold into unew, coarse-fine flux correction, and
+// restriction from the finest level down.
+#include <cstdarg>
+#include <cstring>
+
+#include "rg_internal.hpp"
+
+namespace rg {
+
+namespace {
+thread_local std::string g_detail;
+}
+
+void set_detail(const std::string &s) { g_detail = s; }
+
+rg_status fail(rg_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_detail = std::string(rg_status_string(st)) + ": " + buf;
+    return st;
+}
+
+rg_status launch_status(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(RG_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return RG_OK;
+}
+
+struct LevelArgs;
+rg_status hydro_level(const LevelArgs &a, int form, const rg_tuning *tune, hipStream_t s);
+
+}  // namespace rg
+
+using namespace rg;
+
+extern "C" {
+
+int rg_abi_version(void) { return RG_ABI_VERSION; }
+
+const char *rg_status_string(int status)
+{
+    switch (status) {
+    case RG_OK: return "RG_OK";
+    case RG_EINVAL: return "RG_EINVAL";
+    case RG_EFULL: return "RG_EFULL";
+    case RG_EDUPKEY: return "RG_EDUPKEY";
+    case RG_EUNGRADED: return "RG_EUNGRADED";
+    case RG_ENONFINITE: return "RG_ENONFINITE";
+    case RG_EHIP: return "RG_EHIP";
+    case RG_ENOTSUP: return "RG_ENOTSUP";
+    default: return "RG_UNKNOWN";
+    }
+}
+
+size_t rg_last_error_detail(char *buf, size_t len)
+{
+    if (buf && len) {
+        size_t n = g_detail.size() < len - 1 ? g_detail.size() : len - 1;
+        memcpy(buf, g_detail.data(), n);
+        buf[n] = '\0';
+    }
+    return g_detail.size();
+}
+
+rg_status rg_step(const rg_tree *t, const double *d_uold, double *d_unew, double gamma, double cfl, int form,
+                  unsigned flags, double *d_dt, const rg_tuning *tune, void *stream)
+{
+    RG_REQUIRE(t && d_uold && d_unew && d_dt, "null pointer");
+    RG_REQUIRE(t->n_oct > 0 && t->lmin >= 1 && t->lmax >= t->lmin && t->lmax <= RG_MAX_LEVEL, "bad tree");
+    RG_REQUIRE(t->level_begin[t->lmin] == 0 && t->level_begin[t->lmax + 1] == t->n_oct, "bad level ranges");
+    RG_REQUIRE(t->lmin == t->lmax || t->d_corr, "a multilevel tree needs a correction buffer");
+    if (flags & RG_STEP_REBUILD) {
+        RG_TRY(rg_hash_build(t->d_keys, t->n_oct, t->d_hash_ws, t->hash_ws_bytes, stream));
+        RG_TRY(rg_build_neighbours(t->d_hash_ws, t->d_keys, t->n_oct, t->lmin, t->bc, t->d_nbr27, t->d_father_cell,
+                                   t->d_son_mask, stream));
+    }
+    RG_TRY(rg_cfl_dt(d_uold, t->d_son_mask, t->level_begin, t->lmin, t->lmax, gamma, cfl, d_dt, stream));
+    const int64_t corr_base = t->level_begin[t->lmin + 1];
+    for (int l = t->lmin; l <= t->lmax; ++l) {
+        const int64_t b = t->level_begin[l], e = t->level_begin[l + 1];
+        if (e == b) continue;
+        RG_TRY(rg_hydro_step_level(ldexp(1.0, -l), d_dt, gamma, d_uold, d_unew, t->d_nbr27, t->d_son_mask, b, e,
+                                   l > t->lmin ? t->d_corr : nullptr, corr_base, form, tune, stream));
+    }
+    if (t->lmax > t->lmin) {
+        RG_TRY(rg_apply_coarse_corrections(d_unew, t->d_corr, corr_base, t->d_nbr27, corr_base, t->n_oct, stream));
+        for (int l = t->lmax; l > t->lmin; --l)
+            RG_TRY(rg_restrict_level(d_unew, t->d_father_cell, t->level_begin[l], t->level_begin[l + 1], stream));
+    }
+    return RG_OK;
+}
+
+}  // extern "C"

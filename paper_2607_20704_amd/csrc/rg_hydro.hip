@@ -1,0 +1,612 @@
+// rg_hydro.hip -- per-level hydrodynamics update on gfx950.
+//
+// Paper Sec. 3: a second-order Godunov MUSCL-Hancock predictor-corrector
+// with an HLLC Riemann solver; each oct is updated from a local stencil of
+// 6x6x6 cells (the oct plus two ghost cells per side) holding uold:
+// conservative -> primitive, face-centred states, Riemann fluxes, update into
+// unew.  Table 1 rows "compute dt" and "hydro - upload" are rg_cfl_dt and
+// rg_restrict_level.
+//
+// Kernel shape: a workgroup serves G consecutive octs of one level (Hilbert
+// order keeps them spatially close).  Every phase is a flat loop over
+// (oct, item) pairs so the 64-wide wavefronts stay busy:
+//   A gather + primitive variables for the 80 stencil cells an oct needs
+//   B slopes, predictor, face states for the 32 cells touching its faces
+//   C HLLC on the 36 faces of its 8 cells
+//   D conservative update of its 40 (cell, variable) values
+//   E fluxes owed to coarse neighbours (6 sides x 5 variables)
+// All intermediate data stay in LDS; HBM sees uold (stencil reads, mostly
+// L2 hits between neighbouring octs), the neighbour list and unew.
+#include "rg_internal.hpp"
+
+namespace rg {
+namespace {
+
+constexpr int NV = 5;
+
+// ---------------------------------------------------------------------------
+// stencil tables (positions are cell offsets from the oct origin, -2..3)
+// ---------------------------------------------------------------------------
+
+struct StencilTables {
+    int8_t wpos[80][3];    // cells whose primitive variables are needed
+    int8_t rpos[32][3];    // cells that are reconstructed (8 own + 24 face layer)
+    int8_t tile2w[216];    // (x+2) + 6(y+2) + 36(z+2) -> index into wpos, -1 if unused
+};
+
+constexpr int tile_index(int x, int y, int z) { return (x + 2) + 6 * (y + 2) + 36 * (z + 2); }
+
+constexpr StencilTables make_tables()
+{
+    StencilTables t{};
+    for (int i = 0; i < 216; ++i) t.tile2w[i] = -1;
+    int nw = 0, nr = 0;
+    // own cells
+    for (int c = 0; c < 8; ++c) {
+        int p[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+        for (int a = 0; a < 3; ++a) {
+            t.wpos[nw][a] = static_cast<int8_t>(p[a]);
+            t.rpos[nr][a] = static_cast<int8_t>(p[a]);
+        }
+        t.tile2w[tile_index(p[0], p[1], p[2])] = static_cast<int8_t>(nw);
+        ++nw;
+        ++nr;
+    }
+    // face layer (reconstructed) then outer layer, along each axis
+    for (int layer = 0; layer < 2; ++layer)
+        for (int a = 0; a < 3; ++a)
+            for (int side = 0; side < 2; ++side)
+                for (int q = 0; q < 4; ++q) {
+                    int p[3];
+                    int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+                    p[a] = layer == 0 ? (side ? 2 : -1) : (side ? 3 : -2);
+                    p[t1] = q & 1;
+                    p[t2] = q >> 1;
+                    for (int b = 0; b < 3; ++b) t.wpos[nw][b] = static_cast<int8_t>(p[b]);
+                    t.tile2w[tile_index(p[0], p[1], p[2])] = static_cast<int8_t>(nw);
+                    ++nw;
+                    if (layer == 0) {
+                        for (int b = 0; b < 3; ++b) t.rpos[nr][b] = static_cast<int8_t>(p[b]);
+                        ++nr;
+                    }
+                }
+    // edge cells: two coordinates in {-1, 2}, the third in {0, 1}
+    for (int a = 0; a < 3; ++a)        // the axis that stays inside
+        for (int q = 0; q < 8; ++q) {
+            int p[3];
+            int u = a == 0 ? 1 : 0, v = a == 2 ? 1 : 2;
+            p[a] = q & 1;
+            p[u] = (q >> 1) & 1 ? 2 : -1;
+            p[v] = (q >> 2) & 1 ? 2 : -1;
+            for (int b = 0; b < 3; ++b) t.wpos[nw][b] = static_cast<int8_t>(p[b]);
+            t.tile2w[tile_index(p[0], p[1], p[2])] = static_cast<int8_t>(nw);
+            ++nw;
+        }
+    return t;
+}
+
+__constant__ StencilTables c_tab = make_tables();
+
+// face f = 12 a + 4 c + t1 + 2 t2 on axis a between cells c-1 and c along a;
+// (t1, t2) are the other two axes in increasing order
+__device__ __forceinline__ int face_id(int a, int c, int t1, int t2) { return 12 * a + 4 * c + t1 + 2 * t2; }
+
+__device__ __forceinline__ int nslot(int sx, int sy, int sz) { return (sx + 1) + 3 * (sy + 1) + 9 * (sz + 1); }
+
+__device__ __forceinline__ int slot_of(int x) { return x < 0 ? -1 : (x > 1 ? 1 : 0); }
+
+// ---------------------------------------------------------------------------
+// per-cell and per-face arithmetic; FP64 instances follow the CPU
+// reference's expression order exactly (the library is built without FMA
+// contraction)
+// ---------------------------------------------------------------------------
+
+template <typename R> struct Math;
+
+template <> struct Math<double> {
+    static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+    static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+};
+
+template <> struct Math<float> {
+    static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+};
+
+// conservative -> primitive in double, floors applied
+__device__ __forceinline__ void prim64(const double *U, double gamma, double *W)
+{
+    double rho = U[0] < RG_RHO_MIN ? RG_RHO_MIN : U[0];
+    double inv = 1.0 / rho;
+    double u = U[1] * inv;
+    double v = U[2] * inv;
+    double w = U[3] * inv;
+    double q = (u * u + v * v) + w * w;
+    double ek = 0.5 * rho * q;
+    double p = (gamma - 1.0) * (U[4] - ek);
+    if (p < RG_P_MIN) p = RG_P_MIN;
+    W[0] = rho;
+    W[1] = u;
+    W[2] = v;
+    W[3] = w;
+    W[4] = p;
+}
+
+template <typename R> __device__ __forceinline__ R minmod(R a, R b)
+{
+    if (a > R(0) && b > R(0)) return a < b ? a : b;
+    if (a < R(0) && b < R(0)) return a > b ? a : b;
+    return R(0);
+}
+
+// Hancock half step W' = W - h sum_d A_d(W) dW_d (primitive Euler equations)
+template <typename R>
+__device__ __forceinline__ void predict(const R *W, const R (*dW)[NV], R h, R gamma, R *Wp)
+{
+    const R rho = W[0], u = W[1], v = W[2], w = W[3], p = W[4];
+    const R inv = Math<R>::div(R(1), rho);
+    const R div = (dW[0][1] + dW[1][2]) + dW[2][3];
+    Wp[0] = rho - h * (((u * dW[0][0] + v * dW[1][0]) + w * dW[2][0]) + rho * div);
+    Wp[1] = u - h * (((u * dW[0][1] + v * dW[1][1]) + w * dW[2][1]) + dW[0][4] * inv);
+    Wp[2] = v - h * (((u * dW[0][2] + v * dW[1][2]) + w * dW[2][2]) + dW[1][4] * inv);
+    Wp[3] = w - h * (((u * dW[0][3] + v * dW[1][3]) + w * dW[2][3]) + dW[2][4] * inv);
+    Wp[4] = p - h * (((u * dW[0][4] + v * dW[1][4]) + w * dW[2][4]) + (gamma * p) * div);
+}
+
+// HLLC across a face normal to axis `dir`: Davis wave speeds, contact speed
+// and star pressure in the form symmetric in the two sides, region chosen
+// by S_L > 0, S* > 0, S_R > 0 in that order.  Computed branch-free: both
+// candidate states are formed and one is selected.
+template <typename R>
+__device__ __forceinline__ void hllc(const R *WL, const R *WR, int dir, R gamma, R g1, R *F)
+{
+    const R rl = WL[0], pl = WL[4], ul = WL[1 + dir];
+    const R rr = WR[0], pr = WR[4], ur = WR[1 + dir];
+    const R cl = Math<R>::sqrt_(Math<R>::div(gamma * pl, rl));
+    const R cr = Math<R>::sqrt_(Math<R>::div(gamma * pr, rr));
+    const R sl = (ul - cl) < (ur - cr) ? (ul - cl) : (ur - cr);
+    const R sr = (ul + cl) > (ur + cr) ? (ul + cl) : (ur + cr);
+    const R ml = rl * (ul - sl);
+    const R mr = rr * (sr - ur);
+    const R inv = Math<R>::div(R(1), ml + mr);
+    const R sstar = ((mr * ur + ml * ul) + (pl - pr)) * inv;
+    const R pstar = ((mr * pl + ml * pr) + ml * mr * (ul - ur)) * inv;
+
+    const bool useL = (sl > R(0)) || (sstar > R(0));
+    const bool outer = useL ? (sl > R(0)) : !(sr > R(0));
+    const R *W = useL ? WL : WR;
+    const R s = useL ? sl : sr;
+    const R rho = W[0], un = W[1 + dir], p = W[4];
+    const R q = (W[1] * W[1] + W[2] * W[2]) + W[3] * W[3];
+    const R E = p * g1 + R(0.5) * rho * q;
+    const R d = Math<R>::div(R(1), s - sstar);
+    const R rs = outer ? rho : rho * (s - un) * d;
+    const R es = outer ? E : (((s - un) * E - p * un) + pstar * sstar) * d;
+    const R ss = outer ? un : sstar;
+    const R ps = outer ? p : pstar;
+    const R m = rs * ss;
+    F[0] = m;
+    F[1] = dir == 0 ? (m * ss + ps) : (m * W[1]);
+    F[2] = dir == 1 ? (m * ss + ps) : (m * W[2]);
+    F[3] = dir == 2 ? (m * ss + ps) : (m * W[3]);
+    F[4] = (es + ps) * ss;
+}
+
+// ---------------------------------------------------------------------------
+// the level kernel
+// ---------------------------------------------------------------------------
+
+struct LevelArgs {
+    const double *uold;
+    double *unew;
+    const int32_t *nbr27;
+    const uint32_t *son;
+    double *corr;
+    int64_t corr_base;
+    int64_t oct_begin, oct_end;
+    const double *dt;     // device scalar
+    double dx;
+    double gamma;
+};
+
+template <typename R, int G> struct Smem {
+    int32_t nb[G][27];
+    uint32_t sm[G][7];          // son masks: own, then sides x-, x+, y-, y+, z-, z+
+    double u[G][8][NV];         // uold of the oct's own cells
+    R w[G][80][NV];             // primitive variables of the stencil cells
+    R fs[G][36][2][NV];         // face states: [face][0] left of the face, [1] right
+    double g[G][36][NV];        // G = F dt/dx per face
+};
+
+template <typename R, int G, int NT>
+__device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, int count, Smem<R, G> &S)
+{
+    const int tid = threadIdx.x;
+    const double r = *a.dt / a.dx;
+    const double h64 = 0.5 * r;
+    const R h = static_cast<R>(h64);
+    const R gam = static_cast<R>(a.gamma);
+    const double g1d = 1.0 / (a.gamma - 1.0);
+    const R g1 = static_cast<R>(g1d);
+
+    // neighbour entries and son masks
+    for (int it = tid; it < G * 27; it += NT) {
+        int g = it / 27, s = it - 27 * g;
+        S.nb[g][s] = g < count ? a.nbr27[27 * (first + g) + s] : 0;
+    }
+    __syncthreads();
+    for (int it = tid; it < G * 7; it += NT) {
+        int g = it / 7, k = it - 7 * g;
+        uint32_t m = 0;
+        if (g < count) {
+            int e;
+            if (k == 0) {
+                e = static_cast<int>(first + g);
+            } else {
+                int ax = (k - 1) >> 1, hi = (k - 1) & 1;
+                int sx = ax == 0 ? (hi ? 1 : -1) : 0, sy = ax == 1 ? (hi ? 1 : -1) : 0, sz = ax == 2 ? (hi ? 1 : -1) : 0;
+                e = S.nb[g][nslot(sx, sy, sz)];
+            }
+            if (e >= 0) m = a.son[e];
+        }
+        S.sm[g][k] = m;
+    }
+
+    // A: gather uold for the stencil cells, primitive variables
+    for (int it = tid; it < G * 80; it += NT) {
+        int g = it / 80, wc = it - 80 * g;
+        if (g >= count) continue;
+        int c[3] = {c_tab.wpos[wc][0], c_tab.wpos[wc][1], c_tab.wpos[wc][2]};
+        int s[3] = {slot_of(c[0]), slot_of(c[1]), slot_of(c[2])};
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            if (s[ax] != 0) {
+                int fs = nslot(ax == 0 ? s[0] : 0, ax == 1 ? s[1] : 0, ax == 2 ? s[2] : 0);
+                if (S.nb[g][fs] == RG_NBR_OUTSIDE) {
+                    c[ax] = s[ax] > 0 ? 1 : 0;
+                    s[ax] = 0;
+                }
+            }
+        }
+        int e = S.nb[g][nslot(s[0], s[1], s[2])];
+        // a consistent list never leaves an outside slot here; an
+        // inconsistent one reads the oct itself rather than stray memory
+        if (e == RG_NBR_OUTSIDE) e = static_cast<int>(first + g);
+        const int64_t cell = e >= 0 ? 8 * int64_t(e) + ((c[0] & 1) + 2 * (c[1] & 1) + 4 * (c[2] & 1))
+                                    : (-1 - int64_t(e));
+        double U[NV], W[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) U[v] = a.uold[NV * cell + v];
+        prim64(U, a.gamma, W);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) S.w[g][wc][v] = static_cast<R>(W[v]);
+        if (wc < 8) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) S.u[g][wc][v] = U[v];
+        }
+    }
+    __syncthreads();
+
+    // B: slopes, predictor and face states
+    for (int it = tid; it < G * 32; it += NT) {
+        int g = it / 32, rc = it - 32 * g;
+        if (g >= count) continue;
+        const int x = c_tab.rpos[rc][0], y = c_tab.rpos[rc][1], z = c_tab.rpos[rc][2];
+        const R *w0 = S.w[g][c_tab.tile2w[tile_index(x, y, z)]];
+        R dW[3][NV];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const R *wm = S.w[g][c_tab.tile2w[tile_index(x - (ax == 0), y - (ax == 1), z - (ax == 2))]];
+            const R *wp = S.w[g][c_tab.tile2w[tile_index(x + (ax == 0), y + (ax == 1), z + (ax == 2))]];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) dW[ax][v] = minmod<R>(w0[v] - wm[v], wp[v] - w0[v]);
+        }
+        R W0[NV], Wp[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) W0[v] = w0[v];
+        predict<R>(W0, dW, h, gam, Wp);
+        const int p[3] = {x, y, z};
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const int t1 = ax == 0 ? 1 : 0, t2 = ax == 2 ? 1 : 2;
+            const bool inside_t = p[t1] >= 0 && p[t1] <= 1 && p[t2] >= 0 && p[t2] <= 1;
+            if (!inside_t) continue;
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                // high-side state sits left of face c = p+1; low-side state right of face c = p
+                const int c = side ? p[ax] + 1 : p[ax];
+                if (c < 0 || c > 2) continue;
+                R st[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    st[v] = side ? (Wp[v] + R(0.5) * dW[ax][v]) : (Wp[v] - R(0.5) * dW[ax][v]);
+                if (st[0] < R(RG_RHO_MIN)) st[0] = R(RG_RHO_MIN);
+                if (st[4] < R(RG_P_MIN)) st[4] = R(RG_P_MIN);
+                R *dst = S.fs[g][face_id(ax, c, p[t1], p[t2])][side ? 0 : 1];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) dst[v] = st[v];
+            }
+        }
+    }
+    __syncthreads();
+
+    // C: HLLC on the 36 faces
+    for (int it = tid; it < G * 36; it += NT) {
+        int g = it / 36, f = it - 36 * g;
+        if (g >= count) continue;
+        const int ax = f / 12, c = (f / 4) % 3, t1 = f & 1, t2 = (f >> 1) & 1;
+        R L[NV], Rr[NV], F[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            L[v] = S.fs[g][f][0][v];
+            Rr[v] = S.fs[g][f][1][v];
+        }
+        hllc<R>(L, Rr, ax, gam, g1, F);
+        // split test for the two cells: position c-1 and c along the axis
+        bool zero = false;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int pa = c - 1 + k;
+            int px[3];
+            px[ax] = pa;
+            px[ax == 0 ? 1 : 0] = t1;
+            px[ax == 2 ? 1 : 2] = t2;
+            const int bit = (px[0] & 1) + 2 * (px[1] & 1) + 4 * (px[2] & 1);
+            const uint32_t m = pa < 0 ? S.sm[g][1 + 2 * ax] : (pa > 1 ? S.sm[g][2 + 2 * ax] : S.sm[g][0]);
+            zero = zero || ((m >> bit) & 1u);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) S.g[g][f][v] = zero ? 0.0 : static_cast<double>(F[v]) * r;
+    }
+    __syncthreads();
+
+    // D: update
+    for (int it = tid; it < G * 8 * NV; it += NT) {
+        int g = it / (8 * NV), k = it - 8 * NV * g;
+        if (g >= count) continue;
+        const int cidx = k / NV, v = k - NV * cidx;
+        const int ix = cidx & 1, iy = (cidx >> 1) & 1, iz = cidx >> 2;
+        const double gxm = S.g[g][face_id(0, ix, iy, iz)][v], gxp = S.g[g][face_id(0, ix + 1, iy, iz)][v];
+        const double gym = S.g[g][face_id(1, iy, ix, iz)][v], gyp = S.g[g][face_id(1, iy + 1, ix, iz)][v];
+        const double gzm = S.g[g][face_id(2, iz, ix, iy)][v], gzp = S.g[g][face_id(2, iz + 1, ix, iy)][v];
+        a.unew[8 * NV * (first + g) + k] = ((S.u[g][cidx][v] + (gxm - gxp)) + (gym - gyp)) + (gzm - gzp);
+    }
+
+    // E: flux owed to coarse neighbours
+    if (a.corr) {
+        for (int it = tid; it < G * 6 * NV; it += NT) {
+            int g = it / (6 * NV), k = it - 6 * NV * g;
+            if (g >= count) continue;
+            const int side = k / NV, v = k - NV * side;
+            const int ax = side >> 1, hi = side & 1;
+            const int e = S.nb[g][nslot(ax == 0 ? (hi ? 1 : -1) : 0, ax == 1 ? (hi ? 1 : -1) : 0,
+                                        ax == 2 ? (hi ? 1 : -1) : 0)];
+            if (!(e < 0 && e != RG_NBR_OUTSIDE)) continue;
+            const int c = hi ? 2 : 0;
+            const double sum = (S.g[g][face_id(ax, c, 0, 0)][v] + S.g[g][face_id(ax, c, 1, 0)][v]) +
+                               (S.g[g][face_id(ax, c, 0, 1)][v] + S.g[g][face_id(ax, c, 1, 1)][v]);
+            const double d = 0.125 * sum;
+            a.corr[30 * (first + g - a.corr_base) + k] = hi ? d : -d;
+        }
+    }
+}
+
+template <typename R, int G, int NT>
+__global__ __launch_bounds__(NT) void k_hydro_level(LevelArgs a)
+{
+    __shared__ Smem<R, G> S;
+    const int64_t first = a.oct_begin + int64_t(blockIdx.x) * G;
+    const int64_t left = a.oct_end - first;
+    const int count = left < G ? static_cast<int>(left) : G;
+    hydro_group<R, G, NT>(a, first, count, S);
+}
+
+// ---------------------------------------------------------------------------
+// CFL time step, corrections, restriction
+// ---------------------------------------------------------------------------
+
+struct DtArgs {
+    const double *u;
+    const uint32_t *son;
+    int64_t begin[RG_MAX_LEVEL + 2];
+    int lmin, lmax;
+    double gamma, cfl;
+    int64_t n_cell;
+    unsigned long long *dt_bits;
+};
+
+__global__ void k_set_u64(unsigned long long *p, unsigned long long v) { *p = v; }
+
+__global__ __launch_bounds__(256) void k_cfl_dt(DtArgs a)
+{
+    const int64_t cell = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    double best = __longlong_as_double(0x7ff0000000000000ll);   // +inf
+    if (cell < a.n_cell) {
+        const int64_t o = cell >> 3;
+        const int c = static_cast<int>(cell & 7);
+        if (!((a.son[o] >> c) & 1u)) {
+            int l = a.lmin;
+            while (l < a.lmax && o >= a.begin[l + 1]) ++l;
+            const double dx = ldexp(1.0, -l);
+            double U[NV], W[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) U[v] = a.u[NV * cell + v];
+            prim64(U, a.gamma, W);
+            const double cs = sqrt((a.gamma * W[4]) / W[0]);
+            const double sp = ((fabs(W[1]) + fabs(W[2])) + fabs(W[3])) + 3.0 * cs;
+            const double d = dx / sp;
+            // cfl * min(d) == min(cfl * d): rounding a product by a positive
+            // constant is monotone
+            const double cd = a.cfl * d;
+            if (cd < best) best = cd;
+        }
+    }
+    // wavefront minimum, then across the block's waves, then one atomic
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        double o = __shfl_xor(best, off, 64);
+        best = o < best ? o : best;
+    }
+    __shared__ double s_min[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) s_min[wave] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = s_min[0];
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = s_min[k] < m ? s_min[k] : m;
+        // positive doubles order like their bit patterns; NaN never wins
+        if (m < __longlong_as_double(0x7ff0000000000000ll))
+            atomicMin(a.dt_bits, static_cast<unsigned long long>(__double_as_longlong(m)));
+    }
+}
+
+__global__ void k_coarse_corr(double *__restrict__ unew, const double *__restrict__ corr, int64_t corr_base,
+                              const int32_t *__restrict__ nbr27, int64_t ob, int64_t oe, int side)
+{
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t o = ob + t / NV;
+    const int v = static_cast<int>(t % NV);
+    if (o >= oe) return;
+    const int ax = side >> 1, hi = side & 1;
+    const int slot = nslot(ax == 0 ? (hi ? 1 : -1) : 0, ax == 1 ? (hi ? 1 : -1) : 0, ax == 2 ? (hi ? 1 : -1) : 0);
+    const int32_t e = nbr27[27 * o + slot];
+    if (!(e < 0 && e != RG_NBR_OUTSIDE)) return;
+    const int64_t C = -1 - int64_t(e);
+    unew[NV * C + v] = unew[NV * C + v] + corr[30 * (o - corr_base) + NV * side + v];
+}
+
+__global__ void k_restrict(double *__restrict__ u, const int32_t *__restrict__ father, int64_t ob, int64_t oe)
+{
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t o = ob + t / NV;
+    const int v = static_cast<int>(t % NV);
+    if (o >= oe) return;
+    const double *c = u + 8 * NV * o + v;
+    const double sum = ((c[0] + c[5]) + (c[10] + c[15])) + ((c[20] + c[25]) + (c[30] + c[35]));
+    u[NV * int64_t(father[o]) + v] = 0.125 * sum;
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------
+
+template <typename R, int G, int NT> rg_status launch_level(const LevelArgs &a, hipStream_t s)
+{
+    const int64_t n = a.oct_end - a.oct_begin;
+    const unsigned blocks = static_cast<unsigned>((n + G - 1) / G);
+    k_hydro_level<R, G, NT><<<blocks, NT, 0, s>>>(a);
+    return launch_status("rg_hydro_step_level");
+}
+
+template <typename R> rg_status launch_form(const LevelArgs &a, const rg_tuning *tune, hipStream_t s)
+{
+    const int g = tune && tune->octs_per_group ? tune->octs_per_group : 4;
+    const int nt = tune && tune->threads ? tune->threads : 256;
+    if (g == 4 && nt == 256) return launch_level<R, 4, 256>(a, s);
+    if (g == 2 && nt == 128) return launch_level<R, 2, 128>(a, s);
+    if (g == 8 && nt == 256) return launch_level<R, 8, 256>(a, s);
+    if (g == 7 && nt == 256) return launch_level<R, 7, 256>(a, s);
+    if (g == 3 && nt == 128) return launch_level<R, 3, 128>(a, s);
+    return fail(RG_ENOTSUP, "no hydro kernel for %d octs per group and %d threads", g, nt);
+}
+
+}  // namespace
+
+rg_status hydro_level(const LevelArgs &a, int form, const rg_tuning *tune, hipStream_t s)
+{
+    if (a.oct_end <= a.oct_begin) return RG_OK;
+    if (form == RG_FP64) return launch_form<double>(a, tune, s);
+    return launch_form<float>(a, tune, s);
+}
+
+}  // namespace rg
+
+using namespace rg;
+
+extern "C" {
+
+size_t rg_corr_workspace_bytes(int64_t n_octs) { return static_cast<size_t>(n_octs < 0 ? 0 : n_octs) * 30 * 8; }
+
+rg_status rg_hydro_step_level(double dx, const double *d_dt, double gamma, const double *d_uold, double *d_unew,
+                              const int32_t *d_nbr27, const uint32_t *d_son_mask, int64_t oct_begin, int64_t oct_end,
+                              double *d_corr, int64_t corr_base, int form, const rg_tuning *tune, void *stream)
+{
+    RG_REQUIRE(oct_begin >= 0 && oct_end >= oct_begin && oct_end <= (int64_t(1) << 28), "bad oct range");
+    if (oct_end == oct_begin) return RG_OK;
+    RG_REQUIRE(d_dt && d_uold && d_unew && d_nbr27 && d_son_mask, "null pointer");
+    RG_REQUIRE(d_uold != d_unew, "uold and unew must not alias");
+    RG_REQUIRE(aligned(d_uold, 8) && aligned(d_unew, 8) && aligned(d_dt, 8), "misaligned pointer");
+    RG_REQUIRE(form == RG_FP64 || form == RG_MIXED, "bad form %d", form);
+    RG_REQUIRE(dx > 0 && gamma > 1, "bad dx or gamma");
+    RG_REQUIRE(!d_corr || corr_base <= oct_begin, "corr_base beyond the oct range");
+    LevelArgs a;
+    a.uold = d_uold;
+    a.unew = d_unew;
+    a.nbr27 = d_nbr27;
+    a.son = d_son_mask;
+    a.corr = d_corr;
+    a.corr_base = corr_base;
+    a.oct_begin = oct_begin;
+    a.oct_end = oct_end;
+    a.dt = d_dt;
+    a.dx = dx;
+    a.gamma = gamma;
+    return hydro_level(a, form, tune, as_stream(stream));
+}
+
+rg_status rg_apply_coarse_corrections(double *d_unew, const double *d_corr, int64_t corr_base, const int32_t *d_nbr27,
+                                      int64_t oct_begin, int64_t oct_end, void *stream)
+{
+    RG_REQUIRE(oct_begin >= 0 && oct_end >= oct_begin, "bad oct range");
+    if (oct_end == oct_begin) return RG_OK;
+    RG_REQUIRE(d_unew && d_corr && d_nbr27, "null pointer");
+    RG_REQUIRE(corr_base <= oct_begin, "corr_base beyond the oct range");
+    hipStream_t s = as_stream(stream);
+    const int64_t items = (oct_end - oct_begin) * NV;
+    for (int side = 0; side < 6; ++side) {
+        k_coarse_corr<<<grid_for(items, 256), 256, 0, s>>>(d_unew, d_corr, corr_base, d_nbr27, oct_begin, oct_end,
+                                                           side);
+        RG_TRY(launch_status("rg_apply_coarse_corrections"));
+    }
+    return RG_OK;
+}
+
+rg_status rg_restrict_level(double *d_u, const int32_t *d_father_cell, int64_t oct_begin, int64_t oct_end,
+                            void *stream)
+{
+    RG_REQUIRE(oct_begin >= 0 && oct_end >= oct_begin, "bad oct range");
+    if (oct_end == oct_begin) return RG_OK;
+    RG_REQUIRE(d_u && d_father_cell, "null pointer");
+    const int64_t items = (oct_end - oct_begin) * NV;
+    k_restrict<<<grid_for(items, 256), 256, 0, as_stream(stream)>>>(d_u, d_father_cell, oct_begin, oct_end);
+    return launch_status("rg_restrict_level");
+}
+
+rg_status rg_cfl_dt(const double *d_u, const uint32_t *d_son_mask, const int64_t *h_level_begin, int lmin, int lmax,
+                    double gamma, double cfl, double *d_dt, void *stream)
+{
+    RG_REQUIRE(d_u && d_son_mask && h_level_begin && d_dt, "null pointer");
+    RG_REQUIRE(lmin >= 1 && lmax >= lmin && lmax <= RG_MAX_LEVEL, "bad level range");
+    RG_REQUIRE(gamma > 1 && cfl > 0, "bad gamma or cfl");
+    RG_REQUIRE(aligned(d_dt, 8), "misaligned dt");
+    DtArgs a;
+    a.u = d_u;
+    a.son = d_son_mask;
+    for (int l = 0; l < RG_MAX_LEVEL + 2; ++l) a.begin[l] = h_level_begin[l];
+    a.lmin = lmin;
+    a.lmax = lmax;
+    a.gamma = gamma;
+    a.cfl = cfl;
+    const int64_t n_oct = h_level_begin[lmax + 1] - h_level_begin[lmin];
+    RG_REQUIRE(h_level_begin[lmin] == 0 && n_oct >= 0, "level ranges must start at 0");
+    a.n_cell = 8 * n_oct;
+    a.dt_bits = reinterpret_cast<unsigned long long *>(d_dt);
+    hipStream_t s = as_stream(stream);
+    k_set_u64<<<1, 1, 0, s>>>(a.dt_bits, 0x7ff0000000000000ull);
+    RG_TRY(launch_status("rg_cfl_dt init"));
+    if (a.n_cell == 0) return RG_OK;
+    k_cfl_dt<<<grid_for(a.n_cell, 256), 256, 0, s>>>(a);
+    return launch_status("rg_cfl_dt");
+}
+
+}  // extern "C"

@@ -1,0 +1,270 @@
+// rg_internal.hpp -- shared pieces of the gfx950 library behind include/rg.h.
+//
+// Device helpers for the oct keys (Sec. 2.1 key tuple, Sec. 2.2 Hilbert
+// order) and the FNV-1a hash (Sec. 2.1, Sec. 6), the hash workspace header,
+// and host-side error plumbing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "rg.h"
+
+namespace rg {
+
+// ---------------------------------------------------------------------------
+// error plumbing (host)
+// ---------------------------------------------------------------------------
+
+void set_detail(const std::string &s);
+rg_status fail(rg_status st, const char *fmt, ...);
+// checks hipGetLastError() after a launch
+rg_status launch_status(const char *what);
+
+#define RG_REQUIRE(cond, ...)                                 \
+    do {                                                      \
+        if (!(cond)) return ::rg::fail(RG_EINVAL, __VA_ARGS__); \
+    } while (0)
+
+#define RG_TRY(expr)                          \
+    do {                                      \
+        rg_status _st = (expr);               \
+        if (_st != RG_OK) return _st;         \
+    } while (0)
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+inline unsigned grid_for(int64_t items, int threads)
+{
+    int64_t g = (items + threads - 1) / threads;
+    return static_cast<unsigned>(g < 1 ? 1 : g);
+}
+
+// ---------------------------------------------------------------------------
+// keys: 3-D Hilbert index after Skilling (2004), evaluated at order 20
+// ---------------------------------------------------------------------------
+
+constexpr int kHilbertOrder = 20;
+
+// every third bit: bit b of v goes to bit 3b
+__host__ __device__ inline uint64_t spread3(uint32_t v)
+{
+    uint64_t x = v & 0x1fffffull;
+    x = (x | (x << 32)) & 0x001f00000000ffffull;
+    x = (x | (x << 16)) & 0x001f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+// inverse of spread3
+__host__ __device__ inline uint32_t gather3(uint64_t x)
+{
+    x &= 0x1249249249249249ull;
+    x = (x | (x >> 2)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x >> 4)) & 0x100f00f00f00f00full;
+    x = (x | (x >> 8)) & 0x001f0000ff0000ffull;
+    x = (x | (x >> 16)) & 0x001f00000000ffffull;
+    x = (x | (x >> 32)) & 0x1fffffull;
+    return static_cast<uint32_t>(x);
+}
+
+// One bit plane of the axes -> transpose pass: for every axis, reflect the
+// low bits of axis 0 when that axis has the plane bit set, otherwise swap
+// the low bits of axis 0 and that axis.
+__host__ __device__ inline void hilbert_plane(uint32_t &a0, uint32_t &a1, uint32_t &a2, uint32_t q)
+{
+    const uint32_t low = q - 1;
+    if (a0 & q) a0 ^= low;
+    if (a1 & q) {
+        a0 ^= low;
+    } else {
+        uint32_t d = (a0 ^ a1) & low;
+        a0 ^= d;
+        a1 ^= d;
+    }
+    if (a2 & q) {
+        a0 ^= low;
+    } else {
+        uint32_t d = (a0 ^ a2) & low;
+        a0 ^= d;
+        a2 ^= d;
+    }
+}
+
+// index of (x, y, z), 0 <= x, y, z < 2^20, on the order-20 curve
+__host__ __device__ inline uint64_t hilbert_index20(uint32_t x, uint32_t y, uint32_t z)
+{
+    uint32_t a0 = x, a1 = y, a2 = z;
+#pragma unroll
+    for (int b = kHilbertOrder - 1; b >= 1; --b) hilbert_plane(a0, a1, a2, 1u << b);
+    // Gray code across the axes, then the parity correction of the top axis
+    a1 ^= a0;
+    a2 ^= a1;
+    uint32_t flip = 0;
+#pragma unroll
+    for (int b = kHilbertOrder - 1; b >= 1; --b)
+        if (a2 & (1u << b)) flip ^= (1u << b) - 1;
+    a0 ^= flip;
+    a1 ^= flip;
+    a2 ^= flip;
+    // transposed index: bit b of axis 0 is index bit 3b+2, axis 1 -> 3b+1, axis 2 -> 3b
+    return (spread3(a0) << 2) | (spread3(a1) << 1) | spread3(a2);
+}
+
+// point of the order-20 curve at index h
+__host__ __device__ inline void hilbert_point20(uint64_t h, uint32_t &x, uint32_t &y, uint32_t &z)
+{
+    uint32_t a0 = gather3(h >> 2), a1 = gather3(h >> 1), a2 = gather3(h);
+    // undo the Gray code
+    uint32_t t = a2 >> 1;
+    a2 ^= a1;
+    a1 ^= a0;
+    a0 ^= t;
+    // undo the plane passes, lowest plane first, axes in reverse order
+#pragma unroll
+    for (int b = 1; b < kHilbertOrder; ++b) {
+        const uint32_t q = 1u << b, low = q - 1;
+        if (a2 & q) {
+            a0 ^= low;
+        } else {
+            uint32_t d = (a0 ^ a2) & low;
+            a0 ^= d;
+            a2 ^= d;
+        }
+        if (a1 & q) {
+            a0 ^= low;
+        } else {
+            uint32_t d = (a0 ^ a1) & low;
+            a0 ^= d;
+            a1 ^= d;
+        }
+        if (a0 & q) a0 ^= low;
+    }
+    x = a0;
+    y = a1;
+    z = a2;
+}
+
+// K = 2^(3(l-1)) + H_(l-1)(i,j,k); 0 for coordinates out of range
+__host__ __device__ inline uint64_t oct_key(int32_t i, int32_t j, int32_t k, int32_t l)
+{
+    if (l < 1 || l > RG_MAX_LEVEL) return 0;
+    const int b = l - 1;
+    const int32_t n = 1 << b;
+    if (i < 0 || j < 0 || k < 0 || i >= n || j >= n || k >= n) return 0;
+    const int s = kHilbertOrder - b;
+    uint64_t h = hilbert_index20(static_cast<uint32_t>(i) << s, static_cast<uint32_t>(j) << s,
+                                 static_cast<uint32_t>(k) << s) >> (3 * s);
+    return (uint64_t(1) << (3 * b)) + h;
+}
+
+__host__ __device__ inline int key_level(uint64_t key)
+{
+#ifdef __HIP_DEVICE_COMPILE__
+    int top = 63 - __clzll(static_cast<long long>(key));
+#else
+    int top = 63 - __builtin_clzll(key);
+#endif
+    return top / 3 + 1;
+}
+
+// (i, j, k, l) of a valid key
+__host__ __device__ inline void key_coords(uint64_t key, int32_t &i, int32_t &j, int32_t &k, int32_t &l)
+{
+    l = key_level(key);
+    const int b = l - 1;
+    const int s = kHilbertOrder - b;
+    uint64_t h = key - (uint64_t(1) << (3 * b));
+    uint32_t x, y, z;
+    hilbert_point20(h << (3 * s), x, y, z);
+    i = static_cast<int32_t>(x >> s);
+    j = static_cast<int32_t>(y >> s);
+    k = static_cast<int32_t>(z >> s);
+}
+
+// ---------------------------------------------------------------------------
+// FNV-1a, 64 bit, over the 8 little-endian bytes of a key
+// ---------------------------------------------------------------------------
+
+__host__ __device__ inline uint64_t fnv1a64(uint64_t key)
+{
+    uint64_t h = 0xcbf29ce484222325ull;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        h ^= (key >> (8 * b)) & 0xffull;
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+
+// ---------------------------------------------------------------------------
+// hash workspace: header, then keys[cap], then values[cap]
+// ---------------------------------------------------------------------------
+
+struct HashHeader {
+    uint64_t cap;      // power of two
+    int64_t n;         // keys inserted by the last build
+    int32_t err;       // first device-side error (rg_status), 0 if none
+    int32_t pad;
+    int64_t bad;       // offending key index / oct index
+    uint64_t reserved[28];
+};
+static_assert(sizeof(HashHeader) == 256, "hash header is 256 bytes");
+
+inline uint64_t hash_capacity(int64_t n)
+{
+    uint64_t want = static_cast<uint64_t>(n < 8 ? 8 : n) * 2;
+    uint64_t cap = 16;
+    while (cap < want) cap <<= 1;
+    return cap;
+}
+
+struct HashView {
+    HashHeader *hdr;
+    uint64_t *keys;
+    int32_t *vals;
+    uint64_t mask;
+};
+
+inline HashView hash_view(void *ws, uint64_t cap)
+{
+    HashView v;
+    v.hdr = static_cast<HashHeader *>(ws);
+    v.keys = reinterpret_cast<uint64_t *>(static_cast<char *>(ws) + sizeof(HashHeader));
+    v.vals = reinterpret_cast<int32_t *>(v.keys + cap);
+    v.mask = cap - 1;
+    return v;
+}
+
+__device__ inline void flag_error(HashHeader *hdr, int code, int64_t bad)
+{
+    if (atomicCAS(&hdr->err, 0, code) == 0) hdr->bad = bad;
+}
+
+__device__ inline int32_t hash_probe(const uint64_t *keys, const int32_t *vals, uint64_t mask, uint64_t key)
+{
+    uint64_t s = fnv1a64(key) & mask;
+    for (uint64_t it = 0; it <= mask; ++it) {
+        uint64_t k = keys[s];
+        if (k == key) return vals[s];
+        if (k == 0) return -1;
+        s = (s + 1) & mask;
+    }
+    return -1;
+}
+
+// ---------------------------------------------------------------------------
+// misc launches shared by several files
+// ---------------------------------------------------------------------------
+
+rg_status fill_u32(uint32_t *d, int64_t n, uint32_t v, hipStream_t s);
+rg_status fill_u64(uint64_t *d, int64_t n, uint64_t v, hipStream_t s);
+
+}  // namespace rg

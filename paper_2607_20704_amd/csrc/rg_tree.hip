@@ -1,0 +1,394 @@
+// rg_tree.hip -- oct keys, sort, hash table and neighbour lists (gfx950).
+//
+// Paper: an oct is the key tuple (i,j,k,l) mapped to its position in device
+// memory through an fnv64 hash with linear probing (Sec. 2.1); octs are
+// sorted by level and along a Hilbert curve (Sec. 2.2); father and
+// neighbour index arrays are precomputed per oct for stencils, with ghost
+// values where the neighbour oct does not exist (Sec. 2.3); the neighbour
+// topology is a flat 27-entry list per oct built from hash lookups (Sec. 5);
+// insertion claims a slot with compare-and-swap (Sec. 6; gfx950 has native
+// 64-bit CAS, so the key itself is the CAS target).
+#include <hipcub/hipcub.hpp>
+
+#include "rg_internal.hpp"
+
+namespace rg {
+namespace {
+
+__global__ void k_fill_u32(uint32_t *d, int64_t n, uint32_t v)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = v;
+}
+
+__global__ void k_fill_u64(uint64_t *d, int64_t n, uint64_t v)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = v;
+}
+
+__global__ void k_encode(const int32_t *__restrict__ ijkl, int64_t n, uint64_t *__restrict__ keys)
+{
+    int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (o >= n) return;
+    const int4 c = reinterpret_cast<const int4 *>(ijkl)[o];
+    keys[o] = oct_key(c.x, c.y, c.z, c.w);
+}
+
+__global__ void k_decode(const uint64_t *__restrict__ keys, int64_t n, int32_t *__restrict__ ijkl)
+{
+    int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (o >= n) return;
+    int32_t i, j, k, l;
+    key_coords(keys[o], i, j, k, l);
+    reinterpret_cast<int4 *>(ijkl)[o] = make_int4(i, j, k, l);
+}
+
+__global__ void k_iota(int32_t *d, int64_t n)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = static_cast<int32_t>(i);
+}
+
+// begin[l] = first position whose level is >= l; one writer per entry
+__global__ void k_level_ranges(const uint64_t *__restrict__ keys, int64_t n, int64_t *__restrict__ begin)
+{
+    int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (o >= n) return;
+    int lv = key_level(keys[o]);
+    int prev = (o == 0) ? 0 : key_level(keys[o - 1]);
+    if (o == 0) begin[0] = 0;
+    for (int l = prev + 1; l <= lv && l <= RG_MAX_LEVEL + 1; ++l) begin[l] = o;
+    if (o == n - 1)
+        for (int l = lv + 1; l <= RG_MAX_LEVEL + 1; ++l) begin[l] = n;
+}
+
+__global__ void k_zero_i64(int64_t *d, int n)
+{
+    int i = threadIdx.x;
+    if (i < n) d[i] = 0;
+}
+
+__global__ void k_permute_rows(const double *__restrict__ in, const int32_t *__restrict__ perm, int64_t rows, int rd,
+                               double *__restrict__ out)
+{
+    int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= rows * rd) return;
+    int64_t r = t / rd;
+    int e = static_cast<int>(t - r * rd);
+    out[t] = in[int64_t(perm[r]) * rd + e];
+}
+
+// clears every slot; thread 0 also resets the header
+__global__ void k_hash_clear(HashHeader *hdr, uint64_t *keys, uint64_t cap, int64_t n)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < static_cast<int64_t>(cap)) keys[i] = 0;
+    if (i == 0) {
+        hdr->cap = cap;
+        hdr->n = n;
+        hdr->err = 0;
+        hdr->bad = -1;
+    }
+}
+
+__global__ void k_hash_insert(const uint64_t *__restrict__ in, int64_t n, HashHeader *hdr, uint64_t *keys,
+                              int32_t *vals, uint64_t mask)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t key = in[i];
+    if (key == 0) {
+        flag_error(hdr, RG_EINVAL, i);
+        return;
+    }
+    uint64_t s = fnv1a64(key) & mask;
+    for (uint64_t it = 0; it <= mask; ++it) {
+        unsigned long long prev =
+            atomicCAS(reinterpret_cast<unsigned long long *>(keys + s), 0ull, static_cast<unsigned long long>(key));
+        if (prev == 0ull) {
+            vals[s] = static_cast<int32_t>(i);
+            return;
+        }
+        if (prev == key) {
+            flag_error(hdr, RG_EDUPKEY, i);
+            return;
+        }
+        s = (s + 1) & mask;
+    }
+    flag_error(hdr, RG_EFULL, i);
+}
+
+__global__ void k_hash_lookup(const uint64_t *__restrict__ keys, const int32_t *__restrict__ vals, uint64_t mask,
+                              const uint64_t *__restrict__ q, int64_t m, int32_t *__restrict__ out)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const uint64_t key = q[i];
+    out[i] = key == 0 ? -1 : hash_probe(keys, vals, mask, key);
+}
+
+// Neighbour lists.  A block of 256 threads serves 9 octs, 27 threads each
+// (one per offset); the octs' coordinates are decoded once into LDS.
+constexpr int kNbrOcts = 9;
+
+__global__ __launch_bounds__(256) void k_neighbours(const uint64_t *__restrict__ okeys, int64_t n, int lmin, int bc,
+                                                    HashHeader *hdr, const uint64_t *__restrict__ keys,
+                                                    const int32_t *__restrict__ vals, uint64_t mask,
+                                                    int32_t *__restrict__ nbr27, int32_t *__restrict__ father_cell,
+                                                    uint32_t *__restrict__ son_mask)
+{
+    __shared__ int32_t s_c[kNbrOcts][4];
+    const int64_t first = int64_t(blockIdx.x) * kNbrOcts;
+    const int t = threadIdx.x;
+    if (t < kNbrOcts && first + t < n) {
+        int32_t i, j, k, l;
+        key_coords(okeys[first + t], i, j, k, l);
+        s_c[t][0] = i;
+        s_c[t][1] = j;
+        s_c[t][2] = k;
+        s_c[t][3] = l;
+    }
+    __syncthreads();
+    if (t >= 27 * kNbrOcts) return;
+    const int g = t / 27, slot = t - 27 * g;
+    const int64_t o = first + g;
+    if (o >= n) return;
+    const int32_t i = s_c[g][0], j = s_c[g][1], k = s_c[g][2], l = s_c[g][3];
+    if (slot == 13) {
+        nbr27[27 * o + 13] = static_cast<int32_t>(o);
+        if (l > lmin) {
+            int32_t f = hash_probe(keys, vals, mask, okeys[o] >> 3);
+            if (f < 0) {
+                flag_error(hdr, RG_EUNGRADED, o);
+                father_cell[o] = -1;
+            } else {
+                const int bit = (i & 1) + 2 * (j & 1) + 4 * (k & 1);
+                father_cell[o] = 8 * f + bit;
+                atomicOr(son_mask + f, 1u << bit);
+            }
+        } else {
+            father_cell[o] = -1;
+        }
+        return;
+    }
+    const int dx = slot % 3 - 1, dy = (slot / 3) % 3 - 1, dz = slot / 9 - 1;
+    const int32_t N = 1 << (l - 1);
+    int32_t ni = i + dx, nj = j + dy, nk = k + dz;
+    if (bc == RG_BC_PERIODIC) {
+        ni &= N - 1;
+        nj &= N - 1;
+        nk &= N - 1;
+    } else if (ni < 0 || nj < 0 || nk < 0 || ni >= N || nj >= N || nk >= N) {
+        nbr27[27 * o + slot] = RG_NBR_OUTSIDE;
+        return;
+    }
+    const uint64_t kn = oct_key(ni, nj, nk, l);
+    int32_t e = hash_probe(keys, vals, mask, kn);
+    if (e < 0) {
+        int32_t f = (l > 1) ? hash_probe(keys, vals, mask, kn >> 3) : -1;
+        if (f < 0) {
+            flag_error(hdr, RG_EUNGRADED, o);
+            e = 0;
+        } else {
+            e = -1 - (8 * f + (ni & 1) + 2 * (nj & 1) + 4 * (nk & 1));
+        }
+    }
+    nbr27[27 * o + slot] = e;
+}
+
+}  // namespace
+
+rg_status fill_u32(uint32_t *d, int64_t n, uint32_t v, hipStream_t s)
+{
+    if (n <= 0) return RG_OK;
+    k_fill_u32<<<grid_for(n, 256), 256, 0, s>>>(d, n, v);
+    return launch_status("fill_u32");
+}
+
+rg_status fill_u64(uint64_t *d, int64_t n, uint64_t v, hipStream_t s)
+{
+    if (n <= 0) return RG_OK;
+    k_fill_u64<<<grid_for(n, 256), 256, 0, s>>>(d, n, v);
+    return launch_status("fill_u64");
+}
+
+}  // namespace rg
+
+using namespace rg;
+
+extern "C" {
+
+rg_status rg_encode_keys(const int32_t *d_ijkl, int64_t n, uint64_t *d_keys, void *stream)
+{
+    RG_REQUIRE(n >= 0, "n < 0");
+    if (n == 0) return RG_OK;
+    RG_REQUIRE(d_ijkl && d_keys, "null pointer");
+    RG_REQUIRE(aligned(d_ijkl, 16) && aligned(d_keys, 8), "misaligned pointer");
+    k_encode<<<grid_for(n, 256), 256, 0, as_stream(stream)>>>(d_ijkl, n, d_keys);
+    return launch_status("rg_encode_keys");
+}
+
+rg_status rg_decode_keys(const uint64_t *d_keys, int64_t n, int32_t *d_ijkl, void *stream)
+{
+    RG_REQUIRE(n >= 0, "n < 0");
+    if (n == 0) return RG_OK;
+    RG_REQUIRE(d_ijkl && d_keys, "null pointer");
+    RG_REQUIRE(aligned(d_ijkl, 16) && aligned(d_keys, 8), "misaligned pointer");
+    k_decode<<<grid_for(n, 256), 256, 0, as_stream(stream)>>>(d_keys, n, d_ijkl);
+    return launch_status("rg_decode_keys");
+}
+
+size_t rg_sort_workspace_bytes(int64_t n)
+{
+    if (n <= 0) return 256;
+    size_t temp = 0;
+    hipcub::DeviceRadixSort::SortPairs(nullptr, temp, static_cast<const uint64_t *>(nullptr),
+                                       static_cast<uint64_t *>(nullptr), static_cast<const int32_t *>(nullptr),
+                                       static_cast<int32_t *>(nullptr), static_cast<int>(n));
+    size_t iota = (static_cast<size_t>(n) * sizeof(int32_t) + 255) & ~size_t(255);
+    return iota + ((temp + 255) & ~size_t(255)) + 256;
+}
+
+rg_status rg_sort_keys(const uint64_t *d_keys_in, int64_t n, uint64_t *d_keys_out, int32_t *d_perm, void *d_ws,
+                       size_t ws_bytes, void *stream)
+{
+    RG_REQUIRE(n >= 0 && n <= INT32_MAX, "n out of range");
+    if (n == 0) return RG_OK;
+    RG_REQUIRE(d_keys_in && d_keys_out && d_perm && d_ws, "null pointer");
+    RG_REQUIRE(d_keys_in != d_keys_out, "in-place sort is not supported");
+    RG_REQUIRE(ws_bytes >= rg_sort_workspace_bytes(n), "sort workspace too small");
+    RG_REQUIRE(aligned(d_ws, 256), "workspace must be 256-byte aligned");
+    hipStream_t s = as_stream(stream);
+    int32_t *iota = static_cast<int32_t *>(d_ws);
+    size_t iota_bytes = (static_cast<size_t>(n) * sizeof(int32_t) + 255) & ~size_t(255);
+    void *temp = static_cast<char *>(d_ws) + iota_bytes;
+    size_t temp_bytes = ws_bytes - iota_bytes;
+    k_iota<<<grid_for(n, 256), 256, 0, s>>>(iota, n);
+    RG_TRY(launch_status("rg_sort_keys iota"));
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, d_keys_in, d_keys_out, iota, d_perm,
+                                                      static_cast<int>(n), 0, 64, s);
+    if (e != hipSuccess) return fail(RG_EHIP, "radix sort: %s", hipGetErrorString(e));
+    return launch_status("rg_sort_keys");
+}
+
+rg_status rg_level_ranges(const uint64_t *d_sorted_keys, int64_t n, int64_t *d_level_begin, void *stream)
+{
+    RG_REQUIRE(n >= 0, "n < 0");
+    RG_REQUIRE(d_level_begin, "null pointer");
+    hipStream_t s = as_stream(stream);
+    if (n == 0) {
+        k_zero_i64<<<1, 64, 0, s>>>(d_level_begin, RG_MAX_LEVEL + 2);
+        return launch_status("rg_level_ranges");
+    }
+    RG_REQUIRE(d_sorted_keys, "null pointer");
+    k_level_ranges<<<grid_for(n, 256), 256, 0, s>>>(d_sorted_keys, n, d_level_begin);
+    return launch_status("rg_level_ranges");
+}
+
+rg_status rg_permute_rows(const double *d_in, const int32_t *d_perm, int64_t n_rows, int row_doubles, double *d_out,
+                          void *stream)
+{
+    RG_REQUIRE(n_rows >= 0 && row_doubles > 0, "bad size");
+    if (n_rows == 0) return RG_OK;
+    RG_REQUIRE(d_in && d_perm && d_out, "null pointer");
+    RG_REQUIRE(d_in != d_out, "in-place permutation is not supported");
+    k_permute_rows<<<grid_for(n_rows * row_doubles, 256), 256, 0, as_stream(stream)>>>(d_in, d_perm, n_rows,
+                                                                                      row_doubles, d_out);
+    return launch_status("rg_permute_rows");
+}
+
+size_t rg_hash_workspace_bytes(int64_t n_keys)
+{
+    uint64_t cap = hash_capacity(n_keys < 0 ? 0 : n_keys);
+    return sizeof(HashHeader) + cap * (sizeof(uint64_t) + sizeof(int32_t));
+}
+
+uint64_t rg_fnv1a64(uint64_t key) { return fnv1a64(key); }
+
+uint64_t rg_key_host(int32_t i, int32_t j, int32_t k, int32_t l) { return oct_key(i, j, k, l); }
+
+void rg_key_coords_host(uint64_t key, int32_t *h_ijkl)
+{
+    if (!h_ijkl) return;
+    key_coords(key, h_ijkl[0], h_ijkl[1], h_ijkl[2], h_ijkl[3]);
+}
+
+rg_status rg_hash_build(const uint64_t *d_keys, int64_t n, void *d_ws, size_t ws_bytes, void *stream)
+{
+    RG_REQUIRE(n >= 0 && n <= INT32_MAX, "n out of range");
+    RG_REQUIRE(d_ws && (n == 0 || d_keys), "null pointer");
+    RG_REQUIRE(aligned(d_ws, 256), "workspace must be 256-byte aligned");
+    const uint64_t cap = hash_capacity(n);
+    if (ws_bytes < rg_hash_workspace_bytes(n))
+        return fail(RG_EFULL, "hash workspace holds %zu bytes, %zu needed", ws_bytes, rg_hash_workspace_bytes(n));
+    HashView h = hash_view(d_ws, cap);
+    hipStream_t s = as_stream(stream);
+    k_hash_clear<<<grid_for(static_cast<int64_t>(cap), 256), 256, 0, s>>>(h.hdr, h.keys, cap, n);
+    RG_TRY(launch_status("rg_hash_build clear"));
+    if (n > 0) {
+        k_hash_insert<<<grid_for(n, 256), 256, 0, s>>>(d_keys, n, h.hdr, h.keys, h.vals, h.mask);
+        RG_TRY(launch_status("rg_hash_build insert"));
+    }
+    return RG_OK;
+}
+
+// The capacity is recorded in the header on the device; host callers pass the
+// key count they built with, which fixes the capacity the same way.
+static rg_status read_capacity(const void *d_ws, uint64_t &cap, hipStream_t s)
+{
+    HashHeader h;
+    hipError_t e = hipMemcpyAsync(&h, d_ws, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(RG_EHIP, "reading hash header: %s", hipGetErrorString(e));
+    cap = h.cap;
+    return RG_OK;
+}
+
+rg_status rg_hash_lookup(const void *d_ws, const uint64_t *d_q, int64_t m, int32_t *d_idx, void *stream)
+{
+    RG_REQUIRE(m >= 0, "m < 0");
+    if (m == 0) return RG_OK;
+    RG_REQUIRE(d_ws && d_q && d_idx, "null pointer");
+    hipStream_t s = as_stream(stream);
+    uint64_t cap = 0;
+    RG_TRY(read_capacity(d_ws, cap, s));
+    RG_REQUIRE(cap >= 16 && (cap & (cap - 1)) == 0, "workspace holds no built table");
+    HashView h = hash_view(const_cast<void *>(d_ws), cap);
+    k_hash_lookup<<<grid_for(m, 256), 256, 0, s>>>(h.keys, h.vals, h.mask, d_q, m, d_idx);
+    return launch_status("rg_hash_lookup");
+}
+
+rg_status rg_check(const void *d_ws, int64_t *h_bad_index, void *stream)
+{
+    RG_REQUIRE(d_ws, "null pointer");
+    HashHeader h;
+    hipStream_t s = as_stream(stream);
+    hipError_t e = hipMemcpyAsync(&h, d_ws, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(RG_EHIP, "rg_check: %s", hipGetErrorString(e));
+    if (h_bad_index) *h_bad_index = h.err ? h.bad : -1;
+    if (h.err) return fail(static_cast<rg_status>(h.err), "device reported %s at index %lld",
+                           rg_status_string(h.err), static_cast<long long>(h.bad));
+    return RG_OK;
+}
+
+rg_status rg_build_neighbours(void *d_ws, const uint64_t *d_keys, int64_t n, int lmin, int bc, int32_t *d_nbr27,
+                              int32_t *d_father_cell, uint32_t *d_son_mask, void *stream)
+{
+    RG_REQUIRE(n >= 0 && n <= (int64_t(1) << 28), "n out of range");
+    if (n == 0) return RG_OK;
+    RG_REQUIRE(d_ws && d_keys && d_nbr27 && d_father_cell && d_son_mask, "null pointer");
+    RG_REQUIRE(bc == RG_BC_PERIODIC || bc == RG_BC_OUTFLOW, "bad boundary type %d", bc);
+    RG_REQUIRE(lmin >= 1 && lmin <= RG_MAX_LEVEL, "bad lmin %d", lmin);
+    const uint64_t cap = hash_capacity(n);
+    HashView h = hash_view(d_ws, cap);
+    hipStream_t s = as_stream(stream);
+    RG_TRY(fill_u32(d_son_mask, n, 0u, s));
+    const int64_t blocks = (n + kNbrOcts - 1) / kNbrOcts;
+    k_neighbours<<<static_cast<unsigned>(blocks), 256, 0, s>>>(d_keys, n, lmin, bc, h.hdr, h.keys, h.vals, h.mask,
+                                                               d_nbr27, d_father_cell, d_son_mask);
+    return launch_status("rg_build_neighbours");
+}
+
+}  // extern "C"

@@ -1,0 +1,112 @@
+"""GPU parity of the integer path (keys, radix sort, level ranges, FNV hash,
+neighbour lists) against the oracle: bit-exact."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import build_both, say, small_trees
+from oracle import oracle as O
+from paper_2607_20704_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def test_keys_match_oracle_random_deep():
+    from paper_2607_20704_amd import api
+    rng = np.random.default_rng(9)
+    rows = []
+    for l in range(1, 22):
+        n = 1 << (l - 1)
+        for _ in range(300):
+            rows.append([*rng.integers(0, n, 3), l])
+    ijkl = np.array(rows, np.int32)
+    say("keys: %d random octs on levels 1..21" % len(ijkl))
+    keys = api.encode_keys(torch.as_tensor(ijkl).cuda()).cpu().numpy()
+    assert np.array_equal(keys, O.keys(ijkl))
+    back = api.decode_keys(torch.as_tensor(keys.astype(np.int64)).cuda().view(torch.uint64)).cpu().numpy()
+    assert np.array_equal(back, ijkl)
+
+
+@pytest.mark.parametrize("name", ["sod_l5", "sedov_l6_l8", "uniform_l8"])
+def test_sort_and_level_ranges(name):
+    from paper_2607_20704_amd import api
+    ijkl = {"sod_l5": lambda: I.uniform_tree(5), "sedov_l6_l8": lambda: I.sedov_amr().ijkl,
+            "uniform_l8": lambda: I.uniform_tree(8)}[name]()
+    # shuffle the input so the sort has work to do
+    ijkl = ijkl[np.random.default_rng(1).permutation(len(ijkl))]
+    say("sort: %s, %d octs" % (name, len(ijkl)))
+    keys = api.encode_keys(torch.as_tensor(ijkl).cuda())
+    skeys, perm = api.sort_keys(keys)
+    assert np.array_equal(perm.cpu().numpy(), O.tree_order(ijkl))
+    sk = skeys.cpu().numpy()
+    assert np.array_equal(sk, np.sort(O.keys(ijkl)))
+    begin = api.level_ranges(skeys).cpu().numpy()
+    lv = ijkl[:, 3]
+    for l in range(0, 23):
+        assert begin[l] == np.count_nonzero(lv < l), l
+
+
+def test_hash_lookup_and_errors():
+    from paper_2607_20704_amd import api
+    from paper_2607_20704_amd import _lib as L
+    ijkl = I.sedov_amr().ijkl
+    say("hash: sedov tree, %d keys" % len(ijkl))
+    keys = torch.as_tensor(O.keys(ijkl).astype(np.int64)).cuda().view(torch.uint64)
+    ws = api.hash_build(keys)
+    assert api.check_ws(ws) == (L.RG_OK, -1)
+    idx = api.hash_lookup(ws, keys).cpu().numpy()
+    assert np.array_equal(idx, np.arange(len(ijkl)))
+    # absent keys: children of the finest level, and key 0
+    absent = O.keys(np.concatenate([2 * ijkl[-50:, :3], ijkl[-50:, 3:] + 1], 1))
+    q = torch.as_tensor(np.concatenate([absent, [0]]).astype(np.int64)).cuda().view(torch.uint64)
+    assert np.all(api.hash_lookup(ws, q).cpu().numpy() == -1)
+    # duplicate key
+    hk = O.keys(ijkl).astype(np.int64)
+    dup = torch.as_tensor(np.concatenate([hk[:100], hk[:1]])).cuda().view(torch.uint64)
+    ws2 = api.hash_build(dup)
+    st, bad = api.check_ws(ws2)
+    assert st == L.RG_EDUPKEY and bad in (0, 100)
+    # zero key
+    z = hk[:10].copy()
+    z[3] = 0
+    ws3 = api.hash_build(torch.as_tensor(z).cuda().view(torch.uint64))
+    assert api.check_ws(ws3) == (L.RG_EINVAL, 3)
+
+
+@pytest.mark.parametrize("case", small_trees(), ids=[c[0] for c in small_trees()])
+def test_neighbours_match_oracle(case):
+    name, ijkl, bc, _ = case
+    say("neighbours:", name, len(ijkl))
+    T, D = build_both(ijkl, bc)
+    assert np.array_equal(D.nbr27.cpu().numpy(), T.nbr27)
+    assert np.array_equal(D.father_cell.cpu().numpy(), T.father_cell)
+    assert np.array_equal(D.son_mask.cpu().numpy(), T.son_mask.astype(np.int32))
+
+
+@pytest.mark.parametrize("name", ["sedov_l6_l8", "uniform_l8_periodic", "uniform_l5_outflow"])
+def test_neighbours_match_oracle_large(name):
+    w = {"sedov_l6_l8": lambda: (I.sedov_amr().ijkl, I.PERIODIC),
+         "uniform_l8_periodic": lambda: (I.uniform_tree(8), I.PERIODIC),
+         "uniform_l5_outflow": lambda: (I.uniform_tree(5), I.OUTFLOW)}[name]
+    ijkl, bc = w()
+    say("neighbours:", name, len(ijkl))
+    T, D = build_both(ijkl, bc)
+    assert np.array_equal(D.nbr27.cpu().numpy(), T.nbr27)
+    assert np.array_equal(D.father_cell.cpu().numpy(), T.father_cell)
+    assert np.array_equal(D.son_mask.cpu().numpy(), T.son_mask.astype(np.int32))
+
+
+def test_ungraded_tree_is_reported():
+    from paper_2607_20704_amd import api
+    from paper_2607_20704_amd import _lib as L
+    base = I.uniform_tree(2)
+    tree = np.concatenate([base, [[2, 2, 2, 3]], [[4, 4, 4, 4]]]).astype(np.int32)
+    perm = O.tree_order(tree)
+    st_o, bad_o, *_ = O.neighbours(tree[perm], I.PERIODIC)
+    say("ungraded tree, %d octs" % len(tree))
+    keys = torch.as_tensor(O.keys(tree[perm]).astype(np.int64)).cuda().view(torch.uint64)
+    ws = api.hash_build(keys)
+    api.build_neighbours(ws, keys, 2, I.PERIODIC)
+    st, bad = api.check_ws(ws)
+    assert st == L.RG_EUNGRADED == st_o
+    assert bad == bad_o

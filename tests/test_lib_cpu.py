@@ -1,0 +1,117 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every symbol the
+header declares, its host key function matches the oracle's Hilbert keys, its
+FNV-1a matches the published definition, and argument errors are reported
+without touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2607_20704_amd import _lib as L
+from paper_2607_20704_amd import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "rg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rg_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    syms = header_symbols()
+    assert len(syms) >= 20
+    for s in syms:
+        assert hasattr(lib, s), s
+        assert s in L.SIGNATURES, "binding lacks " + s
+
+
+def test_abi_version_and_status_strings():
+    lib = L.lib()
+    assert lib.rg_abi_version() == 1
+    assert lib.rg_status_string(L.RG_EUNGRADED) == b"RG_EUNGRADED"
+    assert lib.rg_status_string(99) == b"RG_UNKNOWN"
+
+
+def fnv1a64_bytes(data):
+    """FNV-1a 64 from the published definition: offset basis, then for each
+    byte xor and multiply by the FNV prime modulo 2^64."""
+    h = 0xCBF29CE484222325
+    for b in data:
+        h ^= b
+        h = (h * 0x100000001B3) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def test_fnv_reference_vectors():
+    # published FNV-1a 64 test vectors
+    assert fnv1a64_bytes(b"") == 0xCBF29CE484222325
+    assert fnv1a64_bytes(b"a") == 0xAF63DC4C8601EC8C
+    assert fnv1a64_bytes(b"foobar") == 0x85944171F73967E8
+
+
+def test_library_fnv_hashes_the_8_key_bytes():
+    rng = np.random.default_rng(4)
+    for K in [1, 8, 0x1234, 2 ** 60 + 12345] + [int(x) for x in rng.integers(1, 2 ** 62, 50)]:
+        assert api.fnv1a64(K) == fnv1a64_bytes(int(K).to_bytes(8, "little"))
+
+
+@pytest.mark.parametrize("l", [1, 2, 3, 4, 5, 6])
+def test_host_keys_equal_oracle_keys_exhaustive(l):
+    n = 1 << (l - 1)
+    for i in range(n):
+        for j in range(n):
+            for k in range(0, n, max(1, n // 8)):
+                K = api.key_host(i, j, k, l)
+                assert K == O.key(i, j, k, l)
+                assert api.key_coords_host(K) == (i, j, k, l)
+
+
+def test_host_keys_equal_oracle_keys_deep():
+    rng = np.random.default_rng(5)
+    for l in range(7, 22):
+        n = 1 << (l - 1)
+        for _ in range(100):
+            i, j, k = (int(x) for x in rng.integers(0, n, 3))
+            K = api.key_host(i, j, k, l)
+            assert K == O.key(i, j, k, l)
+            assert api.key_coords_host(K) == (i, j, k, l)
+
+
+def test_out_of_range_coordinates_give_key_zero():
+    assert api.key_host(4, 0, 0, 3) == 0
+    assert api.key_host(0, -1, 0, 3) == 0
+    assert api.key_host(0, 0, 0, 0) == 0
+    assert api.key_host(0, 0, 0, 22) == 0
+
+
+def test_argument_errors_are_reported_without_a_device():
+    lib = L.lib()
+    assert lib.rg_encode_keys(None, 5, None, None) == L.RG_EINVAL
+    assert b"null pointer" in L.detail().encode()
+    assert lib.rg_hash_build(None, -1, None, 0, None) == L.RG_EINVAL
+    # a workspace that is too small is refused before anything is enqueued
+    fake = ctypes.c_void_p(256)
+    assert lib.rg_hash_build(fake, 100, fake, 64, None) == L.RG_EFULL
+    assert lib.rg_build_neighbours(fake, fake, 10, 1, 7, fake, fake, fake, None) == L.RG_EINVAL
+    assert lib.rg_hydro_step_level(1.0, None, 1.4, None, None, None, None, 0, 10, None, 0, 0, None, None) == L.RG_EINVAL
+    assert lib.rg_hydro_step_level(1.0, fake, 1.4, fake, fake, fake, fake, 0, 10, None, 0, 5, None, None) \
+        == L.RG_EINVAL
+    lb = (ctypes.c_int64 * 23)()
+    assert lib.rg_cfl_dt(fake, fake, lb, 3, 2, 1.4, 0.8, fake, None) == L.RG_EINVAL
+    assert lib.rg_step(None, None, None, 1.4, 0.8, 0, 0, None, None, None) == L.RG_EINVAL
+    # zero-sized work is a no-op
+    assert lib.rg_encode_keys(None, 0, None, None) == L.RG_OK
+
+
+def test_workspace_sizes():
+    lib = L.lib()
+    assert lib.rg_hash_workspace_bytes(0) == 256 + 16 * 12
+    assert lib.rg_hash_workspace_bytes(4096) == 256 + 8192 * 12
+    assert lib.rg_hash_workspace_bytes(4097) == 256 + 16384 * 12
+    assert lib.rg_corr_workspace_bytes(10) == 2400

@@ -180,10 +180,29 @@ rg_status rg_build_neighbours(void *d_ws, const uint64_t *d_keys, int64_t n, int
 
 /* Kernel choice; zero-initialised means "library default". */
 typedef struct rg_tuning {
-    int32_t octs_per_group;   /* octs handled by one workgroup (1..16, 0 = default) */
-    int32_t threads;          /* workgroup size: 64, 128, 192 or 256 (0 = default) */
-    int32_t reserved[6];
+    int32_t octs_per_group;   /* per-oct kernel: octs handled by one workgroup (0 = default) */
+    int32_t threads;          /* per-oct kernel: workgroup size (0 = default) */
+    int32_t no_bricks;        /* 1: scheduled updates use the per-oct kernel for every oct */
+    int32_t reserved[5];
 } rg_tuning;
+
+/* Kernel schedule of a tree.  A brick is a Hilbert-aligned cube of 8x8x8
+ * octs of one level (keys 512 P .. 512 P + 511, so consecutive in memory);
+ * a complete brick none of whose octs borders a coarse ghost is updated by
+ * the brick kernel, which marches the brick plane by plane and shares the
+ * stencil of all its octs (the paper's larger-block idea, Sec. 3); all other
+ * octs use the per-oct kernel.  For level l, d_list holds
+ * [brick_begin[l], +brick_count[l]) first octs of bricks and
+ * [rest_begin[l], +rest_count[l]) octs for the per-oct kernel.  The schedule
+ * depends only on the keys and neighbour lists: rebuild it when the tree
+ * changes. */
+typedef struct rg_schedule {
+    int64_t brick_begin[RG_MAX_LEVEL + 2];
+    int64_t brick_count[RG_MAX_LEVEL + 2];
+    int64_t rest_begin[RG_MAX_LEVEL + 2];
+    int64_t rest_count[RG_MAX_LEVEL + 2];
+    const int32_t *d_list;
+} rg_schedule;
 
 /* Bytes of the coarse-fine correction buffer for octs [corr_base, n_oct):
  * 30 doubles (6 sides x 5 variables) per oct. */
@@ -248,21 +267,51 @@ typedef struct rg_tree {
     int32_t bc;                               /* RG_BC_* */
     int32_t pad0;
     int64_t level_begin[RG_MAX_LEVEL + 2];    /* host copy of the level ranges */
-    const uint64_t *d_keys;                   /* sorted keys [n_oct] */
+    uint64_t *d_keys;                         /* sorted keys [n_oct] */
     void *d_hash_ws;                          /* rg_hash_workspace_bytes(n_oct) */
     size_t hash_ws_bytes;
     int32_t *d_nbr27;                         /* [n_oct][27] */
     int32_t *d_father_cell;                   /* [n_oct] */
     uint32_t *d_son_mask;                     /* [n_oct] */
     double *d_corr;                           /* 30 doubles per oct of levels > lmin; NULL if lmin == lmax */
+    /* used by RG_STEP_REKEY only (may be NULL otherwise): */
+    const int32_t *d_ijkl;                    /* key-ordered oct coordinates [n_oct][4] */
+    uint64_t *d_keys_scratch;                 /* [n_oct] unsorted keys */
+    int32_t *d_perm;                          /* [n_oct] sort permutation (identity for a static tree) */
+    void *d_sort_ws;                          /* rg_sort_workspace_bytes(n_oct) */
+    size_t sort_ws_bytes;
+    int64_t *d_level_begin;                   /* device level ranges [RG_MAX_LEVEL + 2] */
+    const rg_schedule *sched;                 /* optional kernel schedule (NULL: per-oct kernel) */
 } rg_tree;
 
+/* Builds the schedule of tree t (keys, level ranges and neighbour lists must
+ * be current) into the caller's d_list (capacity >= n_oct int32 entries).
+ * Reads the keys and neighbour lists back to the host: synchronises. */
+rg_status rg_schedule_build(const rg_tree *t, int32_t *d_list, int64_t capacity, rg_schedule *out, void *stream);
+
+/* One level's update following a schedule: the level's bricks with the
+ * brick kernel, its other octs with the per-oct kernel (which also records
+ * the coarse-side fluxes in t->d_corr).  Same results, bit for bit, as
+ * rg_hydro_step_level over the whole level. */
+rg_status rg_hydro_step_scheduled(const rg_tree *t, const rg_schedule *sched, int level, const double *d_dt,
+                                  double gamma, const double *d_uold, double *d_unew, int form,
+                                  const rg_tuning *tune, void *stream);
+
 #define RG_STEP_REBUILD 1u    /* rebuild the hash table and neighbour lists first */
+#define RG_STEP_REKEY 2u      /* recompute keys from d_ijkl, radix-sort them, level ranges */
+
+/* The tree bookkeeping of a step (Sec. 2.1-2.3; Table 1 "refine"/"cache"
+ * rows for a static tree): with RG_STEP_REKEY, keys from d_ijkl, radix sort
+ * into d_keys / d_perm and device level ranges; with RG_STEP_REBUILD, hash
+ * build from d_keys and neighbour lists.  Errors found on the device are
+ * reported by rg_check(d_hash_ws). */
+rg_status rg_prepare_tree(const rg_tree *t, unsigned flags, void *stream);
 
 /* One step with a global time step (no subcycling):
- *   [if RG_STEP_REBUILD] hash build + neighbour lists;
+ *   rg_prepare_tree(t, flags) (nothing when flags == 0);
  *   dt = rg_cfl_dt(uold) into *d_dt;
- *   every level: rg_hydro_step_level(uold -> unew);
+ *   every level: rg_hydro_step_scheduled if t->sched is set, else
+ *   rg_hydro_step_level over the level (uold -> unew);
  *   rg_apply_coarse_corrections over all levels above lmin;
  *   rg_restrict_level from lmax down to lmin + 1 on unew.
  * The caller swaps uold and unew afterwards. */

@@ -15,6 +15,7 @@ RG_FP64, RG_MIXED = 0, 1
 RG_MAX_LEVEL = 21
 RG_NBR_OUTSIDE = -(2 ** 31)
 RG_STEP_REBUILD = 1
+RG_STEP_REKEY = 2
 
 # every symbol include/rg.h declares, with (restype, argtypes)
 P = ctypes.c_void_p
@@ -24,14 +25,22 @@ st = ctypes.c_int
 
 
 class RgTuning(ctypes.Structure):
-    _fields_ = [("octs_per_group", i32), ("threads", i32), ("reserved", i32 * 6)]
+    _fields_ = [("octs_per_group", i32), ("threads", i32), ("no_bricks", i32), ("reserved", i32 * 5)]
+
+
+class RgSchedule(ctypes.Structure):
+    _fields_ = [("brick_begin", i64 * (RG_MAX_LEVEL + 2)), ("brick_count", i64 * (RG_MAX_LEVEL + 2)),
+                ("rest_begin", i64 * (RG_MAX_LEVEL + 2)), ("rest_count", i64 * (RG_MAX_LEVEL + 2)),
+                ("d_list", P)]
 
 
 class RgTree(ctypes.Structure):
     _fields_ = [("n_oct", i64), ("lmin", i32), ("lmax", i32), ("bc", i32), ("pad0", i32),
                 ("level_begin", i64 * (RG_MAX_LEVEL + 2)),
                 ("d_keys", P), ("d_hash_ws", P), ("hash_ws_bytes", sz),
-                ("d_nbr27", P), ("d_father_cell", P), ("d_son_mask", P), ("d_corr", P)]
+                ("d_nbr27", P), ("d_father_cell", P), ("d_son_mask", P), ("d_corr", P),
+                ("d_ijkl", P), ("d_keys_scratch", P), ("d_perm", P), ("d_sort_ws", P), ("sort_ws_bytes", sz),
+                ("d_level_begin", P), ("sched", ctypes.POINTER(RgSchedule))]
 
 
 SIGNATURES = {
@@ -58,6 +67,10 @@ SIGNATURES = {
     "rg_apply_coarse_corrections": (st, [P, P, i64, P, i64, i64, P]),
     "rg_restrict_level": (st, [P, P, i64, i64, P]),
     "rg_cfl_dt": (st, [P, P, P, ctypes.c_int, ctypes.c_int, f64, f64, P, P]),
+    "rg_prepare_tree": (st, [ctypes.POINTER(RgTree), ctypes.c_uint, P]),
+    "rg_schedule_build": (st, [ctypes.POINTER(RgTree), P, i64, ctypes.POINTER(RgSchedule), P]),
+    "rg_hydro_step_scheduled": (st, [ctypes.POINTER(RgTree), ctypes.POINTER(RgSchedule), ctypes.c_int, P, f64, P,
+                                     P, ctypes.c_int, ctypes.POINTER(RgTuning), P]),
     "rg_step": (st, [ctypes.POINTER(RgTree), P, P, f64, f64, ctypes.c_int, ctypes.c_uint, P,
                      ctypes.POINTER(RgTuning), P]),
 }

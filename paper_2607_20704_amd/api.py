@@ -30,10 +30,12 @@ def _ptr(t):
 
 
 def _tuning(tune):
+    """tune: None or (octs_per_group, threads[, no_bricks])."""
     if tune is None:
         return None
     t = RgTuning()
     t.octs_per_group, t.threads = int(tune[0]), int(tune[1])
+    t.no_bricks = int(tune[2]) if len(tune) > 2 else 0
     return ctypes.byref(t)
 
 
@@ -165,7 +167,7 @@ class DeviceTree:
     lists and the coarse-fine correction buffer, built from oct coordinates
     by the library (encode, radix sort, level ranges, hash, neighbours)."""
 
-    def __init__(self, ijkl, bc):
+    def __init__(self, ijkl, bc, schedule=True):
         ijkl_d = torch.as_tensor(np.ascontiguousarray(ijkl, dtype=np.int32)).to("cuda")
         self.bc = int(bc)
         self.n = int(ijkl_d.shape[0])
@@ -182,11 +184,42 @@ class DeviceTree:
         self.corr_base = int(begin[self.lmin + 1])
         nfine = self.n - self.corr_base
         self.corr = torch.empty(max(nfine, 1) * 30, dtype=torch.float64, device="cuda") if nfine > 0 else None
+        # key-ordered coordinates and scratch for re-keying inside a step
+        self.ijkl_sorted = decode_keys(self.keys)
+        self.keys_scratch = torch.empty_like(self.keys)
+        self.perm_scratch = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        self.sort_ws = _u8(L.lib().rg_sort_workspace_bytes(self.n))
+        self.level_begin_dev = torch.empty(RG_MAX_LEVEL + 2, dtype=torch.int64, device="cuda")
         self.rebuild()
         st, bad = check_ws(self.hash_ws)
         if st != L.RG_OK:
             raise RgError(st, "tree build failed (%s) at index %d" % (L.lib().rg_status_string(st).decode(), bad))
         self._desc = self._descriptor()
+        self.sched = None
+        if schedule:
+            self.sched_list = torch.empty(self.n, dtype=torch.int32, device="cuda")
+            self.sched = L.RgSchedule()
+            check(L.lib().rg_schedule_build(ctypes.byref(self._desc), _ptr(self.sched_list), self.n,
+                                            ctypes.byref(self.sched), _stream()))
+            self._desc.sched = ctypes.pointer(self.sched)
+
+    def schedule_counts(self):
+        """{level: (bricks, per-oct)} of the kernel schedule."""
+        if self.sched is None:
+            return {}
+        return {l: (int(self.sched.brick_count[l]), int(self.sched.rest_count[l]))
+                for l in range(self.lmin, self.lmax + 1)}
+
+    def hydro_level(self, level, dt, gamma, uold, unew, form=RG_FP64, tune=None):
+        """The update of one level (scheduled when a schedule exists)."""
+        if self.sched is not None:
+            check(L.lib().rg_hydro_step_scheduled(ctypes.byref(self._desc), ctypes.byref(self.sched), int(level),
+                                                  _ptr(dt), float(gamma), _ptr(uold), _ptr(unew), int(form),
+                                                  _tuning(tune), _stream()))
+        else:
+            ob, oe = int(self.level_begin[level]), int(self.level_begin[level + 1])
+            hydro_step_level(0.5 ** level, dt, gamma, uold, unew, self.nbr27, self.son_mask, ob, oe,
+                             self.corr if level > self.lmin else None, self.corr_base, form, tune)
 
     def rebuild(self):
         hash_build(self.keys, self.hash_ws)
@@ -204,7 +237,17 @@ class DeviceTree:
         t.d_father_cell = self.father_cell.data_ptr()
         t.d_son_mask = self.son_mask.data_ptr()
         t.d_corr = self.corr.data_ptr() if self.corr is not None else None
+        t.d_ijkl = self.ijkl_sorted.data_ptr()
+        t.d_keys_scratch = self.keys_scratch.data_ptr()
+        t.d_perm = self.perm_scratch.data_ptr()
+        t.d_sort_ws = self.sort_ws.data_ptr()
+        t.sort_ws_bytes = self.sort_ws.numel()
+        t.d_level_begin = self.level_begin_dev.data_ptr()
         return t
+
+    def prepare(self, flags=L.RG_STEP_REKEY | RG_STEP_REBUILD):
+        """Re-key / re-sort / rebuild hash and neighbour lists on the device."""
+        check(L.lib().rg_prepare_tree(ctypes.byref(self._desc), int(flags), _stream()))
 
     def to_key_order(self, u_input_order):
         """Device copy of a per-cell state given in input oct order, in key order."""
@@ -212,8 +255,10 @@ class DeviceTree:
         return permute_rows(u, self.perm)
 
     def step(self, uold, unew, gamma, cfl, form=RG_FP64, rebuild=False, dt=None, tune=None):
+        """One step; rebuild=True re-keys, re-sorts and rebuilds the hash and
+        neighbour lists first (the whole tree bookkeeping of a step)."""
         dt = dt if dt is not None else torch.empty(1, dtype=torch.float64, device="cuda")
-        flags = RG_STEP_REBUILD if rebuild else 0
+        flags = (RG_STEP_REBUILD | L.RG_STEP_REKEY) if rebuild else 0
         check(L.lib().rg_step(ctypes.byref(self._desc), _ptr(uold), _ptr(unew), float(gamma), float(cfl), int(form),
                               flags, _ptr(dt), _tuning(tune), _stream()))
         return dt

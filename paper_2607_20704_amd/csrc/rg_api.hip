@@ -72,6 +72,26 @@ size_t rg_last_error_detail(char *buf, size_t len)
     return g_detail.size();
 }
 
+rg_status rg_prepare_tree(const rg_tree *t, unsigned flags, void *stream)
+{
+    RG_REQUIRE(t && t->n_oct > 0, "bad tree");
+    RG_REQUIRE((flags & ~(RG_STEP_REBUILD | RG_STEP_REKEY)) == 0, "unknown flags %u", flags);
+    if (flags & RG_STEP_REKEY) {
+        RG_REQUIRE(t->d_ijkl && t->d_keys_scratch && t->d_perm && t->d_sort_ws && t->d_level_begin,
+                   "RG_STEP_REKEY needs coordinates, scratch keys, permutation, sort workspace and level ranges");
+        RG_TRY(rg_encode_keys(t->d_ijkl, t->n_oct, t->d_keys_scratch, stream));
+        RG_TRY(sort_keys_bits(t->d_keys_scratch, t->n_oct, t->d_keys, t->d_perm, t->d_sort_ws, t->sort_ws_bytes,
+                              3 * t->lmax, as_stream(stream)));
+        RG_TRY(rg_level_ranges(t->d_keys, t->n_oct, t->d_level_begin, stream));
+    }
+    if (flags & RG_STEP_REBUILD) {
+        RG_TRY(rg_hash_build(t->d_keys, t->n_oct, t->d_hash_ws, t->hash_ws_bytes, stream));
+        RG_TRY(rg_build_neighbours(t->d_hash_ws, t->d_keys, t->n_oct, t->lmin, t->bc, t->d_nbr27, t->d_father_cell,
+                                   t->d_son_mask, stream));
+    }
+    return RG_OK;
+}
+
 rg_status rg_step(const rg_tree *t, const double *d_uold, double *d_unew, double gamma, double cfl, int form,
                   unsigned flags, double *d_dt, const rg_tuning *tune, void *stream)
 {
@@ -79,18 +99,18 @@ rg_status rg_step(const rg_tree *t, const double *d_uold, double *d_unew, double
     RG_REQUIRE(t->n_oct > 0 && t->lmin >= 1 && t->lmax >= t->lmin && t->lmax <= RG_MAX_LEVEL, "bad tree");
     RG_REQUIRE(t->level_begin[t->lmin] == 0 && t->level_begin[t->lmax + 1] == t->n_oct, "bad level ranges");
     RG_REQUIRE(t->lmin == t->lmax || t->d_corr, "a multilevel tree needs a correction buffer");
-    if (flags & RG_STEP_REBUILD) {
-        RG_TRY(rg_hash_build(t->d_keys, t->n_oct, t->d_hash_ws, t->hash_ws_bytes, stream));
-        RG_TRY(rg_build_neighbours(t->d_hash_ws, t->d_keys, t->n_oct, t->lmin, t->bc, t->d_nbr27, t->d_father_cell,
-                                   t->d_son_mask, stream));
-    }
+    if (flags) RG_TRY(rg_prepare_tree(t, flags, stream));
     RG_TRY(rg_cfl_dt(d_uold, t->d_son_mask, t->level_begin, t->lmin, t->lmax, gamma, cfl, d_dt, stream));
     const int64_t corr_base = t->level_begin[t->lmin + 1];
     for (int l = t->lmin; l <= t->lmax; ++l) {
         const int64_t b = t->level_begin[l], e = t->level_begin[l + 1];
         if (e == b) continue;
-        RG_TRY(rg_hydro_step_level(ldexp(1.0, -l), d_dt, gamma, d_uold, d_unew, t->d_nbr27, t->d_son_mask, b, e,
-                                   l > t->lmin ? t->d_corr : nullptr, corr_base, form, tune, stream));
+        if (t->sched) {
+            RG_TRY(rg_hydro_step_scheduled(t, t->sched, l, d_dt, gamma, d_uold, d_unew, form, tune, stream));
+        } else {
+            RG_TRY(rg_hydro_step_level(ldexp(1.0, -l), d_dt, gamma, d_uold, d_unew, t->d_nbr27, t->d_son_mask, b, e,
+                                       l > t->lmin ? t->d_corr : nullptr, corr_base, form, tune, stream));
+        }
     }
     if (t->lmax > t->lmin) {
         RG_TRY(rg_apply_coarse_corrections(d_unew, t->d_corr, corr_base, t->d_nbr27, corr_base, t->n_oct, stream));

@@ -1,0 +1,401 @@
+// rg_brick.hip -- hydro update of complete 8x8x8-oct bricks on gfx950.
+//
+// Paper Sec. 3 (the rock/paper kernels): larger blocks of octs share their
+// stencil so that fewer ghost cells are reconstructed redundantly; the
+// paper's "paper" kernel sweeps a planar stencil through the block.  Here a
+// brick is a Hilbert-aligned cube of 8^3 octs (16^3 cells) that all exist at
+// one level; because an aligned sub-cube is a contiguous stretch of the
+// Hilbert order, its 512 octs are consecutive in memory.  One workgroup of
+// four wavefronts marches through the brick plane by plane along z:
+//   - thread t owns interior column (x, y) = (t % 16, t / 16) and keeps the
+//     primitive variables of planes z-1, z, z+1 of that column in registers;
+//   - the current plane's primitive variables, the face states and the face
+//     fluxes are exchanged through LDS;
+//   - the ghost ring of the plane (two cells wide) is shared by all columns,
+//     so a cell is reconstructed once per brick instead of once per oct.
+// The arithmetic is the same per-cell/per-face code as the per-oct kernel
+// (rg_math.hpp), evaluated on the same operands in the same order, so the
+// two kernels produce identical bits.
+//
+// Bricks are used only where every neighbour oct of the brick exists at the
+// same level or lies outside the domain; octs of other bricks (touching a
+// coarse ghost, or partial) go to the per-oct kernel.
+#include "rg_internal.hpp"
+#include "rg_math.hpp"
+
+namespace rg {
+namespace {
+
+constexpr int BO = 8;          // octs per brick side
+constexpr int BC = 16;         // cells per brick side
+constexpr int BT = 256;        // threads per workgroup
+constexpr int PW = BC + 4;     // plane width with two ghost cells per side
+constexpr int HS = BO + 2;     // slot table side: octs -1..8
+
+struct BrickArgs {
+    const double *uold;
+    double *unew;
+    const int32_t *nbr27;
+    const uint32_t *son;
+    const uint64_t *keys;
+    const int32_t *bricks;     // first oct of each brick
+    int64_t nbricks;
+    const double *dt;
+    double dx;
+    double gamma;
+    int outflow;               // clamp positions outside the domain (zero gradient)
+};
+
+template <typename R> struct BrickSmem {
+    int32_t loc2oct[BO * BO * BO];
+    int32_t slot[HS * HS * HS];     // neighbour entry of every halo oct slot
+    uint32_t hsplit[HS * HS * HS];  // son mask of same-level slot octs (interior and halo), 0 otherwise
+    R w[PW * PW][NV];               // primitive variables of the current plane
+    R sxp[BC + 1][BC][NV];          // [x][y]: x+ state of cell x-1 (x = 0..16 -> cells -1..15)
+    R sxm_hi[BC][NV];               // x- state of the halo cell x = 16
+    R syp[BC + 1][BC][NV];          // [y][x]: y+ state of cell y-1
+    R sym_hi[BC][NV];
+    double gx[BC + 1][BC][NV];      // [x][y]: G on face (x-1 | x)
+    double gy[BC + 1][BC][NV];      // [y][x]
+    uint8_t split[PW * PW];         // split flag of the current plane's cells
+};
+
+struct Geom {
+    int cx0, cy0, cz0;   // global cell coordinates of the brick origin
+    int ncell;           // cells per side of the level
+    int outflow;
+};
+
+// brick-relative slot index of an oct slot (sa, sb, sc) in [-1, 8]^3
+__device__ __forceinline__ int slot_index(int sa, int sb, int sc) { return (sa + 1) + HS * (sb + 1) + HS * HS * (sc + 1); }
+
+// Source of the cell at brick-relative position (x, y, z): its global cell
+// id, and whether it is a split cell.  Outside the domain (outflow) the
+// position takes the nearest cell inside (zero gradient) and counts as not
+// split; a missing same-level oct gives its coarse cell (injection).
+template <typename R>
+__device__ __forceinline__ int64_t source_cell(const BrickSmem<R> &S, const Geom &g, int x, int y, int z, bool &split)
+{
+    bool clamped = false;
+    if (g.outflow) {
+        const int gx = g.cx0 + x, gy = g.cy0 + y, gz = g.cz0 + z;
+        if (gx < 0) { x = -g.cx0; clamped = true; }
+        if (gx >= g.ncell) { x = g.ncell - 1 - g.cx0; clamped = true; }
+        if (gy < 0) { y = -g.cy0; clamped = true; }
+        if (gy >= g.ncell) { y = g.ncell - 1 - g.cy0; clamped = true; }
+        if (gz < 0) { z = -g.cz0; clamped = true; }
+        if (gz >= g.ncell) { z = g.ncell - 1 - g.cz0; clamped = true; }
+    }
+    const int sa = x >> 1, sb = y >> 1, sc = z >> 1;
+    const int bit = (x & 1) + 2 * (y & 1) + 4 * (z & 1);
+    const int si = slot_index(sa, sb, sc);
+    int32_t e;
+    if (sa >= 0 && sa < BO && sb >= 0 && sb < BO && sc >= 0 && sc < BO)
+        e = S.loc2oct[sa + BO * sb + BO * BO * sc];
+    else
+        e = S.slot[si];
+    split = !clamped && ((S.hsplit[si] >> bit) & 1u);
+    if (e == RG_NBR_OUTSIDE) e = S.loc2oct[0];   // unreachable for a consistent list
+    return e >= 0 ? 8 * int64_t(e) + bit : (-1 - int64_t(e));
+}
+
+__device__ __forceinline__ void load_u(const double *__restrict__ u, int64_t cell, double *U)
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) U[v] = u[NV * cell + v];
+}
+
+template <typename R> __device__ __forceinline__ void to_prim(const double *U, double gamma, R *W)
+{
+    double w[NV];
+    prim64(U, gamma, w);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) W[v] = static_cast<R>(w[v]);
+}
+
+template <typename R> __device__ __forceinline__ void copy5(R *d, const R *s)
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) d[v] = s[v];
+}
+
+// position of the secondary (ghost ring) role of a thread:
+//   kind 1: face layer (x = -1 or 16, or y = -1 or 16), reconstructed
+//   kind 2: outer ring (x = -2 or 17, or y = -2 or 17)
+//   kind 3: inner corners (-1,-1), (16,-1), (-1,16), (16,16)
+__device__ __forceinline__ void ring_pos(int kind, int lane, int &x, int &y)
+{
+    const int q = lane >> 4, k = lane & 15;
+    if (kind == 3) {
+        x = (lane & 1) ? BC : -1;
+        y = (lane & 2) ? BC : -1;
+        return;
+    }
+    const int lo = kind == 1 ? -1 : -2, hi = kind == 1 ? BC : BC + 1;
+    if (q == 0) { x = lo; y = k; }
+    else if (q == 1) { x = hi; y = k; }
+    else if (q == 2) { x = k; y = lo; }
+    else { x = k; y = hi; }
+}
+
+template <typename R>
+__global__ __launch_bounds__(BT) void k_hydro_brick(BrickArgs a)
+{
+    __shared__ BrickSmem<R> S;
+    const int tid = threadIdx.x;
+    // consecutive bricks on one XCD: workgroups are dealt round-robin to the
+    // eight XCDs, so give each XCD a contiguous Hilbert range of bricks
+    const int64_t per_xcd = (a.nbricks + 7) / 8;
+    const int64_t b = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (b >= a.nbricks) return;
+    const int64_t base = a.bricks[b];
+
+    // ---- brick geometry and slot tables
+    for (int k = tid; k < BO * BO * BO; k += BT) {
+        int32_t i, j, kk, l;
+        key_coords(a.keys[base + k], i, j, kk, l);
+        S.loc2oct[(i & 7) + BO * (j & 7) + BO * BO * (kk & 7)] = static_cast<int32_t>(base + k);
+    }
+    Geom g;
+    {
+        int32_t i, j, kk, l;
+        key_coords(a.keys[base], i, j, kk, l);
+        g.cx0 = 2 * (i & ~7);
+        g.cy0 = 2 * (j & ~7);
+        g.cz0 = 2 * (kk & ~7);
+        g.ncell = 1 << l;
+        g.outflow = a.outflow;
+    }
+    __syncthreads();
+    for (int s = tid; s < HS * HS * HS; s += BT) {
+        const int sa = s % HS - 1, sb = (s / HS) % HS - 1, sc = s / (HS * HS) - 1;
+        const int out = (sa < 0 || sa >= BO) + (sb < 0 || sb >= BO) + (sc < 0 || sc >= BO);
+        int32_t e = RG_NBR_OUTSIDE;
+        if (out == 0) {
+            e = S.loc2oct[sa + BO * sb + BO * BO * sc];
+        } else if (out <= 2) {
+            // the nearest brick oct and its neighbour entry towards this slot
+            const int ca = sa < 0 ? 0 : (sa >= BO ? BO - 1 : sa);
+            const int cb = sb < 0 ? 0 : (sb >= BO ? BO - 1 : sb);
+            const int cc = sc < 0 ? 0 : (sc >= BO ? BO - 1 : sc);
+            const int32_t o = S.loc2oct[ca + BO * cb + BO * BO * cc];
+            e = a.nbr27[27 * int64_t(o) + (sa - ca + 1) + 3 * (sb - cb + 1) + 9 * (sc - cc + 1)];
+        }
+        S.slot[s] = e;
+        S.hsplit[s] = e >= 0 ? a.son[e] : 0u;
+    }
+    __syncthreads();
+
+    const double r = *a.dt / a.dx;
+    const R h = static_cast<R>(0.5 * r);
+    const R gam = static_cast<R>(a.gamma);
+    const R g1 = static_cast<R>(1.0 / (a.gamma - 1.0));
+
+    // ---- roles
+    const int x = tid & 15, y = tid >> 4;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int ew = static_cast<int>(b & 3);         // wave holding the reconstructed ghost ring this brick
+    const int kind = wave == ew ? 1 : (wave == ((ew + 1) & 3) ? 2 : (wave == ((ew + 2) & 3) && lane < 4 ? 3 : 0));
+    int hx = 0, hy = 0;
+    if (kind) ring_pos(kind, lane, hx, hy);
+    const bool extra_faces = wave == ((ew + 1) & 3) && lane < 2 * BC;   // faces x = 16 and y = 16
+
+    // own column: U and W of planes r-1, r, r+1; secondary position likewise
+    double Ucur[NV], Un[NV], HUn[NV];
+    R Wm[NV], W0[NV], Wp[NV], HWm[NV], HW0[NV], HWp[NV];
+    bool sp_prev = false, sp_cur, hsp_cur = false;
+    bool sp_next;
+    // prologue: planes -2 and -1 of the own column, plane -1 (and 0 for the
+    // outer ring) of the secondary position
+    {
+        double U[NV];
+        bool sdummy;
+        load_u(a.uold, source_cell(S, g, x, y, -2, sdummy), U);
+        to_prim(U, a.gamma, Wm);
+        load_u(a.uold, source_cell(S, g, x, y, -1, sp_cur), Ucur);
+        to_prim(Ucur, a.gamma, W0);
+        load_u(a.uold, source_cell(S, g, x, y, 0, sp_next), Un);
+        if (kind == 1) {
+            load_u(a.uold, source_cell(S, g, hx, hy, -2, sdummy), U);
+            to_prim(U, a.gamma, HWm);
+            load_u(a.uold, source_cell(S, g, hx, hy, -1, hsp_cur), U);
+            to_prim(U, a.gamma, HW0);
+            load_u(a.uold, source_cell(S, g, hx, hy, 0, sdummy), HUn);
+        } else if (kind >= 2) {
+            load_u(a.uold, source_cell(S, g, hx, hy, 0, sdummy), HUn);
+        }
+    }
+    double acc_prev[NV], gz_prev[NV];
+    R zp_prev[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        acc_prev[v] = 0.0;
+        gz_prev[v] = 0.0;
+        zp_prev[v] = R(0);
+    }
+
+    for (int rz = -1; rz <= BC; ++rz) {
+        // 1. primitive variables of plane rz+1 (own column, secondary ring
+        //    position); prefetch plane rz+2
+        bool sp_n2 = false;
+        double Unn[NV], HUnn[NV];
+        const bool more = rz + 2 <= BC + 1;
+        if (more) load_u(a.uold, source_cell(S, g, x, y, rz + 2, sp_n2), Unn);
+        to_prim(Un, a.gamma, Wp);
+        bool hsp_dummy;
+        if (kind == 1) {
+            if (rz + 2 <= BC) load_u(a.uold, source_cell(S, g, hx, hy, rz + 2, hsp_dummy), HUnn);
+            to_prim(HUn, a.gamma, HWp);
+        } else if (kind >= 2) {
+            if (rz + 1 <= BC - 1) load_u(a.uold, source_cell(S, g, hx, hy, rz + 1, hsp_dummy), HUnn);
+        }
+
+        // 2. plane rz into LDS: W and split flags
+        copy5(S.w[(x + 2) + PW * (y + 2)], W0);
+        S.split[(x + 2) + PW * (y + 2)] = sp_cur;
+        if (kind == 1) {
+            copy5(S.w[(hx + 2) + PW * (hy + 2)], HW0);
+            S.split[(hx + 2) + PW * (hy + 2)] = hsp_cur;
+        } else if (kind >= 2 && rz >= 0 && rz < BC) {
+            R Wr[NV];
+            to_prim(HUn, a.gamma, Wr);
+            copy5(S.w[(hx + 2) + PW * (hy + 2)], Wr);
+        }
+        __syncthreads();
+
+        // 3. reconstruction of plane rz
+        R sxm[NV], sym[NV], szm[NV], szp[NV];
+        {
+            R dW[3][NV], Wq[NV], st[NV];
+            const int c = (x + 2) + PW * (y + 2);
+            reconstruct<R>(W0, S.w[c - 1], S.w[c + 1], S.w[c - PW], S.w[c + PW], Wm, Wp, h, gam, dW, Wq);
+            face_state<R>(Wq, dW[2], false, szm);
+            face_state<R>(Wq, dW[2], true, szp);
+            if (rz >= 0 && rz < BC) {
+                face_state<R>(Wq, dW[0], false, sxm);
+                face_state<R>(Wq, dW[1], false, sym);
+                face_state<R>(Wq, dW[0], true, st);
+                copy5(S.sxp[x + 1][y], st);
+                face_state<R>(Wq, dW[1], true, st);
+                copy5(S.syp[y + 1][x], st);
+            }
+        }
+        if (kind == 1 && rz >= 0 && rz < BC) {
+            R dW[3][NV], Wq[NV], st[NV];
+            const int c = (hx + 2) + PW * (hy + 2);
+            reconstruct<R>(HW0, S.w[c - 1], S.w[c + 1], S.w[c - PW], S.w[c + PW], HWm, HWp, h, gam, dW, Wq);
+            const int q = lane >> 4, k = lane & 15;
+            if (q == 0) {            // x = -1: its x+ state feeds face (-1|0)
+                face_state<R>(Wq, dW[0], true, st);
+                copy5(S.sxp[0][k], st);
+            } else if (q == 1) {     // x = 16: x- state feeds face (15|16)
+                face_state<R>(Wq, dW[0], false, st);
+                copy5(S.sxm_hi[k], st);
+            } else if (q == 2) {     // y = -1
+                face_state<R>(Wq, dW[1], true, st);
+                copy5(S.syp[0][k], st);
+            } else {                 // y = 16
+                face_state<R>(Wq, dW[1], false, st);
+                copy5(S.sym_hi[k], st);
+            }
+        }
+        __syncthreads();
+
+        // 4. fluxes: own low x and y faces of plane rz, the z face (rz-1 | rz),
+        //    and the high x = 16 / y = 16 faces by the extra lanes
+        double gz[NV];
+        if (rz >= 0 && rz < BC) {
+            double G[NV];
+            const bool zx = S.split[(x + 1) + PW * (y + 2)] || sp_cur;
+            face_flux<R>(S.sxp[x][y], sxm, 0, gam, g1, r, zx, G);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) S.gx[x][y][v] = G[v];
+            const bool zy = S.split[(x + 2) + PW * (y + 1)] || sp_cur;
+            face_flux<R>(S.syp[y][x], sym, 1, gam, g1, r, zy, G);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) S.gy[y][x][v] = G[v];
+            if (extra_faces) {
+                const int k = lane & 15;
+                if (lane < BC) {
+                    const bool z2 = S.split[(BC + 1) + PW * (k + 2)] || S.split[(BC + 2) + PW * (k + 2)];
+                    face_flux<R>(S.sxp[BC][k], S.sxm_hi[k], 0, gam, g1, r, z2, G);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) S.gx[BC][k][v] = G[v];
+                } else {
+                    const bool z2 = S.split[(k + 2) + PW * (BC + 1)] || S.split[(k + 2) + PW * (BC + 2)];
+                    face_flux<R>(S.syp[BC][k], S.sym_hi[k], 1, gam, g1, r, z2, G);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) S.gy[BC][k][v] = G[v];
+                }
+            }
+        }
+        if (rz >= 0) face_flux<R>(zp_prev, szm, 2, gam, g1, r, sp_prev || sp_cur, gz);
+        __syncthreads();
+
+        // 5. update: x/y part of plane rz, then plane rz-1 is complete
+        if (rz >= 1) {
+            double out[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) out[v] = acc_prev[v] + (gz_prev[v] - gz[v]);
+            bool sdummy;
+            const int64_t cell = source_cell(S, g, x, y, rz - 1, sdummy);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) a.unew[NV * cell + v] = out[v];
+        }
+        if (rz >= 0 && rz < BC) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                acc_prev[v] = (Ucur[v] + (S.gx[x][y][v] - S.gx[x + 1][y][v])) + (S.gy[y][x][v] - S.gy[y + 1][x][v]);
+        }
+        // shift the plane window
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            gz_prev[v] = rz >= 0 ? gz[v] : 0.0;
+            zp_prev[v] = szp[v];
+            Wm[v] = W0[v];
+            W0[v] = Wp[v];
+            Ucur[v] = Un[v];
+            Un[v] = Unn[v];
+            HWm[v] = HW0[v];
+            HW0[v] = HWp[v];
+            HUn[v] = HUnn[v];
+        }
+        sp_prev = sp_cur;
+        sp_cur = sp_next;
+        sp_next = sp_n2;
+        if (kind == 1) {
+            bool hs;
+            (void)source_cell(S, g, hx, hy, rz + 1, hs);
+            hsp_cur = hs;
+        }
+    }
+}
+
+}  // namespace
+
+rg_status hydro_bricks(const double *uold, double *unew, const int32_t *nbr27, const uint32_t *son,
+                       const uint64_t *keys, const int32_t *bricks, int64_t nbricks, const double *dt, double dx,
+                       double gamma, int outflow, int form, hipStream_t s)
+{
+    if (nbricks <= 0) return RG_OK;
+    BrickArgs a;
+    a.uold = uold;
+    a.unew = unew;
+    a.nbr27 = nbr27;
+    a.son = son;
+    a.keys = keys;
+    a.bricks = bricks;
+    a.nbricks = nbricks;
+    a.dt = dt;
+    a.dx = dx;
+    a.gamma = gamma;
+    a.outflow = outflow;
+    const unsigned grid = static_cast<unsigned>(8 * ((nbricks + 7) / 8));
+    if (form == RG_FP64)
+        k_hydro_brick<double><<<grid, BT, 0, s>>>(a);
+    else
+        k_hydro_brick<float><<<grid, BT, 0, s>>>(a);
+    return launch_status("hydro bricks");
+}
+
+}  // namespace rg

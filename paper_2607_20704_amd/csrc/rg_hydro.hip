@@ -18,11 +18,10 @@
 // All intermediate data stay in LDS; HBM sees uold (stencil reads, mostly
 // L2 hits between neighbouring octs), the neighbour list and unew.
 #include "rg_internal.hpp"
+#include "rg_math.hpp"
 
 namespace rg {
 namespace {
-
-constexpr int NV = 5;
 
 // ---------------------------------------------------------------------------
 // stencil tables (positions are cell offsets from the oct origin, -2..3)
@@ -57,7 +56,7 @@ constexpr StencilTables make_tables()
         for (int a = 0; a < 3; ++a)
             for (int side = 0; side < 2; ++side)
                 for (int q = 0; q < 4; ++q) {
-                    int p[3];
+                    int p[3] = {0, 0, 0};
                     int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
                     p[a] = layer == 0 ? (side ? 2 : -1) : (side ? 3 : -2);
                     p[t1] = q & 1;
@@ -73,7 +72,7 @@ constexpr StencilTables make_tables()
     // edge cells: two coordinates in {-1, 2}, the third in {0, 1}
     for (int a = 0; a < 3; ++a)        // the axis that stays inside
         for (int q = 0; q < 8; ++q) {
-            int p[3];
+            int p[3] = {0, 0, 0};
             int u = a == 0 ? 1 : 0, v = a == 2 ? 1 : 2;
             p[a] = q & 1;
             p[u] = (q >> 1) & 1 ? 2 : -1;
@@ -96,107 +95,11 @@ __device__ __forceinline__ int nslot(int sx, int sy, int sz) { return (sx + 1) +
 __device__ __forceinline__ int slot_of(int x) { return x < 0 ? -1 : (x > 1 ? 1 : 0); }
 
 // ---------------------------------------------------------------------------
-// per-cell and per-face arithmetic; FP64 instances follow the CPU
-// reference's expression order exactly (the library is built without FMA
-// contraction)
-// ---------------------------------------------------------------------------
-
-template <typename R> struct Math;
-
-template <> struct Math<double> {
-    static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
-    static __device__ __forceinline__ double div(double a, double b) { return a / b; }
-};
-
-template <> struct Math<float> {
-    static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
-    static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-};
-
-// conservative -> primitive in double, floors applied
-__device__ __forceinline__ void prim64(const double *U, double gamma, double *W)
-{
-    double rho = U[0] < RG_RHO_MIN ? RG_RHO_MIN : U[0];
-    double inv = 1.0 / rho;
-    double u = U[1] * inv;
-    double v = U[2] * inv;
-    double w = U[3] * inv;
-    double q = (u * u + v * v) + w * w;
-    double ek = 0.5 * rho * q;
-    double p = (gamma - 1.0) * (U[4] - ek);
-    if (p < RG_P_MIN) p = RG_P_MIN;
-    W[0] = rho;
-    W[1] = u;
-    W[2] = v;
-    W[3] = w;
-    W[4] = p;
-}
-
-template <typename R> __device__ __forceinline__ R minmod(R a, R b)
-{
-    if (a > R(0) && b > R(0)) return a < b ? a : b;
-    if (a < R(0) && b < R(0)) return a > b ? a : b;
-    return R(0);
-}
-
-// Hancock half step W' = W - h sum_d A_d(W) dW_d (primitive Euler equations)
-template <typename R>
-__device__ __forceinline__ void predict(const R *W, const R (*dW)[NV], R h, R gamma, R *Wp)
-{
-    const R rho = W[0], u = W[1], v = W[2], w = W[3], p = W[4];
-    const R inv = Math<R>::div(R(1), rho);
-    const R div = (dW[0][1] + dW[1][2]) + dW[2][3];
-    Wp[0] = rho - h * (((u * dW[0][0] + v * dW[1][0]) + w * dW[2][0]) + rho * div);
-    Wp[1] = u - h * (((u * dW[0][1] + v * dW[1][1]) + w * dW[2][1]) + dW[0][4] * inv);
-    Wp[2] = v - h * (((u * dW[0][2] + v * dW[1][2]) + w * dW[2][2]) + dW[1][4] * inv);
-    Wp[3] = w - h * (((u * dW[0][3] + v * dW[1][3]) + w * dW[2][3]) + dW[2][4] * inv);
-    Wp[4] = p - h * (((u * dW[0][4] + v * dW[1][4]) + w * dW[2][4]) + (gamma * p) * div);
-}
-
-// HLLC across a face normal to axis `dir`: Davis wave speeds, contact speed
-// and star pressure in the form symmetric in the two sides, region chosen
-// by S_L > 0, S* > 0, S_R > 0 in that order.  Computed branch-free: both
-// candidate states are formed and one is selected.
-template <typename R>
-__device__ __forceinline__ void hllc(const R *WL, const R *WR, int dir, R gamma, R g1, R *F)
-{
-    const R rl = WL[0], pl = WL[4], ul = WL[1 + dir];
-    const R rr = WR[0], pr = WR[4], ur = WR[1 + dir];
-    const R cl = Math<R>::sqrt_(Math<R>::div(gamma * pl, rl));
-    const R cr = Math<R>::sqrt_(Math<R>::div(gamma * pr, rr));
-    const R sl = (ul - cl) < (ur - cr) ? (ul - cl) : (ur - cr);
-    const R sr = (ul + cl) > (ur + cr) ? (ul + cl) : (ur + cr);
-    const R ml = rl * (ul - sl);
-    const R mr = rr * (sr - ur);
-    const R inv = Math<R>::div(R(1), ml + mr);
-    const R sstar = ((mr * ur + ml * ul) + (pl - pr)) * inv;
-    const R pstar = ((mr * pl + ml * pr) + ml * mr * (ul - ur)) * inv;
-
-    const bool useL = (sl > R(0)) || (sstar > R(0));
-    const bool outer = useL ? (sl > R(0)) : !(sr > R(0));
-    const R *W = useL ? WL : WR;
-    const R s = useL ? sl : sr;
-    const R rho = W[0], un = W[1 + dir], p = W[4];
-    const R q = (W[1] * W[1] + W[2] * W[2]) + W[3] * W[3];
-    const R E = p * g1 + R(0.5) * rho * q;
-    const R d = Math<R>::div(R(1), s - sstar);
-    const R rs = outer ? rho : rho * (s - un) * d;
-    const R es = outer ? E : (((s - un) * E - p * un) + pstar * sstar) * d;
-    const R ss = outer ? un : sstar;
-    const R ps = outer ? p : pstar;
-    const R m = rs * ss;
-    F[0] = m;
-    F[1] = dir == 0 ? (m * ss + ps) : (m * W[1]);
-    F[2] = dir == 1 ? (m * ss + ps) : (m * W[2]);
-    F[3] = dir == 2 ? (m * ss + ps) : (m * W[3]);
-    F[4] = (es + ps) * ss;
-}
-
-// ---------------------------------------------------------------------------
 // the level kernel
 // ---------------------------------------------------------------------------
 
 struct LevelArgs {
+    const int32_t *list;  // if set, the octs are list[oct_begin .. oct_end)
     const double *uold;
     double *unew;
     const int32_t *nbr27;
@@ -210,6 +113,7 @@ struct LevelArgs {
 };
 
 template <typename R, int G> struct Smem {
+    int64_t oct[G];
     int32_t nb[G][27];
     uint32_t sm[G][7];          // son masks: own, then sides x-, x+, y-, y+, z-, z+
     double u[G][8][NV];         // uold of the oct's own cells
@@ -229,10 +133,12 @@ __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, i
     const double g1d = 1.0 / (a.gamma - 1.0);
     const R g1 = static_cast<R>(g1d);
 
-    // neighbour entries and son masks
+    // oct indices, neighbour entries and son masks
+    if (tid < G) S.oct[tid] = tid < count ? (a.list ? int64_t(a.list[first + tid]) : first + tid) : 0;
+    __syncthreads();
     for (int it = tid; it < G * 27; it += NT) {
         int g = it / 27, s = it - 27 * g;
-        S.nb[g][s] = g < count ? a.nbr27[27 * (first + g) + s] : 0;
+        S.nb[g][s] = g < count ? a.nbr27[27 * S.oct[g] + s] : 0;
     }
     __syncthreads();
     for (int it = tid; it < G * 7; it += NT) {
@@ -241,7 +147,7 @@ __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, i
         if (g < count) {
             int e;
             if (k == 0) {
-                e = static_cast<int>(first + g);
+                e = static_cast<int>(S.oct[g]);
             } else {
                 int ax = (k - 1) >> 1, hi = (k - 1) & 1;
                 int sx = ax == 0 ? (hi ? 1 : -1) : 0, sy = ax == 1 ? (hi ? 1 : -1) : 0, sz = ax == 2 ? (hi ? 1 : -1) : 0;
@@ -271,7 +177,7 @@ __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, i
         int e = S.nb[g][nslot(s[0], s[1], s[2])];
         // a consistent list never leaves an outside slot here; an
         // inconsistent one reads the oct itself rather than stray memory
-        if (e == RG_NBR_OUTSIDE) e = static_cast<int>(first + g);
+        if (e == RG_NBR_OUTSIDE) e = static_cast<int>(S.oct[g]);
         const int64_t cell = e >= 0 ? 8 * int64_t(e) + ((c[0] & 1) + 2 * (c[1] & 1) + 4 * (c[2] & 1))
                                     : (-1 - int64_t(e));
         double U[NV], W[NV];
@@ -293,18 +199,11 @@ __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, i
         if (g >= count) continue;
         const int x = c_tab.rpos[rc][0], y = c_tab.rpos[rc][1], z = c_tab.rpos[rc][2];
         const R *w0 = S.w[g][c_tab.tile2w[tile_index(x, y, z)]];
-        R dW[3][NV];
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            const R *wm = S.w[g][c_tab.tile2w[tile_index(x - (ax == 0), y - (ax == 1), z - (ax == 2))]];
-            const R *wp = S.w[g][c_tab.tile2w[tile_index(x + (ax == 0), y + (ax == 1), z + (ax == 2))]];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) dW[ax][v] = minmod<R>(w0[v] - wm[v], wp[v] - w0[v]);
-        }
-        R W0[NV], Wp[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) W0[v] = w0[v];
-        predict<R>(W0, dW, h, gam, Wp);
+        R dW[3][NV], Wp[NV];
+        reconstruct<R>(w0, S.w[g][c_tab.tile2w[tile_index(x - 1, y, z)]], S.w[g][c_tab.tile2w[tile_index(x + 1, y, z)]],
+                       S.w[g][c_tab.tile2w[tile_index(x, y - 1, z)]], S.w[g][c_tab.tile2w[tile_index(x, y + 1, z)]],
+                       S.w[g][c_tab.tile2w[tile_index(x, y, z - 1)]], S.w[g][c_tab.tile2w[tile_index(x, y, z + 1)]], h,
+                       gam, dW, Wp);
         const int p[3] = {x, y, z};
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
@@ -317,11 +216,7 @@ __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, i
                 const int c = side ? p[ax] + 1 : p[ax];
                 if (c < 0 || c > 2) continue;
                 R st[NV];
-#pragma unroll
-                for (int v = 0; v < NV; ++v)
-                    st[v] = side ? (Wp[v] + R(0.5) * dW[ax][v]) : (Wp[v] - R(0.5) * dW[ax][v]);
-                if (st[0] < R(RG_RHO_MIN)) st[0] = R(RG_RHO_MIN);
-                if (st[4] < R(RG_P_MIN)) st[4] = R(RG_P_MIN);
+                face_state<R>(Wp, dW[ax], side != 0, st);
                 R *dst = S.fs[g][face_id(ax, c, p[t1], p[t2])][side ? 0 : 1];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) dst[v] = st[v];
@@ -335,13 +230,12 @@ __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, i
         int g = it / 36, f = it - 36 * g;
         if (g >= count) continue;
         const int ax = f / 12, c = (f / 4) % 3, t1 = f & 1, t2 = (f >> 1) & 1;
-        R L[NV], Rr[NV], F[NV];
+        R L[NV], Rr[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             L[v] = S.fs[g][f][0][v];
             Rr[v] = S.fs[g][f][1][v];
         }
-        hllc<R>(L, Rr, ax, gam, g1, F);
         // split test for the two cells: position c-1 and c along the axis
         bool zero = false;
 #pragma unroll
@@ -355,8 +249,10 @@ __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, i
             const uint32_t m = pa < 0 ? S.sm[g][1 + 2 * ax] : (pa > 1 ? S.sm[g][2 + 2 * ax] : S.sm[g][0]);
             zero = zero || ((m >> bit) & 1u);
         }
+        double gf[NV];
+        face_flux<R>(L, Rr, ax, gam, g1, r, zero, gf);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) S.g[g][f][v] = zero ? 0.0 : static_cast<double>(F[v]) * r;
+        for (int v = 0; v < NV; ++v) S.g[g][f][v] = gf[v];
     }
     __syncthreads();
 
@@ -369,7 +265,7 @@ __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, i
         const double gxm = S.g[g][face_id(0, ix, iy, iz)][v], gxp = S.g[g][face_id(0, ix + 1, iy, iz)][v];
         const double gym = S.g[g][face_id(1, iy, ix, iz)][v], gyp = S.g[g][face_id(1, iy + 1, ix, iz)][v];
         const double gzm = S.g[g][face_id(2, iz, ix, iy)][v], gzp = S.g[g][face_id(2, iz + 1, ix, iy)][v];
-        a.unew[8 * NV * (first + g) + k] = ((S.u[g][cidx][v] + (gxm - gxp)) + (gym - gyp)) + (gzm - gzp);
+        a.unew[8 * NV * S.oct[g] + k] = ((S.u[g][cidx][v] + (gxm - gxp)) + (gym - gyp)) + (gzm - gzp);
     }
 
     // E: flux owed to coarse neighbours
@@ -386,7 +282,7 @@ __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, i
             const double sum = (S.g[g][face_id(ax, c, 0, 0)][v] + S.g[g][face_id(ax, c, 1, 0)][v]) +
                                (S.g[g][face_id(ax, c, 0, 1)][v] + S.g[g][face_id(ax, c, 1, 1)][v]);
             const double d = 0.125 * sum;
-            a.corr[30 * (first + g - a.corr_base) + k] = hi ? d : -d;
+            a.corr[30 * (S.oct[g] - a.corr_base) + k] = hi ? d : -d;
         }
     }
 }
@@ -519,6 +415,28 @@ rg_status hydro_level(const LevelArgs &a, int form, const rg_tuning *tune, hipSt
     return launch_form<float>(a, tune, s);
 }
 
+// octs list[0..count) (or first..first+count when list is null)
+rg_status hydro_level_list(const double *uold, double *unew, const int32_t *nbr27, const uint32_t *son,
+                           const int32_t *list, int64_t count, double *corr, int64_t corr_base, const double *dt,
+                           double dx, double gamma, int form, const rg_tuning *tune, hipStream_t s, int64_t first)
+{
+    if (count <= 0) return RG_OK;
+    LevelArgs a;
+    a.list = list;
+    a.uold = uold;
+    a.unew = unew;
+    a.nbr27 = nbr27;
+    a.son = son;
+    a.corr = corr;
+    a.corr_base = corr_base;
+    a.oct_begin = list ? 0 : first;
+    a.oct_end = a.oct_begin + count;
+    a.dt = dt;
+    a.dx = dx;
+    a.gamma = gamma;
+    return hydro_level(a, form, tune, s);
+}
+
 }  // namespace rg
 
 using namespace rg;
@@ -540,6 +458,7 @@ rg_status rg_hydro_step_level(double dx, const double *d_dt, double gamma, const
     RG_REQUIRE(dx > 0 && gamma > 1, "bad dx or gamma");
     RG_REQUIRE(!d_corr || corr_base <= oct_begin, "corr_base beyond the oct range");
     LevelArgs a;
+    a.list = nullptr;
     a.uold = d_uold;
     a.unew = d_unew;
     a.nbr27 = d_nbr27;

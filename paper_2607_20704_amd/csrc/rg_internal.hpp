@@ -265,6 +265,8 @@ __device__ inline int32_t hash_probe(const uint64_t *keys, const int32_t *vals, 
 // ---------------------------------------------------------------------------
 
 rg_status fill_u32(uint32_t *d, int64_t n, uint32_t v, hipStream_t s);
+rg_status sort_keys_bits(const uint64_t *d_keys_in, int64_t n, uint64_t *d_keys_out, int32_t *d_perm, void *d_ws,
+                         size_t ws_bytes, int end_bit, hipStream_t s);
 rg_status fill_u64(uint64_t *d, int64_t n, uint64_t v, hipStream_t s);
 
 }  // namespace rg

@@ -1,0 +1,147 @@
+// rg_math.hpp -- per-cell and per-face arithmetic of the hydro update,
+// shared by every kernel variant so that all of them produce the same bits.
+//
+// Paper Sec. 3: MUSCL-Hancock predictor-corrector with an HLLC Riemann
+// solver.  The FP64 instances follow the CPU reference's expression order
+// exactly (the library is built without FMA contraction); the float
+// instances serve the mixed form.
+#pragma once
+
+#include "rg_internal.hpp"
+
+namespace rg {
+
+constexpr int NV = 5;
+
+template <typename R> struct Math;
+
+template <> struct Math<double> {
+    static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+    static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+};
+
+template <> struct Math<float> {
+    static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+};
+
+// conservative -> primitive in double, floors applied
+__device__ __forceinline__ void prim64(const double *U, double gamma, double *W)
+{
+    double rho = U[0] < RG_RHO_MIN ? RG_RHO_MIN : U[0];
+    double inv = 1.0 / rho;
+    double u = U[1] * inv;
+    double v = U[2] * inv;
+    double w = U[3] * inv;
+    double q = (u * u + v * v) + w * w;
+    double ek = 0.5 * rho * q;
+    double p = (gamma - 1.0) * (U[4] - ek);
+    if (p < RG_P_MIN) p = RG_P_MIN;
+    W[0] = rho;
+    W[1] = u;
+    W[2] = v;
+    W[3] = w;
+    W[4] = p;
+}
+
+template <typename R> __device__ __forceinline__ R minmod(R a, R b)
+{
+    if (a > R(0) && b > R(0)) return a < b ? a : b;
+    if (a < R(0) && b < R(0)) return a > b ? a : b;
+    return R(0);
+}
+
+// Hancock half step W' = W - h sum_d A_d(W) dW_d (primitive Euler equations)
+template <typename R>
+__device__ __forceinline__ void predict(const R *W, const R (*dW)[NV], R h, R gamma, R *Wp)
+{
+    const R rho = W[0], u = W[1], v = W[2], w = W[3], p = W[4];
+    const R inv = Math<R>::div(R(1), rho);
+    const R div = (dW[0][1] + dW[1][2]) + dW[2][3];
+    Wp[0] = rho - h * (((u * dW[0][0] + v * dW[1][0]) + w * dW[2][0]) + rho * div);
+    Wp[1] = u - h * (((u * dW[0][1] + v * dW[1][1]) + w * dW[2][1]) + dW[0][4] * inv);
+    Wp[2] = v - h * (((u * dW[0][2] + v * dW[1][2]) + w * dW[2][2]) + dW[1][4] * inv);
+    Wp[3] = w - h * (((u * dW[0][3] + v * dW[1][3]) + w * dW[2][3]) + dW[2][4] * inv);
+    Wp[4] = p - h * (((u * dW[0][4] + v * dW[1][4]) + w * dW[2][4]) + (gamma * p) * div);
+}
+
+// HLLC across a face normal to axis `dir`: Davis wave speeds, contact speed
+// and star pressure in the form symmetric in the two sides, region chosen
+// by S_L > 0, S* > 0, S_R > 0 in that order.  Computed branch-free: both
+// candidate states are formed and one is selected.
+template <typename R>
+__device__ __forceinline__ void hllc(const R *WL, const R *WR, int dir, R gamma, R g1, R *F)
+{
+    const R rl = WL[0], pl = WL[4], ul = WL[1 + dir];
+    const R rr = WR[0], pr = WR[4], ur = WR[1 + dir];
+    const R cl = Math<R>::sqrt_(Math<R>::div(gamma * pl, rl));
+    const R cr = Math<R>::sqrt_(Math<R>::div(gamma * pr, rr));
+    const R sl = (ul - cl) < (ur - cr) ? (ul - cl) : (ur - cr);
+    const R sr = (ul + cl) > (ur + cr) ? (ul + cl) : (ur + cr);
+    const R ml = rl * (ul - sl);
+    const R mr = rr * (sr - ur);
+    const R inv = Math<R>::div(R(1), ml + mr);
+    const R sstar = ((mr * ur + ml * ul) + (pl - pr)) * inv;
+    const R pstar = ((mr * pl + ml * pr) + ml * mr * (ul - ur)) * inv;
+
+    const bool useL = (sl > R(0)) || (sstar > R(0));
+    const bool outer = useL ? (sl > R(0)) : !(sr > R(0));
+    const R *W = useL ? WL : WR;
+    const R s = useL ? sl : sr;
+    const R rho = W[0], un = W[1 + dir], p = W[4];
+    const R q = (W[1] * W[1] + W[2] * W[2]) + W[3] * W[3];
+    const R E = p * g1 + R(0.5) * rho * q;
+    const R d = Math<R>::div(R(1), s - sstar);
+    const R rs = outer ? rho : rho * (s - un) * d;
+    const R es = outer ? E : (((s - un) * E - p * un) + pstar * sstar) * d;
+    const R ss = outer ? un : sstar;
+    const R ps = outer ? p : pstar;
+    const R m = rs * ss;
+    F[0] = m;
+    F[1] = dir == 0 ? (m * ss + ps) : (m * W[1]);
+    F[2] = dir == 1 ? (m * ss + ps) : (m * W[2]);
+    F[3] = dir == 2 ? (m * ss + ps) : (m * W[3]);
+    F[4] = (es + ps) * ss;
+}
+
+
+}  // namespace rg
+
+namespace rg {
+
+// minmod slopes along x, y, z of primitive cell W0 from its six neighbours,
+// then the Hancock half step W'
+template <typename R>
+__device__ __forceinline__ void reconstruct(const R *w0, const R *wxm, const R *wxp, const R *wym, const R *wyp,
+                                            const R *wzm, const R *wzp, R h, R gamma, R (*dW)[NV], R *Wp)
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        dW[0][v] = minmod<R>(w0[v] - wxm[v], wxp[v] - w0[v]);
+        dW[1][v] = minmod<R>(w0[v] - wym[v], wyp[v] - w0[v]);
+        dW[2][v] = minmod<R>(w0[v] - wzm[v], wzp[v] - w0[v]);
+    }
+    predict<R>(w0, dW, h, gamma, Wp);
+}
+
+// face state on the high (W' + dW/2) or low (W' - dW/2) side of a cell along
+// one axis, density and pressure floored
+template <typename R> __device__ __forceinline__ void face_state(const R *Wp, const R *dWa, bool high, R *st)
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) st[v] = high ? (Wp[v] + R(0.5) * dWa[v]) : (Wp[v] - R(0.5) * dWa[v]);
+    if (st[0] < R(RG_RHO_MIN)) st[0] = R(RG_RHO_MIN);
+    if (st[4] < R(RG_P_MIN)) st[4] = R(RG_P_MIN);
+}
+
+// G = F dt/dx in double, or zero on a face touching a split cell
+template <typename R> __device__ __forceinline__ void face_flux(const R *L, const R *Rt, int dir, R gamma, R g1,
+                                                                double r, bool zero, double *G)
+{
+    R F[NV];
+    hllc<R>(L, Rt, dir, gamma, g1, F);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) G[v] = zero ? 0.0 : static_cast<double>(F[v]) * r;
+}
+
+}  // namespace rg

@@ -1,0 +1,114 @@
+// rg_sched.hip -- kernel schedule of a tree and the scheduled level update.
+//
+// Paper Sec. 3: grouping octs into larger blocks (nsubgrid) shares the
+// stencil and removes redundant ghost-cell work; in a cell-by-cell tree only
+// some regions are covered by complete blocks.  The schedule finds, per
+// level, the complete Hilbert-aligned 8^3-oct bricks that border no coarse
+// ghost, and lists every other oct for the per-oct kernel.
+#include <vector>
+
+#include "rg_internal.hpp"
+
+namespace rg {
+rg_status hydro_level_list(const double *uold, double *unew, const int32_t *nbr27, const uint32_t *son,
+                           const int32_t *list, int64_t count, double *corr, int64_t corr_base, const double *dt,
+                           double dx, double gamma, int form, const rg_tuning *tune, hipStream_t s,
+                           int64_t first = 0);
+rg_status hydro_bricks(const double *uold, double *unew, const int32_t *nbr27, const uint32_t *son,
+                       const uint64_t *keys, const int32_t *bricks, int64_t nbricks, const double *dt, double dx,
+                       double gamma, int outflow, int form, hipStream_t s);
+}  // namespace rg
+
+using namespace rg;
+
+namespace {
+constexpr int64_t kBrickOcts = 512;
+}
+
+extern "C" {
+
+rg_status rg_schedule_build(const rg_tree *t, int32_t *d_list, int64_t capacity, rg_schedule *out, void *stream)
+{
+    RG_REQUIRE(t && d_list && out, "null pointer");
+    RG_REQUIRE(t->n_oct > 0 && capacity >= t->n_oct, "list capacity below n_oct");
+    RG_REQUIRE(t->lmin >= 1 && t->lmax >= t->lmin && t->lmax <= RG_MAX_LEVEL, "bad levels");
+    const int64_t n = t->n_oct;
+    hipStream_t s = as_stream(stream);
+    std::vector<uint64_t> keys(n);
+    std::vector<int32_t> nbr(static_cast<size_t>(27) * n);
+    hipError_t e = hipMemcpyAsync(keys.data(), t->d_keys, n * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(nbr.data(), t->d_nbr27, nbr.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(RG_EHIP, "schedule readback: %s", hipGetErrorString(e));
+
+    std::vector<int32_t> list;
+    list.reserve(n);
+    for (int l = 0; l < RG_MAX_LEVEL + 2; ++l)
+        out->brick_begin[l] = out->brick_count[l] = out->rest_begin[l] = out->rest_count[l] = 0;
+    for (int l = t->lmin; l <= t->lmax; ++l) {
+        const int64_t b = t->level_begin[l], end = t->level_begin[l + 1];
+        std::vector<uint8_t> covered(end - b, 0);
+        out->brick_begin[l] = static_cast<int64_t>(list.size());
+        for (int64_t o = b; o + kBrickOcts <= end;) {
+            const uint64_t k = keys[o];
+            if ((k & (kBrickOcts - 1)) == 0 && keys[o + kBrickOcts - 1] == k + kBrickOcts - 1) {
+                bool coarse = false;
+                for (int64_t q = o; q < o + kBrickOcts && !coarse; ++q)
+                    for (int j = 0; j < 27; ++j) {
+                        const int32_t v = nbr[27 * q + j];
+                        if (v < 0 && v != RG_NBR_OUTSIDE) { coarse = true; break; }
+                    }
+                if (!coarse) {
+                    list.push_back(static_cast<int32_t>(o));
+                    for (int64_t q = o; q < o + kBrickOcts; ++q) covered[q - b] = 1;
+                }
+                o += kBrickOcts;
+            } else {
+                ++o;
+            }
+        }
+        out->brick_count[l] = static_cast<int64_t>(list.size()) - out->brick_begin[l];
+        out->rest_begin[l] = static_cast<int64_t>(list.size());
+        for (int64_t o = b; o < end; ++o)
+            if (!covered[o - b]) list.push_back(static_cast<int32_t>(o));
+        out->rest_count[l] = static_cast<int64_t>(list.size()) - out->rest_begin[l];
+    }
+    if (static_cast<int64_t>(list.size()) > capacity) return fail(RG_EINVAL, "schedule exceeds list capacity");
+    if (!list.empty()) {
+        e = hipMemcpyAsync(d_list, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return fail(RG_EHIP, "schedule upload: %s", hipGetErrorString(e));
+    }
+    out->d_list = d_list;
+    return RG_OK;
+}
+
+rg_status rg_hydro_step_scheduled(const rg_tree *t, const rg_schedule *sc, int level, const double *d_dt,
+                                  double gamma, const double *d_uold, double *d_unew, int form,
+                                  const rg_tuning *tune, void *stream)
+{
+    RG_REQUIRE(t && sc && sc->d_list && d_dt && d_uold && d_unew, "null pointer");
+    RG_REQUIRE(level >= t->lmin && level <= t->lmax, "level %d not in the tree", level);
+    RG_REQUIRE(d_uold != d_unew, "uold and unew must not alias");
+    RG_REQUIRE(form == RG_FP64 || form == RG_MIXED, "bad form %d", form);
+    RG_REQUIRE(gamma > 1, "bad gamma");
+    hipStream_t s = as_stream(stream);
+    const double dx = ldexp(1.0, -level);
+    const int64_t corr_base = t->level_begin[t->lmin + 1];
+    double *corr = level > t->lmin ? t->d_corr : nullptr;
+    const bool bricks = !(tune && tune->no_bricks);
+    if (bricks) {
+        RG_TRY(hydro_bricks(d_uold, d_unew, t->d_nbr27, t->d_son_mask, t->d_keys, sc->d_list + sc->brick_begin[level],
+                            sc->brick_count[level], d_dt, dx, gamma, t->bc == RG_BC_OUTFLOW, form, s));
+        RG_TRY(hydro_level_list(d_uold, d_unew, t->d_nbr27, t->d_son_mask, sc->d_list + sc->rest_begin[level],
+                                sc->rest_count[level], corr, corr_base, d_dt, dx, gamma, form, tune, s));
+    } else {
+        RG_TRY(hydro_level_list(d_uold, d_unew, t->d_nbr27, t->d_son_mask, nullptr,
+                                t->level_begin[level + 1] - t->level_begin[level], corr, corr_base, d_dt, dx, gamma,
+                                form, tune, s, t->level_begin[level]));
+    }
+    return RG_OK;
+}
+
+}  // extern "C"

@@ -250,8 +250,11 @@ size_t rg_sort_workspace_bytes(int64_t n)
     return iota + ((temp + 255) & ~size_t(255)) + 256;
 }
 
-rg_status rg_sort_keys(const uint64_t *d_keys_in, int64_t n, uint64_t *d_keys_out, int32_t *d_perm, void *d_ws,
-                       size_t ws_bytes, void *stream)
+}  // extern "C"
+
+// radix sort over the low `end_bit` bits (keys of levels <= L fit 3L bits)
+rg_status rg::sort_keys_bits(const uint64_t *d_keys_in, int64_t n, uint64_t *d_keys_out, int32_t *d_perm, void *d_ws,
+                             size_t ws_bytes, int end_bit, hipStream_t s)
 {
     RG_REQUIRE(n >= 0 && n <= INT32_MAX, "n out of range");
     if (n == 0) return RG_OK;
@@ -259,17 +262,25 @@ rg_status rg_sort_keys(const uint64_t *d_keys_in, int64_t n, uint64_t *d_keys_ou
     RG_REQUIRE(d_keys_in != d_keys_out, "in-place sort is not supported");
     RG_REQUIRE(ws_bytes >= rg_sort_workspace_bytes(n), "sort workspace too small");
     RG_REQUIRE(aligned(d_ws, 256), "workspace must be 256-byte aligned");
-    hipStream_t s = as_stream(stream);
+    RG_REQUIRE(end_bit > 0 && end_bit <= 64, "bad key width");
     int32_t *iota = static_cast<int32_t *>(d_ws);
     size_t iota_bytes = (static_cast<size_t>(n) * sizeof(int32_t) + 255) & ~size_t(255);
     void *temp = static_cast<char *>(d_ws) + iota_bytes;
     size_t temp_bytes = ws_bytes - iota_bytes;
     k_iota<<<grid_for(n, 256), 256, 0, s>>>(iota, n);
-    RG_TRY(launch_status("rg_sort_keys iota"));
+    RG_TRY(launch_status("sort iota"));
     hipError_t e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, d_keys_in, d_keys_out, iota, d_perm,
-                                                      static_cast<int>(n), 0, 64, s);
+                                                      static_cast<int>(n), 0, end_bit, s);
     if (e != hipSuccess) return fail(RG_EHIP, "radix sort: %s", hipGetErrorString(e));
-    return launch_status("rg_sort_keys");
+    return launch_status("radix sort");
+}
+
+extern "C" {
+
+rg_status rg_sort_keys(const uint64_t *d_keys_in, int64_t n, uint64_t *d_keys_out, int32_t *d_perm, void *d_ws,
+                       size_t ws_bytes, void *stream)
+{
+    return sort_keys_bits(d_keys_in, n, d_keys_out, d_perm, d_ws, ws_bytes, 64, as_stream(stream));
 }
 
 rg_status rg_level_ranges(const uint64_t *d_sorted_keys, int64_t n, int64_t *d_level_begin, void *stream)

@@ -201,6 +201,10 @@ typedef struct rg_schedule {
     int64_t brick_count[RG_MAX_LEVEL + 2];
     int64_t rest_begin[RG_MAX_LEVEL + 2];
     int64_t rest_count[RG_MAX_LEVEL + 2];
+    /* neighbour-list build: every complete brick (coarse neighbours allowed;
+     * only the slots around the brick are hashed) and the other octs */
+    int64_t nbr_brick_begin, nbr_brick_count;
+    int64_t nbr_rest_begin, nbr_rest_count;
     const int32_t *d_list;
 } rg_schedule;
 
@@ -285,8 +289,10 @@ typedef struct rg_tree {
 } rg_tree;
 
 /* Builds the schedule of tree t (keys, level ranges and neighbour lists must
- * be current) into the caller's d_list (capacity >= n_oct int32 entries).
- * Reads the keys and neighbour lists back to the host: synchronises. */
+ * be current) into the caller's d_list (capacity >= 2 n_oct int32 entries).
+ * Reads the keys and neighbour lists back to the host: synchronises.  Once
+ * t->sched points to it, rg_prepare_tree builds neighbour lists brick by
+ * brick. */
 rg_status rg_schedule_build(const rg_tree *t, int32_t *d_list, int64_t capacity, rg_schedule *out, void *stream);
 
 /* One level's update following a schedule: the level's bricks with the

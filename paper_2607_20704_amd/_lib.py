@@ -31,7 +31,8 @@ class RgTuning(ctypes.Structure):
 class RgSchedule(ctypes.Structure):
     _fields_ = [("brick_begin", i64 * (RG_MAX_LEVEL + 2)), ("brick_count", i64 * (RG_MAX_LEVEL + 2)),
                 ("rest_begin", i64 * (RG_MAX_LEVEL + 2)), ("rest_count", i64 * (RG_MAX_LEVEL + 2)),
-                ("d_list", P)]
+                ("nbr_brick_begin", i64), ("nbr_brick_count", i64), ("nbr_rest_begin", i64),
+                ("nbr_rest_count", i64), ("d_list", P)]
 
 
 class RgTree(ctypes.Structure):

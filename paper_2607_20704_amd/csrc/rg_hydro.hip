@@ -313,29 +313,29 @@ struct DtArgs {
 
 __global__ void k_set_u64(unsigned long long *p, unsigned long long v) { *p = v; }
 
+// Grid-stride over cells: a bounded grid keeps the final atomics few.
 __global__ __launch_bounds__(256) void k_cfl_dt(DtArgs a)
 {
-    const int64_t cell = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     double best = __longlong_as_double(0x7ff0000000000000ll);   // +inf
-    if (cell < a.n_cell) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t cell = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; cell < a.n_cell; cell += stride) {
         const int64_t o = cell >> 3;
         const int c = static_cast<int>(cell & 7);
-        if (!((a.son[o] >> c) & 1u)) {
-            int l = a.lmin;
-            while (l < a.lmax && o >= a.begin[l + 1]) ++l;
-            const double dx = ldexp(1.0, -l);
-            double U[NV], W[NV];
+        if ((a.son[o] >> c) & 1u) continue;
+        int l = a.lmin;
+        while (l < a.lmax && o >= a.begin[l + 1]) ++l;
+        const double dx = ldexp(1.0, -l);
+        double U[NV], W[NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) U[v] = a.u[NV * cell + v];
-            prim64(U, a.gamma, W);
-            const double cs = sqrt((a.gamma * W[4]) / W[0]);
-            const double sp = ((fabs(W[1]) + fabs(W[2])) + fabs(W[3])) + 3.0 * cs;
-            const double d = dx / sp;
-            // cfl * min(d) == min(cfl * d): rounding a product by a positive
-            // constant is monotone
-            const double cd = a.cfl * d;
-            if (cd < best) best = cd;
-        }
+        for (int v = 0; v < NV; ++v) U[v] = a.u[NV * cell + v];
+        prim64(U, a.gamma, W);
+        const double cs = sqrt((a.gamma * W[4]) / W[0]);
+        const double sp = ((fabs(W[1]) + fabs(W[2])) + fabs(W[3])) + 3.0 * cs;
+        const double d = dx / sp;
+        // cfl * min(d) == min(cfl * d): rounding a product by a positive
+        // constant is monotone
+        const double cd = a.cfl * d;
+        if (cd < best) best = cd;
     }
     // wavefront minimum, then across the block's waves, then one atomic
 #pragma unroll
@@ -524,7 +524,8 @@ rg_status rg_cfl_dt(const double *d_u, const uint32_t *d_son_mask, const int64_t
     k_set_u64<<<1, 1, 0, s>>>(a.dt_bits, 0x7ff0000000000000ull);
     RG_TRY(launch_status("rg_cfl_dt init"));
     if (a.n_cell == 0) return RG_OK;
-    k_cfl_dt<<<grid_for(a.n_cell, 256), 256, 0, s>>>(a);
+    const unsigned blocks = grid_for(a.n_cell, 256);
+    k_cfl_dt<<<blocks < 2048 ? blocks : 2048, 256, 0, s>>>(a);
     return launch_status("rg_cfl_dt");
 }
 

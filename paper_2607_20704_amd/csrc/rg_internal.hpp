@@ -265,6 +265,9 @@ __device__ inline int32_t hash_probe(const uint64_t *keys, const int32_t *vals, 
 // ---------------------------------------------------------------------------
 
 rg_status fill_u32(uint32_t *d, int64_t n, uint32_t v, hipStream_t s);
+rg_status neighbours_scheduled(void *d_ws, const uint64_t *d_keys, int64_t n, int lmin, int bc, const int32_t *bricks,
+                               int64_t nbricks, const int32_t *rest, int64_t nrest, int32_t *d_nbr27,
+                               int32_t *d_father_cell, uint32_t *d_son_mask, hipStream_t s);
 rg_status sort_keys_bits(const uint64_t *d_keys_in, int64_t n, uint64_t *d_keys_out, int32_t *d_perm, void *d_ws,
                          size_t ws_bytes, int end_bit, hipStream_t s);
 rg_status fill_u64(uint64_t *d, int64_t n, uint64_t v, hipStream_t s);

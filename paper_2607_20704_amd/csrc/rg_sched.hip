@@ -30,7 +30,7 @@ extern "C" {
 rg_status rg_schedule_build(const rg_tree *t, int32_t *d_list, int64_t capacity, rg_schedule *out, void *stream)
 {
     RG_REQUIRE(t && d_list && out, "null pointer");
-    RG_REQUIRE(t->n_oct > 0 && capacity >= t->n_oct, "list capacity below n_oct");
+    RG_REQUIRE(t->n_oct > 0 && capacity >= 2 * t->n_oct, "list capacity below 2 n_oct");
     RG_REQUIRE(t->lmin >= 1 && t->lmax >= t->lmin && t->lmax <= RG_MAX_LEVEL, "bad levels");
     const int64_t n = t->n_oct;
     hipStream_t s = as_stream(stream);
@@ -42,17 +42,19 @@ rg_status rg_schedule_build(const rg_tree *t, int32_t *d_list, int64_t capacity,
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(RG_EHIP, "schedule readback: %s", hipGetErrorString(e));
 
-    std::vector<int32_t> list;
-    list.reserve(n);
+    std::vector<int32_t> list, all_bricks, other;
+    list.reserve(2 * n);
     for (int l = 0; l < RG_MAX_LEVEL + 2; ++l)
         out->brick_begin[l] = out->brick_count[l] = out->rest_begin[l] = out->rest_count[l] = 0;
     for (int l = t->lmin; l <= t->lmax; ++l) {
         const int64_t b = t->level_begin[l], end = t->level_begin[l + 1];
-        std::vector<uint8_t> covered(end - b, 0);
+        std::vector<uint8_t> covered(end - b, 0), complete(end - b, 0);
         out->brick_begin[l] = static_cast<int64_t>(list.size());
         for (int64_t o = b; o + kBrickOcts <= end;) {
             const uint64_t k = keys[o];
             if ((k & (kBrickOcts - 1)) == 0 && keys[o + kBrickOcts - 1] == k + kBrickOcts - 1) {
+                all_bricks.push_back(static_cast<int32_t>(o));
+                for (int64_t q = o; q < o + kBrickOcts; ++q) complete[q - b] = 1;
                 bool coarse = false;
                 for (int64_t q = o; q < o + kBrickOcts && !coarse; ++q)
                     for (int j = 0; j < 27; ++j) {
@@ -73,7 +75,15 @@ rg_status rg_schedule_build(const rg_tree *t, int32_t *d_list, int64_t capacity,
         for (int64_t o = b; o < end; ++o)
             if (!covered[o - b]) list.push_back(static_cast<int32_t>(o));
         out->rest_count[l] = static_cast<int64_t>(list.size()) - out->rest_begin[l];
+        for (int64_t o = b; o < end; ++o)
+            if (!complete[o - b]) other.push_back(static_cast<int32_t>(o));
     }
+    out->nbr_brick_begin = static_cast<int64_t>(list.size());
+    out->nbr_brick_count = static_cast<int64_t>(all_bricks.size());
+    list.insert(list.end(), all_bricks.begin(), all_bricks.end());
+    out->nbr_rest_begin = static_cast<int64_t>(list.size());
+    out->nbr_rest_count = static_cast<int64_t>(other.size());
+    list.insert(list.end(), other.begin(), other.end());
     if (static_cast<int64_t>(list.size()) > capacity) return fail(RG_EINVAL, "schedule exceeds list capacity");
     if (!list.empty()) {
         e = hipMemcpyAsync(d_list, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);

@@ -132,28 +132,32 @@ __global__ void k_hash_lookup(const uint64_t *__restrict__ keys, const int32_t *
 // (one per offset); the octs' coordinates are decoded once into LDS.
 constexpr int kNbrOcts = 9;
 
-__global__ __launch_bounds__(256) void k_neighbours(const uint64_t *__restrict__ okeys, int64_t n, int lmin, int bc,
-                                                    HashHeader *hdr, const uint64_t *__restrict__ keys,
-                                                    const int32_t *__restrict__ vals, uint64_t mask,
-                                                    int32_t *__restrict__ nbr27, int32_t *__restrict__ father_cell,
-                                                    uint32_t *__restrict__ son_mask)
+// `list` (optional) maps positions 0..n-1 to oct indices
+__global__ __launch_bounds__(256) void k_neighbours(const uint64_t *__restrict__ okeys, const int32_t *__restrict__ list,
+                                                    int64_t n, int lmin, int bc, HashHeader *hdr,
+                                                    const uint64_t *__restrict__ keys, const int32_t *__restrict__ vals,
+                                                    uint64_t mask, int32_t *__restrict__ nbr27,
+                                                    int32_t *__restrict__ father_cell, uint32_t *__restrict__ son_mask)
 {
     __shared__ int32_t s_c[kNbrOcts][4];
+    __shared__ int64_t s_o[kNbrOcts];
     const int64_t first = int64_t(blockIdx.x) * kNbrOcts;
     const int t = threadIdx.x;
     if (t < kNbrOcts && first + t < n) {
+        const int64_t o = list ? int64_t(list[first + t]) : first + t;
         int32_t i, j, k, l;
-        key_coords(okeys[first + t], i, j, k, l);
+        key_coords(okeys[o], i, j, k, l);
         s_c[t][0] = i;
         s_c[t][1] = j;
         s_c[t][2] = k;
         s_c[t][3] = l;
+        s_o[t] = o;
     }
     __syncthreads();
     if (t >= 27 * kNbrOcts) return;
     const int g = t / 27, slot = t - 27 * g;
-    const int64_t o = first + g;
-    if (o >= n) return;
+    if (first + g >= n) return;
+    const int64_t o = s_o[g];
     const int32_t i = s_c[g][0], j = s_c[g][1], k = s_c[g][2], l = s_c[g][3];
     if (slot == 13) {
         nbr27[27 * o + 13] = static_cast<int32_t>(o);
@@ -197,7 +201,115 @@ __global__ __launch_bounds__(256) void k_neighbours(const uint64_t *__restrict__
     nbr27[27 * o + slot] = e;
 }
 
+// Neighbour lists of complete bricks (8^3 octs, keys 512 P .. 512 P + 511,
+// consecutive in memory).  Inside the brick every neighbour follows from the
+// decoded positions; only the 488 oct slots around the brick are looked up
+// in the hash table (with the coarse-cell fallback), and each sibling
+// group's father is looked up once.  Every child of the brick's fathers lies
+// in the brick, so their son masks are complete (all 8 bits) and are stored
+// directly.
+__global__ __launch_bounds__(256) void k_neighbours_brick(const uint64_t *__restrict__ okeys,
+                                                          const int32_t *__restrict__ bricks, int64_t nbricks,
+                                                          int lmin, int bc, HashHeader *hdr,
+                                                          const uint64_t *__restrict__ keys,
+                                                          const int32_t *__restrict__ vals, uint64_t mask,
+                                                          int32_t *__restrict__ nbr27,
+                                                          int32_t *__restrict__ father_cell,
+                                                          uint32_t *__restrict__ son_mask)
+{
+    constexpr int BO = 8, HS = 10;
+    __shared__ int32_t s_slot[HS * HS * HS];
+    __shared__ int16_t s_pos[BO * BO * BO];       // local position of the k-th oct in key order
+    __shared__ int32_t s_father[BO * BO];         // father oct of each sibling group
+    const int tid = threadIdx.x;
+    const int64_t per_xcd = (nbricks + 7) / 8;
+    const int64_t b = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (b >= nbricks) return;
+    const int64_t base = bricks[b];
+    int32_t i0, j0, k0, l;
+    key_coords(okeys[base], i0, j0, k0, l);
+    i0 &= ~(BO - 1);
+    j0 &= ~(BO - 1);
+    k0 &= ~(BO - 1);
+    for (int k = tid; k < BO * BO * BO; k += 256) {
+        int32_t i, j, kk, ll;
+        key_coords(okeys[base + k], i, j, kk, ll);
+        const int p = (i & 7) + BO * (j & 7) + BO * BO * (kk & 7);
+        s_pos[k] = static_cast<int16_t>(p);
+        s_slot[((p & 7) + 1) + HS * (((p >> 3) & 7) + 1) + HS * HS * ((p >> 6) + 1)] = static_cast<int32_t>(base + k);
+    }
+    const int32_t N = 1 << (l - 1);
+    for (int sidx = tid; sidx < HS * HS * HS; sidx += 256) {
+        const int sa = sidx % HS - 1, sb = (sidx / HS) % HS - 1, sc = sidx / (HS * HS) - 1;
+        if (sa >= 0 && sa < BO && sb >= 0 && sb < BO && sc >= 0 && sc < BO) continue;
+        int32_t ni = i0 + sa, nj = j0 + sb, nk = k0 + sc;
+        int32_t e;
+        if (bc == RG_BC_PERIODIC) {
+            ni &= N - 1;
+            nj &= N - 1;
+            nk &= N - 1;
+        } else if (ni < 0 || nj < 0 || nk < 0 || ni >= N || nj >= N || nk >= N) {
+            s_slot[sidx] = RG_NBR_OUTSIDE;
+            continue;
+        }
+        const uint64_t kn = oct_key(ni, nj, nk, l);
+        e = hash_probe(keys, vals, mask, kn);
+        if (e < 0) {
+            const int32_t f = (l > 1) ? hash_probe(keys, vals, mask, kn >> 3) : -1;
+            if (f < 0) {
+                flag_error(hdr, RG_EUNGRADED, base);
+                e = 0;
+            } else {
+                e = -1 - (8 * f + (ni & 1) + 2 * (nj & 1) + 4 * (nk & 1));
+            }
+        }
+        s_slot[sidx] = e;
+    }
+    if (tid < BO * BO) {
+        int32_t f = -1;
+        if (l > lmin) {
+            f = hash_probe(keys, vals, mask, okeys[base + 8 * tid] >> 3);
+            if (f < 0) flag_error(hdr, RG_EUNGRADED, base + 8 * tid);
+            else son_mask[f] = 0xffu;
+        }
+        s_father[tid] = f;
+    }
+    __syncthreads();
+    for (int q = tid; q < 27 * BO * BO * BO; q += 256) {
+        const int k = q / 27, e = q - 27 * k;
+        const int p = s_pos[k];
+        const int a = (p & 7) + e % 3, bb = ((p >> 3) & 7) + (e / 3) % 3, c = (p >> 6) + e / 9;
+        nbr27[27 * base + q] = s_slot[a + HS * bb + HS * HS * c];
+    }
+    for (int k = tid; k < BO * BO * BO; k += 256) {
+        const int p = s_pos[k];
+        const int32_t f = s_father[k >> 3];
+        father_cell[base + k] = f < 0 ? -1 : 8 * f + ((p & 1) + 2 * ((p >> 3) & 1) + 4 * ((p >> 6) & 1));
+    }
+}
+
 }  // namespace
+
+rg_status neighbours_scheduled(void *d_ws, const uint64_t *d_keys, int64_t n, int lmin, int bc, const int32_t *bricks,
+                               int64_t nbricks, const int32_t *rest, int64_t nrest, int32_t *d_nbr27,
+                               int32_t *d_father_cell, uint32_t *d_son_mask, hipStream_t s)
+{
+    const uint64_t cap = hash_capacity(n);
+    HashView h = hash_view(d_ws, cap);
+    RG_TRY(fill_u32(d_son_mask, n, 0u, s));
+    if (nbricks > 0) {
+        k_neighbours_brick<<<static_cast<unsigned>(8 * ((nbricks + 7) / 8)), 256, 0, s>>>(
+            d_keys, bricks, nbricks, lmin, bc, h.hdr, h.keys, h.vals, h.mask, d_nbr27, d_father_cell, d_son_mask);
+        RG_TRY(launch_status("brick neighbours"));
+    }
+    if (nrest > 0) {
+        const int64_t blocks = (nrest + kNbrOcts - 1) / kNbrOcts;
+        k_neighbours<<<static_cast<unsigned>(blocks), 256, 0, s>>>(d_keys, rest, nrest, lmin, bc, h.hdr, h.keys,
+                                                                   h.vals, h.mask, d_nbr27, d_father_cell, d_son_mask);
+        RG_TRY(launch_status("neighbours"));
+    }
+    return RG_OK;
+}
 
 rg_status fill_u32(uint32_t *d, int64_t n, uint32_t v, hipStream_t s)
 {
@@ -397,8 +509,8 @@ rg_status rg_build_neighbours(void *d_ws, const uint64_t *d_keys, int64_t n, int
     hipStream_t s = as_stream(stream);
     RG_TRY(fill_u32(d_son_mask, n, 0u, s));
     const int64_t blocks = (n + kNbrOcts - 1) / kNbrOcts;
-    k_neighbours<<<static_cast<unsigned>(blocks), 256, 0, s>>>(d_keys, n, lmin, bc, h.hdr, h.keys, h.vals, h.mask,
-                                                               d_nbr27, d_father_cell, d_son_mask);
+    k_neighbours<<<static_cast<unsigned>(blocks), 256, 0, s>>>(d_keys, nullptr, n, lmin, bc, h.hdr, h.keys, h.vals,
+                                                               h.mask, d_nbr27, d_father_cell, d_son_mask);
     return launch_status("rg_build_neighbours");
 }
 

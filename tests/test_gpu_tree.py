@@ -78,22 +78,41 @@ def test_neighbours_match_oracle(case):
     name, ijkl, bc, _ = case
     say("neighbours:", name, len(ijkl))
     T, D = build_both(ijkl, bc)
+    check_lists(T, D)
+
+
+def check_lists(T, D):
+    """Lists of the plain build, then of the scheduled (brick-local) rebuild
+    after re-keying, all equal to the oracle's."""
+    from paper_2607_20704_amd import api
+    assert np.array_equal(D.nbr27.cpu().numpy(), T.nbr27)
+    assert np.array_equal(D.father_cell.cpu().numpy(), T.father_cell)
+    assert np.array_equal(D.son_mask.cpu().numpy(), T.son_mask.astype(np.int32))
+    say("  schedule", D.schedule_counts(), "bricks for lists", D.sched.nbr_brick_count,
+        "other octs", D.sched.nbr_rest_count)
+    D.nbr27.fill_(-7)
+    D.father_cell.fill_(-7)
+    D.son_mask.fill_(-7)
+    D.prepare()
+    assert api.check_ws(D.hash_ws)[0] == 0
+    assert np.array_equal(D.keys.cpu().numpy(), T.keys)
+    assert np.array_equal(D.perm_scratch.cpu().numpy(), np.arange(T.n))
+    assert np.array_equal(D.level_begin_dev.cpu().numpy(), D.level_begin)
     assert np.array_equal(D.nbr27.cpu().numpy(), T.nbr27)
     assert np.array_equal(D.father_cell.cpu().numpy(), T.father_cell)
     assert np.array_equal(D.son_mask.cpu().numpy(), T.son_mask.astype(np.int32))
 
 
-@pytest.mark.parametrize("name", ["sedov_l6_l8", "uniform_l8_periodic", "uniform_l5_outflow"])
+@pytest.mark.parametrize("name", ["sedov_l6_l8", "uniform_l8_periodic", "uniform_l5_outflow", "sedov_l4_l6"])
 def test_neighbours_match_oracle_large(name):
     w = {"sedov_l6_l8": lambda: (I.sedov_amr().ijkl, I.PERIODIC),
          "uniform_l8_periodic": lambda: (I.uniform_tree(8), I.PERIODIC),
-         "uniform_l5_outflow": lambda: (I.uniform_tree(5), I.OUTFLOW)}[name]
+         "uniform_l5_outflow": lambda: (I.uniform_tree(5), I.OUTFLOW),
+         "sedov_l4_l6": lambda: (I.sedov_amr(base=4, lmax=6).ijkl, I.PERIODIC)}[name]
     ijkl, bc = w()
     say("neighbours:", name, len(ijkl))
     T, D = build_both(ijkl, bc)
-    assert np.array_equal(D.nbr27.cpu().numpy(), T.nbr27)
-    assert np.array_equal(D.father_cell.cpu().numpy(), T.father_cell)
-    assert np.array_equal(D.son_mask.cpu().numpy(), T.son_mask.astype(np.int32))
+    check_lists(T, D)
 
 
 def test_ungraded_tree_is_reported():

@@ -140,6 +140,8 @@ def main():
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-octs", type=int, default=1 << 20)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         sys.exit("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus)
@@ -155,6 +157,14 @@ def main():
     u0 = D.to_key_order(w.u)
     torch.cuda.synchronize()
     cells = 8 * D.n
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     res = {}
     for f in forms:

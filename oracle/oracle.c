@@ -272,18 +272,18 @@ int orc_neighbours(int64_t n, const int32_t *ijkl, int bc, int32_t *nbr27,
 
 /* Conservative (rho, rho u, rho v, rho w, E) -> primitive (rho, u, v, w, p),
  * ideal gas, with the density floor applied before dividing and the pressure
- * floor applied last. */
+ * floor applied last (floors are max(value, floor), fmax: a NaN value gives
+ * the floor). */
 void orc_prim(const double *U, double gamma, double *W)
 {
-    double rho = U[0] < ORC_RHO_MIN ? ORC_RHO_MIN : U[0];
+    double rho = fmax(U[0], ORC_RHO_MIN);
     double inv = 1.0 / rho;
     double u = U[1] * inv;
     double v = U[2] * inv;
     double w = U[3] * inv;
     double q = (u * u + v * v) + w * w;
     double ek = 0.5 * rho * q;
-    double p = (gamma - 1.0) * (U[4] - ek);
-    if (p < ORC_P_MIN) p = ORC_P_MIN;
+    double p = fmax((gamma - 1.0) * (U[4] - ek), ORC_P_MIN);
     W[0] = rho; W[1] = u; W[2] = v; W[3] = w; W[4] = p;
 }
 
@@ -326,8 +326,8 @@ void orc_hllc(const double *WL, const double *WR, int dir, double gamma, double 
     double rr = WR[0], pr = WR[4], ur = WR[1 + dir];
     double cl = sqrt((gamma * pl) / rl);
     double cr = sqrt((gamma * pr) / rr);
-    double sl = (ul - cl) < (ur - cr) ? (ul - cl) : (ur - cr);
-    double sr = (ul + cl) > (ur + cr) ? (ul + cl) : (ur + cr);
+    double sl = fmin(ul - cl, ur - cr);
+    double sr = fmax(ul + cl, ur + cr);
     double ml = rl * (ul - sl);        /* mass flux through the left wave  */
     double mr = rr * (sr - ur);        /* mass flux through the right wave */
     double inv = 1.0 / (ml + mr);
@@ -452,8 +452,8 @@ static void hydro_oct(const orc_tree *t, int64_t o, const double *uold, double *
                         double *st = S[a][side][TI(z)][TI(y)][TI(x)];
                         for (int v = 0; v < 5; ++v)
                             st[v] = side ? (Wp[v] + 0.5 * dW[a][v]) : (Wp[v] - 0.5 * dW[a][v]);
-                        if (st[0] < ORC_RHO_MIN) st[0] = ORC_RHO_MIN;
-                        if (st[4] < ORC_P_MIN) st[4] = ORC_P_MIN;
+                        st[0] = fmax(st[0], ORC_RHO_MIN);
+                        st[4] = fmax(st[4], ORC_P_MIN);
                     }
             }
 

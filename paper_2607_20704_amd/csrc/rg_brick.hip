@@ -47,16 +47,22 @@ struct BrickArgs {
 };
 
 template <typename R> struct BrickSmem {
-    int32_t loc2oct[BO * BO * BO];
-    int32_t slot[HS * HS * HS];     // neighbour entry of every halo oct slot
-    uint32_t hsplit[HS * HS * HS];  // son mask of same-level slot octs (interior and halo), 0 otherwise
+    int32_t slot[HS * HS * HS];     // oct slots -1..8 around the brick: oct index inside, neighbour entry outside
+    uint8_t son[HS * HS * HS];      // son mask of same-level slot octs, 0 otherwise
     R w[PW * PW][NV];               // primitive variables of the current plane
-    R sxp[BC + 1][BC][NV];          // [x][y]: x+ state of cell x-1 (x = 0..16 -> cells -1..15)
-    R sxm_hi[BC][NV];               // x- state of the halo cell x = 16
-    R syp[BC + 1][BC][NV];          // [y][x]: y+ state of cell y-1
-    R sym_hi[BC][NV];
-    double gx[BC + 1][BC][NV];      // [x][y]: G on face (x-1 | x)
-    double gy[BC + 1][BC][NV];      // [y][x]
+    R hw[3][4 * BC][NV];            // primitive variables of the reconstructed ghost ring, planes r-1, r, r+1
+    union {
+        struct {                    // face states, live from reconstruction to flux evaluation
+            R sxp[BC + 1][BC][NV];  // [x][y]: x+ state of cell x-1 (x = 0..16 -> cells -1..15)
+            R syp[BC + 1][BC][NV];  // [y][x]: y+ state of cell y-1
+            R sxm_hi[BC][NV];       // x- state of the ghost cell x = 16
+            R sym_hi[BC][NV];
+        } st;
+        struct {                    // fluxes F (zero on faces touching split cells), live until the update
+            R fx[BC + 1][BC][NV];   // [x][y]: face (x-1 | x)
+            R fy[BC + 1][BC][NV];   // [y][x]: face (y-1 | y)
+        } fl;
+    } u;
     uint8_t split[PW * PW];         // split flag of the current plane's cells
 };
 
@@ -66,7 +72,7 @@ struct Geom {
     int outflow;
 };
 
-// brick-relative slot index of an oct slot (sa, sb, sc) in [-1, 8]^3
+// slot index of the oct slot (sa, sb, sc) in [-1, 8]^3
 __device__ __forceinline__ int slot_index(int sa, int sb, int sc) { return (sa + 1) + HS * (sb + 1) + HS * HS * (sc + 1); }
 
 // Source of the cell at brick-relative position (x, y, z): its global cell
@@ -86,16 +92,11 @@ __device__ __forceinline__ int64_t source_cell(const BrickSmem<R> &S, const Geom
         if (gz < 0) { z = -g.cz0; clamped = true; }
         if (gz >= g.ncell) { z = g.ncell - 1 - g.cz0; clamped = true; }
     }
-    const int sa = x >> 1, sb = y >> 1, sc = z >> 1;
     const int bit = (x & 1) + 2 * (y & 1) + 4 * (z & 1);
-    const int si = slot_index(sa, sb, sc);
-    int32_t e;
-    if (sa >= 0 && sa < BO && sb >= 0 && sb < BO && sc >= 0 && sc < BO)
-        e = S.loc2oct[sa + BO * sb + BO * BO * sc];
-    else
-        e = S.slot[si];
-    split = !clamped && ((S.hsplit[si] >> bit) & 1u);
-    if (e == RG_NBR_OUTSIDE) e = S.loc2oct[0];   // unreachable for a consistent list
+    const int si = slot_index(x >> 1, y >> 1, z >> 1);
+    int32_t e = S.slot[si];
+    split = !clamped && ((S.son[si] >> bit) & 1u);
+    if (e == RG_NBR_OUTSIDE) e = S.slot[slot_index(0, 0, 0)];   // unreachable for a consistent list
     return e >= 0 ? 8 * int64_t(e) + bit : (-1 - int64_t(e));
 }
 
@@ -138,6 +139,15 @@ __device__ __forceinline__ void ring_pos(int kind, int lane, int &x, int &y)
     else { x = k; y = hi; }
 }
 
+// hllc flux of one face, zeroed when it touches a split cell
+template <typename R>
+__device__ __forceinline__ void face_F(const R *L, const R *Rt, int dir, R gamma, R g1, bool zero, R *F)
+{
+    hllc<R>(L, Rt, dir, gamma, g1, F);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = zero ? R(0) : F[v];
+}
+
 template <typename R>
 __global__ __launch_bounds__(BT) void k_hydro_brick(BrickArgs a)
 {
@@ -150,11 +160,11 @@ __global__ __launch_bounds__(BT) void k_hydro_brick(BrickArgs a)
     if (b >= a.nbricks) return;
     const int64_t base = a.bricks[b];
 
-    // ---- brick geometry and slot tables
+    // ---- brick geometry and slot table
     for (int k = tid; k < BO * BO * BO; k += BT) {
         int32_t i, j, kk, l;
         key_coords(a.keys[base + k], i, j, kk, l);
-        S.loc2oct[(i & 7) + BO * (j & 7) + BO * BO * (kk & 7)] = static_cast<int32_t>(base + k);
+        S.slot[slot_index(i & 7, j & 7, kk & 7)] = static_cast<int32_t>(base + k);
     }
     Geom g;
     {
@@ -172,17 +182,17 @@ __global__ __launch_bounds__(BT) void k_hydro_brick(BrickArgs a)
         const int out = (sa < 0 || sa >= BO) + (sb < 0 || sb >= BO) + (sc < 0 || sc >= BO);
         int32_t e = RG_NBR_OUTSIDE;
         if (out == 0) {
-            e = S.loc2oct[sa + BO * sb + BO * BO * sc];
+            e = S.slot[s];
         } else if (out <= 2) {
             // the nearest brick oct and its neighbour entry towards this slot
             const int ca = sa < 0 ? 0 : (sa >= BO ? BO - 1 : sa);
             const int cb = sb < 0 ? 0 : (sb >= BO ? BO - 1 : sb);
             const int cc = sc < 0 ? 0 : (sc >= BO ? BO - 1 : sc);
-            const int32_t o = S.loc2oct[ca + BO * cb + BO * BO * cc];
+            const int32_t o = S.slot[slot_index(ca, cb, cc)];
             e = a.nbr27[27 * int64_t(o) + (sa - ca + 1) + 3 * (sb - cb + 1) + 9 * (sc - cc + 1)];
         }
-        S.slot[s] = e;
-        S.hsplit[s] = e >= 0 ? a.son[e] : 0u;
+        S.son[s] = e >= 0 ? static_cast<uint8_t>(a.son[e]) : 0;
+        if (out) S.slot[s] = e;
     }
     __syncthreads();
 
@@ -199,30 +209,25 @@ __global__ __launch_bounds__(BT) void k_hydro_brick(BrickArgs a)
     int hx = 0, hy = 0;
     if (kind) ring_pos(kind, lane, hx, hy);
     const bool extra_faces = wave == ((ew + 1) & 3) && lane < 2 * BC;   // faces x = 16 and y = 16
+    const int hq = lane >> 4, hk = lane & 15;
 
-    // own column: U and W of planes r-1, r, r+1; secondary position likewise
-    double Ucur[NV], Un[NV], HUn[NV];
-    R Wm[NV], W0[NV], Wp[NV], HWm[NV], HW0[NV], HWp[NV];
-    bool sp_prev = false, sp_cur, hsp_cur = false;
-    bool sp_next;
-    // prologue: planes -2 and -1 of the own column, plane -1 (and 0 for the
-    // outer ring) of the secondary position
+    // own column: primitive variables of planes r-1, r, r+1 and conserved
+    // variables of planes r (update) and r+1 (next primitives); secondary
+    // position: the conserved variables it needs next
+    R Wm[NV], W0[NV], Wp[NV];
+    bool sp_prev = false, sp_cur, sp_next;
     {
         double U[NV];
         bool sdummy;
         load_u(a.uold, source_cell(S, g, x, y, -2, sdummy), U);
         to_prim(U, a.gamma, Wm);
-        load_u(a.uold, source_cell(S, g, x, y, -1, sp_cur), Ucur);
-        to_prim(Ucur, a.gamma, W0);
-        load_u(a.uold, source_cell(S, g, x, y, 0, sp_next), Un);
+        load_u(a.uold, source_cell(S, g, x, y, -1, sp_cur), U);
+        to_prim(U, a.gamma, W0);
         if (kind == 1) {
-            load_u(a.uold, source_cell(S, g, hx, hy, -2, sdummy), U);
-            to_prim(U, a.gamma, HWm);
-            load_u(a.uold, source_cell(S, g, hx, hy, -1, hsp_cur), U);
-            to_prim(U, a.gamma, HW0);
-            load_u(a.uold, source_cell(S, g, hx, hy, 0, sdummy), HUn);
-        } else if (kind >= 2) {
-            load_u(a.uold, source_cell(S, g, hx, hy, 0, sdummy), HUn);
+            load_u(a.uold, source_cell(S, g, hx, hy, -1, sdummy), U);
+            R Wh[NV];
+            to_prim(U, a.gamma, Wh);
+            copy5(S.hw[2][lane], Wh);
         }
     }
     double acc_prev[NV], gz_prev[NV];
@@ -235,104 +240,108 @@ __global__ __launch_bounds__(BT) void k_hydro_brick(BrickArgs a)
     }
 
     for (int rz = -1; rz <= BC; ++rz) {
-        // 1. primitive variables of plane rz+1 (own column, secondary ring
-        //    position); prefetch plane rz+2
-        bool sp_n2 = false;
-        double Unn[NV], HUnn[NV];
-        const bool more = rz + 2 <= BC + 1;
-        if (more) load_u(a.uold, source_cell(S, g, x, y, rz + 2, sp_n2), Unn);
-        to_prim(Un, a.gamma, Wp);
-        bool hsp_dummy;
+        const bool inner = rz >= 0 && rz < BC;      // plane with x/y faces
+        double Un[NV];                               // conserved variables of plane rz+1, own column
+        load_u(a.uold, source_cell(S, g, x, y, rz + 1, sp_next), Un);
+        // 1. the reconstructed ghost ring: primitive variables of plane rz+1
+        bool hsplit = false;
         if (kind == 1) {
-            if (rz + 2 <= BC) load_u(a.uold, source_cell(S, g, hx, hy, rz + 2, hsp_dummy), HUnn);
-            to_prim(HUn, a.gamma, HWp);
-        } else if (kind >= 2) {
-            if (rz + 1 <= BC - 1) load_u(a.uold, source_cell(S, g, hx, hy, rz + 1, hsp_dummy), HUnn);
+            if (rz + 1 <= BC) {
+                double U[NV];
+                R Wh[NV];
+                load_u(a.uold, source_cell(S, g, hx, hy, rz + 1, hsplit), U);
+                to_prim(U, a.gamma, Wh);
+                copy5(S.hw[(rz + 4) % 3][lane], Wh);
+            }
+            (void)source_cell(S, g, hx, hy, rz, hsplit);
         }
-
         // 2. plane rz into LDS: W and split flags
         copy5(S.w[(x + 2) + PW * (y + 2)], W0);
         S.split[(x + 2) + PW * (y + 2)] = sp_cur;
         if (kind == 1) {
-            copy5(S.w[(hx + 2) + PW * (hy + 2)], HW0);
-            S.split[(hx + 2) + PW * (hy + 2)] = hsp_cur;
-        } else if (kind >= 2 && rz >= 0 && rz < BC) {
+            copy5(S.w[(hx + 2) + PW * (hy + 2)], S.hw[(rz + 3) % 3][lane]);
+            S.split[(hx + 2) + PW * (hy + 2)] = hsplit;
+        } else if (kind >= 2 && inner) {
+            double U[NV];
             R Wr[NV];
-            to_prim(HUn, a.gamma, Wr);
+            load_u(a.uold, source_cell(S, g, hx, hy, rz, hsplit), U);
+            to_prim(U, a.gamma, Wr);
             copy5(S.w[(hx + 2) + PW * (hy + 2)], Wr);
         }
         __syncthreads();
 
-        // 3. reconstruction of plane rz
-        R sxm[NV], sym[NV], szm[NV], szp[NV];
-        {
-            R dW[3][NV], Wq[NV], st[NV];
-            const int c = (x + 2) + PW * (y + 2);
-            reconstruct<R>(W0, S.w[c - 1], S.w[c + 1], S.w[c - PW], S.w[c + PW], Wm, Wp, h, gam, dW, Wq);
-            face_state<R>(Wq, dW[2], false, szm);
-            face_state<R>(Wq, dW[2], true, szp);
-            if (rz >= 0 && rz < BC) {
-                face_state<R>(Wq, dW[0], false, sxm);
-                face_state<R>(Wq, dW[1], false, sym);
-                face_state<R>(Wq, dW[0], true, st);
-                copy5(S.sxp[x + 1][y], st);
-                face_state<R>(Wq, dW[1], true, st);
-                copy5(S.syp[y + 1][x], st);
-            }
-        }
-        if (kind == 1 && rz >= 0 && rz < BC) {
+        // 3. reconstruction of plane rz: the ghost ring first, then the own
+        //    column, whose z face (rz-1 | rz) is evaluated at once
+        if (kind == 1 && inner) {
             R dW[3][NV], Wq[NV], st[NV];
             const int c = (hx + 2) + PW * (hy + 2);
-            reconstruct<R>(HW0, S.w[c - 1], S.w[c + 1], S.w[c - PW], S.w[c + PW], HWm, HWp, h, gam, dW, Wq);
-            const int q = lane >> 4, k = lane & 15;
-            if (q == 0) {            // x = -1: its x+ state feeds face (-1|0)
+            reconstruct<R>(S.hw[(rz + 3) % 3][lane], S.w[c - 1], S.w[c + 1], S.w[c - PW], S.w[c + PW],
+                           S.hw[(rz + 2) % 3][lane], S.hw[(rz + 4) % 3][lane], h, gam, dW, Wq);
+            if (hq == 0) {            // x = -1: its x+ state feeds face (-1|0)
                 face_state<R>(Wq, dW[0], true, st);
-                copy5(S.sxp[0][k], st);
-            } else if (q == 1) {     // x = 16: x- state feeds face (15|16)
+                copy5(S.u.st.sxp[0][hk], st);
+            } else if (hq == 1) {     // x = 16: x- state feeds face (15|16)
                 face_state<R>(Wq, dW[0], false, st);
-                copy5(S.sxm_hi[k], st);
-            } else if (q == 2) {     // y = -1
+                copy5(S.u.st.sxm_hi[hk], st);
+            } else if (hq == 2) {     // y = -1
                 face_state<R>(Wq, dW[1], true, st);
-                copy5(S.syp[0][k], st);
-            } else {                 // y = 16
+                copy5(S.u.st.syp[0][hk], st);
+            } else {                  // y = 16
                 face_state<R>(Wq, dW[1], false, st);
-                copy5(S.sym_hi[k], st);
+                copy5(S.u.st.sym_hi[hk], st);
             }
+        }
+        R sxm[NV], sym[NV];
+        double gz[NV];
+        to_prim(Un, a.gamma, Wp);
+        {
+            R dW[3][NV], Wq[NV], st[NV], szm[NV];
+            const int c = (x + 2) + PW * (y + 2);
+            reconstruct<R>(W0, S.w[c - 1], S.w[c + 1], S.w[c - PW], S.w[c + PW], Wm, Wp, h, gam, dW, Wq);
+            if (inner) {
+                face_state<R>(Wq, dW[0], true, st);
+                copy5(S.u.st.sxp[x + 1][y], st);
+                face_state<R>(Wq, dW[1], true, st);
+                copy5(S.u.st.syp[y + 1][x], st);
+                face_state<R>(Wq, dW[0], false, sxm);
+                face_state<R>(Wq, dW[1], false, sym);
+            }
+            face_state<R>(Wq, dW[2], false, szm);
+            if (rz >= 0) face_flux<R>(zp_prev, szm, 2, gam, g1, r, sp_prev || sp_cur, gz);
+            face_state<R>(Wq, dW[2], true, zp_prev);
         }
         __syncthreads();
 
-        // 4. fluxes: own low x and y faces of plane rz, the z face (rz-1 | rz),
-        //    and the high x = 16 / y = 16 faces by the extra lanes
-        double gz[NV];
-        if (rz >= 0 && rz < BC) {
-            double G[NV];
-            const bool zx = S.split[(x + 1) + PW * (y + 2)] || sp_cur;
-            face_flux<R>(S.sxp[x][y], sxm, 0, gam, g1, r, zx, G);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) S.gx[x][y][v] = G[v];
-            const bool zy = S.split[(x + 2) + PW * (y + 1)] || sp_cur;
-            face_flux<R>(S.syp[y][x], sym, 1, gam, g1, r, zy, G);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) S.gy[y][x][v] = G[v];
+        // 4a. fluxes into registers: the own low x and y faces, and the
+        //     x = 16 / y = 16 faces on the extra lanes
+        R Fx[NV], Fy[NV], Fe[NV];
+        if (inner) {
+            face_F<R>(S.u.st.sxp[x][y], sxm, 0, gam, g1, S.split[(x + 1) + PW * (y + 2)] || sp_cur, Fx);
+            face_F<R>(S.u.st.syp[y][x], sym, 1, gam, g1, S.split[(x + 2) + PW * (y + 1)] || sp_cur, Fy);
             if (extra_faces) {
-                const int k = lane & 15;
                 if (lane < BC) {
-                    const bool z2 = S.split[(BC + 1) + PW * (k + 2)] || S.split[(BC + 2) + PW * (k + 2)];
-                    face_flux<R>(S.sxp[BC][k], S.sxm_hi[k], 0, gam, g1, r, z2, G);
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) S.gx[BC][k][v] = G[v];
+                    const bool z2 = S.split[(BC + 1) + PW * (hk + 2)] || S.split[(BC + 2) + PW * (hk + 2)];
+                    face_F<R>(S.u.st.sxp[BC][hk], S.u.st.sxm_hi[hk], 0, gam, g1, z2, Fe);
                 } else {
-                    const bool z2 = S.split[(k + 2) + PW * (BC + 1)] || S.split[(k + 2) + PW * (BC + 2)];
-                    face_flux<R>(S.syp[BC][k], S.sym_hi[k], 1, gam, g1, r, z2, G);
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) S.gy[BC][k][v] = G[v];
+                    const bool z2 = S.split[(hk + 2) + PW * (BC + 1)] || S.split[(hk + 2) + PW * (BC + 2)];
+                    face_F<R>(S.u.st.syp[BC][hk], S.u.st.sym_hi[hk], 1, gam, g1, z2, Fe);
                 }
             }
         }
-        if (rz >= 0) face_flux<R>(zp_prev, szm, 2, gam, g1, r, sp_prev || sp_cur, gz);
         __syncthreads();
 
-        // 5. update: x/y part of plane rz, then plane rz-1 is complete
+        // 4b. publish the x/y fluxes (over the face states)
+        if (inner) {
+            copy5(S.u.fl.fx[x][y], Fx);
+            copy5(S.u.fl.fy[y][x], Fy);
+            if (extra_faces) {
+                if (lane < BC) copy5(S.u.fl.fx[BC][hk], Fe);
+                else copy5(S.u.fl.fy[BC][hk], Fe);
+            }
+        }
+        __syncthreads();
+
+        // 5. update: plane rz-1 is complete; x/y part of plane rz
         if (rz >= 1) {
             double out[NV];
 #pragma unroll
@@ -342,32 +351,28 @@ __global__ __launch_bounds__(BT) void k_hydro_brick(BrickArgs a)
 #pragma unroll
             for (int v = 0; v < NV; ++v) a.unew[NV * cell + v] = out[v];
         }
-        if (rz >= 0 && rz < BC) {
+        if (inner) {
+            double Ucur[NV];
+            bool sdummy;
+            load_u(a.uold, source_cell(S, g, x, y, rz, sdummy), Ucur);
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
-                acc_prev[v] = (Ucur[v] + (S.gx[x][y][v] - S.gx[x + 1][y][v])) + (S.gy[y][x][v] - S.gy[y + 1][x][v]);
+            for (int v = 0; v < NV; ++v) {
+                const double gxm = static_cast<double>(S.u.fl.fx[x][y][v]) * r;
+                const double gxp = static_cast<double>(S.u.fl.fx[x + 1][y][v]) * r;
+                const double gym = static_cast<double>(S.u.fl.fy[y][x][v]) * r;
+                const double gyp = static_cast<double>(S.u.fl.fy[y + 1][x][v]) * r;
+                acc_prev[v] = (Ucur[v] + (gxm - gxp)) + (gym - gyp);
+            }
         }
-        // shift the plane window
+        // shift the plane window; prefetch plane rz+2 of the own column
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             gz_prev[v] = rz >= 0 ? gz[v] : 0.0;
-            zp_prev[v] = szp[v];
             Wm[v] = W0[v];
             W0[v] = Wp[v];
-            Ucur[v] = Un[v];
-            Un[v] = Unn[v];
-            HWm[v] = HW0[v];
-            HW0[v] = HWp[v];
-            HUn[v] = HUnn[v];
         }
         sp_prev = sp_cur;
         sp_cur = sp_next;
-        sp_next = sp_n2;
-        if (kind == 1) {
-            bool hs;
-            (void)source_cell(S, g, hx, hy, rz + 1, hs);
-            hsp_cur = hs;
-        }
     }
 }
 

@@ -28,15 +28,14 @@ template <> struct Math<float> {
 // conservative -> primitive in double, floors applied
 __device__ __forceinline__ void prim64(const double *U, double gamma, double *W)
 {
-    double rho = U[0] < RG_RHO_MIN ? RG_RHO_MIN : U[0];
+    double rho = fmax(U[0], RG_RHO_MIN);
     double inv = 1.0 / rho;
     double u = U[1] * inv;
     double v = U[2] * inv;
     double w = U[3] * inv;
     double q = (u * u + v * v) + w * w;
     double ek = 0.5 * rho * q;
-    double p = (gamma - 1.0) * (U[4] - ek);
-    if (p < RG_P_MIN) p = RG_P_MIN;
+    double p = fmax((gamma - 1.0) * (U[4] - ek), RG_P_MIN);
     W[0] = rho;
     W[1] = u;
     W[2] = v;
@@ -44,11 +43,12 @@ __device__ __forceinline__ void prim64(const double *U, double gamma, double *W)
     W[4] = p;
 }
 
+// zero unless a and b have the same strict sign, else the one of smaller
+// magnitude (written as copysign(min(|a|, |b|), a) under the sign test)
 template <typename R> __device__ __forceinline__ R minmod(R a, R b)
 {
-    if (a > R(0) && b > R(0)) return a < b ? a : b;
-    if (a < R(0) && b < R(0)) return a > b ? a : b;
-    return R(0);
+    const bool same = (a > R(0) && b > R(0)) || (a < R(0) && b < R(0));
+    return same ? copysign(fmin(fabs(a), fabs(b)), a) : R(0);
 }
 
 // Hancock half step W' = W - h sum_d A_d(W) dW_d (primitive Euler equations)
@@ -76,8 +76,8 @@ __device__ __forceinline__ void hllc(const R *WL, const R *WR, int dir, R gamma,
     const R rr = WR[0], pr = WR[4], ur = WR[1 + dir];
     const R cl = Math<R>::sqrt_(Math<R>::div(gamma * pl, rl));
     const R cr = Math<R>::sqrt_(Math<R>::div(gamma * pr, rr));
-    const R sl = (ul - cl) < (ur - cr) ? (ul - cl) : (ur - cr);
-    const R sr = (ul + cl) > (ur + cr) ? (ul + cl) : (ur + cr);
+    const R sl = fmin(ul - cl, ur - cr);
+    const R sr = fmax(ul + cl, ur + cr);
     const R ml = rl * (ul - sl);
     const R mr = rr * (sr - ur);
     const R inv = Math<R>::div(R(1), ml + mr);
@@ -130,8 +130,8 @@ template <typename R> __device__ __forceinline__ void face_state(const R *Wp, co
 {
 #pragma unroll
     for (int v = 0; v < NV; ++v) st[v] = high ? (Wp[v] + R(0.5) * dWa[v]) : (Wp[v] - R(0.5) * dWa[v]);
-    if (st[0] < R(RG_RHO_MIN)) st[0] = R(RG_RHO_MIN);
-    if (st[4] < R(RG_P_MIN)) st[4] = R(RG_P_MIN);
+    st[0] = fmax(st[0], R(RG_RHO_MIN));
+    st[4] = fmax(st[4], R(RG_P_MIN));
 }
 
 // G = F dt/dx in double, or zero on a face touching a split cell

@@ -37,7 +37,7 @@ def log(*a):
 
 def kernel_source_digest():
     h = hashlib.sha256()
-    for f in ("rg_brick.hip", "rg_math.hpp", "rg_internal.hpp"):
+    for f in ("rg_brick.hip", "rg_brick.hpp", "rg_math.hpp", "rg_internal.hpp"):
         with open(os.path.join(ROOT, "paper_2607_20704_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

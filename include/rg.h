@@ -183,7 +183,9 @@ typedef struct rg_tuning {
     int32_t octs_per_group;   /* per-oct kernel: octs handled by one workgroup (0 = default) */
     int32_t threads;          /* per-oct kernel: workgroup size (0 = default) */
     int32_t no_bricks;        /* 1: scheduled updates use the per-oct kernel for every oct */
-    int32_t reserved[5];
+    int32_t persistent;       /* batched form: 1 = persistent grids looping over the work list,
+                                 0 = one workgroup per work item */
+    int32_t reserved[4];
 } rg_tuning;
 
 /* Kernel schedule of a tree.  A brick is a Hilbert-aligned cube of 8x8x8
@@ -323,6 +325,56 @@ rg_status rg_prepare_tree(const rg_tree *t, unsigned flags, void *stream);
  * The caller swaps uold and unew afterwards. */
 rg_status rg_step(const rg_tree *t, const double *d_uold, double *d_unew, double gamma, double cfl, int form,
                   unsigned flags, double *d_dt, const rg_tuning *tune, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Many independent trees in one graph launch                             */
+/* ---------------------------------------------------------------------- */
+
+/* The per-step phases of Table 1 (compute dt, godunov, set unew, upload) for
+ * many independent trees at once.  This batched form is an addition of this
+ * library, not a scheme of the paper: it fills the GPU with many small
+ * boxes, each keeping its own time step.  Each phase of a step is one
+ * persistent kernel looping over a work list that spans every tree: hash
+ * rebuild and neighbour lists (with RG_STEP_REBUILD), CFL dt per tree, the
+ * hydro update of every level of every tree (bricks and per-oct groups as in
+ * the tree's schedule), the coarse-fine corrections (six passes), and the
+ * restriction (one pass per depth below each tree's finest level).  The
+ * phases of all `nsteps` steps are captured into one HIP graph.
+ *
+ * Tree t alternates between its two state buffers: step s reads d_u0 when s
+ * is even (d_u1 when odd) and writes the other one, so after an even number
+ * of steps the result is in d_u0.  The time step of tree t at step s is
+ * written to d_dt[s * ntree + t] (device, double[nsteps * ntree]).  A tree
+ * gives the same bits, state and dt, as rg_step run on it alone with the same
+ * form and flags.
+ *
+ * Every tree needs a schedule (t->sched, rg_schedule_build) and a correction
+ * buffer if it has more than one level; keys, level ranges, hash workspace
+ * and neighbour lists must be current when the graph runs (flags may only be
+ * 0 or RG_STEP_REBUILD).  The trees must not share any device buffer.  The
+ * rg_tree and rg_batch_tree structs are read during this call only; the
+ * device buffers they point to are used by every rg_batch_run.
+ * tune: octs_per_group 2, 4 (default) or 8; no_bricks 1 runs every oct
+ * through the per-oct body; persistent selects persistent grids.  Every
+ * choice gives the same bits.  Allocates one device table (work lists and
+ * tree descriptors) and the graph; synchronises `stream` once. */
+typedef struct rg_batch_tree {
+    const rg_tree *tree;
+    double *d_u0, *d_u1;       /* state buffers, 8 n_oct x 5 doubles each */
+    double gamma, cfl;
+} rg_batch_tree;
+
+typedef struct rg_batch rg_batch;
+
+rg_status rg_batch_create(const rg_batch_tree *trees, int ntree, int form, int nsteps, unsigned flags,
+                          const rg_tuning *tune, double *d_dt, void *stream, rg_batch **out);
+
+/* Launches the captured graph (all steps) on `stream`; asynchronous. */
+rg_status rg_batch_run(rg_batch *b, void *stream);
+
+/* Frees the graph and the device table; NULL is allowed.  The caller makes
+ * sure no launch of the graph is still running. */
+rg_status rg_batch_destroy(rg_batch *b);
 
 #ifdef __cplusplus
 }

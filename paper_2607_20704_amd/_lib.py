@@ -25,7 +25,8 @@ st = ctypes.c_int
 
 
 class RgTuning(ctypes.Structure):
-    _fields_ = [("octs_per_group", i32), ("threads", i32), ("no_bricks", i32), ("reserved", i32 * 5)]
+    _fields_ = [("octs_per_group", i32), ("threads", i32), ("no_bricks", i32), ("persistent", i32),
+                ("reserved", i32 * 4)]
 
 
 class RgSchedule(ctypes.Structure):
@@ -42,6 +43,10 @@ class RgTree(ctypes.Structure):
                 ("d_nbr27", P), ("d_father_cell", P), ("d_son_mask", P), ("d_corr", P),
                 ("d_ijkl", P), ("d_keys_scratch", P), ("d_perm", P), ("d_sort_ws", P), ("sort_ws_bytes", sz),
                 ("d_level_begin", P), ("sched", ctypes.POINTER(RgSchedule))]
+
+
+class RgBatchTree(ctypes.Structure):
+    _fields_ = [("tree", ctypes.POINTER(RgTree)), ("d_u0", P), ("d_u1", P), ("gamma", f64), ("cfl", f64)]
 
 
 SIGNATURES = {
@@ -74,6 +79,10 @@ SIGNATURES = {
                                      P, ctypes.c_int, ctypes.POINTER(RgTuning), P]),
     "rg_step": (st, [ctypes.POINTER(RgTree), P, P, f64, f64, ctypes.c_int, ctypes.c_uint, P,
                      ctypes.POINTER(RgTuning), P]),
+    "rg_batch_create": (st, [ctypes.POINTER(RgBatchTree), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint,
+                             ctypes.POINTER(RgTuning), P, P, ctypes.POINTER(P)]),
+    "rg_batch_run": (st, [P, P]),
+    "rg_batch_destroy": (st, [P]),
 }
 
 _lib = None

@@ -30,12 +30,13 @@ def _ptr(t):
 
 
 def _tuning(tune):
-    """tune: None or (octs_per_group, threads[, no_bricks])."""
+    """tune: None or (octs_per_group, threads[, no_bricks[, persistent]])."""
     if tune is None:
         return None
     t = RgTuning()
     t.octs_per_group, t.threads = int(tune[0]), int(tune[1])
     t.no_bricks = int(tune[2]) if len(tune) > 2 else 0
+    t.persistent = int(tune[3]) if len(tune) > 3 else 0
     return ctypes.byref(t)
 
 
@@ -271,3 +272,58 @@ class DeviceTree:
             self.step(a, b, gamma, cfl, form, rebuild, dts[s:s + 1], tune)
             a, b = b, a
         return a, dts
+
+
+# ---------------------------------------------------------------- many trees
+
+class Batch:
+    """Independent trees advanced together: every phase of a step is one
+    kernel over a work list spanning all trees, and all `nsteps` steps are one
+    captured graph (rg_batch_create / rg_batch_run).  Each tree keeps its own
+    time step.  `states` are key-ordered device states (copied); after a run
+    the result is in `state(t)`, and with an even `nsteps` a further run()
+    continues from it."""
+
+    def __init__(self, trees, states, gammas, cfls, nsteps, form=RG_FP64, rebuild=False, tune=None):
+        if len(trees) == 0 or not (len(trees) == len(states) == len(gammas) == len(cfls)):
+            raise ValueError("trees, states, gammas and cfls must be non-empty lists of one length")
+        for t in trees:
+            if t.sched is None:
+                raise ValueError("every tree needs a schedule (DeviceTree(..., schedule=True))")
+        self.trees = list(trees)
+        self.nsteps = int(nsteps)
+        self.u = [[s.clone() for s in states], [torch.empty_like(s) for s in states]]
+        self.dt = torch.empty(self.nsteps * len(trees), dtype=torch.float64, device="cuda")
+        arr = (L.RgBatchTree * len(trees))()
+        for k, t in enumerate(trees):
+            arr[k].tree = ctypes.pointer(t._desc)
+            arr[k].d_u0 = self.u[0][k].data_ptr()
+            arr[k].d_u1 = self.u[1][k].data_ptr()
+            arr[k].gamma = float(gammas[k])
+            arr[k].cfl = float(cfls[k])
+        self._h = ctypes.c_void_p()
+        flags = RG_STEP_REBUILD if rebuild else 0
+        check(L.lib().rg_batch_create(arr, len(trees), int(form), self.nsteps, flags, _tuning(tune), _ptr(self.dt),
+                                      _stream(), ctypes.byref(self._h)))
+
+    def run(self):
+        check(L.lib().rg_batch_run(self._h, _stream()))
+
+    def state(self, t):
+        """State of tree t after the last run (key order)."""
+        return self.u[self.nsteps % 2][t]
+
+    def dts(self):
+        """Time steps of the last run, [nsteps, ntree]."""
+        return self.dt.view(self.nsteps, len(self.trees))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().rg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

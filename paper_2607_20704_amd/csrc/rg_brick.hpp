@@ -1,0 +1,360 @@
+// rg_brick.hpp -- plane-sweep hydro update of one complete 8x8x8-oct brick.
+//
+// Paper Sec. 3 (rock/paper kernels): larger blocks of octs share their
+// stencil; the "paper" kernel sweeps a planar stencil through the block.
+// Shared by the single-level brick kernel and the batched persistent kernel.
+#pragma once
+
+#include "rg_internal.hpp"
+#include "rg_math.hpp"
+
+namespace rg {
+namespace {
+
+constexpr int BO = 8;          // octs per brick side
+constexpr int BC = 16;         // cells per brick side
+constexpr int BT = 256;        // threads per workgroup
+constexpr int PW = BC + 4;     // plane width with two ghost cells per side
+constexpr int HS = BO + 2;     // slot table side: octs -1..8
+
+struct BrickArgs {
+    const double *uold;
+    double *unew;
+    const int32_t *nbr27;
+    const uint32_t *son;
+    const uint64_t *keys;
+    const int32_t *bricks;     // first oct of each brick
+    int64_t nbricks;
+    const double *dt;
+    double dx;
+    double gamma;
+    int outflow;               // clamp positions outside the domain (zero gradient)
+};
+
+template <typename R> struct BrickSmem {
+    int32_t slot[HS * HS * HS];     // oct slots -1..8 around the brick: oct index inside, neighbour entry outside
+    uint8_t son[HS * HS * HS];      // son mask of same-level slot octs, 0 otherwise
+    R w[PW * PW][NV];               // primitive variables of the current plane
+    R hw[3][4 * BC][NV];            // primitive variables of the reconstructed ghost ring, planes r-1, r, r+1
+    union {
+        struct {                    // face states, live from reconstruction to flux evaluation
+            R sxp[BC + 1][BC][NV];  // [x][y]: x+ state of cell x-1 (x = 0..16 -> cells -1..15)
+            R syp[BC + 1][BC][NV];  // [y][x]: y+ state of cell y-1
+            R sxm_hi[BC][NV];       // x- state of the ghost cell x = 16
+            R sym_hi[BC][NV];
+        } st;
+        struct {                    // fluxes F (zero on faces touching split cells), live until the update
+            R fx[BC + 1][BC][NV];   // [x][y]: face (x-1 | x)
+            R fy[BC + 1][BC][NV];   // [y][x]: face (y-1 | y)
+        } fl;
+    } u;
+    uint8_t split[PW * PW];         // split flag of the current plane's cells
+};
+
+struct Geom {
+    int cx0, cy0, cz0;   // global cell coordinates of the brick origin
+    int ncell;           // cells per side of the level
+    int outflow;
+};
+
+// slot index of the oct slot (sa, sb, sc) in [-1, 8]^3
+__device__ __forceinline__ int slot_index(int sa, int sb, int sc) { return (sa + 1) + HS * (sb + 1) + HS * HS * (sc + 1); }
+
+// Source of the cell at brick-relative position (x, y, z): its global cell
+// id, and whether it is a split cell.  Outside the domain (outflow) the
+// position takes the nearest cell inside (zero gradient) and counts as not
+// split; a missing same-level oct gives its coarse cell (injection).
+template <typename R>
+__device__ __forceinline__ int64_t source_cell(const BrickSmem<R> &S, const Geom &g, int x, int y, int z, bool &split)
+{
+    bool clamped = false;
+    if (g.outflow) {
+        const int gx = g.cx0 + x, gy = g.cy0 + y, gz = g.cz0 + z;
+        if (gx < 0) { x = -g.cx0; clamped = true; }
+        if (gx >= g.ncell) { x = g.ncell - 1 - g.cx0; clamped = true; }
+        if (gy < 0) { y = -g.cy0; clamped = true; }
+        if (gy >= g.ncell) { y = g.ncell - 1 - g.cy0; clamped = true; }
+        if (gz < 0) { z = -g.cz0; clamped = true; }
+        if (gz >= g.ncell) { z = g.ncell - 1 - g.cz0; clamped = true; }
+    }
+    const int bit = (x & 1) + 2 * (y & 1) + 4 * (z & 1);
+    const int si = slot_index(x >> 1, y >> 1, z >> 1);
+    int32_t e = S.slot[si];
+    split = !clamped && ((S.son[si] >> bit) & 1u);
+    if (e == RG_NBR_OUTSIDE) e = S.slot[slot_index(0, 0, 0)];   // unreachable for a consistent list
+    return e >= 0 ? 8 * int64_t(e) + bit : (-1 - int64_t(e));
+}
+
+__device__ __forceinline__ void load_u(const double *__restrict__ u, int64_t cell, double *U)
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) U[v] = u[NV * cell + v];
+}
+
+template <typename R> __device__ __forceinline__ void to_prim(const double *U, double gamma, R *W)
+{
+    double w[NV];
+    prim64(U, gamma, w);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) W[v] = static_cast<R>(w[v]);
+}
+
+template <typename R> __device__ __forceinline__ void copy5(R *d, const R *s)
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) d[v] = s[v];
+}
+
+// position of the secondary (ghost ring) role of a thread:
+//   kind 1: face layer (x = -1 or 16, or y = -1 or 16), reconstructed
+//   kind 2: outer ring (x = -2 or 17, or y = -2 or 17)
+//   kind 3: inner corners (-1,-1), (16,-1), (-1,16), (16,16)
+__device__ __forceinline__ void ring_pos(int kind, int lane, int &x, int &y)
+{
+    const int q = lane >> 4, k = lane & 15;
+    if (kind == 3) {
+        x = (lane & 1) ? BC : -1;
+        y = (lane & 2) ? BC : -1;
+        return;
+    }
+    const int lo = kind == 1 ? -1 : -2, hi = kind == 1 ? BC : BC + 1;
+    if (q == 0) { x = lo; y = k; }
+    else if (q == 1) { x = hi; y = k; }
+    else if (q == 2) { x = k; y = lo; }
+    else { x = k; y = hi; }
+}
+
+// hllc flux of one face, zeroed when it touches a split cell
+template <typename R>
+__device__ __forceinline__ void face_F(const R *L, const R *Rt, int dir, R gamma, R g1, bool zero, R *F)
+{
+    hllc<R>(L, Rt, dir, gamma, g1, F);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = zero ? R(0) : F[v];
+}
+
+// one brick (first oct `base`, rotation index b for the ghost-ring roles)
+// by one workgroup of BT threads
+template <typename R>
+__device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int64_t b, BrickSmem<R> &S)
+{
+    const int tid = threadIdx.x;
+
+    // ---- brick geometry and slot table
+    for (int k = tid; k < BO * BO * BO; k += BT) {
+        int32_t i, j, kk, l;
+        key_coords(a.keys[base + k], i, j, kk, l);
+        S.slot[slot_index(i & 7, j & 7, kk & 7)] = static_cast<int32_t>(base + k);
+    }
+    Geom g;
+    {
+        int32_t i, j, kk, l;
+        key_coords(a.keys[base], i, j, kk, l);
+        g.cx0 = 2 * (i & ~7);
+        g.cy0 = 2 * (j & ~7);
+        g.cz0 = 2 * (kk & ~7);
+        g.ncell = 1 << l;
+        g.outflow = a.outflow;
+    }
+    __syncthreads();
+    for (int s = tid; s < HS * HS * HS; s += BT) {
+        const int sa = s % HS - 1, sb = (s / HS) % HS - 1, sc = s / (HS * HS) - 1;
+        const int out = (sa < 0 || sa >= BO) + (sb < 0 || sb >= BO) + (sc < 0 || sc >= BO);
+        int32_t e = RG_NBR_OUTSIDE;
+        if (out == 0) {
+            e = S.slot[s];
+        } else if (out <= 2) {
+            // the nearest brick oct and its neighbour entry towards this slot
+            const int ca = sa < 0 ? 0 : (sa >= BO ? BO - 1 : sa);
+            const int cb = sb < 0 ? 0 : (sb >= BO ? BO - 1 : sb);
+            const int cc = sc < 0 ? 0 : (sc >= BO ? BO - 1 : sc);
+            const int32_t o = S.slot[slot_index(ca, cb, cc)];
+            e = a.nbr27[27 * int64_t(o) + (sa - ca + 1) + 3 * (sb - cb + 1) + 9 * (sc - cc + 1)];
+        }
+        S.son[s] = e >= 0 ? static_cast<uint8_t>(a.son[e]) : 0;
+        if (out) S.slot[s] = e;
+    }
+    __syncthreads();
+
+    const double r = *a.dt / a.dx;
+    const R h = static_cast<R>(0.5 * r);
+    const R gam = static_cast<R>(a.gamma);
+    const R g1 = static_cast<R>(1.0 / (a.gamma - 1.0));
+
+    // ---- roles
+    const int x = tid & 15, y = tid >> 4;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int ew = static_cast<int>(b & 3);         // wave holding the reconstructed ghost ring this brick
+    const int kind = wave == ew ? 1 : (wave == ((ew + 1) & 3) ? 2 : (wave == ((ew + 2) & 3) && lane < 4 ? 3 : 0));
+    int hx = 0, hy = 0;
+    if (kind) ring_pos(kind, lane, hx, hy);
+    const bool extra_faces = wave == ((ew + 1) & 3) && lane < 2 * BC;   // faces x = 16 and y = 16
+    const int hq = lane >> 4, hk = lane & 15;
+
+    // own column: primitive variables of planes r-1, r, r+1 and conserved
+    // variables of planes r (update) and r+1 (next primitives); secondary
+    // position: the conserved variables it needs next
+    R Wm[NV], W0[NV], Wp[NV];
+    bool sp_prev = false, sp_cur, sp_next;
+    {
+        double U[NV];
+        bool sdummy;
+        load_u(a.uold, source_cell(S, g, x, y, -2, sdummy), U);
+        to_prim(U, a.gamma, Wm);
+        load_u(a.uold, source_cell(S, g, x, y, -1, sp_cur), U);
+        to_prim(U, a.gamma, W0);
+        if (kind == 1) {
+            load_u(a.uold, source_cell(S, g, hx, hy, -1, sdummy), U);
+            R Wh[NV];
+            to_prim(U, a.gamma, Wh);
+            copy5(S.hw[2][lane], Wh);
+        }
+    }
+    double acc_prev[NV], gz_prev[NV];
+    R zp_prev[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        acc_prev[v] = 0.0;
+        gz_prev[v] = 0.0;
+        zp_prev[v] = R(0);
+    }
+
+    for (int rz = -1; rz <= BC; ++rz) {
+        const bool inner = rz >= 0 && rz < BC;      // plane with x/y faces
+        double Un[NV];                               // conserved variables of plane rz+1, own column
+        load_u(a.uold, source_cell(S, g, x, y, rz + 1, sp_next), Un);
+        // 1. the reconstructed ghost ring: primitive variables of plane rz+1
+        bool hsplit = false;
+        if (kind == 1) {
+            if (rz + 1 <= BC) {
+                double U[NV];
+                R Wh[NV];
+                load_u(a.uold, source_cell(S, g, hx, hy, rz + 1, hsplit), U);
+                to_prim(U, a.gamma, Wh);
+                copy5(S.hw[(rz + 4) % 3][lane], Wh);
+            }
+            (void)source_cell(S, g, hx, hy, rz, hsplit);
+        }
+        // 2. plane rz into LDS: W and split flags
+        copy5(S.w[(x + 2) + PW * (y + 2)], W0);
+        S.split[(x + 2) + PW * (y + 2)] = sp_cur;
+        if (kind == 1) {
+            copy5(S.w[(hx + 2) + PW * (hy + 2)], S.hw[(rz + 3) % 3][lane]);
+            S.split[(hx + 2) + PW * (hy + 2)] = hsplit;
+        } else if (kind >= 2 && inner) {
+            double U[NV];
+            R Wr[NV];
+            load_u(a.uold, source_cell(S, g, hx, hy, rz, hsplit), U);
+            to_prim(U, a.gamma, Wr);
+            copy5(S.w[(hx + 2) + PW * (hy + 2)], Wr);
+        }
+        __syncthreads();
+
+        // 3. reconstruction of plane rz: the ghost ring first, then the own
+        //    column, whose z face (rz-1 | rz) is evaluated at once
+        if (kind == 1 && inner) {
+            R dW[3][NV], Wq[NV], st[NV];
+            const int c = (hx + 2) + PW * (hy + 2);
+            reconstruct<R>(S.hw[(rz + 3) % 3][lane], S.w[c - 1], S.w[c + 1], S.w[c - PW], S.w[c + PW],
+                           S.hw[(rz + 2) % 3][lane], S.hw[(rz + 4) % 3][lane], h, gam, dW, Wq);
+            if (hq == 0) {            // x = -1: its x+ state feeds face (-1|0)
+                face_state<R>(Wq, dW[0], true, st);
+                copy5(S.u.st.sxp[0][hk], st);
+            } else if (hq == 1) {     // x = 16: x- state feeds face (15|16)
+                face_state<R>(Wq, dW[0], false, st);
+                copy5(S.u.st.sxm_hi[hk], st);
+            } else if (hq == 2) {     // y = -1
+                face_state<R>(Wq, dW[1], true, st);
+                copy5(S.u.st.syp[0][hk], st);
+            } else {                  // y = 16
+                face_state<R>(Wq, dW[1], false, st);
+                copy5(S.u.st.sym_hi[hk], st);
+            }
+        }
+        R sxm[NV], sym[NV];
+        double gz[NV];
+        to_prim(Un, a.gamma, Wp);
+        {
+            R dW[3][NV], Wq[NV], st[NV], szm[NV];
+            const int c = (x + 2) + PW * (y + 2);
+            reconstruct<R>(W0, S.w[c - 1], S.w[c + 1], S.w[c - PW], S.w[c + PW], Wm, Wp, h, gam, dW, Wq);
+            if (inner) {
+                face_state<R>(Wq, dW[0], true, st);
+                copy5(S.u.st.sxp[x + 1][y], st);
+                face_state<R>(Wq, dW[1], true, st);
+                copy5(S.u.st.syp[y + 1][x], st);
+                face_state<R>(Wq, dW[0], false, sxm);
+                face_state<R>(Wq, dW[1], false, sym);
+            }
+            face_state<R>(Wq, dW[2], false, szm);
+            if (rz >= 0) face_flux<R>(zp_prev, szm, 2, gam, g1, r, sp_prev || sp_cur, gz);
+            face_state<R>(Wq, dW[2], true, zp_prev);
+        }
+        __syncthreads();
+
+        // 4a. fluxes into registers: the own low x and y faces, and the
+        //     x = 16 / y = 16 faces on the extra lanes
+        R Fx[NV], Fy[NV], Fe[NV];
+        if (inner) {
+            face_F<R>(S.u.st.sxp[x][y], sxm, 0, gam, g1, S.split[(x + 1) + PW * (y + 2)] || sp_cur, Fx);
+            face_F<R>(S.u.st.syp[y][x], sym, 1, gam, g1, S.split[(x + 2) + PW * (y + 1)] || sp_cur, Fy);
+            if (extra_faces) {
+                if (lane < BC) {
+                    const bool z2 = S.split[(BC + 1) + PW * (hk + 2)] || S.split[(BC + 2) + PW * (hk + 2)];
+                    face_F<R>(S.u.st.sxp[BC][hk], S.u.st.sxm_hi[hk], 0, gam, g1, z2, Fe);
+                } else {
+                    const bool z2 = S.split[(hk + 2) + PW * (BC + 1)] || S.split[(hk + 2) + PW * (BC + 2)];
+                    face_F<R>(S.u.st.syp[BC][hk], S.u.st.sym_hi[hk], 1, gam, g1, z2, Fe);
+                }
+            }
+        }
+        __syncthreads();
+
+        // 4b. publish the x/y fluxes (over the face states)
+        if (inner) {
+            copy5(S.u.fl.fx[x][y], Fx);
+            copy5(S.u.fl.fy[y][x], Fy);
+            if (extra_faces) {
+                if (lane < BC) copy5(S.u.fl.fx[BC][hk], Fe);
+                else copy5(S.u.fl.fy[BC][hk], Fe);
+            }
+        }
+        __syncthreads();
+
+        // 5. update: plane rz-1 is complete; x/y part of plane rz
+        if (rz >= 1) {
+            double out[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) out[v] = acc_prev[v] + (gz_prev[v] - gz[v]);
+            bool sdummy;
+            const int64_t cell = source_cell(S, g, x, y, rz - 1, sdummy);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) a.unew[NV * cell + v] = out[v];
+        }
+        if (inner) {
+            double Ucur[NV];
+            bool sdummy;
+            load_u(a.uold, source_cell(S, g, x, y, rz, sdummy), Ucur);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double gxm = static_cast<double>(S.u.fl.fx[x][y][v]) * r;
+                const double gxp = static_cast<double>(S.u.fl.fx[x + 1][y][v]) * r;
+                const double gym = static_cast<double>(S.u.fl.fy[y][x][v]) * r;
+                const double gyp = static_cast<double>(S.u.fl.fy[y + 1][x][v]) * r;
+                acc_prev[v] = (Ucur[v] + (gxm - gxp)) + (gym - gyp);
+            }
+        }
+        // shift the plane window; prefetch plane rz+2 of the own column
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            gz_prev[v] = rz >= 0 ? gz[v] : 0.0;
+            Wm[v] = W0[v];
+            W0[v] = Wp[v];
+        }
+        sp_prev = sp_cur;
+        sp_cur = sp_next;
+    }
+}
+
+}  // namespace
+}  // namespace rg

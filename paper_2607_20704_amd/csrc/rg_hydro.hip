@@ -19,273 +19,10 @@
 // L2 hits between neighbouring octs), the neighbour list and unew.
 #include "rg_internal.hpp"
 #include "rg_math.hpp"
+#include "rg_oct.hpp"
 
 namespace rg {
 namespace {
-
-// ---------------------------------------------------------------------------
-// stencil tables (positions are cell offsets from the oct origin, -2..3)
-// ---------------------------------------------------------------------------
-
-struct StencilTables {
-    int8_t wpos[80][3];    // cells whose primitive variables are needed
-    int8_t rpos[32][3];    // cells that are reconstructed (8 own + 24 face layer)
-    int8_t tile2w[216];    // (x+2) + 6(y+2) + 36(z+2) -> index into wpos, -1 if unused
-};
-
-constexpr int tile_index(int x, int y, int z) { return (x + 2) + 6 * (y + 2) + 36 * (z + 2); }
-
-constexpr StencilTables make_tables()
-{
-    StencilTables t{};
-    for (int i = 0; i < 216; ++i) t.tile2w[i] = -1;
-    int nw = 0, nr = 0;
-    // own cells
-    for (int c = 0; c < 8; ++c) {
-        int p[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
-        for (int a = 0; a < 3; ++a) {
-            t.wpos[nw][a] = static_cast<int8_t>(p[a]);
-            t.rpos[nr][a] = static_cast<int8_t>(p[a]);
-        }
-        t.tile2w[tile_index(p[0], p[1], p[2])] = static_cast<int8_t>(nw);
-        ++nw;
-        ++nr;
-    }
-    // face layer (reconstructed) then outer layer, along each axis
-    for (int layer = 0; layer < 2; ++layer)
-        for (int a = 0; a < 3; ++a)
-            for (int side = 0; side < 2; ++side)
-                for (int q = 0; q < 4; ++q) {
-                    int p[3] = {0, 0, 0};
-                    int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
-                    p[a] = layer == 0 ? (side ? 2 : -1) : (side ? 3 : -2);
-                    p[t1] = q & 1;
-                    p[t2] = q >> 1;
-                    for (int b = 0; b < 3; ++b) t.wpos[nw][b] = static_cast<int8_t>(p[b]);
-                    t.tile2w[tile_index(p[0], p[1], p[2])] = static_cast<int8_t>(nw);
-                    ++nw;
-                    if (layer == 0) {
-                        for (int b = 0; b < 3; ++b) t.rpos[nr][b] = static_cast<int8_t>(p[b]);
-                        ++nr;
-                    }
-                }
-    // edge cells: two coordinates in {-1, 2}, the third in {0, 1}
-    for (int a = 0; a < 3; ++a)        // the axis that stays inside
-        for (int q = 0; q < 8; ++q) {
-            int p[3] = {0, 0, 0};
-            int u = a == 0 ? 1 : 0, v = a == 2 ? 1 : 2;
-            p[a] = q & 1;
-            p[u] = (q >> 1) & 1 ? 2 : -1;
-            p[v] = (q >> 2) & 1 ? 2 : -1;
-            for (int b = 0; b < 3; ++b) t.wpos[nw][b] = static_cast<int8_t>(p[b]);
-            t.tile2w[tile_index(p[0], p[1], p[2])] = static_cast<int8_t>(nw);
-            ++nw;
-        }
-    return t;
-}
-
-__constant__ StencilTables c_tab = make_tables();
-
-// face f = 12 a + 4 c + t1 + 2 t2 on axis a between cells c-1 and c along a;
-// (t1, t2) are the other two axes in increasing order
-__device__ __forceinline__ int face_id(int a, int c, int t1, int t2) { return 12 * a + 4 * c + t1 + 2 * t2; }
-
-__device__ __forceinline__ int nslot(int sx, int sy, int sz) { return (sx + 1) + 3 * (sy + 1) + 9 * (sz + 1); }
-
-__device__ __forceinline__ int slot_of(int x) { return x < 0 ? -1 : (x > 1 ? 1 : 0); }
-
-// ---------------------------------------------------------------------------
-// the level kernel
-// ---------------------------------------------------------------------------
-
-struct LevelArgs {
-    const int32_t *list;  // if set, the octs are list[oct_begin .. oct_end)
-    const double *uold;
-    double *unew;
-    const int32_t *nbr27;
-    const uint32_t *son;
-    double *corr;
-    int64_t corr_base;
-    int64_t oct_begin, oct_end;
-    const double *dt;     // device scalar
-    double dx;
-    double gamma;
-};
-
-template <typename R, int G> struct Smem {
-    int64_t oct[G];
-    int32_t nb[G][27];
-    uint32_t sm[G][7];          // son masks: own, then sides x-, x+, y-, y+, z-, z+
-    double u[G][8][NV];         // uold of the oct's own cells
-    R w[G][80][NV];             // primitive variables of the stencil cells
-    R fs[G][36][2][NV];         // face states: [face][0] left of the face, [1] right
-    double g[G][36][NV];        // G = F dt/dx per face
-};
-
-template <typename R, int G, int NT>
-__device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, int count, Smem<R, G> &S)
-{
-    const int tid = threadIdx.x;
-    const double r = *a.dt / a.dx;
-    const double h64 = 0.5 * r;
-    const R h = static_cast<R>(h64);
-    const R gam = static_cast<R>(a.gamma);
-    const double g1d = 1.0 / (a.gamma - 1.0);
-    const R g1 = static_cast<R>(g1d);
-
-    // oct indices, neighbour entries and son masks
-    if (tid < G) S.oct[tid] = tid < count ? (a.list ? int64_t(a.list[first + tid]) : first + tid) : 0;
-    __syncthreads();
-    for (int it = tid; it < G * 27; it += NT) {
-        int g = it / 27, s = it - 27 * g;
-        S.nb[g][s] = g < count ? a.nbr27[27 * S.oct[g] + s] : 0;
-    }
-    __syncthreads();
-    for (int it = tid; it < G * 7; it += NT) {
-        int g = it / 7, k = it - 7 * g;
-        uint32_t m = 0;
-        if (g < count) {
-            int e;
-            if (k == 0) {
-                e = static_cast<int>(S.oct[g]);
-            } else {
-                int ax = (k - 1) >> 1, hi = (k - 1) & 1;
-                int sx = ax == 0 ? (hi ? 1 : -1) : 0, sy = ax == 1 ? (hi ? 1 : -1) : 0, sz = ax == 2 ? (hi ? 1 : -1) : 0;
-                e = S.nb[g][nslot(sx, sy, sz)];
-            }
-            if (e >= 0) m = a.son[e];
-        }
-        S.sm[g][k] = m;
-    }
-
-    // A: gather uold for the stencil cells, primitive variables
-    for (int it = tid; it < G * 80; it += NT) {
-        int g = it / 80, wc = it - 80 * g;
-        if (g >= count) continue;
-        int c[3] = {c_tab.wpos[wc][0], c_tab.wpos[wc][1], c_tab.wpos[wc][2]};
-        int s[3] = {slot_of(c[0]), slot_of(c[1]), slot_of(c[2])};
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            if (s[ax] != 0) {
-                int fs = nslot(ax == 0 ? s[0] : 0, ax == 1 ? s[1] : 0, ax == 2 ? s[2] : 0);
-                if (S.nb[g][fs] == RG_NBR_OUTSIDE) {
-                    c[ax] = s[ax] > 0 ? 1 : 0;
-                    s[ax] = 0;
-                }
-            }
-        }
-        int e = S.nb[g][nslot(s[0], s[1], s[2])];
-        // a consistent list never leaves an outside slot here; an
-        // inconsistent one reads the oct itself rather than stray memory
-        if (e == RG_NBR_OUTSIDE) e = static_cast<int>(S.oct[g]);
-        const int64_t cell = e >= 0 ? 8 * int64_t(e) + ((c[0] & 1) + 2 * (c[1] & 1) + 4 * (c[2] & 1))
-                                    : (-1 - int64_t(e));
-        double U[NV], W[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) U[v] = a.uold[NV * cell + v];
-        prim64(U, a.gamma, W);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) S.w[g][wc][v] = static_cast<R>(W[v]);
-        if (wc < 8) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v) S.u[g][wc][v] = U[v];
-        }
-    }
-    __syncthreads();
-
-    // B: slopes, predictor and face states
-    for (int it = tid; it < G * 32; it += NT) {
-        int g = it / 32, rc = it - 32 * g;
-        if (g >= count) continue;
-        const int x = c_tab.rpos[rc][0], y = c_tab.rpos[rc][1], z = c_tab.rpos[rc][2];
-        const R *w0 = S.w[g][c_tab.tile2w[tile_index(x, y, z)]];
-        R dW[3][NV], Wp[NV];
-        reconstruct<R>(w0, S.w[g][c_tab.tile2w[tile_index(x - 1, y, z)]], S.w[g][c_tab.tile2w[tile_index(x + 1, y, z)]],
-                       S.w[g][c_tab.tile2w[tile_index(x, y - 1, z)]], S.w[g][c_tab.tile2w[tile_index(x, y + 1, z)]],
-                       S.w[g][c_tab.tile2w[tile_index(x, y, z - 1)]], S.w[g][c_tab.tile2w[tile_index(x, y, z + 1)]], h,
-                       gam, dW, Wp);
-        const int p[3] = {x, y, z};
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            const int t1 = ax == 0 ? 1 : 0, t2 = ax == 2 ? 1 : 2;
-            const bool inside_t = p[t1] >= 0 && p[t1] <= 1 && p[t2] >= 0 && p[t2] <= 1;
-            if (!inside_t) continue;
-#pragma unroll
-            for (int side = 0; side < 2; ++side) {
-                // high-side state sits left of face c = p+1; low-side state right of face c = p
-                const int c = side ? p[ax] + 1 : p[ax];
-                if (c < 0 || c > 2) continue;
-                R st[NV];
-                face_state<R>(Wp, dW[ax], side != 0, st);
-                R *dst = S.fs[g][face_id(ax, c, p[t1], p[t2])][side ? 0 : 1];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) dst[v] = st[v];
-            }
-        }
-    }
-    __syncthreads();
-
-    // C: HLLC on the 36 faces
-    for (int it = tid; it < G * 36; it += NT) {
-        int g = it / 36, f = it - 36 * g;
-        if (g >= count) continue;
-        const int ax = f / 12, c = (f / 4) % 3, t1 = f & 1, t2 = (f >> 1) & 1;
-        R L[NV], Rr[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            L[v] = S.fs[g][f][0][v];
-            Rr[v] = S.fs[g][f][1][v];
-        }
-        // split test for the two cells: position c-1 and c along the axis
-        bool zero = false;
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const int pa = c - 1 + k;
-            int px[3];
-            px[ax] = pa;
-            px[ax == 0 ? 1 : 0] = t1;
-            px[ax == 2 ? 1 : 2] = t2;
-            const int bit = (px[0] & 1) + 2 * (px[1] & 1) + 4 * (px[2] & 1);
-            const uint32_t m = pa < 0 ? S.sm[g][1 + 2 * ax] : (pa > 1 ? S.sm[g][2 + 2 * ax] : S.sm[g][0]);
-            zero = zero || ((m >> bit) & 1u);
-        }
-        double gf[NV];
-        face_flux<R>(L, Rr, ax, gam, g1, r, zero, gf);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) S.g[g][f][v] = gf[v];
-    }
-    __syncthreads();
-
-    // D: update
-    for (int it = tid; it < G * 8 * NV; it += NT) {
-        int g = it / (8 * NV), k = it - 8 * NV * g;
-        if (g >= count) continue;
-        const int cidx = k / NV, v = k - NV * cidx;
-        const int ix = cidx & 1, iy = (cidx >> 1) & 1, iz = cidx >> 2;
-        const double gxm = S.g[g][face_id(0, ix, iy, iz)][v], gxp = S.g[g][face_id(0, ix + 1, iy, iz)][v];
-        const double gym = S.g[g][face_id(1, iy, ix, iz)][v], gyp = S.g[g][face_id(1, iy + 1, ix, iz)][v];
-        const double gzm = S.g[g][face_id(2, iz, ix, iy)][v], gzp = S.g[g][face_id(2, iz + 1, ix, iy)][v];
-        a.unew[8 * NV * S.oct[g] + k] = ((S.u[g][cidx][v] + (gxm - gxp)) + (gym - gyp)) + (gzm - gzp);
-    }
-
-    // E: flux owed to coarse neighbours
-    if (a.corr) {
-        for (int it = tid; it < G * 6 * NV; it += NT) {
-            int g = it / (6 * NV), k = it - 6 * NV * g;
-            if (g >= count) continue;
-            const int side = k / NV, v = k - NV * side;
-            const int ax = side >> 1, hi = side & 1;
-            const int e = S.nb[g][nslot(ax == 0 ? (hi ? 1 : -1) : 0, ax == 1 ? (hi ? 1 : -1) : 0,
-                                        ax == 2 ? (hi ? 1 : -1) : 0)];
-            if (!(e < 0 && e != RG_NBR_OUTSIDE)) continue;
-            const int c = hi ? 2 : 0;
-            const double sum = (S.g[g][face_id(ax, c, 0, 0)][v] + S.g[g][face_id(ax, c, 1, 0)][v]) +
-                               (S.g[g][face_id(ax, c, 0, 1)][v] + S.g[g][face_id(ax, c, 1, 1)][v]);
-            const double d = 0.125 * sum;
-            a.corr[30 * (S.oct[g] - a.corr_base) + k] = hi ? d : -d;
-        }
-    }
-}
 
 template <typename R, int G, int NT>
 __global__ __launch_bounds__(NT) void k_hydro_level(LevelArgs a)

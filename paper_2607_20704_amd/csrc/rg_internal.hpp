@@ -260,6 +260,32 @@ __device__ inline int32_t hash_probe(const uint64_t *keys, const int32_t *vals, 
     return -1;
 }
 
+// insert key (index i) by linear probing with a 64-bit compare-and-swap;
+// errors are flagged in the header
+__device__ inline void hash_insert_one(HashHeader *hdr, uint64_t *keys, int32_t *vals, uint64_t mask, uint64_t key,
+                                       int64_t i)
+{
+    if (key == 0) {
+        flag_error(hdr, RG_EINVAL, i);
+        return;
+    }
+    uint64_t s = fnv1a64(key) & mask;
+    for (uint64_t it = 0; it <= mask; ++it) {
+        unsigned long long prev =
+            atomicCAS(reinterpret_cast<unsigned long long *>(keys + s), 0ull, static_cast<unsigned long long>(key));
+        if (prev == 0ull) {
+            vals[s] = static_cast<int32_t>(i);
+            return;
+        }
+        if (prev == key) {
+            flag_error(hdr, RG_EDUPKEY, i);
+            return;
+        }
+        s = (s + 1) & mask;
+    }
+    flag_error(hdr, RG_EFULL, i);
+}
+
 // ---------------------------------------------------------------------------
 // misc launches shared by several files
 // ---------------------------------------------------------------------------

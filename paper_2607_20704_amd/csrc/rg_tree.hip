@@ -11,6 +11,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include "rg_internal.hpp"
+#include "rg_nbr.hpp"
 
 namespace rg {
 namespace {
@@ -96,27 +97,7 @@ __global__ void k_hash_insert(const uint64_t *__restrict__ in, int64_t n, HashHe
                               int32_t *vals, uint64_t mask)
 {
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint64_t key = in[i];
-    if (key == 0) {
-        flag_error(hdr, RG_EINVAL, i);
-        return;
-    }
-    uint64_t s = fnv1a64(key) & mask;
-    for (uint64_t it = 0; it <= mask; ++it) {
-        unsigned long long prev =
-            atomicCAS(reinterpret_cast<unsigned long long *>(keys + s), 0ull, static_cast<unsigned long long>(key));
-        if (prev == 0ull) {
-            vals[s] = static_cast<int32_t>(i);
-            return;
-        }
-        if (prev == key) {
-            flag_error(hdr, RG_EDUPKEY, i);
-            return;
-        }
-        s = (s + 1) & mask;
-    }
-    flag_error(hdr, RG_EFULL, i);
+    if (i < n) hash_insert_one(hdr, keys, vals, mask, in[i], i);
 }
 
 __global__ void k_hash_lookup(const uint64_t *__restrict__ keys, const int32_t *__restrict__ vals, uint64_t mask,
@@ -128,10 +109,6 @@ __global__ void k_hash_lookup(const uint64_t *__restrict__ keys, const int32_t *
     out[i] = key == 0 ? -1 : hash_probe(keys, vals, mask, key);
 }
 
-// Neighbour lists.  A block of 256 threads serves 9 octs, 27 threads each
-// (one per offset); the octs' coordinates are decoded once into LDS.
-constexpr int kNbrOcts = 9;
-
 // `list` (optional) maps positions 0..n-1 to oct indices
 __global__ __launch_bounds__(256) void k_neighbours(const uint64_t *__restrict__ okeys, const int32_t *__restrict__ list,
                                                     int64_t n, int lmin, int bc, HashHeader *hdr,
@@ -139,75 +116,13 @@ __global__ __launch_bounds__(256) void k_neighbours(const uint64_t *__restrict__
                                                     uint64_t mask, int32_t *__restrict__ nbr27,
                                                     int32_t *__restrict__ father_cell, uint32_t *__restrict__ son_mask)
 {
-    __shared__ int32_t s_c[kNbrOcts][4];
-    __shared__ int64_t s_o[kNbrOcts];
+    __shared__ NbrGroup grp;
     const int64_t first = int64_t(blockIdx.x) * kNbrOcts;
-    const int t = threadIdx.x;
-    if (t < kNbrOcts && first + t < n) {
-        const int64_t o = list ? int64_t(list[first + t]) : first + t;
-        int32_t i, j, k, l;
-        key_coords(okeys[o], i, j, k, l);
-        s_c[t][0] = i;
-        s_c[t][1] = j;
-        s_c[t][2] = k;
-        s_c[t][3] = l;
-        s_o[t] = o;
-    }
-    __syncthreads();
-    if (t >= 27 * kNbrOcts) return;
-    const int g = t / 27, slot = t - 27 * g;
-    if (first + g >= n) return;
-    const int64_t o = s_o[g];
-    const int32_t i = s_c[g][0], j = s_c[g][1], k = s_c[g][2], l = s_c[g][3];
-    if (slot == 13) {
-        nbr27[27 * o + 13] = static_cast<int32_t>(o);
-        if (l > lmin) {
-            int32_t f = hash_probe(keys, vals, mask, okeys[o] >> 3);
-            if (f < 0) {
-                flag_error(hdr, RG_EUNGRADED, o);
-                father_cell[o] = -1;
-            } else {
-                const int bit = (i & 1) + 2 * (j & 1) + 4 * (k & 1);
-                father_cell[o] = 8 * f + bit;
-                atomicOr(son_mask + f, 1u << bit);
-            }
-        } else {
-            father_cell[o] = -1;
-        }
-        return;
-    }
-    const int dx = slot % 3 - 1, dy = (slot / 3) % 3 - 1, dz = slot / 9 - 1;
-    const int32_t N = 1 << (l - 1);
-    int32_t ni = i + dx, nj = j + dy, nk = k + dz;
-    if (bc == RG_BC_PERIODIC) {
-        ni &= N - 1;
-        nj &= N - 1;
-        nk &= N - 1;
-    } else if (ni < 0 || nj < 0 || nk < 0 || ni >= N || nj >= N || nk >= N) {
-        nbr27[27 * o + slot] = RG_NBR_OUTSIDE;
-        return;
-    }
-    const uint64_t kn = oct_key(ni, nj, nk, l);
-    int32_t e = hash_probe(keys, vals, mask, kn);
-    if (e < 0) {
-        int32_t f = (l > 1) ? hash_probe(keys, vals, mask, kn >> 3) : -1;
-        if (f < 0) {
-            flag_error(hdr, RG_EUNGRADED, o);
-            e = 0;
-        } else {
-            e = -1 - (8 * f + (ni & 1) + 2 * (nj & 1) + 4 * (nk & 1));
-        }
-    }
-    nbr27[27 * o + slot] = e;
+    const int64_t left = n - first;
+    const NbrTable tab{okeys, hdr, keys, vals, mask, nbr27, father_cell, son_mask, lmin, bc};
+    nbr_octs_body(tab, list, first, left < kNbrOcts ? static_cast<int>(left) : kNbrOcts, grp);
 }
 
-// Neighbour lists of complete bricks (8^3 octs, keys 512 P .. 512 P + 511,
-// consecutive in memory).  Inside the brick every neighbour follows from the
-// decoded positions; only the 488 oct slots around the brick are looked up
-// in the hash table (with the coarse-cell fallback), and each sibling
-// group's father is looked up once.  Every child of the brick's fathers lies
-// in the brick, so their son masks are complete (all 8 bits) and are stored
-// directly.
 __global__ __launch_bounds__(256) void k_neighbours_brick(const uint64_t *__restrict__ okeys,
                                                           const int32_t *__restrict__ bricks, int64_t nbricks,
                                                           int lmin, int bc, HashHeader *hdr,
@@ -217,75 +132,12 @@ __global__ __launch_bounds__(256) void k_neighbours_brick(const uint64_t *__rest
                                                           int32_t *__restrict__ father_cell,
                                                           uint32_t *__restrict__ son_mask)
 {
-    constexpr int BO = 8, HS = 10;
-    __shared__ int32_t s_slot[HS * HS * HS];
-    __shared__ int16_t s_pos[BO * BO * BO];       // local position of the k-th oct in key order
-    __shared__ int32_t s_father[BO * BO];         // father oct of each sibling group
-    const int tid = threadIdx.x;
+    __shared__ NbrBrick nb;
     const int64_t per_xcd = (nbricks + 7) / 8;
     const int64_t b = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (b >= nbricks) return;
-    const int64_t base = bricks[b];
-    int32_t i0, j0, k0, l;
-    key_coords(okeys[base], i0, j0, k0, l);
-    i0 &= ~(BO - 1);
-    j0 &= ~(BO - 1);
-    k0 &= ~(BO - 1);
-    for (int k = tid; k < BO * BO * BO; k += 256) {
-        int32_t i, j, kk, ll;
-        key_coords(okeys[base + k], i, j, kk, ll);
-        const int p = (i & 7) + BO * (j & 7) + BO * BO * (kk & 7);
-        s_pos[k] = static_cast<int16_t>(p);
-        s_slot[((p & 7) + 1) + HS * (((p >> 3) & 7) + 1) + HS * HS * ((p >> 6) + 1)] = static_cast<int32_t>(base + k);
-    }
-    const int32_t N = 1 << (l - 1);
-    for (int sidx = tid; sidx < HS * HS * HS; sidx += 256) {
-        const int sa = sidx % HS - 1, sb = (sidx / HS) % HS - 1, sc = sidx / (HS * HS) - 1;
-        if (sa >= 0 && sa < BO && sb >= 0 && sb < BO && sc >= 0 && sc < BO) continue;
-        int32_t ni = i0 + sa, nj = j0 + sb, nk = k0 + sc;
-        int32_t e;
-        if (bc == RG_BC_PERIODIC) {
-            ni &= N - 1;
-            nj &= N - 1;
-            nk &= N - 1;
-        } else if (ni < 0 || nj < 0 || nk < 0 || ni >= N || nj >= N || nk >= N) {
-            s_slot[sidx] = RG_NBR_OUTSIDE;
-            continue;
-        }
-        const uint64_t kn = oct_key(ni, nj, nk, l);
-        e = hash_probe(keys, vals, mask, kn);
-        if (e < 0) {
-            const int32_t f = (l > 1) ? hash_probe(keys, vals, mask, kn >> 3) : -1;
-            if (f < 0) {
-                flag_error(hdr, RG_EUNGRADED, base);
-                e = 0;
-            } else {
-                e = -1 - (8 * f + (ni & 1) + 2 * (nj & 1) + 4 * (nk & 1));
-            }
-        }
-        s_slot[sidx] = e;
-    }
-    if (tid < BO * BO) {
-        int32_t f = -1;
-        if (l > lmin) {
-            f = hash_probe(keys, vals, mask, okeys[base + 8 * tid] >> 3);
-            if (f < 0) flag_error(hdr, RG_EUNGRADED, base + 8 * tid);
-            else son_mask[f] = 0xffu;
-        }
-        s_father[tid] = f;
-    }
-    __syncthreads();
-    for (int q = tid; q < 27 * BO * BO * BO; q += 256) {
-        const int k = q / 27, e = q - 27 * k;
-        const int p = s_pos[k];
-        const int a = (p & 7) + e % 3, bb = ((p >> 3) & 7) + (e / 3) % 3, c = (p >> 6) + e / 9;
-        nbr27[27 * base + q] = s_slot[a + HS * bb + HS * HS * c];
-    }
-    for (int k = tid; k < BO * BO * BO; k += 256) {
-        const int p = s_pos[k];
-        const int32_t f = s_father[k >> 3];
-        father_cell[base + k] = f < 0 ? -1 : 8 * f + ((p & 1) + 2 * ((p >> 3) & 1) + 4 * ((p >> 6) & 1));
-    }
+    const NbrTable tab{okeys, hdr, keys, vals, mask, nbr27, father_cell, son_mask, lmin, bc};
+    nbr_brick_body(tab, bricks[b], nb);
 }
 
 }  // namespace

@@ -109,6 +109,38 @@ def test_argument_errors_are_reported_without_a_device():
     assert lib.rg_encode_keys(None, 0, None, None) == L.RG_OK
 
 
+def test_batch_argument_errors_without_a_device():
+    """rg_batch_create validates every tree on the host before any device
+    call; rg_batch_run refuses a null batch and rg_batch_destroy accepts one."""
+    lib = L.lib()
+    out = ctypes.c_void_p()
+    fake = ctypes.c_void_p(256)
+    assert lib.rg_batch_create(None, 1, 0, 2, 0, None, fake, None, ctypes.byref(out)) == L.RG_EINVAL
+    tree = L.RgTree()
+    tree.n_oct, tree.lmin, tree.lmax = 8, 2, 2
+    bt = (L.RgBatchTree * 1)()
+    bt[0].tree = ctypes.pointer(tree)
+    bt[0].d_u0, bt[0].d_u1, bt[0].gamma, bt[0].cfl = 256, 512, 1.4, 0.8
+    # no schedule
+    assert lib.rg_batch_create(bt, 1, 0, 2, 0, None, fake, None, ctypes.byref(out)) == L.RG_EINVAL
+    assert b"schedule" in L.detail().encode()
+    sched = L.RgSchedule()
+    sched.d_list = 1024
+    tree.sched = ctypes.pointer(sched)
+    # bad form, flags, step count, group size, aliasing state buffers
+    assert lib.rg_batch_create(bt, 1, 7, 2, 0, None, fake, None, ctypes.byref(out)) == L.RG_EINVAL
+    assert lib.rg_batch_create(bt, 1, 0, 2, L.RG_STEP_REKEY, None, fake, None, ctypes.byref(out)) == L.RG_EINVAL
+    assert lib.rg_batch_create(bt, 1, 0, 0, 0, None, fake, None, ctypes.byref(out)) == L.RG_EINVAL
+    tune = L.RgTuning()
+    tune.octs_per_group = 3
+    assert lib.rg_batch_create(bt, 1, 0, 2, 0, ctypes.byref(tune), fake, None, ctypes.byref(out)) == L.RG_EINVAL
+    bt[0].d_u1 = 256
+    assert lib.rg_batch_create(bt, 1, 0, 2, 0, None, fake, None, ctypes.byref(out)) == L.RG_EINVAL
+    assert out.value is None
+    assert lib.rg_batch_run(None, None) == L.RG_EINVAL
+    assert lib.rg_batch_destroy(None) == L.RG_OK
+
+
 def test_workspace_sizes():
     lib = L.lib()
     assert lib.rg_hash_workspace_bytes(0) == 256 + 16 * 12

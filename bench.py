@@ -10,7 +10,13 @@ restriction (the last two are empty on a single level).  Inputs are resident
 in HBM before the timed region starts.
 
 Prints one JSON line.  `value` is FP64 cell-updates/s; the mixed form
-(FP32 reconstruction/HLLC, FP64 state) is reported under "mixed".
+(FP32 reconstruction/HLLC, FP64 state) is reported under "mixed".  Two more
+workloads are reported beside it: "batched" (64 seeded boxes of uneven size
+and depth, 20 steps in one graph launch, against the same boxes stepped one
+at a time) and "deep_amr" (clumpy gas on a base-7 tree refined to level 12,
+about 28 M cells, with the mixed form's L1 error against FP64).  The kernel
+variants are chosen by the autotuner before timing (they give identical
+bits).
 """
 import argparse
 import hashlib
@@ -56,7 +62,7 @@ def measured_traffic(form):
     return float(m.group(1)) if m else None
 
 
-def time_form(D, u0, w, form, steps, warmup, api):
+def time_form(D, u0, w, form, steps, warmup, api, tune=None):
     import torch
     a, b = u0.clone(), torch.empty_like(u0)
     dt = torch.empty(1, dtype=torch.float64, device="cuda")
@@ -68,7 +74,7 @@ def time_form(D, u0, w, form, steps, warmup, api):
         if h0 is not None:
             h0.record()
         for l in range(D.lmin, D.lmax + 1):
-            D.hydro_level(l, dt, w.gamma, a, b, form)
+            D.hydro_level(l, dt, w.gamma, a, b, form, tune)
         if h1 is not None:
             h1.record()
         if D.lmax > D.lmin:
@@ -101,13 +107,112 @@ def time_form(D, u0, w, form, steps, warmup, api):
     for k in range(steps):
         api.cfl_dt(a, D.son_mask, D.level_begin, D.lmin, D.lmax, w.gamma, w.cfl, dt)
         for l in range(D.lmin, D.lmax + 1):
-            D.hydro_level(l, dt, w.gamma, a, b, form)
+            D.hydro_level(l, dt, w.gamma, a, b, form, tune)
         a, b = b, a
     e2.record()
     torch.cuda.synchronize()
     hydro_only_ms = s2.elapsed_time(e2) / steps
     return {"ms_per_step": ms, "wall_ms_per_step": 1e3 * wall / steps, "hydro_kernel_ms": hydro_ms,
             "hydro_only_ms_per_step": hydro_only_ms, "state": a}
+
+
+def time_batched(forms, nsteps, reps, api, inputs, autotune):
+    """The batched workload: 64 seeded boxes of uneven size and depth, all
+    advanced `nsteps` steps by one graph launch; against the same boxes
+    stepped one after another with rg_step (same kernels, one tree at a
+    time)."""
+    import torch
+    boxes = inputs.batched_boxes(nbox=64, seed=20704, nsteps=nsteps)
+    trees = [api.DeviceTree(b.ijkl, b.bc) for b in boxes]
+    states = [D.to_key_order(b.u.reshape(-1, 5)) for D, b in zip(trees, boxes)]
+    torch.cuda.synchronize()
+    cells = sum(8 * D.n for D in trees)
+    gammas, cfls = [b.gamma for b in boxes], [b.cfl for b in boxes]
+    out = {"workload": "64 boxes, seed 20704: base level 4-7, 0-2 extra levels on a random sphere, Sod/Sedov/random "
+                       "initial states; %d steps per box, one graph launch" % nsteps,
+           "boxes": len(boxes), "cells": cells, "octs": sum(D.n for D in trees)}
+    for f in forms:
+        form = api.RG_FP64 if f == "fp64" else api.RG_MIXED
+        tune, _ = autotune.tune_batch(trees, states, gammas, cfls, form)
+        B = api.Batch(trees, states, gammas, cfls, nsteps, form=form, tune=tune)
+        B.run()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            B.run()
+            b.record()
+            b.synchronize()
+            ms.append(a.elapsed_time(b))
+        ms.sort()
+        batched_ms = ms[len(ms) // 2]
+        B.close()
+        # the same boxes one after another
+        us = [s.clone() for s in states]
+        vs = [torch.empty_like(s) for s in states]
+        dt = torch.empty(1, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for k, D in enumerate(trees):
+            x, y = us[k], vs[k]
+            for _ in range(nsteps):
+                D.step(x, y, gammas[k], cfls[k], form, dt=dt)
+                x, y = y, x
+        b.record()
+        b.synchronize()
+        seq_ms = a.elapsed_time(b)
+        out[f] = {"cell_updates_per_s": cells * nsteps / (batched_ms * 1e-3),
+                  "ms_per_launch": round(batched_ms, 3), "tune": list(tune),
+                  "one_tree_at_a_time_cell_updates_per_s": cells * nsteps / (seq_ms * 1e-3)}
+    return out
+
+
+def time_deep_amr(forms, nsteps, api, inputs):
+    """The clumpy-gas deep tree (base 7 up to level 12, about 28 M cells):
+    `nsteps` whole steps per form (dt, every level, corrections,
+    restriction; lists prebuilt), and the mixed form's L1 error per
+    conserved field against FP64 after those steps (leaf cells, volume
+    weighted)."""
+    import numpy as np
+    import torch
+    w = inputs.deep_amr(nsteps=nsteps)
+    D = api.DeviceTree(w.ijkl, w.bc)
+    u0 = D.to_key_order(w.u)
+    lv = torch.as_tensor(np.repeat(D.ijkl_sorted.cpu().numpy()[:, 3], 8), device="cuda")
+    bits = torch.arange(8, device="cuda", dtype=torch.int32).repeat(D.n)
+    leaf = ((D.son_mask.repeat_interleave(8) >> bits) & 1) == 0
+    vol = torch.where(leaf, torch.pow(2.0, -3.0 * lv.double()), torch.zeros((), dtype=torch.float64, device="cuda"))
+    cells = 8 * D.n
+    out = {"workload": "clumpy gas, base level 7 refined cell by cell to level 12 where rho > 8 mean rho; 2000 "
+                       "Gaussian clumps (seed 20705, lognormal amplitudes sigma %.4g), at rest, p = rho^(5/3), "
+                       "gamma 5/3, periodic; %d steps" % (w.meta["sigma_a"], nsteps),
+           "octs": D.n, "cells": cells,
+           "octs_per_level": {str(l): int(D.level_begin[l + 1] - D.level_begin[l]) for l in range(D.lmin, D.lmax + 1)},
+           "schedule": {str(l): {"bricks": c[0], "per_oct": c[1]} for l, c in D.schedule_counts().items()}}
+    states = {}
+    for f in forms:
+        form = api.RG_FP64 if f == "fp64" else api.RG_MIXED
+        D.run(u0, w.gamma, w.cfl, 1, form=form)       # warm-up
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        u, _ = D.run(u0, w.gamma, w.cfl, nsteps, form=form)
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b) / nsteps
+        states[f] = u
+        out[f] = {"cell_updates_per_s": cells / (ms * 1e-3), "ms_per_step": round(ms, 4)}
+    if "fp64" in states and "mixed" in states:
+        x, y = states["fp64"], states["mixed"]
+        num = (vol[:, None] * (x - y).abs()).sum(0)
+        den = (vol[:, None] * x.abs()).sum(0)
+        rho_den = den[0]
+        l1 = [float(num[0] / den[0])] + [float(num[v] / rho_den) for v in (1, 2, 3)] + [float(num[4] / den[4])]
+        out["mixed"]["l1_vs_fp64_after_%d_steps" % nsteps] = l1
+        out["mixed"]["l1_note"] = "momenta start at rest: their L1 is relative to the density norm"
+    return out
 
 
 def cpu_baseline(w, sample_octs):
@@ -140,6 +245,9 @@ def main():
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-octs", type=int, default=1 << 20)
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-box batched workload")
+    ap.add_argument("--no-tune", action="store_true", help="library default kernels instead of autotuned ones")
+    ap.add_argument("--no-deep-amr", action="store_true", help="skip the clumpy-gas deep-AMR workload")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -149,7 +257,7 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2607_20704_amd import api, inputs
+    from paper_2607_20704_amd import api, autotune, inputs
     torch.cuda.set_device(0)
     log("generating the 256^3 random-field box")
     w = inputs.random_uniform()
@@ -169,8 +277,13 @@ def main():
     res = {}
     for f in forms:
         form = api.RG_FP64 if f == "fp64" else api.RG_MIXED
+        tune = None
+        if not args.no_tune:
+            tune, _ = autotune.tune_tree(D, u0, w.gamma, form)
+            log("form %s: autotuned %s" % (f, tune))
         log("timing form %s: %d warmup + %d steps" % (f, args.warmup, args.steps))
-        res[f] = time_form(D, u0, w, form, args.steps, args.warmup, api)
+        res[f] = time_form(D, u0, w, form, args.steps, args.warmup, api, tune)
+        res[f]["tune"] = list(tune) if tune else None
         log("  %.3f ms/step, hydro kernel %.3f ms" % (res[f]["ms_per_step"], res[f]["hydro_kernel_ms"]))
 
     def roof(r, f):
@@ -184,7 +297,7 @@ def main():
         return {"value": cells / (r["ms_per_step"] * 1e-3), "ms_per_step": round(r["ms_per_step"], 4),
                 "hydro_only_cell_updates_per_s": cells / (r["hydro_only_ms_per_step"] * 1e-3),
                 "hydro_only_ms_per_step": round(r["hydro_only_ms_per_step"], 4),
-                "ns_per_cell": r["ms_per_step"] * 1e6 / cells, "roofline": roof(r, f)}
+                "ns_per_cell": r["ms_per_step"] * 1e6 / cells, "tune": r["tune"], "roofline": roof(r, f)}
 
     primary = "fp64" if "fp64" in res else forms[0]
     out = {"metric": METRIC, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -200,6 +313,7 @@ def main():
                      "step": "rekey+sort+hash+neighbours+dt+hydro(+corrections+restriction)"}
     out["roofline"] = s["roofline"]
     out["hydro_only_cell_updates_per_s"] = s["hydro_only_cell_updates_per_s"]
+    out["tune"] = s["tune"]
     out["ns_per_cell"] = s["ns_per_cell"]
     for f in forms:
         if f != primary:
@@ -209,6 +323,16 @@ def main():
         a, b = res["fp64"]["state"], res["mixed"]["state"]
         l1 = ((a - b).abs().sum(0) / a.abs().sum(0).clamp_min(1e-300)).cpu().numpy()
         out["mixed"]["l1_vs_fp64_after_%d_steps" % (2 * args.steps + args.warmup)] = [float(x) for x in l1]
+    if not args.no_batched:
+        log("batched workload")
+        del res
+        torch.cuda.empty_cache()
+        out["batched"] = time_batched(forms, 20, 5, api, inputs, autotune)
+        torch.cuda.empty_cache()
+    if not args.no_deep_amr:
+        log("deep-AMR workload: generating")
+        out["deep_amr"] = time_deep_amr(forms, 10, api, inputs)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("oracle CPU baseline on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_octs)

@@ -14,6 +14,7 @@ neighbours present (after periodic wrap, or clipped at outflow walls), so every
 missing neighbour of an oct is covered by a coarse leaf cell.  Split cells hold
 the mean of their children.
 """
+import math
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -264,6 +265,110 @@ def grid_to_tree_state(ijkl, grid_level, fields, gamma):
     return fill_split_cells(ijkl, u)
 
 
+class ClumpField:
+    """Uniform background plus Gaussian clumps:
+    rho(x) = 1 + sum_c A_c prod_axes exp(-d_a^2 / (2 R_c^2)),
+    d_a the minimum-image distance to clump centre c along axis a (periodic
+    unit box).  Centres uniform, radii R uniform in [r_min, r_max] cells of
+    `base_level`, amplitudes lognormal A = exp(sigma_a g)."""
+
+    def __init__(self, nclump, seed, sigma_a, base_level, r_cells=(2.0, 20.0)):
+        rng = np.random.default_rng(seed)
+        self.centre = rng.uniform(0.0, 1.0, (nclump, 3))
+        self.radius = rng.uniform(r_cells[0], r_cells[1], nclump) / (1 << base_level)
+        self.amp = np.exp(sigma_a * rng.standard_normal(nclump))
+
+    def mean(self):
+        """Box average of rho (each clump integrates to A (sqrt(2 pi) R
+        erf(1 / (2 sqrt 2 R)))^3 over its minimum-image cell)."""
+        one = np.array([math.sqrt(2.0 * math.pi) * r * math.erf(1.0 / (2.0 * math.sqrt(2.0) * r))
+                        for r in self.radius])
+        return 1.0 + float(np.sum(self.amp * one ** 3))
+
+    def _axis(self, level, axis):
+        n = 1 << level
+        x = (np.arange(n) + 0.5) / n
+        d = x[None, :] - self.centre[:, axis:axis + 1]
+        d -= np.round(d)
+        return np.exp(-0.5 * (d / self.radius[:, None]) ** 2)
+
+    def at_cells(self, level, ci, cj, ck, tile=16, batch=16):
+        """rho at the centres of the level-`level` cells (ci, cj, ck): the
+        separable sum is evaluated on the tile x tile x tile blocks that hold
+        the requested cells, as one matrix product per block."""
+        ci, cj, ck = (np.asarray(a, np.int64) for a in (ci, cj, ck))
+        if len(ci) == 0:
+            return np.zeros(0)
+        n = 1 << level
+        t = min(tile, n)
+        nt = n // t
+        ex, ey, ez = (self._axis(level, a) for a in range(3))
+        tid = ((ck // t) * nt + (cj // t)) * nt + (ci // t)
+        tiles, inv = np.unique(tid, return_inverse=True)
+        tx, ty, tz = tiles % nt, (tiles // nt) % nt, tiles // (nt * nt)
+        ar = np.arange(t)
+        vals = np.empty((len(tiles), t, t, t))
+        for b0 in range(0, len(tiles), batch):
+            sl = slice(b0, min(b0 + batch, len(tiles)))
+            I, J, K = tx[sl, None] * t + ar, ty[sl, None] * t + ar, tz[sl, None] * t + ar
+            X = ex[:, I].transpose(1, 2, 0)                                      # [b, i, c]
+            Y = ey[:, J].transpose(1, 0, 2)[:, :, :, None]                       # [b, c, j, 1]
+            Z = ez[:, K].transpose(1, 0, 2)[:, :, None, :]                       # [b, c, 1, k]
+            M = (self.amp[None, :, None, None] * Y * Z).reshape(len(I), len(self.amp), t * t)
+            vals[sl] = (X @ M).reshape(len(I), t, t, t)                          # [b, i, j, k]
+        return 1.0 + vals[inv, ci % t, cj % t, ck % t]
+
+
+def _oct_cells(octs, level):
+    """Cell indices (ci, cj, ck) of the 8 cells of each oct code, [n*8]."""
+    i, j, k = _decode(octs, 1 << (level - 1))
+    c = np.arange(8)
+    return ((2 * i[:, None] + (c & 1)).ravel(), (2 * j[:, None] + ((c >> 1) & 1)).ravel(),
+            (2 * k[:, None] + ((c >> 2) & 1)).ravel())
+
+
+def clump_tree(fieldobj, base, lmax, threshold, max_passes=8):
+    """Periodic tree refined cell by cell wherever rho(cell centre) >
+    `threshold`, from the complete `base` level up to `lmax`, with the grading
+    closure; flagging is repeated for octs the closure adds.  Returns (ijkl,
+    {level: (oct codes, rho of their 8 cells)})."""
+    levels = {base: np.arange((1 << (base - 1)) ** 3, dtype=np.int64)}
+    rho = {}          # level -> dict code -> row in a values array
+    cache = {}
+
+    def values(l, octs):
+        codes, vals = cache.get(l, (np.zeros(0, np.int64), np.zeros((0, 8))))
+        new = np.setdiff1d(octs, codes, assume_unique=True)
+        if len(new):
+            v = fieldobj.at_cells(l, *_oct_cells(new, l)).reshape(-1, 8)
+            codes = np.concatenate([codes, new])
+            vals = np.concatenate([vals, v])
+            order = np.argsort(codes)
+            codes, vals = codes[order], vals[order]
+            cache[l] = (codes, vals)
+        pos = np.searchsorted(codes, octs)
+        return vals[pos]
+
+    for _ in range(max_passes):
+        before = {l: len(v) for l, v in levels.items()}
+        for l in range(base, lmax):
+            octs = levels.get(l)
+            if octs is None or len(octs) == 0:
+                break
+            f = values(l, octs) > threshold
+            oo, cc = np.nonzero(f)
+            i, j, k = _decode(octs[oo], 1 << (l - 1))
+            new = _code(2 * i + (cc & 1), 2 * j + ((cc >> 1) & 1), 2 * k + ((cc >> 2) & 1), 1 << l)
+            levels[l + 1] = np.unique(np.concatenate([levels.get(l + 1, np.zeros(0, np.int64)), new]))
+        levels = _close(levels, base, PERIODIC)
+        if {l: len(v) for l, v in levels.items()} == before:
+            break
+    levels = {l: v for l, v in levels.items() if len(v)}
+    for l, octs in levels.items():
+        rho[l] = (np.sort(octs), values(l, np.sort(octs)))
+    return _levels_to_ijkl(levels), rho
+
+
 # --------------------------------------------------------------------------
 # named workloads
 # --------------------------------------------------------------------------
@@ -342,3 +447,30 @@ def batched_boxes(nbox=64, seed=20704, nsteps=20, base_range=(4, 7), extra_range
         boxes.append(Workload("box%02d" % b, t, u, gam, 0.8, bc, nsteps,
                               {"base": base, "extra": extra, "kind": ["sod", "sedov", "random"][kind]}))
     return boxes
+
+
+# Amplitude spread of the clumpy-gas workload's lognormal clumps, bisected
+# over [2.5, 2.7] so that the base-7 / level-12 tree with 2000 clumps of seed
+# 20705 holds 30 M +- 10 % cells: sigma 2.6 -> 54.4 M, 2.55 -> 20.7 M,
+# 2.575 -> 36.3 M, 2.5625 -> 28.1 M cells (3,516,930 octs).
+DEEP_AMR_SIGMA_A = 2.5625
+
+
+def deep_amr(base=7, lmax=12, nclump=2000, seed=20705, sigma_a=None, nsteps=10, radius_level=7):
+    """Clumpy gas on a deep cell-by-cell tree: background density 1 plus
+    `nclump` seeded Gaussian clumps (lognormal amplitudes, radii 2-20 cells
+    of level `radius_level`), at rest, p = rho^(5/3), gamma 5/3, periodic.
+    A cell of level base .. lmax-1 is refined where its centre density
+    exceeds 8 times the box mean, with the grading closure."""
+    sig = DEEP_AMR_SIGMA_A if sigma_a is None else sigma_a
+    fld = ClumpField(nclump, seed, sig, radius_level)
+    mean = fld.mean()
+    ijkl, rho = clump_tree(fld, base, lmax, 8.0 * mean)
+    gam = 5.0 / 3.0
+    # per-cell density in input order (levels ascending, codes ascending)
+    r = np.concatenate([rho[l][1] for l in sorted(rho)]).reshape(-1)
+    z = np.zeros_like(r)
+    u = conserved(r, z, z, z, r ** gam, gam).reshape(-1, 5)
+    u = fill_split_cells(ijkl, u)
+    return Workload("deep_amr_l%d_l%d" % (base, lmax), ijkl, u, gam, 0.8, PERIODIC, nsteps,
+                    {"sigma_a": sig, "nclump": nclump, "seed": seed, "mean_rho": mean})

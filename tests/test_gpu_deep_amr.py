@@ -1,0 +1,97 @@
+"""The clumpy-gas deep-AMR workload (base 7 up to level 12): a small variant
+against the oracle over 10 steps (FP64 parity, mixed L1), and the full
+30 M-cell tree in the launch shape of the benchmark, compared with the
+oracle on sampled octs."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import build_both, l1_rel, leaf_and_volume, parity_metric, say
+from oracle import oracle as O
+from paper_2607_20704_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def small():
+    return I.deep_amr(base=4, lmax=7, nclump=60, sigma_a=2.0)
+
+
+def test_small_deep_amr_fp64_parity():
+    from paper_2607_20704_amd import api
+    w = small()
+    say("deep amr small fp64: octs", len(w.ijkl))
+    T, D = build_both(w.ijkl, w.bc)
+    u, dts = D.run(D.to_key_order(w.u), w.gamma, w.cfl, 10, form=api.RG_FP64)
+    torch.cuda.synchronize()
+    ref = T.permute_cells(w.u)
+    ref_dts = T.run(ref, w.gamma, w.cfl, 10)
+    worst, dmax = parity_metric(u.cpu().numpy(), ref)
+    say("  worst ratio %.3g max |diff| %.3g" % (worst, dmax))
+    assert worst <= 1e-12
+    assert np.all(np.abs(dts.cpu().numpy() - ref_dts) <= 1e-12 * ref_dts)
+
+
+def test_small_deep_amr_mixed_l1():
+    from paper_2607_20704_amd import api
+    w = small()
+    T, D = build_both(w.ijkl, w.bc)
+    u, _ = D.run(D.to_key_order(w.u), w.gamma, w.cfl, 10, form=api.RG_MIXED)
+    torch.cuda.synchronize()
+    ref = T.permute_cells(w.u)
+    T.run(ref, w.gamma, w.cfl, 10)
+    leaf, vol = leaf_and_volume(T)
+    l1 = l1_rel(u.cpu().numpy(), ref, leaf, vol)
+    say("deep amr small mixed L1", l1)
+    assert np.all(l1[[0, 4]] <= 1e-5)
+    # momenta start at zero: compare against the density scale
+    rho_scale = (vol * leaf * np.abs(ref[:, 0])).sum()
+    mom = (vol[:, None] * leaf[:, None] * np.abs(u.cpu().numpy()[:, 1:4] - ref[:, 1:4])).sum(0) / rho_scale
+    assert np.all(mom <= 1e-5), mom
+
+
+def test_full_deep_amr_sampled():
+    """28 M cells, 3.5 M octs on levels 7-12: one FP64 update of every level
+    (the launches the benchmark times) against the oracle's update of 1500
+    sampled octs, including the fluxes they owe to coarse neighbours."""
+    from paper_2607_20704_amd import api
+    say("deep amr full: generating")
+    w = I.deep_amr()
+    say("  octs", len(w.ijkl), "levels", np.bincount(w.ijkl[:, 3])[7:].tolist())
+    D = api.DeviceTree(w.ijkl, w.bc)
+    T = O.Tree(w.ijkl, w.bc)
+    assert np.array_equal(D.keys.cpu().numpy(), T.keys)
+    say("  schedule", D.schedule_counts())
+    u0 = D.to_key_order(w.u)
+    u1 = torch.zeros_like(u0)
+    dt = api.cfl_dt(u0, D.son_mask, D.level_begin, D.lmin, D.lmax, w.gamma, w.cfl)
+    for l in range(D.lmin, D.lmax + 1):
+        D.hydro_level(l, dt, w.gamma, u0, u1, api.RG_FP64)
+    torch.cuda.synchronize()
+    ref0 = T.permute_cells(w.u)
+    dt_ref = T.cfl_dt(ref0, w.gamma, w.cfl)
+    assert dt.cpu().numpy()[0] == dt_ref
+    rng = np.random.default_rng(91)
+    lv = T.ijkl[:, 3]
+    # half the sample from the finest two levels, where the coarse-fine faces are
+    fine = np.nonzero(lv >= 11)[0]
+    sample = np.unique(np.concatenate([rng.integers(0, T.n, 750), fine[rng.integers(0, len(fine), 750)]]))
+    ref = np.zeros_like(ref0)
+    corr = np.zeros(30 * T.n)
+    for o in sample:
+        O.hydro_octs(T.ijkl, T.nbr27, T.son_mask, int(o), int(o) + 1, ref0, ref, corr, dt_ref, w.gamma)
+    got = u1.cpu().numpy().reshape(-1, 8, 5)[sample].reshape(-1, 5)
+    worst, dmax = parity_metric(got, ref.reshape(-1, 8, 5)[sample].reshape(-1, 5))
+    say("  fp64 sampled worst ratio %.3g max |diff| %.3g" % (worst, dmax))
+    assert worst <= 1e-12
+    # the fluxes owed to coarse neighbours, on the sides that have one
+    cb = D.corr_base
+    dc = D.corr.cpu().numpy().reshape(-1, 6, 5)
+    s2 = sample[sample >= cb]
+    want = corr.reshape(-1, 6, 5)[s2]
+    nb = T.nbr27[s2][:, [(1 if a != 0 else 2 * hi) + 3 * (1 if a != 1 else 2 * hi) + 9 * (1 if a != 2 else 2 * hi)
+                          for a in range(3) for hi in (0, 1)]]
+    coarse = (nb < 0) & (nb != api.RG_NBR_OUTSIDE)
+    say("  coarse sides compared:", int(coarse.sum()))
+    assert coarse.sum() > 0
+    assert np.array_equal(dc[s2 - cb][coarse], want[coarse])

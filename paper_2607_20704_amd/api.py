@@ -30,13 +30,14 @@ def _ptr(t):
 
 
 def _tuning(tune):
-    """tune: None or (octs_per_group, threads[, no_bricks[, persistent]])."""
+    """tune: None or (octs_per_group, threads[, no_bricks[, persistent[, brick_waves]]])."""
     if tune is None:
         return None
     t = RgTuning()
     t.octs_per_group, t.threads = int(tune[0]), int(tune[1])
     t.no_bricks = int(tune[2]) if len(tune) > 2 else 0
     t.persistent = int(tune[3]) if len(tune) > 3 else 0
+    t.brick_waves = int(tune[4]) if len(tune) > 4 else 0
     return ctypes.byref(t)
 
 
@@ -138,10 +139,10 @@ def build_neighbours(ws, keys, lmin, bc, nbr27=None, father_cell=None, son_mask=
 # ---------------------------------------------------------------- hydro
 
 def hydro_step_level(dx, dt, gamma, uold, unew, nbr27, son_mask, oct_begin, oct_end, corr=None, corr_base=0,
-                     form=RG_FP64, tune=None):
+                     form=RG_FP64, tune=None, cfl=0.0, dt_next=None):
     check(L.lib().rg_hydro_step_level(float(dx), _ptr(dt), float(gamma), _ptr(uold), _ptr(unew), _ptr(nbr27),
                                       _ptr(son_mask), int(oct_begin), int(oct_end), _ptr(corr), int(corr_base),
-                                      int(form), _tuning(tune), _stream()))
+                                      float(cfl), _ptr(dt_next), int(form), _tuning(tune), _stream()))
 
 
 def apply_coarse_corrections(unew, corr, corr_base, nbr27, oct_begin, oct_end):
@@ -159,6 +160,12 @@ def cfl_dt(u, son_mask, level_begin, lmin, lmax, gamma, cfl, dt=None):
     check(L.lib().rg_cfl_dt(_ptr(u), _ptr(son_mask), lb.ctypes.data_as(ctypes.c_void_p), int(lmin), int(lmax),
                             float(gamma), float(cfl), _ptr(dt), _stream()))
     return dt
+
+
+def cfl_dt_corrected(u, nbr27, level_begin, lmin, lmax, gamma, cfl, dt):
+    lb = np.ascontiguousarray(level_begin, dtype=np.int64)
+    check(L.lib().rg_cfl_dt_corrected(_ptr(u), _ptr(nbr27), lb.ctypes.data_as(ctypes.c_void_p), int(lmin), int(lmax),
+                                      float(gamma), float(cfl), _ptr(dt), _stream()))
 
 
 # ---------------------------------------------------------------- whole tree
@@ -211,16 +218,17 @@ class DeviceTree:
         return {l: (int(self.sched.brick_count[l]), int(self.sched.rest_count[l]))
                 for l in range(self.lmin, self.lmax + 1)}
 
-    def hydro_level(self, level, dt, gamma, uold, unew, form=RG_FP64, tune=None):
-        """The update of one level (scheduled when a schedule exists)."""
+    def hydro_level(self, level, dt, gamma, uold, unew, form=RG_FP64, tune=None, cfl=0.0, dt_next=None):
+        """The update of one level (scheduled when a schedule exists); with
+        dt_next, also folds the new state's CFL limit into it."""
         if self.sched is not None:
             check(L.lib().rg_hydro_step_scheduled(ctypes.byref(self._desc), ctypes.byref(self.sched), int(level),
-                                                  _ptr(dt), float(gamma), _ptr(uold), _ptr(unew), int(form),
-                                                  _tuning(tune), _stream()))
+                                                  _ptr(dt), float(gamma), _ptr(uold), _ptr(unew), float(cfl),
+                                                  _ptr(dt_next), int(form), _tuning(tune), _stream()))
         else:
             ob, oe = int(self.level_begin[level]), int(self.level_begin[level + 1])
             hydro_step_level(0.5 ** level, dt, gamma, uold, unew, self.nbr27, self.son_mask, ob, oe,
-                             self.corr if level > self.lmin else None, self.corr_base, form, tune)
+                             self.corr if level > self.lmin else None, self.corr_base, form, tune, cfl, dt_next)
 
     def rebuild(self):
         hash_build(self.keys, self.hash_ws)
@@ -255,23 +263,31 @@ class DeviceTree:
         u = torch.as_tensor(np.ascontiguousarray(u_input_order, dtype=np.float64)).to("cuda")
         return permute_rows(u, self.perm)
 
-    def step(self, uold, unew, gamma, cfl, form=RG_FP64, rebuild=False, dt=None, tune=None):
+    def step(self, uold, unew, gamma, cfl, form=RG_FP64, rebuild=False, dt=None, tune=None, chain=False):
         """One step; rebuild=True re-keys, re-sorts and rebuilds the hash and
-        neighbour lists first (the whole tree bookkeeping of a step)."""
-        dt = dt if dt is not None else torch.empty(1, dtype=torch.float64, device="cuda")
+        neighbour lists first (the whole tree bookkeeping of a step).  With
+        chain=True, dt[0] is this step's time step and the next one is
+        written to dt[1] from the new state."""
+        dt = dt if dt is not None else torch.empty(2 if chain else 1, dtype=torch.float64, device="cuda")
         flags = (RG_STEP_REBUILD | L.RG_STEP_REKEY) if rebuild else 0
+        if chain:
+            flags |= L.RG_STEP_CHAIN_DT
         check(L.lib().rg_step(ctypes.byref(self._desc), _ptr(uold), _ptr(unew), float(gamma), float(cfl), int(form),
                               flags, _ptr(dt), _tuning(tune), _stream()))
         return dt
 
-    def run(self, u, gamma, cfl, nsteps, form=RG_FP64, rebuild=False, tune=None):
-        """nsteps steps; returns (state, dts) with the state in key order."""
+    def run(self, u, gamma, cfl, nsteps, form=RG_FP64, rebuild=False, tune=None, chain=False):
+        """nsteps steps; returns (state, dts) with the state in key order.
+        With chain=True each step computes the next step's dt inside its
+        update (the first one comes from cfl_dt)."""
         a, b = u.clone(), torch.empty_like(u)
-        dts = torch.empty(nsteps, dtype=torch.float64, device="cuda")
+        dts = torch.empty(nsteps + 1, dtype=torch.float64, device="cuda")
+        if chain:
+            cfl_dt(a, self.son_mask, self.level_begin, self.lmin, self.lmax, gamma, cfl, dts[0:1])
         for s in range(nsteps):
-            self.step(a, b, gamma, cfl, form, rebuild, dts[s:s + 1], tune)
+            self.step(a, b, gamma, cfl, form, rebuild, dts[s:s + 2] if chain else dts[s:s + 1], tune, chain)
             a, b = b, a
-        return a, dts
+        return a, dts[:nsteps]
 
 
 # ---------------------------------------------------------------- many trees

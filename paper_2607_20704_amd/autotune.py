@@ -1,8 +1,8 @@
 """Kernel-variant selection by measurement.
 
 Every variant the library offers for a workload (octs per workgroup of the
-per-oct kernel, bricks on or off, persistent or one-item-per-workgroup
-batched grids) computes the same bits -- the GPU tests check this -- so the
+per-oct kernel, bricks on or off, the brick kernel's register budget,
+persistent or one-item-per-workgroup batched grids) computes the same bits -- the GPU tests check this -- so the
 choice only changes speed.  The tuner times each candidate with HIP events
 on the caller's device and keeps the fastest in a JSON cache keyed by device
 name, form and a coarse workload signature, so later runs reuse it.
@@ -18,8 +18,20 @@ import torch
 
 from . import api
 
-# (octs_per_group, threads, no_bricks)
-TREE_CANDIDATES = [(4, 256, 0), (2, 128, 0), (8, 256, 0), (7, 256, 0), (3, 128, 0), (4, 256, 1)]
+# (octs_per_group, threads, no_bricks, persistent, brick_waves): per-oct
+# workgroup shapes, bricks off, and the brick kernel's register budgets
+TREE_CANDIDATES = [(4, 256, 0, 0, 0), (2, 128, 0, 0, 0), (8, 256, 0, 0, 0), (7, 256, 0, 0, 0), (3, 128, 0, 0, 0),
+                   (4, 256, 1, 0, 0)]
+BRICK_WAVES = {api.RG_FP64: (2, 3), api.RG_MIXED: (3, 4)}
+
+
+def tree_candidates(form):
+    out = list(TREE_CANDIDATES)
+    for w in BRICK_WAVES[form]:
+        out.append((4, 256, 0, 0, w))
+    return out
+
+
 # (octs_per_group, threads, no_bricks, persistent)
 BATCH_CANDIDATES = [(g, 256, nb, p) for g in (2, 4, 8) for nb in (0, 1) for p in (0, 1)]
 
@@ -83,7 +95,7 @@ def tree_signature(D):
     return "n%d_l%d-%d_b%d" % (_bucket(D.n), D.lmin, D.lmax, _bucket(512 * bricks + 1))
 
 
-def tune_tree(D, u, gamma, form, reps=5, use_cache=True, candidates=TREE_CANDIDATES):
+def tune_tree(D, u, gamma, form, reps=5, use_cache=True, candidates=None):
     """Fastest tuning for the update of every level of tree D (state u, key
     order).  Returns (tuning tuple, {candidate: ms})."""
     key = "tree|%s|%s|%s" % (_device(), "fp64" if form == api.RG_FP64 else "mixed", tree_signature(D))
@@ -91,6 +103,7 @@ def tune_tree(D, u, gamma, form, reps=5, use_cache=True, candidates=TREE_CANDIDA
         hit = _load().get(key)
         if hit:
             return tuple(hit["best"]), {}
+    candidates = candidates or tree_candidates(form)
     dt = api.cfl_dt(u, D.son_mask, D.level_begin, D.lmin, D.lmax, gamma, 0.8)
     out = torch.empty_like(u)
     times = {}

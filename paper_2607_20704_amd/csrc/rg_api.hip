@@ -107,21 +107,36 @@ rg_status rg_step(const rg_tree *t, const double *d_uold, double *d_unew, double
     RG_REQUIRE(t->n_oct > 0 && t->lmin >= 1 && t->lmax >= t->lmin && t->lmax <= RG_MAX_LEVEL, "bad tree");
     RG_REQUIRE(t->level_begin[t->lmin] == 0 && t->level_begin[t->lmax + 1] == t->n_oct, "bad level ranges");
     RG_REQUIRE(t->lmin == t->lmax || t->d_corr, "a multilevel tree needs a correction buffer");
-    if (flags) RG_TRY(rg_prepare_tree(t, flags, stream));
-    RG_TRY(rg_cfl_dt(d_uold, t->d_son_mask, t->level_begin, t->lmin, t->lmax, gamma, cfl, d_dt, stream));
+    RG_REQUIRE((flags & ~(RG_STEP_REBUILD | RG_STEP_REKEY | RG_STEP_CHAIN_DT)) == 0, "unknown flags %u", flags);
+    RG_REQUIRE(gamma > 1 && cfl > 0, "bad gamma or cfl");
+    hipStream_t s = as_stream(stream);
+    const unsigned prep = flags & (RG_STEP_REBUILD | RG_STEP_REKEY);
+    if (prep) RG_TRY(rg_prepare_tree(t, prep, stream));
+    const bool chain = (flags & RG_STEP_CHAIN_DT) != 0;
+    double *dt_next = chain ? d_dt + 1 : nullptr;
+    if (chain) {
+        RG_TRY(set_u64(reinterpret_cast<uint64_t *>(dt_next), 0x7ff0000000000000ull, s));
+    } else {
+        RG_TRY(rg_cfl_dt(d_uold, t->d_son_mask, t->level_begin, t->lmin, t->lmax, gamma, cfl, d_dt, stream));
+    }
     const int64_t corr_base = t->level_begin[t->lmin + 1];
     for (int l = t->lmin; l <= t->lmax; ++l) {
         const int64_t b = t->level_begin[l], e = t->level_begin[l + 1];
         if (e == b) continue;
         if (t->sched) {
-            RG_TRY(rg_hydro_step_scheduled(t, t->sched, l, d_dt, gamma, d_uold, d_unew, form, tune, stream));
+            RG_TRY(rg_hydro_step_scheduled(t, t->sched, l, d_dt, gamma, d_uold, d_unew, cfl, dt_next, form, tune,
+                                           stream));
         } else {
             RG_TRY(rg_hydro_step_level(ldexp(1.0, -l), d_dt, gamma, d_uold, d_unew, t->d_nbr27, t->d_son_mask, b, e,
-                                       l > t->lmin ? t->d_corr : nullptr, corr_base, form, tune, stream));
+                                       l > t->lmin ? t->d_corr : nullptr, corr_base, cfl, dt_next, form, tune,
+                                       stream));
         }
     }
     if (t->lmax > t->lmin) {
         RG_TRY(rg_apply_coarse_corrections(d_unew, t->d_corr, corr_base, t->d_nbr27, corr_base, t->n_oct, stream));
+        if (chain)
+            RG_TRY(rg_cfl_dt_corrected(d_unew, t->d_nbr27, t->level_begin, t->lmin, t->lmax, gamma, cfl, dt_next,
+                                       stream));
         for (int l = t->lmax; l > t->lmin; --l)
             RG_TRY(rg_restrict_level(d_unew, t->d_father_cell, t->level_begin[l], t->level_begin[l + 1], stream));
     }

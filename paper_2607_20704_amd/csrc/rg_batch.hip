@@ -161,6 +161,8 @@ __global__ __launch_bounds__(BT) void k_batch_bricks(const BTree *__restrict__ t
         a.dx = ldexp(1.0, -(I.a >> 2));
         a.gamma = T.gamma;
         a.outflow = T.bc == RG_BC_OUTFLOW;
+        a.cfl = T.cfl;
+        a.dt_next = nullptr;
         brick_body<R>(a, T.list[I.first], I.first, S);
         __syncthreads();
     }
@@ -189,6 +191,8 @@ __global__ __launch_bounds__(kT) void k_batch_octs(const BTree *__restrict__ tre
         a.dt = dt + I.tree;
         a.dx = ldexp(1.0, -level);
         a.gamma = T.gamma;
+        a.cfl = T.cfl;
+        a.dt_next = nullptr;
         hydro_group<R, G, kT>(a, I.first, static_cast<int>(I.count), S);
         __syncthreads();
     }

@@ -27,8 +27,10 @@
 namespace rg {
 namespace {
 
-template <typename R>
-__global__ __launch_bounds__(BT) void k_hydro_brick(BrickArgs a)
+// W: waves per SIMD the register allocation is sized for (the compiler
+// spills beyond it); every W gives the same bits
+template <typename R, int W>
+__global__ __launch_bounds__(BT, W) void k_hydro_brick(BrickArgs a)
 {
     __shared__ BrickSmem<R> S;
     // consecutive bricks on one XCD: workgroups are dealt round-robin to the
@@ -43,7 +45,7 @@ __global__ __launch_bounds__(BT) void k_hydro_brick(BrickArgs a)
 
 rg_status hydro_bricks(const double *uold, double *unew, const int32_t *nbr27, const uint32_t *son,
                        const uint64_t *keys, const int32_t *bricks, int64_t nbricks, const double *dt, double dx,
-                       double gamma, int outflow, int form, hipStream_t s)
+                       double gamma, int outflow, int form, double cfl, double *dt_next, int waves, hipStream_t s)
 {
     if (nbricks <= 0) return RG_OK;
     BrickArgs a;
@@ -58,11 +60,24 @@ rg_status hydro_bricks(const double *uold, double *unew, const int32_t *nbr27, c
     a.dx = dx;
     a.gamma = gamma;
     a.outflow = outflow;
+    a.cfl = cfl;
+    a.dt_next = reinterpret_cast<unsigned long long *>(dt_next);
     const unsigned grid = static_cast<unsigned>(8 * ((nbricks + 7) / 8));
-    if (form == RG_FP64)
-        k_hydro_brick<double><<<grid, BT, 0, s>>>(a);
-    else
-        k_hydro_brick<float><<<grid, BT, 0, s>>>(a);
+    if (form == RG_FP64) {
+        if (waves == 3)
+            k_hydro_brick<double, 3><<<grid, BT, 0, s>>>(a);
+        else if (waves == 0 || waves == 2)
+            k_hydro_brick<double, 2><<<grid, BT, 0, s>>>(a);
+        else
+            return fail(RG_ENOTSUP, "no FP64 brick kernel for %d waves per SIMD", waves);
+    } else {
+        if (waves == 4)
+            k_hydro_brick<float, 4><<<grid, BT, 0, s>>>(a);
+        else if (waves == 0 || waves == 3)
+            k_hydro_brick<float, 3><<<grid, BT, 0, s>>>(a);
+        else
+            return fail(RG_ENOTSUP, "no mixed brick kernel for %d waves per SIMD", waves);
+    }
     return launch_status("hydro bricks");
 }
 

@@ -29,6 +29,8 @@ struct BrickArgs {
     double dx;
     double gamma;
     int outflow;               // clamp positions outside the domain (zero gradient)
+    double cfl;
+    unsigned long long *dt_next;   // if set: CFL limit of the new state folded in (bits of a positive double)
 };
 
 template <typename R> struct BrickSmem {
@@ -36,19 +38,23 @@ template <typename R> struct BrickSmem {
     uint8_t son[HS * HS * HS];      // son mask of same-level slot octs, 0 otherwise
     R w[PW * PW][NV];               // primitive variables of the current plane
     R hw[3][4 * BC][NV];            // primitive variables of the reconstructed ghost ring, planes r-1, r, r+1
+    // Face states, written by the reconstruction; each is read by exactly
+    // one thread in the flux pass, which then overwrites it with the flux of
+    // that face, so states and fluxes share the storage without a barrier.
     union {
-        struct {                    // face states, live from reconstruction to flux evaluation
+        struct {
             R sxp[BC + 1][BC][NV];  // [x][y]: x+ state of cell x-1 (x = 0..16 -> cells -1..15)
             R syp[BC + 1][BC][NV];  // [y][x]: y+ state of cell y-1
             R sxm_hi[BC][NV];       // x- state of the ghost cell x = 16
             R sym_hi[BC][NV];
         } st;
-        struct {                    // fluxes F (zero on faces touching split cells), live until the update
-            R fx[BC + 1][BC][NV];   // [x][y]: face (x-1 | x)
-            R fy[BC + 1][BC][NV];   // [y][x]: face (y-1 | y)
+        struct {                    // fluxes F (zero on faces touching split cells)
+            R fx[BC + 1][BC][NV];   // [x][y]: face (x-1 | x), in place of sxp[x][y]
+            R fy[BC + 1][BC][NV];   // [y][x]: face (y-1 | y), in place of syp[y][x]
         } fl;
-    } u;
+    } u_;
     uint8_t split[PW * PW];         // split flag of the current plane's cells
+    double red[BT / 64];            // block minimum of the fused CFL limit
 };
 
 struct Geom {
@@ -196,6 +202,11 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
     // position: the conserved variables it needs next
     R Wm[NV], W0[NV], Wp[NV];
     bool sp_prev = false, sp_cur, sp_next;
+    // fused CFL limit: split flags of plane rz-2 and the in-plane neighbours
+    // of plane rz-1 decide whether the cell written next is a leaf that no
+    // coarse-fine correction will change
+    bool sp_prev2 = false, nxy_prev = false, nxy_cur = false;
+    double dt_min = __longlong_as_double(0x7ff0000000000000ll);
     {
         double U[NV];
         bool sdummy;
@@ -259,16 +270,16 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
                            S.hw[(rz + 2) % 3][lane], S.hw[(rz + 4) % 3][lane], h, gam, dW, Wq);
             if (hq == 0) {            // x = -1: its x+ state feeds face (-1|0)
                 face_state<R>(Wq, dW[0], true, st);
-                copy5(S.u.st.sxp[0][hk], st);
+                copy5(S.u_.st.sxp[0][hk], st);
             } else if (hq == 1) {     // x = 16: x- state feeds face (15|16)
                 face_state<R>(Wq, dW[0], false, st);
-                copy5(S.u.st.sxm_hi[hk], st);
+                copy5(S.u_.st.sxm_hi[hk], st);
             } else if (hq == 2) {     // y = -1
                 face_state<R>(Wq, dW[1], true, st);
-                copy5(S.u.st.syp[0][hk], st);
+                copy5(S.u_.st.syp[0][hk], st);
             } else {                  // y = 16
                 face_state<R>(Wq, dW[1], false, st);
-                copy5(S.u.st.sym_hi[hk], st);
+                copy5(S.u_.st.sym_hi[hk], st);
             }
         }
         R sxm[NV], sym[NV];
@@ -277,12 +288,13 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
         {
             R dW[3][NV], Wq[NV], st[NV], szm[NV];
             const int c = (x + 2) + PW * (y + 2);
+            nxy_cur = S.split[c - 1] || S.split[c + 1] || S.split[c - PW] || S.split[c + PW];
             reconstruct<R>(W0, S.w[c - 1], S.w[c + 1], S.w[c - PW], S.w[c + PW], Wm, Wp, h, gam, dW, Wq);
             if (inner) {
                 face_state<R>(Wq, dW[0], true, st);
-                copy5(S.u.st.sxp[x + 1][y], st);
+                copy5(S.u_.st.sxp[x + 1][y], st);
                 face_state<R>(Wq, dW[1], true, st);
-                copy5(S.u.st.syp[y + 1][x], st);
+                copy5(S.u_.st.syp[y + 1][x], st);
                 face_state<R>(Wq, dW[0], false, sxm);
                 face_state<R>(Wq, dW[1], false, sym);
             }
@@ -292,31 +304,25 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
         }
         __syncthreads();
 
-        // 4a. fluxes into registers: the own low x and y faces, and the
-        //     x = 16 / y = 16 faces on the extra lanes
-        R Fx[NV], Fy[NV], Fe[NV];
+        // 4. fluxes of the own low x and y faces, and of the x = 16 / y = 16
+        //    faces on the extra lanes, each written over the face state it
+        //    was computed from
         if (inner) {
-            face_F<R>(S.u.st.sxp[x][y], sxm, 0, gam, g1, S.split[(x + 1) + PW * (y + 2)] || sp_cur, Fx);
-            face_F<R>(S.u.st.syp[y][x], sym, 1, gam, g1, S.split[(x + 2) + PW * (y + 1)] || sp_cur, Fy);
+            R F[NV];
+            face_F<R>(S.u_.st.sxp[x][y], sxm, 0, gam, g1, S.split[(x + 1) + PW * (y + 2)] || sp_cur, F);
+            copy5(S.u_.fl.fx[x][y], F);
+            face_F<R>(S.u_.st.syp[y][x], sym, 1, gam, g1, S.split[(x + 2) + PW * (y + 1)] || sp_cur, F);
+            copy5(S.u_.fl.fy[y][x], F);
             if (extra_faces) {
                 if (lane < BC) {
                     const bool z2 = S.split[(BC + 1) + PW * (hk + 2)] || S.split[(BC + 2) + PW * (hk + 2)];
-                    face_F<R>(S.u.st.sxp[BC][hk], S.u.st.sxm_hi[hk], 0, gam, g1, z2, Fe);
+                    face_F<R>(S.u_.st.sxp[BC][hk], S.u_.st.sxm_hi[hk], 0, gam, g1, z2, F);
+                    copy5(S.u_.fl.fx[BC][hk], F);
                 } else {
                     const bool z2 = S.split[(hk + 2) + PW * (BC + 1)] || S.split[(hk + 2) + PW * (BC + 2)];
-                    face_F<R>(S.u.st.syp[BC][hk], S.u.st.sym_hi[hk], 1, gam, g1, z2, Fe);
+                    face_F<R>(S.u_.st.syp[BC][hk], S.u_.st.sym_hi[hk], 1, gam, g1, z2, F);
+                    copy5(S.u_.fl.fy[BC][hk], F);
                 }
-            }
-        }
-        __syncthreads();
-
-        // 4b. publish the x/y fluxes (over the face states)
-        if (inner) {
-            copy5(S.u.fl.fx[x][y], Fx);
-            copy5(S.u.fl.fy[y][x], Fy);
-            if (extra_faces) {
-                if (lane < BC) copy5(S.u.fl.fx[BC][hk], Fe);
-                else copy5(S.u.fl.fy[BC][hk], Fe);
             }
         }
         __syncthreads();
@@ -330,6 +336,14 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
             const int64_t cell = source_cell(S, g, x, y, rz - 1, sdummy);
 #pragma unroll
             for (int v = 0; v < NV; ++v) a.unew[NV * cell + v] = out[v];
+            if (a.dt_next && !sp_prev && !(nxy_prev || sp_prev2 || sp_cur)) {
+                double Wn[NV];
+                prim64(out, a.gamma, Wn);
+                const double cs = sqrt((a.gamma * Wn[4]) / Wn[0]);
+                const double sp = ((fabs(Wn[1]) + fabs(Wn[2])) + fabs(Wn[3])) + 3.0 * cs;
+                const double cd = a.cfl * (a.dx / sp);
+                dt_min = cd < dt_min ? cd : dt_min;
+            }
         }
         if (inner) {
             double Ucur[NV];
@@ -337,10 +351,10 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
             load_u(a.uold, source_cell(S, g, x, y, rz, sdummy), Ucur);
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const double gxm = static_cast<double>(S.u.fl.fx[x][y][v]) * r;
-                const double gxp = static_cast<double>(S.u.fl.fx[x + 1][y][v]) * r;
-                const double gym = static_cast<double>(S.u.fl.fy[y][x][v]) * r;
-                const double gyp = static_cast<double>(S.u.fl.fy[y + 1][x][v]) * r;
+                const double gxm = static_cast<double>(S.u_.fl.fx[x][y][v]) * r;
+                const double gxp = static_cast<double>(S.u_.fl.fx[x + 1][y][v]) * r;
+                const double gym = static_cast<double>(S.u_.fl.fy[y][x][v]) * r;
+                const double gyp = static_cast<double>(S.u_.fl.fy[y + 1][x][v]) * r;
                 acc_prev[v] = (Ucur[v] + (gxm - gxp)) + (gym - gyp);
             }
         }
@@ -351,8 +365,25 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
             Wm[v] = W0[v];
             W0[v] = Wp[v];
         }
+        sp_prev2 = sp_prev;
         sp_prev = sp_cur;
         sp_cur = sp_next;
+        nxy_prev = nxy_cur;
+    }
+    if (a.dt_next) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double o = __shfl_xor(dt_min, off, 64);
+            dt_min = o < dt_min ? o : dt_min;
+        }
+        if (lane == 0) S.red[wave] = dt_min;
+        __syncthreads();
+        if (tid == 0) {
+            double m = S.red[0];
+            for (int k = 1; k < BT / 64; ++k) m = S.red[k] < m ? S.red[k] : m;
+            if (m < __longlong_as_double(0x7ff0000000000000ll))
+                atomicMin(a.dt_next, static_cast<unsigned long long>(__double_as_longlong(m)));
+        }
     }
 }
 

@@ -108,6 +108,50 @@ __global__ void k_coarse_corr(double *__restrict__ unew, const double *__restric
     unew[NV * C + v] = unew[NV * C + v] + corr[30 * (o - corr_base) + NV * side + v];
 }
 
+// CFL limit of the coarse cells that receive coarse-fine corrections: every
+// coarse face neighbour of an oct above the coarsest level
+__global__ __launch_bounds__(256) void k_cfl_dt_corrected(DtArgs a, const int32_t *__restrict__ nbr27, int64_t ob,
+                                                          int64_t oe)
+{
+    double best = __longlong_as_double(0x7ff0000000000000ll);
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < (oe - ob) * 6; t += stride) {
+        const int64_t o = ob + t / 6;
+        const int side = static_cast<int>(t % 6);
+        const int ax = side >> 1, hi = side & 1;
+        const int32_t e = nbr27[27 * o + nslot(ax == 0 ? (hi ? 1 : -1) : 0, ax == 1 ? (hi ? 1 : -1) : 0,
+                                               ax == 2 ? (hi ? 1 : -1) : 0)];
+        if (!(e < 0 && e != RG_NBR_OUTSIDE)) continue;
+        const int64_t C = -1 - int64_t(e);
+        int l = a.lmin;
+        while (l < a.lmax && o >= a.begin[l + 1]) ++l;
+        const double dx = ldexp(1.0, -(l - 1));
+        double U[NV], W[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) U[v] = a.u[NV * C + v];
+        prim64(U, a.gamma, W);
+        const double cs = sqrt((a.gamma * W[4]) / W[0]);
+        const double sp = ((fabs(W[1]) + fabs(W[2])) + fabs(W[3])) + 3.0 * cs;
+        const double cd = a.cfl * (dx / sp);
+        if (cd < best) best = cd;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        double o = __shfl_xor(best, off, 64);
+        best = o < best ? o : best;
+    }
+    __shared__ double s_min[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) s_min[wave] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = s_min[0];
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = s_min[k] < m ? s_min[k] : m;
+        if (m < __longlong_as_double(0x7ff0000000000000ll))
+            atomicMin(a.dt_bits, static_cast<unsigned long long>(__double_as_longlong(m)));
+    }
+}
+
 __global__ void k_restrict(double *__restrict__ u, const int32_t *__restrict__ father, int64_t ob, int64_t oe)
 {
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -155,7 +199,8 @@ rg_status hydro_level(const LevelArgs &a, int form, const rg_tuning *tune, hipSt
 // octs list[0..count) (or first..first+count when list is null)
 rg_status hydro_level_list(const double *uold, double *unew, const int32_t *nbr27, const uint32_t *son,
                            const int32_t *list, int64_t count, double *corr, int64_t corr_base, const double *dt,
-                           double dx, double gamma, int form, const rg_tuning *tune, hipStream_t s, int64_t first)
+                           double dx, double gamma, int form, const rg_tuning *tune, double cfl, double *dt_next,
+                           hipStream_t s, int64_t first)
 {
     if (count <= 0) return RG_OK;
     LevelArgs a;
@@ -171,6 +216,8 @@ rg_status hydro_level_list(const double *uold, double *unew, const int32_t *nbr2
     a.dt = dt;
     a.dx = dx;
     a.gamma = gamma;
+    a.cfl = cfl;
+    a.dt_next = reinterpret_cast<unsigned long long *>(dt_next);
     return hydro_level(a, form, tune, s);
 }
 
@@ -184,7 +231,8 @@ size_t rg_corr_workspace_bytes(int64_t n_octs) { return static_cast<size_t>(n_oc
 
 rg_status rg_hydro_step_level(double dx, const double *d_dt, double gamma, const double *d_uold, double *d_unew,
                               const int32_t *d_nbr27, const uint32_t *d_son_mask, int64_t oct_begin, int64_t oct_end,
-                              double *d_corr, int64_t corr_base, int form, const rg_tuning *tune, void *stream)
+                              double *d_corr, int64_t corr_base, double cfl, double *d_dt_next, int form,
+                              const rg_tuning *tune, void *stream)
 {
     RG_REQUIRE(oct_begin >= 0 && oct_end >= oct_begin && oct_end <= (int64_t(1) << 28), "bad oct range");
     if (oct_end == oct_begin) return RG_OK;
@@ -194,6 +242,7 @@ rg_status rg_hydro_step_level(double dx, const double *d_dt, double gamma, const
     RG_REQUIRE(form == RG_FP64 || form == RG_MIXED, "bad form %d", form);
     RG_REQUIRE(dx > 0 && gamma > 1, "bad dx or gamma");
     RG_REQUIRE(!d_corr || corr_base <= oct_begin, "corr_base beyond the oct range");
+    RG_REQUIRE(!d_dt_next || (cfl > 0 && aligned(d_dt_next, 8)), "bad cfl or misaligned dt_next");
     LevelArgs a;
     a.list = nullptr;
     a.uold = d_uold;
@@ -207,6 +256,8 @@ rg_status rg_hydro_step_level(double dx, const double *d_dt, double gamma, const
     a.dt = d_dt;
     a.dx = dx;
     a.gamma = gamma;
+    a.cfl = cfl;
+    a.dt_next = reinterpret_cast<unsigned long long *>(d_dt_next);
     return hydro_level(a, form, tune, as_stream(stream));
 }
 
@@ -264,6 +315,31 @@ rg_status rg_cfl_dt(const double *d_u, const uint32_t *d_son_mask, const int64_t
     const unsigned blocks = grid_for(a.n_cell, 256);
     k_cfl_dt<<<blocks < 2048 ? blocks : 2048, 256, 0, s>>>(a);
     return launch_status("rg_cfl_dt");
+}
+
+rg_status rg_cfl_dt_corrected(const double *d_u, const int32_t *d_nbr27, const int64_t *h_level_begin, int lmin,
+                              int lmax, double gamma, double cfl, double *d_dt, void *stream)
+{
+    RG_REQUIRE(d_u && d_nbr27 && h_level_begin && d_dt, "null pointer");
+    RG_REQUIRE(lmin >= 1 && lmax >= lmin && lmax <= RG_MAX_LEVEL, "bad level range");
+    RG_REQUIRE(gamma > 1 && cfl > 0, "bad gamma or cfl");
+    RG_REQUIRE(aligned(d_dt, 8), "misaligned dt");
+    if (lmax == lmin) return RG_OK;
+    DtArgs a;
+    a.u = d_u;
+    a.son = nullptr;
+    for (int l = 0; l < RG_MAX_LEVEL + 2; ++l) a.begin[l] = h_level_begin[l];
+    a.lmin = lmin;
+    a.lmax = lmax;
+    a.gamma = gamma;
+    a.cfl = cfl;
+    a.n_cell = 0;
+    a.dt_bits = reinterpret_cast<unsigned long long *>(d_dt);
+    const int64_t ob = h_level_begin[lmin + 1], oe = h_level_begin[lmax + 1];
+    if (oe <= ob) return RG_OK;
+    const unsigned blocks = grid_for((oe - ob) * 6, 256);
+    k_cfl_dt_corrected<<<blocks < 2048 ? blocks : 2048, 256, 0, as_stream(stream)>>>(a, d_nbr27, ob, oe);
+    return launch_status("rg_cfl_dt_corrected");
 }
 
 }  // extern "C"

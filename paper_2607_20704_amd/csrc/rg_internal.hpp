@@ -297,5 +297,7 @@ rg_status neighbours_scheduled(void *d_ws, const uint64_t *d_keys, int64_t n, in
 rg_status sort_keys_bits(const uint64_t *d_keys_in, int64_t n, uint64_t *d_keys_out, int32_t *d_perm, void *d_ws,
                          size_t ws_bytes, int end_bit, hipStream_t s);
 rg_status fill_u64(uint64_t *d, int64_t n, uint64_t v, hipStream_t s);
+// one 64-bit store by a kernel (graph-capture safe, unlike a memset node)
+inline rg_status set_u64(uint64_t *d, uint64_t v, hipStream_t s) { return fill_u64(d, 1, v, s); }
 
 }  // namespace rg

@@ -99,6 +99,8 @@ struct LevelArgs {
     const double *dt;     // device scalar
     double dx;
     double gamma;
+    double cfl;
+    unsigned long long *dt_next;   // if set: CFL limit of the new state folded in (bits of a positive double)
 };
 
 template <typename R, int G> struct Smem {
@@ -109,6 +111,7 @@ template <typename R, int G> struct Smem {
     R w[G][80][NV];             // primitive variables of the stencil cells
     R fs[G][36][2][NV];         // face states: [face][0] left of the face, [1] right
     double g[G][36][NV];        // G = F dt/dx per face
+    double red[8];              // block minimum of the fused CFL limit (one per wave)
 };
 
 template <typename R, int G, int NT>
@@ -254,7 +257,9 @@ __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, i
         const double gxm = S.g[g][face_id(0, ix, iy, iz)][v], gxp = S.g[g][face_id(0, ix + 1, iy, iz)][v];
         const double gym = S.g[g][face_id(1, iy, ix, iz)][v], gyp = S.g[g][face_id(1, iy + 1, ix, iz)][v];
         const double gzm = S.g[g][face_id(2, iz, ix, iy)][v], gzp = S.g[g][face_id(2, iz + 1, ix, iy)][v];
-        a.unew[8 * NV * S.oct[g] + k] = ((S.u[g][cidx][v] + (gxm - gxp)) + (gym - gyp)) + (gzm - gzp);
+        const double un = ((S.u[g][cidx][v] + (gxm - gxp)) + (gym - gyp)) + (gzm - gzp);
+        a.unew[8 * NV * S.oct[g] + k] = un;
+        S.u[g][cidx][v] = un;
     }
 
     // E: flux owed to coarse neighbours
@@ -272,6 +277,51 @@ __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, i
                                (S.g[g][face_id(ax, c, 0, 1)][v] + S.g[g][face_id(ax, c, 1, 1)][v]);
             const double d = 0.125 * sum;
             a.corr[30 * (S.oct[g] - a.corr_base) + k] = hi ? d : -d;
+        }
+    }
+
+    // F: fused CFL limit of the new state over the group's leaf cells that
+    // no coarse-fine correction will change (no split face neighbour)
+    if (a.dt_next) {
+        __syncthreads();
+        double best = __longlong_as_double(0x7ff0000000000000ll);
+        for (int it = tid; it < G * 8; it += NT) {
+            const int g = it >> 3, cidx = it & 7;
+            if (g >= count) continue;
+            if ((S.sm[g][0] >> cidx) & 1u) continue;
+            const int p[3] = {cidx & 1, (cidx >> 1) & 1, cidx >> 2};
+            bool touch = false;
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                    int px[3] = {p[0], p[1], p[2]};
+                    px[ax] += side ? 1 : -1;
+                    const int bit = (px[0] & 1) + 2 * (px[1] & 1) + 4 * (px[2] & 1);
+                    const uint32_t m = px[ax] < 0 ? S.sm[g][1 + 2 * ax] : (px[ax] > 1 ? S.sm[g][2 + 2 * ax] : S.sm[g][0]);
+                    touch = touch || ((m >> bit) & 1u);
+                }
+            }
+            if (touch) continue;
+            double W[NV];
+            prim64(S.u[g][cidx], a.gamma, W);
+            const double cs = sqrt((a.gamma * W[4]) / W[0]);
+            const double sp = ((fabs(W[1]) + fabs(W[2])) + fabs(W[3])) + 3.0 * cs;
+            const double cd = a.cfl * (a.dx / sp);
+            best = cd < best ? cd : best;
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double o = __shfl_xor(best, off, 64);
+            best = o < best ? o : best;
+        }
+        if ((tid & 63) == 0) S.red[tid >> 6] = best;
+        __syncthreads();
+        if (tid == 0) {
+            double m = S.red[0];
+            for (int k = 1; k < NT / 64; ++k) m = S.red[k] < m ? S.red[k] : m;
+            if (m < __longlong_as_double(0x7ff0000000000000ll))
+                atomicMin(a.dt_next, static_cast<unsigned long long>(__double_as_longlong(m)));
         }
     }
 }

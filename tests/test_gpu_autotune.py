@@ -21,7 +21,8 @@ def test_tune_tree_and_cache(tmp_path, monkeypatch):
     u = D.to_key_order(w.u.reshape(-1, 5))
     best, times = autotune.tune_tree(D, u, w.gamma, api.RG_MIXED, reps=2)
     say("tree tuning", best, times)
-    assert best in autotune.TREE_CANDIDATES and set(times) == set(autotune.TREE_CANDIDATES)
+    cands = autotune.tree_candidates(api.RG_MIXED)
+    assert best in cands and set(times) == set(cands)
     entry = json.loads(cache.read_text())
     assert len(entry) == 1 and list(entry.values())[0]["best"] == list(best)
     again, t2 = autotune.tune_tree(D, u, w.gamma, api.RG_MIXED)

@@ -33,7 +33,9 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     lib = L.lib()
-    assert lib.rg_abi_version() == 1
+    with open(os.path.join(ROOT, "include", "rg.h")) as f:
+        declared = int(re.search(r"#define RG_ABI_VERSION (\d+)", f.read()).group(1))
+    assert lib.rg_abi_version() == declared
     assert lib.rg_status_string(L.RG_EUNGRADED) == b"RG_EUNGRADED"
     assert lib.rg_status_string(99) == b"RG_UNKNOWN"
 
@@ -99,9 +101,14 @@ def test_argument_errors_are_reported_without_a_device():
     fake = ctypes.c_void_p(256)
     assert lib.rg_hash_build(fake, 100, fake, 64, None) == L.RG_EFULL
     assert lib.rg_build_neighbours(fake, fake, 10, 1, 7, fake, fake, fake, None) == L.RG_EINVAL
-    assert lib.rg_hydro_step_level(1.0, None, 1.4, None, None, None, None, 0, 10, None, 0, 0, None, None) == L.RG_EINVAL
-    assert lib.rg_hydro_step_level(1.0, fake, 1.4, fake, fake, fake, fake, 0, 10, None, 0, 5, None, None) \
-        == L.RG_EINVAL
+    assert lib.rg_hydro_step_level(1.0, None, 1.4, None, None, None, None, 0, 10, None, 0, 0.8, None, 0, None,
+                                   None) == L.RG_EINVAL
+    assert lib.rg_hydro_step_level(1.0, fake, 1.4, fake, fake, fake, fake, 0, 10, None, 0, 0.8, None, 5, None,
+                                   None) == L.RG_EINVAL
+    # a fused time step needs a positive CFL number
+    assert lib.rg_hydro_step_level(1.0, fake, 1.4, fake, ctypes.c_void_p(512), fake, fake, 0, 10, None, 0, 0.0,
+                                   fake, 0, None, None) == L.RG_EINVAL
+    assert lib.rg_cfl_dt_corrected(None, None, None, 1, 2, 1.4, 0.8, None, None) == L.RG_EINVAL
     lb = (ctypes.c_int64 * 23)()
     assert lib.rg_cfl_dt(fake, fake, lb, 3, 2, 1.4, 0.8, fake, None) == L.RG_EINVAL
     assert lib.rg_step(None, None, None, 1.4, 0.8, 0, 0, None, None, None) == L.RG_EINVAL

@@ -342,6 +342,7 @@ def main():
                              "+ corrected cells' dt + restriction)"}
     out["roofline"] = s["roofline"]
     out["hydro_only_cell_updates_per_s"] = s["hydro_only_cell_updates_per_s"]
+    out["rekey_ms"] = s["rekey_ms"]
     out["tune"] = s["tune"]
     out["ns_per_cell"] = s["ns_per_cell"]
     for f in forms:

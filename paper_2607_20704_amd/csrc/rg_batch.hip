@@ -141,7 +141,7 @@ __device__ __forceinline__ ItemRange xcd_item(int64_t nitems)
 // With P the grid is persistent and loops over the items; without, each
 // workgroup takes one item (no loop-carried registers).
 template <typename R, bool P>
-__global__ __launch_bounds__(BT) void k_batch_bricks(const BTree *__restrict__ trees, const Item *__restrict__ items,
+__global__ __launch_bounds__(BT, sizeof(R) == 8 ? 2 : 4) void k_batch_bricks(const BTree *__restrict__ trees, const Item *__restrict__ items,
                                                      int64_t nitems, int parity, const double *dt)
 {
     __shared__ BrickSmem<R> S;
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(BT) void k_batch_bricks(const BTree *__restrict__ t
 }
 
 template <typename R, int G, bool P>
-__global__ __launch_bounds__(kT) void k_batch_octs(const BTree *__restrict__ trees, const Item *__restrict__ items,
+__global__ __launch_bounds__(kT, sizeof(R) == 8 ? 4 : 6) void k_batch_octs(const BTree *__restrict__ trees, const Item *__restrict__ items,
                                                    int64_t nitems, int parity, const double *dt)
 {
     __shared__ Smem<R, G> S;

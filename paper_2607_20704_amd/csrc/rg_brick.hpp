@@ -54,7 +54,7 @@ template <typename R> struct BrickSmem {
         } fl;
     } u_;
     uint8_t split[PW * PW];         // split flag of the current plane's cells
-    double red[BT / 64];            // block minimum of the fused CFL limit
+    double red[8];                  // block minimum of the fused CFL limit, one per wave
 };
 
 struct Geom {
@@ -139,8 +139,13 @@ __device__ __forceinline__ void face_F(const R *L, const R *Rt, int dir, R gamma
     for (int v = 0; v < NV; ++v) F[v] = zero ? R(0) : F[v];
 }
 
-// one brick (first oct `base`, rotation index b for the ghost-ring roles)
-// by one workgroup of BT threads
+// One brick (first oct `base`) by one workgroup of BT threads, each owning
+// an interior column.  The ghost ring (loads of the two-cell halo,
+// reconstruction of the face layer x = -1, 16 / y = -1, 16, the fluxes of
+// the faces x = 16 / y = 16) is shared out to whole waves, with the roles
+// rotated by the brick index b so that the extra work lands on a different
+// SIMD from brick to brick.  (A fifth wave holding the whole ring measured
+// slower: the column waves wait for it at every barrier.)
 template <typename R>
 __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int64_t b, BrickSmem<R> &S)
 {
@@ -191,10 +196,12 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
     const int x = tid & 15, y = tid >> 4;
     const int wave = tid >> 6, lane = tid & 63;
     const int ew = static_cast<int>(b & 3);         // wave holding the reconstructed ghost ring this brick
-    const int kind = wave == ew ? 1 : (wave == ((ew + 1) & 3) ? 2 : (wave == ((ew + 2) & 3) && lane < 4 ? 3 : 0));
-    int hx = 0, hy = 0;
-    if (kind) ring_pos(kind, lane, hx, hy);
+    const bool do_face = wave == ew;
+    const bool do_outer = wave == ((ew + 1) & 3);
+    const bool do_corner = wave == ((ew + 2) & 3) && lane < 4;
     const bool extra_faces = wave == ((ew + 1) & 3) && lane < 2 * BC;   // faces x = 16 and y = 16
+    int hx = 0, hy = 0;
+    ring_pos(1, lane, hx, hy);      // face layer position of this lane
     const int hq = lane >> 4, hk = lane & 15;
 
     // own column: primitive variables of planes r-1, r, r+1 and conserved
@@ -210,11 +217,14 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
     {
         double U[NV];
         bool sdummy;
-        load_u(a.uold, source_cell(S, g, x, y, -2, sdummy), U);
-        to_prim(U, a.gamma, Wm);
-        load_u(a.uold, source_cell(S, g, x, y, -1, sp_cur), U);
-        to_prim(U, a.gamma, W0);
-        if (kind == 1) {
+        sp_cur = false;
+        {
+            load_u(a.uold, source_cell(S, g, x, y, -2, sdummy), U);
+            to_prim(U, a.gamma, Wm);
+            load_u(a.uold, source_cell(S, g, x, y, -1, sp_cur), U);
+            to_prim(U, a.gamma, W0);
+        }
+        if (do_face) {
             load_u(a.uold, source_cell(S, g, hx, hy, -1, sdummy), U);
             R Wh[NV];
             to_prim(U, a.gamma, Wh);
@@ -233,10 +243,11 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
     for (int rz = -1; rz <= BC; ++rz) {
         const bool inner = rz >= 0 && rz < BC;      // plane with x/y faces
         double Un[NV];                               // conserved variables of plane rz+1, own column
+        sp_next = false;
         load_u(a.uold, source_cell(S, g, x, y, rz + 1, sp_next), Un);
         // 1. the reconstructed ghost ring: primitive variables of plane rz+1
         bool hsplit = false;
-        if (kind == 1) {
+        if (do_face) {
             if (rz + 1 <= BC) {
                 double U[NV];
                 R Wh[NV];
@@ -247,23 +258,37 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
             (void)source_cell(S, g, hx, hy, rz, hsplit);
         }
         // 2. plane rz into LDS: W and split flags
-        copy5(S.w[(x + 2) + PW * (y + 2)], W0);
-        S.split[(x + 2) + PW * (y + 2)] = sp_cur;
-        if (kind == 1) {
+        {
+            copy5(S.w[(x + 2) + PW * (y + 2)], W0);
+            S.split[(x + 2) + PW * (y + 2)] = sp_cur;
+        }
+        if (do_face) {
             copy5(S.w[(hx + 2) + PW * (hy + 2)], S.hw[(rz + 3) % 3][lane]);
             S.split[(hx + 2) + PW * (hy + 2)] = hsplit;
-        } else if (kind >= 2 && inner) {
+        }
+        if (do_outer && inner) {
             double U[NV];
             R Wr[NV];
-            load_u(a.uold, source_cell(S, g, hx, hy, rz, hsplit), U);
+            int ox, oy;
+            ring_pos(2, lane, ox, oy);
+            load_u(a.uold, source_cell(S, g, ox, oy, rz, hsplit), U);
             to_prim(U, a.gamma, Wr);
-            copy5(S.w[(hx + 2) + PW * (hy + 2)], Wr);
+            copy5(S.w[(ox + 2) + PW * (oy + 2)], Wr);
+        }
+        if (do_corner && inner) {
+            double U[NV];
+            R Wr[NV];
+            int cx, cy;
+            ring_pos(3, lane, cx, cy);
+            load_u(a.uold, source_cell(S, g, cx, cy, rz, hsplit), U);
+            to_prim(U, a.gamma, Wr);
+            copy5(S.w[(cx + 2) + PW * (cy + 2)], Wr);
         }
         __syncthreads();
 
         // 3. reconstruction of plane rz: the ghost ring first, then the own
         //    column, whose z face (rz-1 | rz) is evaluated at once
-        if (kind == 1 && inner) {
+        if (do_face && inner) {
             R dW[3][NV], Wq[NV], st[NV];
             const int c = (hx + 2) + PW * (hy + 2);
             reconstruct<R>(S.hw[(rz + 3) % 3][lane], S.w[c - 1], S.w[c + 1], S.w[c - PW], S.w[c + PW],
@@ -284,8 +309,8 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
         }
         R sxm[NV], sym[NV];
         double gz[NV];
-        to_prim(Un, a.gamma, Wp);
         {
+            to_prim(Un, a.gamma, Wp);
             R dW[3][NV], Wq[NV], st[NV], szm[NV];
             const int c = (x + 2) + PW * (y + 2);
             nxy_cur = S.split[c - 1] || S.split[c + 1] || S.split[c - PW] || S.split[c + PW];
@@ -309,10 +334,12 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
         //    was computed from
         if (inner) {
             R F[NV];
-            face_F<R>(S.u_.st.sxp[x][y], sxm, 0, gam, g1, S.split[(x + 1) + PW * (y + 2)] || sp_cur, F);
-            copy5(S.u_.fl.fx[x][y], F);
-            face_F<R>(S.u_.st.syp[y][x], sym, 1, gam, g1, S.split[(x + 2) + PW * (y + 1)] || sp_cur, F);
-            copy5(S.u_.fl.fy[y][x], F);
+            {
+                face_F<R>(S.u_.st.sxp[x][y], sxm, 0, gam, g1, S.split[(x + 1) + PW * (y + 2)] || sp_cur, F);
+                copy5(S.u_.fl.fx[x][y], F);
+                face_F<R>(S.u_.st.syp[y][x], sym, 1, gam, g1, S.split[(x + 2) + PW * (y + 1)] || sp_cur, F);
+                copy5(S.u_.fl.fy[y][x], F);
+            }
             if (extra_faces) {
                 if (lane < BC) {
                     const bool z2 = S.split[(BC + 1) + PW * (hk + 2)] || S.split[(BC + 2) + PW * (hk + 2)];
@@ -358,12 +385,14 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
                 acc_prev[v] = (Ucur[v] + (gxm - gxp)) + (gym - gyp);
             }
         }
-        // shift the plane window; prefetch plane rz+2 of the own column
+        // shift the plane window
+        {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            gz_prev[v] = rz >= 0 ? gz[v] : 0.0;
-            Wm[v] = W0[v];
-            W0[v] = Wp[v];
+            for (int v = 0; v < NV; ++v) {
+                gz_prev[v] = rz >= 0 ? gz[v] : 0.0;
+                Wm[v] = W0[v];
+                W0[v] = Wp[v];
+            }
         }
         sp_prev2 = sp_prev;
         sp_prev = sp_cur;

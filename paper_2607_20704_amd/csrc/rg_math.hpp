@@ -72,24 +72,32 @@ __device__ __forceinline__ void predict(const R *W, const R (*dW)[NV], R h, R ga
 template <typename R>
 __device__ __forceinline__ void hllc(const R *WL, const R *WR, int dir, R gamma, R g1, R *F)
 {
-    const R rl = WL[0], pl = WL[4], ul = WL[1 + dir];
-    const R rr = WR[0], pr = WR[4], ur = WR[1 + dir];
-    const R cl = Math<R>::sqrt_(Math<R>::div(gamma * pl, rl));
-    const R cr = Math<R>::sqrt_(Math<R>::div(gamma * pr, rr));
+    // Both states are read once into registers and every choice below is a
+    // choice between values: selecting or branching on pointers to the two
+    // states (one may be in LDS, one private) would force the private state
+    // into scratch memory.  The kinetic terms of both sides are formed so
+    // that each loaded value has several uses.
+    const R l0 = WL[0], l1 = WL[1], l2 = WL[2], l3 = WL[3], l4 = WL[4];
+    const R r0 = WR[0], r1 = WR[1], r2 = WR[2], r3 = WR[3], r4 = WR[4];
+    const R ql = (l1 * l1 + l2 * l2) + l3 * l3;
+    const R qr = (r1 * r1 + r2 * r2) + r3 * r3;
+    const R ul = dir == 0 ? l1 : (dir == 1 ? l2 : l3);
+    const R ur = dir == 0 ? r1 : (dir == 1 ? r2 : r3);
+    const R cl = Math<R>::sqrt_(Math<R>::div(gamma * l4, l0));
+    const R cr = Math<R>::sqrt_(Math<R>::div(gamma * r4, r0));
     const R sl = fmin(ul - cl, ur - cr);
     const R sr = fmax(ul + cl, ur + cr);
-    const R ml = rl * (ul - sl);
-    const R mr = rr * (sr - ur);
+    const R ml = l0 * (ul - sl);
+    const R mr = r0 * (sr - ur);
     const R inv = Math<R>::div(R(1), ml + mr);
-    const R sstar = ((mr * ur + ml * ul) + (pl - pr)) * inv;
-    const R pstar = ((mr * pl + ml * pr) + ml * mr * (ul - ur)) * inv;
+    const R sstar = ((mr * ur + ml * ul) + (l4 - r4)) * inv;
+    const R pstar = ((mr * l4 + ml * r4) + ml * mr * (ul - ur)) * inv;
 
     const bool useL = (sl > R(0)) || (sstar > R(0));
     const bool outer = useL ? (sl > R(0)) : !(sr > R(0));
-    const R *W = useL ? WL : WR;
+    const R rho = useL ? l0 : r0, p = useL ? l4 : r4, un = useL ? ul : ur, q = useL ? ql : qr;
+    const R w1 = useL ? l1 : r1, w2 = useL ? l2 : r2, w3 = useL ? l3 : r3;
     const R s = useL ? sl : sr;
-    const R rho = W[0], un = W[1 + dir], p = W[4];
-    const R q = (W[1] * W[1] + W[2] * W[2]) + W[3] * W[3];
     const R E = p * g1 + R(0.5) * rho * q;
     const R d = Math<R>::div(R(1), s - sstar);
     const R rs = outer ? rho : rho * (s - un) * d;
@@ -98,9 +106,9 @@ __device__ __forceinline__ void hllc(const R *WL, const R *WR, int dir, R gamma,
     const R ps = outer ? p : pstar;
     const R m = rs * ss;
     F[0] = m;
-    F[1] = dir == 0 ? (m * ss + ps) : (m * W[1]);
-    F[2] = dir == 1 ? (m * ss + ps) : (m * W[2]);
-    F[3] = dir == 2 ? (m * ss + ps) : (m * W[3]);
+    F[1] = dir == 0 ? (m * ss + ps) : (m * w1);
+    F[2] = dir == 1 ? (m * ss + ps) : (m * w2);
+    F[3] = dir == 2 ? (m * ss + ps) : (m * w3);
     F[4] = (es + ps) * ss;
 }
 

@@ -233,11 +233,12 @@ __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, i
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             const int pa = c - 1 + k;
-            int px[3];
-            px[ax] = pa;
-            px[ax == 0 ? 1 : 0] = t1;
-            px[ax == 2 ? 1 : 2] = t2;
-            const int bit = (px[0] & 1) + 2 * (px[1] & 1) + 4 * (px[2] & 1);
+            // cell position (pa along the axis, t1 / t2 across it) without a
+            // run-time-indexed array, which would live in scratch memory
+            const int px0 = ax == 0 ? pa : t1;
+            const int px1 = ax == 1 ? pa : (ax == 0 ? t1 : t2);
+            const int px2 = ax == 2 ? pa : t2;
+            const int bit = (px0 & 1) + 2 * (px1 & 1) + 4 * (px2 & 1);
             const uint32_t m = pa < 0 ? S.sm[g][1 + 2 * ax] : (pa > 1 ? S.sm[g][2 + 2 * ax] : S.sm[g][0]);
             zero = zero || ((m >> bit) & 1u);
         }

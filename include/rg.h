@@ -186,7 +186,7 @@ typedef struct rg_tuning {
     int32_t persistent;       /* batched form: 1 = persistent grids looping over the work list,
                                  0 = one workgroup per work item */
     int32_t brick_waves;      /* brick kernel register budget: waves per SIMD it is compiled for
-                                 (FP64: 2 or 3, mixed: 3 or 4; 0 = default: 3 for FP64, 4 mixed) */
+                                 (FP64: 2 or 3, mixed: 3 or 4; 0 = default: 2 for FP64, 4 mixed) */
     int32_t reserved[3];
 } rg_tuning;
 

@@ -64,10 +64,10 @@ rg_status hydro_bricks(const double *uold, double *unew, const int32_t *nbr27, c
     a.dt_next = reinterpret_cast<unsigned long long *>(dt_next);
     const unsigned grid = static_cast<unsigned>(8 * ((nbricks + 7) / 8));
     if (form == RG_FP64) {
-        if (waves == 0 || waves == 3)
-            k_hydro_brick<double, 3><<<grid, BT, 0, s>>>(a);
-        else if (waves == 2)
+        if (waves == 0 || waves == 2)
             k_hydro_brick<double, 2><<<grid, BT, 0, s>>>(a);
+        else if (waves == 3)
+            k_hydro_brick<double, 3><<<grid, BT, 0, s>>>(a);
         else
             return fail(RG_ENOTSUP, "no FP64 brick kernel for %d waves per SIMD", waves);
     } else {

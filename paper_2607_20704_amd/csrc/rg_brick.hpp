@@ -231,6 +231,22 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
             copy5(S.hw[2][lane], Wh);
         }
     }
+    // FP64: ghost-ring cells are loaded one plane ahead of their use, so that
+    // no wave waits for memory right before a barrier (the face-layer lanes
+    // hold plane rz+1 for step 1 of iteration rz, the outer-ring and corner
+    // lanes plane rz for step 2).  The mixed form keeps the registers this
+    // costs: it runs more waves per SIMD instead.
+    constexpr bool PF = sizeof(R) == 8;
+    int rx = 0, ry = 0;
+    const bool ring_role = do_outer || do_corner;
+    if (do_corner) ring_pos(3, lane, rx, ry);
+    else if (do_outer) ring_pos(2, lane, rx, ry);
+    double Upf[NV];
+    if constexpr (PF) {
+        bool sdummy;
+        if (do_face) load_u(a.uold, source_cell(S, g, hx, hy, 0, sdummy), Upf);
+        if (ring_role) load_u(a.uold, source_cell(S, g, rx, ry, 0, sdummy), Upf);
+    }
     double acc_prev[NV], gz_prev[NV];
     R zp_prev[NV];
 #pragma unroll
@@ -249,10 +265,16 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
         bool hsplit = false;
         if (do_face) {
             if (rz + 1 <= BC) {
-                double U[NV];
                 R Wh[NV];
-                load_u(a.uold, source_cell(S, g, hx, hy, rz + 1, hsplit), U);
-                to_prim(U, a.gamma, Wh);
+                bool sdummy;
+                if constexpr (PF) {
+                    to_prim(Upf, a.gamma, Wh);
+                    if (rz + 2 <= BC) load_u(a.uold, source_cell(S, g, hx, hy, rz + 2, sdummy), Upf);
+                } else {
+                    double U[NV];
+                    load_u(a.uold, source_cell(S, g, hx, hy, rz + 1, sdummy), U);
+                    to_prim(U, a.gamma, Wh);
+                }
                 copy5(S.hw[(rz + 4) % 3][lane], Wh);
             }
             (void)source_cell(S, g, hx, hy, rz, hsplit);
@@ -266,23 +288,18 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
             copy5(S.w[(hx + 2) + PW * (hy + 2)], S.hw[(rz + 3) % 3][lane]);
             S.split[(hx + 2) + PW * (hy + 2)] = hsplit;
         }
-        if (do_outer && inner) {
-            double U[NV];
+        if (ring_role && inner) {
             R Wr[NV];
-            int ox, oy;
-            ring_pos(2, lane, ox, oy);
-            load_u(a.uold, source_cell(S, g, ox, oy, rz, hsplit), U);
-            to_prim(U, a.gamma, Wr);
-            copy5(S.w[(ox + 2) + PW * (oy + 2)], Wr);
-        }
-        if (do_corner && inner) {
-            double U[NV];
-            R Wr[NV];
-            int cx, cy;
-            ring_pos(3, lane, cx, cy);
-            load_u(a.uold, source_cell(S, g, cx, cy, rz, hsplit), U);
-            to_prim(U, a.gamma, Wr);
-            copy5(S.w[(cx + 2) + PW * (cy + 2)], Wr);
+            bool sdummy;
+            if constexpr (PF) {
+                to_prim(Upf, a.gamma, Wr);
+                if (rz + 1 < BC) load_u(a.uold, source_cell(S, g, rx, ry, rz + 1, sdummy), Upf);
+            } else {
+                double U[NV];
+                load_u(a.uold, source_cell(S, g, rx, ry, rz, sdummy), U);
+                to_prim(U, a.gamma, Wr);
+            }
+            copy5(S.w[(rx + 2) + PW * (ry + 2)], Wr);
         }
         __syncthreads();
 

@@ -367,9 +367,11 @@ rg_status rg_step(const rg_tree *t, const double *d_uold, double *d_unew, double
  * Tree t alternates between its two state buffers: step s reads d_u0 when s
  * is even (d_u1 when odd) and writes the other one, so after an even number
  * of steps the result is in d_u0.  The time step of tree t at step s is
- * written to d_dt[s * ntree + t] (device, double[nsteps * ntree]).  A tree
- * gives the same bits, state and dt, as rg_step run on it alone with the same
- * form and flags.
+ * written to d_dt[s * ntree + t] (device, double[(nsteps + 1) * ntree]): the
+ * first from a pass over the state, each later one folded into the previous
+ * step's update (as rg_step's RG_STEP_CHAIN_DT), and row nsteps holds the
+ * time step a following step would take.  A tree gives the same bits, state
+ * and dt, as rg_step run on it alone with the same form and flags.
  *
  * Every tree needs a schedule (t->sched, rg_schedule_build) and a correction
  * buffer if it has more than one level; keys, level ranges, hash workspace

@@ -309,7 +309,7 @@ class Batch:
         self.trees = list(trees)
         self.nsteps = int(nsteps)
         self.u = [[s.clone() for s in states], [torch.empty_like(s) for s in states]]
-        self.dt = torch.empty(self.nsteps * len(trees), dtype=torch.float64, device="cuda")
+        self.dt = torch.empty((self.nsteps + 1) * len(trees), dtype=torch.float64, device="cuda")
         arr = (L.RgBatchTree * len(trees))()
         for k, t in enumerate(trees):
             arr[k].tree = ctypes.pointer(t._desc)
@@ -331,7 +331,7 @@ class Batch:
 
     def dts(self):
         """Time steps of the last run, [nsteps, ntree]."""
-        return self.dt.view(self.nsteps, len(self.trees))
+        return self.dt.view(self.nsteps + 1, len(self.trees))[:self.nsteps]
 
     def close(self):
         if getattr(self, "_h", None):

@@ -141,8 +141,10 @@ __device__ __forceinline__ ItemRange xcd_item(int64_t nitems)
 // With P the grid is persistent and loops over the items; without, each
 // workgroup takes one item (no loop-carried registers).
 template <typename R, bool P>
-__global__ __launch_bounds__(BT, sizeof(R) == 8 ? 2 : 4) void k_batch_bricks(const BTree *__restrict__ trees, const Item *__restrict__ items,
-                                                     int64_t nitems, int parity, const double *dt)
+__global__ __launch_bounds__(BT, sizeof(R) == 8 ? 2 : 4) void k_batch_bricks(const BTree *__restrict__ trees,
+                                                                            const Item *__restrict__ items,
+                                                                            int64_t nitems, int parity,
+                                                                            const double *dt, double *dt_next)
 {
     __shared__ BrickSmem<R> S;
     const ItemRange r = P ? xcd_items(nitems) : xcd_item(nitems);
@@ -162,15 +164,17 @@ __global__ __launch_bounds__(BT, sizeof(R) == 8 ? 2 : 4) void k_batch_bricks(con
         a.gamma = T.gamma;
         a.outflow = T.bc == RG_BC_OUTFLOW;
         a.cfl = T.cfl;
-        a.dt_next = nullptr;
+        a.dt_next = reinterpret_cast<unsigned long long *>(dt_next + I.tree);
         brick_body<R>(a, T.list[I.first], I.first, S);
         __syncthreads();
     }
 }
 
 template <typename R, int G, bool P>
-__global__ __launch_bounds__(kT, sizeof(R) == 8 ? 4 : 6) void k_batch_octs(const BTree *__restrict__ trees, const Item *__restrict__ items,
-                                                   int64_t nitems, int parity, const double *dt)
+__global__ __launch_bounds__(kT, sizeof(R) == 8 ? 4 : 6) void k_batch_octs(const BTree *__restrict__ trees,
+                                                                          const Item *__restrict__ items,
+                                                                          int64_t nitems, int parity,
+                                                                          const double *dt, double *dt_next)
 {
     __shared__ Smem<R, G> S;
     const ItemRange r = P ? xcd_items(nitems) : xcd_item(nitems);
@@ -192,7 +196,7 @@ __global__ __launch_bounds__(kT, sizeof(R) == 8 ? 4 : 6) void k_batch_octs(const
         a.dx = ldexp(1.0, -level);
         a.gamma = T.gamma;
         a.cfl = T.cfl;
-        a.dt_next = nullptr;
+        a.dt_next = reinterpret_cast<unsigned long long *>(dt_next + I.tree);
         hydro_group<R, G, kT>(a, I.first, static_cast<int>(I.count), S);
         __syncthreads();
     }
@@ -216,6 +220,58 @@ __global__ __launch_bounds__(kT) void k_batch_corr(const BTree *__restrict__ tre
             const int64_t C = -1 - int64_t(e);
             unew[NV * C + v] = unew[NV * C + v] + T.corr[30 * (o - T.corr_base) + NV * side + v];
         }
+    }
+}
+
+// CFL limit of the coarse cells the corrections changed (every coarse face
+// neighbour of the item's octs), folded into the tree's next time step
+__global__ __launch_bounds__(kT) void k_batch_corr_dt(const BTree *__restrict__ trees,
+                                                       const Item *__restrict__ items, int64_t nitems, int parity,
+                                                       double *dt_next)
+{
+    __shared__ double s_min[kT / 64];
+    const ItemRange r = xcd_items(nitems);
+    for (int64_t it = r.begin; it < r.end; it += r.stride) {
+        const Item I = items[it];
+        const BTree &T = trees[I.tree];
+        const double *u = T.u[parity ^ 1];
+        double best = __longlong_as_double(0x7ff0000000000000ll);
+        for (int64_t k = threadIdx.x; k < I.count * 6; k += kT) {
+            const int64_t o = I.first + k / 6;
+            const int side = static_cast<int>(k % 6);
+            const int ax = side >> 1, hi = side & 1;
+            const int slot = (ax == 0 ? (hi ? 2 : 0) : 1) + 3 * (ax == 1 ? (hi ? 2 : 0) : 1) +
+                             9 * (ax == 2 ? (hi ? 2 : 0) : 1);
+            const int32_t e = T.nbr27[27 * o + slot];
+            if (!(e < 0 && e != RG_NBR_OUTSIDE)) continue;
+            const int64_t C = -1 - int64_t(e);
+            int l = T.lmin;
+            while (l < T.lmax && o >= T.level_begin[l + 1]) ++l;
+            const double dx = ldexp(1.0, -(l - 1));
+            double U[NV], W[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) U[v] = u[NV * C + v];
+            prim64(U, T.gamma, W);
+            const double cs = sqrt((T.gamma * W[4]) / W[0]);
+            const double sp = ((fabs(W[1]) + fabs(W[2])) + fabs(W[3])) + 3.0 * cs;
+            const double cd = T.cfl * (dx / sp);
+            if (cd < best) best = cd;
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            double o = __shfl_xor(best, off, 64);
+            best = o < best ? o : best;
+        }
+        if ((threadIdx.x & 63) == 0) s_min[threadIdx.x >> 6] = best;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double m = s_min[0];
+            for (int k = 1; k < kT / 64; ++k) m = s_min[k] < m ? s_min[k] : m;
+            if (m < __longlong_as_double(0x7ff0000000000000ll))
+                atomicMin(reinterpret_cast<unsigned long long *>(dt_next + I.tree),
+                          static_cast<unsigned long long>(__double_as_longlong(m)));
+        }
+        __syncthreads();
     }
 }
 
@@ -335,39 +391,39 @@ unsigned one_shot_grid(int64_t nitems) { return static_cast<unsigned>(8 * ((nite
 
 template <typename R>
 rg_status launch_bricks(bool persistent, const BTree *trees, const Phase &p, int parity, const double *dt,
-                        hipStream_t s)
+                        double *dt_next, hipStream_t s)
 {
     if (p.n == 0) return RG_OK;
     if (persistent) {
         const int grid = persistent_grid(reinterpret_cast<const void *>(&k_batch_bricks<R, true>), BT, p.n);
-        k_batch_bricks<R, true><<<grid, BT, 0, s>>>(trees, p.d_items, p.n, parity, dt);
+        k_batch_bricks<R, true><<<grid, BT, 0, s>>>(trees, p.d_items, p.n, parity, dt, dt_next);
     } else {
-        k_batch_bricks<R, false><<<one_shot_grid(p.n), BT, 0, s>>>(trees, p.d_items, p.n, parity, dt);
+        k_batch_bricks<R, false><<<one_shot_grid(p.n), BT, 0, s>>>(trees, p.d_items, p.n, parity, dt, dt_next);
     }
     return launch_status("batched bricks");
 }
 
 template <typename R, int G>
 rg_status launch_octs(bool persistent, const BTree *trees, const Phase &p, int parity, const double *dt,
-                      hipStream_t s)
+                      double *dt_next, hipStream_t s)
 {
     if (p.n == 0) return RG_OK;
     if (persistent) {
         const int grid = persistent_grid(reinterpret_cast<const void *>(&k_batch_octs<R, G, true>), kT, p.n);
-        k_batch_octs<R, G, true><<<grid, kT, 0, s>>>(trees, p.d_items, p.n, parity, dt);
+        k_batch_octs<R, G, true><<<grid, kT, 0, s>>>(trees, p.d_items, p.n, parity, dt, dt_next);
     } else {
-        k_batch_octs<R, G, false><<<one_shot_grid(p.n), kT, 0, s>>>(trees, p.d_items, p.n, parity, dt);
+        k_batch_octs<R, G, false><<<one_shot_grid(p.n), kT, 0, s>>>(trees, p.d_items, p.n, parity, dt, dt_next);
     }
     return launch_status("batched oct groups");
 }
 
 template <typename R>
 rg_status launch_octs_g(int g, bool persistent, const BTree *trees, const Phase &p, int parity, const double *dt,
-                        hipStream_t s)
+                        double *dt_next, hipStream_t s)
 {
-    if (g == 2) return launch_octs<R, 2>(persistent, trees, p, parity, dt, s);
-    if (g == 8) return launch_octs<R, 8>(persistent, trees, p, parity, dt, s);
-    return launch_octs<R, 4>(persistent, trees, p, parity, dt, s);
+    if (g == 2) return launch_octs<R, 2>(persistent, trees, p, parity, dt, dt_next, s);
+    if (g == 8) return launch_octs<R, 8>(persistent, trees, p, parity, dt, dt_next, s);
+    return launch_octs<R, 4>(persistent, trees, p, parity, dt, dt_next, s);
 }
 
 unsigned small_grid(int64_t n)
@@ -533,14 +589,21 @@ rg_status rg_batch_create(const rg_batch_tree *trees, int ntree, int form, int n
     rg_status st = RG_OK;
     for (int step = 0; step < nsteps && st == RG_OK; ++step) {
         const int parity = step & 1;
+        // row `step` of d_dt is this step's time step (a pass over the state
+        // for the first step, folded into the previous step otherwise); the
+        // update folds the next one into row step+1
         double *dt = d_dt + static_cast<int64_t>(step) * ntree;
+        double *dt_next = dt + ntree;
         if (flags & RG_STEP_REBUILD) {
             k_batch_clear<<<g_clear, kT, 0, cs>>>(d_trees, ph_clear.d_items, ph_clear.n);
             k_batch_insert<<<g_insert, kT, 0, cs>>>(d_trees, ph_insert.d_items, ph_insert.n);
             k_batch_nbr<<<g_nbr, kT, 0, cs>>>(d_trees, ph_nbr.d_items, ph_nbr.n);
         }
-        k_batch_dt_init<<<(ntree + 255) / 256, 256, 0, cs>>>(dt, ntree);
-        k_batch_dt<<<g_dt, kT, 0, cs>>>(d_trees, ph_dt.d_items, ph_dt.n, parity, dt);
+        if (step == 0) {
+            k_batch_dt_init<<<(ntree + 255) / 256, 256, 0, cs>>>(dt, ntree);
+            k_batch_dt<<<g_dt, kT, 0, cs>>>(d_trees, ph_dt.d_items, ph_dt.n, parity, dt);
+        }
+        k_batch_dt_init<<<(ntree + 255) / 256, 256, 0, cs>>>(dt_next, ntree);
         const bool fork = ph_bricks.n > 0 && ph_octs.n > 0;
         if (fork) {
             e = hipEventRecord(ev_fork, cs);
@@ -551,15 +614,15 @@ rg_status rg_batch_create(const rg_batch_tree *trees, int ntree, int form, int n
             }
         }
         if (form == RG_FP64)
-            st = launch_bricks<double>(persistent, d_trees, ph_bricks, parity, dt, cs);
+            st = launch_bricks<double>(persistent, d_trees, ph_bricks, parity, dt, dt_next, cs);
         else
-            st = launch_bricks<float>(persistent, d_trees, ph_bricks, parity, dt, cs);
+            st = launch_bricks<float>(persistent, d_trees, ph_bricks, parity, dt, dt_next, cs);
         if (st != RG_OK) break;
         hipStream_t so = fork ? cs2 : cs;
         if (form == RG_FP64)
-            st = launch_octs_g<double>(g, persistent, d_trees, ph_octs, parity, dt, so);
+            st = launch_octs_g<double>(g, persistent, d_trees, ph_octs, parity, dt, dt_next, so);
         else
-            st = launch_octs_g<float>(g, persistent, d_trees, ph_octs, parity, dt, so);
+            st = launch_octs_g<float>(g, persistent, d_trees, ph_octs, parity, dt, dt_next, so);
         if (st != RG_OK) break;
         if (fork) {
             e = hipEventRecord(ev_join, cs2);
@@ -569,9 +632,11 @@ rg_status rg_batch_create(const rg_batch_tree *trees, int ntree, int form, int n
                 break;
             }
         }
-        if (ph_corr.n)
+        if (ph_corr.n) {
             for (int side = 0; side < 6; ++side)
                 k_batch_corr<<<g_corr, kT, 0, cs>>>(d_trees, ph_corr.d_items, ph_corr.n, parity, side);
+            k_batch_corr_dt<<<g_corr, kT, 0, cs>>>(d_trees, ph_corr.d_items, ph_corr.n, parity, dt_next);
+        }
         for (int k = 0; k < maxdepth; ++k) {
             const Phase &p = phases[P_RESTRICT + k];
             if (p.n) k_batch_restrict<<<g_restrict[k], kT, 0, cs>>>(d_trees, p.d_items, p.n, parity);

@@ -28,8 +28,8 @@ namespace rg {
 namespace {
 
 // W: waves per SIMD the register allocation is sized for (the compiler
-// spills beyond it); every W gives the same bits
-template <typename R, int W>
+// spills beyond it); KU: see brick_body.  Every variant gives the same bits.
+template <typename R, int W, bool KU>
 __global__ __launch_bounds__(BT, W) void k_hydro_brick(BrickArgs a)
 {
     __shared__ BrickSmem<R> S;
@@ -38,7 +38,7 @@ __global__ __launch_bounds__(BT, W) void k_hydro_brick(BrickArgs a)
     const int64_t per_xcd = (a.nbricks + 7) / 8;
     const int64_t b = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (b >= a.nbricks) return;
-    brick_body<R>(a, a.bricks[b], b, S);
+    brick_body<R, KU>(a, a.bricks[b], b, S);
 }
 
 }  // namespace
@@ -65,16 +65,16 @@ rg_status hydro_bricks(const double *uold, double *unew, const int32_t *nbr27, c
     const unsigned grid = static_cast<unsigned>(8 * ((nbricks + 7) / 8));
     if (form == RG_FP64) {
         if (waves == 0 || waves == 2)
-            k_hydro_brick<double, 2><<<grid, BT, 0, s>>>(a);
+            k_hydro_brick<double, 2, true><<<grid, BT, 0, s>>>(a);
         else if (waves == 3)
-            k_hydro_brick<double, 3><<<grid, BT, 0, s>>>(a);
+            k_hydro_brick<double, 3, false><<<grid, BT, 0, s>>>(a);
         else
             return fail(RG_ENOTSUP, "no FP64 brick kernel for %d waves per SIMD", waves);
     } else {
         if (waves == 0 || waves == 4)
-            k_hydro_brick<float, 4><<<grid, BT, 0, s>>>(a);
+            k_hydro_brick<float, 4, false><<<grid, BT, 0, s>>>(a);
         else if (waves == 3)
-            k_hydro_brick<float, 3><<<grid, BT, 0, s>>>(a);
+            k_hydro_brick<float, 3, true><<<grid, BT, 0, s>>>(a);
         else
             return fail(RG_ENOTSUP, "no mixed brick kernel for %d waves per SIMD", waves);
     }

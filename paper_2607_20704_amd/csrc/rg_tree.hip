@@ -100,6 +100,180 @@ __global__ void k_hash_insert(const uint64_t *__restrict__ in, int64_t n, HashHe
     if (i < n) hash_insert_one(hdr, keys, vals, mask, in[i], i);
 }
 
+// ---------------------------------------------------------------------------
+// Segmented table build.  The table is cut into segments of 2^kSegLog slots.
+// Keys are bucketed by the segment of their home slot (a short radix sort of
+// segment numbers); one workgroup then builds each segment in LDS with LDS
+// compare-and-swap and writes it out whole.  A probe sequence that runs past
+// the end of its segment is finished afterwards with global compare-and-swap
+// on the finished table.  Every key ends at the first free slot at or after
+// its home slot at the time it is placed, so the result is a valid
+// linear-probing table (slot positions depend on the placement order, as
+// with any concurrent build; lookups do not).
+// ---------------------------------------------------------------------------
+
+constexpr int kSegLog = 12;
+constexpr int kSegMax = 1 << kSegLog;
+
+struct SegBuild {
+    uint32_t *seg_in, *seg_out, *idx_in, *idx_out;   // [n] each
+    uint32_t *seg_begin, *seg_end;                   // [nseg] each
+    uint32_t *ovf_count;                             // [64] (first used)
+    uint32_t *ovf;                                   // [n]
+    void *temp;
+    size_t temp_bytes;
+    int seg_log, bits;
+    int64_t nseg;
+};
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+int seg_log_for(uint64_t cap)
+{
+    int lc = 0;
+    while ((uint64_t(1) << lc) < cap) ++lc;
+    return lc < kSegLog ? lc : kSegLog;
+}
+
+size_t seg_sort_temp(int64_t n, int bits)
+{
+    if (n <= 0 || bits <= 0) return 0;
+    size_t temp = 0;
+    hipcub::DeviceRadixSort::SortPairs(nullptr, temp, static_cast<const uint32_t *>(nullptr),
+                                       static_cast<uint32_t *>(nullptr), static_cast<const uint32_t *>(nullptr),
+                                       static_cast<uint32_t *>(nullptr), static_cast<int>(n), 0, bits);
+    return temp;
+}
+
+size_t table_bytes(uint64_t cap) { return align256(sizeof(HashHeader) + cap * (sizeof(uint64_t) + sizeof(int32_t))); }
+
+// scratch of the build, placed after the table
+SegBuild seg_build_layout(void *ws, int64_t n, uint64_t cap)
+{
+    SegBuild b;
+    b.seg_log = seg_log_for(cap);
+    int lc = 0;
+    while ((uint64_t(1) << lc) < cap) ++lc;
+    b.bits = lc - b.seg_log;
+    b.nseg = int64_t(1) << b.bits;
+    char *p = static_cast<char *>(ws) + table_bytes(cap);
+    const size_t nb = align256(static_cast<size_t>(n) * sizeof(uint32_t));
+    b.seg_in = reinterpret_cast<uint32_t *>(p);
+    p += nb;
+    b.seg_out = reinterpret_cast<uint32_t *>(p);
+    p += nb;
+    b.idx_in = reinterpret_cast<uint32_t *>(p);
+    p += nb;
+    b.idx_out = reinterpret_cast<uint32_t *>(p);
+    p += nb;
+    b.ovf = reinterpret_cast<uint32_t *>(p);
+    p += nb;
+    b.seg_begin = reinterpret_cast<uint32_t *>(p);
+    b.seg_end = b.seg_begin + b.nseg;
+    b.ovf_count = b.seg_end + b.nseg;
+    p += align256(static_cast<size_t>(2 * b.nseg + 64) * sizeof(uint32_t));
+    b.temp = p;
+    b.temp_bytes = seg_sort_temp(n, b.bits);
+    return b;
+}
+
+size_t seg_build_bytes(int64_t n, uint64_t cap)
+{
+    const int seg_log = seg_log_for(cap);
+    int lc = 0;
+    while ((uint64_t(1) << lc) < cap) ++lc;
+    const int bits = lc - seg_log;
+    const int64_t nseg = int64_t(1) << bits;
+    const size_t nb = align256(static_cast<size_t>(n < 0 ? 0 : n) * sizeof(uint32_t));
+    return 5 * nb + align256(static_cast<size_t>(2 * nseg + 64) * sizeof(uint32_t)) +
+           align256(seg_sort_temp(n, bits));
+}
+
+__global__ void k_seg_prepare(const uint64_t *__restrict__ keys, int64_t n, uint64_t mask, int seg_log,
+                              uint32_t *__restrict__ seg_in, uint32_t *__restrict__ idx_in, HashHeader *hdr,
+                              uint64_t cap)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        hdr->cap = cap;
+        hdr->n = n;
+        hdr->err = 0;
+        hdr->bad = -1;
+    }
+    if (i >= n) return;
+    seg_in[i] = static_cast<uint32_t>((fnv1a64(keys[i]) & mask) >> seg_log);
+    idx_in[i] = static_cast<uint32_t>(i);
+}
+
+__global__ void k_seg_bounds(const uint32_t *__restrict__ seg, int64_t n, uint32_t *seg_begin, uint32_t *seg_end)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t s = seg[i];
+    if (i == 0 || seg[i - 1] != s) seg_begin[s] = static_cast<uint32_t>(i);
+    if (i == n - 1 || seg[i + 1] != s) seg_end[s] = static_cast<uint32_t>(i + 1);
+}
+
+__global__ __launch_bounds__(256) void k_seg_build(const uint64_t *__restrict__ keys,
+                                                   const uint32_t *__restrict__ seg_begin,
+                                                   const uint32_t *__restrict__ seg_end,
+                                                   const uint32_t *__restrict__ idx, HashHeader *hdr,
+                                                   uint64_t *tkeys, int32_t *tvals, uint64_t mask, int seg_log,
+                                                   uint32_t *ovf_count, uint32_t *ovf)
+{
+    __shared__ unsigned long long lk[kSegMax];
+    __shared__ int32_t lv[kSegMax];
+    const int seg = 1 << seg_log;
+    const int64_t s = blockIdx.x;
+    for (int j = threadIdx.x; j < seg; j += blockDim.x) {
+        lk[j] = 0ull;
+        lv[j] = 0;
+    }
+    __syncthreads();
+    const uint64_t base = static_cast<uint64_t>(s) << seg_log;
+    for (uint32_t e = seg_begin[s] + threadIdx.x; e < seg_end[s]; e += blockDim.x) {
+        const uint32_t i = idx[e];
+        const uint64_t key = keys[i];
+        if (key == 0) {
+            flag_error(hdr, RG_EINVAL, i);
+            continue;
+        }
+        int local = static_cast<int>((fnv1a64(key) & mask) - base);
+        bool placed = false;
+        for (; local < seg; ++local) {
+            const unsigned long long prev = atomicCAS(&lk[local], 0ull, static_cast<unsigned long long>(key));
+            if (prev == 0ull) {
+                lv[local] = static_cast<int32_t>(i);
+                placed = true;
+                break;
+            }
+            if (prev == key) {
+                flag_error(hdr, RG_EDUPKEY, i);
+                placed = true;
+                break;
+            }
+        }
+        if (!placed) ovf[atomicAdd(ovf_count, 1u)] = i;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < seg; j += blockDim.x) {
+        tkeys[base + j] = lk[j];
+        tvals[base + j] = lv[j];
+    }
+}
+
+// the probe sequences that ran past their segment, on the finished table
+__global__ void k_seg_overflow(const uint64_t *__restrict__ keys, const uint32_t *ovf_count,
+                               const uint32_t *__restrict__ ovf, HashHeader *hdr, uint64_t *tkeys, int32_t *tvals,
+                               uint64_t mask)
+{
+    const uint32_t m = *ovf_count;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x) {
+        const uint32_t i = ovf[t];
+        hash_insert_one(hdr, tkeys, tvals, mask, keys[i], i);
+    }
+}
+
 __global__ void k_hash_lookup(const uint64_t *__restrict__ keys, const int32_t *__restrict__ vals, uint64_t mask,
                               const uint64_t *__restrict__ q, int64_t m, int32_t *__restrict__ out)
 {
@@ -275,8 +449,9 @@ rg_status rg_permute_rows(const double *d_in, const int32_t *d_perm, int64_t n_r
 
 size_t rg_hash_workspace_bytes(int64_t n_keys)
 {
-    uint64_t cap = hash_capacity(n_keys < 0 ? 0 : n_keys);
-    return sizeof(HashHeader) + cap * (sizeof(uint64_t) + sizeof(int32_t));
+    const int64_t n = n_keys < 0 ? 0 : n_keys;
+    const uint64_t cap = hash_capacity(n);
+    return table_bytes(cap) + seg_build_bytes(n, cap);
 }
 
 uint64_t rg_fnv1a64(uint64_t key) { return fnv1a64(key); }
@@ -299,13 +474,29 @@ rg_status rg_hash_build(const uint64_t *d_keys, int64_t n, void *d_ws, size_t ws
         return fail(RG_EFULL, "hash workspace holds %zu bytes, %zu needed", ws_bytes, rg_hash_workspace_bytes(n));
     HashView h = hash_view(d_ws, cap);
     hipStream_t s = as_stream(stream);
-    k_hash_clear<<<grid_for(static_cast<int64_t>(cap), 256), 256, 0, s>>>(h.hdr, h.keys, cap, n);
-    RG_TRY(launch_status("rg_hash_build clear"));
-    if (n > 0) {
-        k_hash_insert<<<grid_for(n, 256), 256, 0, s>>>(d_keys, n, h.hdr, h.keys, h.vals, h.mask);
-        RG_TRY(launch_status("rg_hash_build insert"));
+    SegBuild b = seg_build_layout(d_ws, n, cap);
+    RG_TRY(fill_u32(b.seg_begin, 2 * b.nseg + 64, 0u, s));
+    k_seg_prepare<<<grid_for(n, 256), 256, 0, s>>>(d_keys, n, h.mask, b.seg_log, b.seg_in, b.idx_in, h.hdr, cap);
+    RG_TRY(launch_status("rg_hash_build prepare"));
+    const uint32_t *seg = b.seg_in, *idx = b.idx_in;
+    if (n > 0 && b.bits > 0) {
+        size_t tb = b.temp_bytes;
+        hipError_t e = hipcub::DeviceRadixSort::SortPairs(b.temp, tb, b.seg_in, b.seg_out, b.idx_in, b.idx_out,
+                                                          static_cast<int>(n), 0, b.bits, s);
+        if (e != hipSuccess) return fail(RG_EHIP, "hash bucket sort: %s", hipGetErrorString(e));
+        RG_TRY(launch_status("rg_hash_build sort"));
+        seg = b.seg_out;
+        idx = b.idx_out;
     }
-    return RG_OK;
+    if (n > 0) {
+        k_seg_bounds<<<grid_for(n, 256), 256, 0, s>>>(seg, n, b.seg_begin, b.seg_end);
+        RG_TRY(launch_status("rg_hash_build bounds"));
+    }
+    k_seg_build<<<static_cast<unsigned>(b.nseg), 256, 0, s>>>(d_keys, b.seg_begin, b.seg_end, idx, h.hdr, h.keys,
+                                                              h.vals, h.mask, b.seg_log, b.ovf_count, b.ovf);
+    RG_TRY(launch_status("rg_hash_build segments"));
+    k_seg_overflow<<<64, 256, 0, s>>>(d_keys, b.ovf_count, b.ovf, h.hdr, h.keys, h.vals, h.mask);
+    return launch_status("rg_hash_build overflow");
 }
 
 // The capacity is recorded in the header on the device; host callers pass the

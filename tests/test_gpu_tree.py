@@ -129,3 +129,52 @@ def test_ungraded_tree_is_reported():
     st, bad = api.check_ws(ws)
     assert st == L.RG_EUNGRADED == st_o
     assert bad == bad_o
+
+
+def _fnv1a64_np(k):
+    """FNV-1a 64 over the 8 little-endian bytes, vectorised (uint64 wraps)."""
+    h = np.full(k.shape, 0xCBF29CE484222325, dtype=np.uint64)
+    for b in range(8):
+        h ^= (k >> np.uint64(8 * b)) & np.uint64(0xFF)
+        h *= np.uint64(0x100000001B3)
+    return h
+
+
+def test_hash_build_probe_runs_leave_their_segment():
+    """Keys chosen so that many home slots fall at the end of 4096-slot
+    segments (and at the end of the table, where probing wraps to slot 0):
+    the probe sequences leave their segment and are finished on the whole
+    table.  Every key is found at its index, absent keys are not, and a
+    duplicate among them is reported."""
+    from paper_2607_20704_amd import api
+    from paper_2607_20704_amd import _lib as L
+    n = 6000
+    cap = 16384
+    rng = np.random.default_rng(5)
+    cand = np.unique(rng.integers(1, 2 ** 63, 4_000_000, dtype=np.int64).astype(np.uint64))
+    assert L.lib().rg_fnv1a64(int(cand[0])) == int(_fnv1a64_np(cand[:1])[0])
+    home = _fnv1a64_np(cand) & np.uint64(cap - 1)
+    # 40 keys on each of the last 8 slots of every segment, then random keys
+    aimed = []
+    for slot in [s0 + j for s0 in range(4095, cap, 4096) for j in range(-7, 1)]:
+        aimed.append(cand[home == np.uint64(slot)][:40])
+    aimed = np.concatenate(aimed)
+    assert len(aimed) == 4 * 8 * 40
+    rest = np.setdiff1d(cand, aimed)
+    chosen = np.concatenate([aimed, rng.permutation(rest)[:n - len(aimed)]])
+    keys_np = rng.permutation(chosen)
+    seen = set(int(k) for k in keys_np)
+    say("hash overflow: %d keys, %d aimed at segment ends" % (n, 4 * 8 * 40))
+    keys = torch.as_tensor(keys_np.view(np.int64)).cuda().view(torch.uint64)
+    ws = api.hash_build(keys)
+    assert api.check_ws(ws) == (L.RG_OK, -1)
+    assert np.array_equal(api.hash_lookup(ws, keys).cpu().numpy(), np.arange(n))
+    absent = np.array([int(k) for k in rest[-2000:] if int(k) not in seen][:500], dtype=np.uint64)
+    q = torch.as_tensor(absent.view(np.int64)).cuda().view(torch.uint64)
+    assert np.all(api.hash_lookup(ws, q).cpu().numpy() == -1)
+    # a duplicate of a key whose home is at a segment end
+    first = int(np.nonzero(np.isin(keys_np, aimed))[0][0])
+    dup = np.concatenate([keys_np, keys_np[first:first + 1]])
+    ws2 = api.hash_build(torch.as_tensor(dup.view(np.int64)).cuda().view(torch.uint64))
+    st, bad = api.check_ws(ws2)
+    assert st == L.RG_EDUPKEY and bad in (first, n)

@@ -150,7 +150,14 @@ def test_batch_argument_errors_without_a_device():
 
 def test_workspace_sizes():
     lib = L.lib()
-    assert lib.rg_hash_workspace_bytes(0) == 256 + 16 * 12
-    assert lib.rg_hash_workspace_bytes(4096) == 256 + 8192 * 12
-    assert lib.rg_hash_workspace_bytes(4097) == 256 + 16384 * 12
+    # the table (256-byte header, capacity = power of two >= 2n slots of 12
+    # bytes) followed by the scratch of the segmented build (five int32 arrays
+    # of n entries, segment bounds, the bucket sort's temporary storage)
+    def table(cap):
+        return (256 + cap * 12 + 255) // 256 * 256
+    for n, cap in ((0, 16), (4096, 8192), (4097, 16384), (1 << 21, 1 << 22)):
+        b = lib.rg_hash_workspace_bytes(n)
+        assert b >= table(cap) + 5 * 4 * n, (n, b)
+        assert b % 256 == 0
+        assert b < table(cap) + 5 * 4 * n + 4 * 1024 * 1024 + n * 16, (n, b)
     assert lib.rg_corr_workspace_bytes(10) == 2400

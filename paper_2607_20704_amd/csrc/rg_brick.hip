@@ -72,7 +72,7 @@ rg_status hydro_bricks(const double *uold, double *unew, const int32_t *nbr27, c
             return fail(RG_ENOTSUP, "no FP64 brick kernel for %d waves per SIMD", waves);
     } else {
         if (waves == 0 || waves == 4)
-            k_hydro_brick<float, 4, false><<<grid, BT, 0, s>>>(a);
+            k_hydro_brick<float, 4, true><<<grid, BT, 0, s>>>(a);
         else if (waves == 3)
             k_hydro_brick<float, 3, true><<<grid, BT, 0, s>>>(a);
         else

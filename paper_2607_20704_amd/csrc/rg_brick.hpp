@@ -55,6 +55,9 @@ template <typename R> struct BrickSmem {
     } u_;
     uint8_t split[PW * PW];         // split flag of the current plane's cells
     double red[8];                  // block minimum of the fused CFL limit, one per wave
+    // mixed form: each column's partial update of the previous plane (its own
+    // slot, no sharing), kept here rather than in registers
+    double acc[sizeof(R) == 4 ? BT : 1][NV];
 };
 
 struct Geom {
@@ -253,6 +256,9 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
         if (do_face) load_u(a.uold, source_cell(S, g, hx, hy, 0, sdummy), Upf);
         if (ring_role) load_u(a.uold, source_cell(S, g, rx, ry, 0, sdummy), Upf);
     }
+    // partial update (uold + x and y flux differences) of plane rz-1: in
+    // registers for FP64, in the column's own LDS slot for the mixed form
+    constexpr bool ACC_LDS = sizeof(R) == 4;
     double acc_prev[NV], gz_prev[NV];
     R zp_prev[NV];
 #pragma unroll
@@ -381,7 +387,8 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
         if (rz >= 1) {
             double out[NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) out[v] = acc_prev[v] + (gz_prev[v] - gz[v]);
+            for (int v = 0; v < NV; ++v)
+                out[v] = (ACC_LDS ? S.acc[ACC_LDS ? tid : 0][v] : acc_prev[v]) + (gz_prev[v] - gz[v]);
             bool sdummy;
             const int64_t cell = source_cell(S, g, x, y, rz - 1, sdummy);
 #pragma unroll
@@ -409,7 +416,11 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
                 const double gxp = static_cast<double>(S.u_.fl.fx[x + 1][y][v]) * r;
                 const double gym = static_cast<double>(S.u_.fl.fy[y][x][v]) * r;
                 const double gyp = static_cast<double>(S.u_.fl.fy[y + 1][x][v]) * r;
-                acc_prev[v] = (Ucur[v] + (gxm - gxp)) + (gym - gyp);
+                const double acc = (Ucur[v] + (gxm - gxp)) + (gym - gyp);
+                if constexpr (ACC_LDS)
+                    S.acc[tid][v] = acc;
+                else
+                    acc_prev[v] = acc;
             }
         }
         // shift the plane window

@@ -137,13 +137,14 @@ rg_status rg_permute_rows(const double *d_in, const int32_t *d_perm, int64_t n_r
 
 /* Workspace for n keys: a 256-byte header, then capacity = the power of two
  * >= 2n (load factor <= 1/2) slots of uint64 keys and int32 values, then the
- * scratch of the build (about 20 n bytes plus the bucket sort's storage). */
+ * scratch of the build (about 9 n bytes). */
 size_t rg_hash_workspace_bytes(int64_t n_keys);
 
 /* Clears the table and inserts (d_keys[i], i) for i < n: slot = FNV-1a-64
  * over the 8 little-endian key bytes, masked by capacity - 1, then linear
  * probing.  Built segment by segment: keys are bucketed by the 4096-slot
- * segment of their home slot, each segment is filled in LDS with 64-bit
+ * segment of their home slot (a counting sort: per-chunk counts, their
+ * prefix, a scatter), each segment is filled in LDS with 64-bit
  * compare-and-swap and written out whole, and the few probe sequences that
  * leave their segment are finished with global compare-and-swap.  Keys must
  * be non-zero and unique; violations are flagged in the header (rg_check).

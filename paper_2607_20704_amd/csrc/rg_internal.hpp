@@ -152,6 +152,56 @@ __host__ __device__ inline void hilbert_point20(uint64_t h, uint32_t &x, uint32_
     z = a2;
 }
 
+// Index of (x, y, z), 0 <= x, y, z < 2^nb, on the order-nb curve.  Equal to
+// hilbert_index20 of the coordinates shifted left by 20 - nb, shifted right
+// by 3 (20 - nb): the bit planes below the shift are zero and every pass on
+// them is a no-op, so only the nb planes of the level are run.
+__host__ __device__ inline uint64_t hilbert_index_bits(uint32_t x, uint32_t y, uint32_t z, int nb)
+{
+    uint32_t a0 = x, a1 = y, a2 = z;
+    for (int b = nb - 1; b >= 1; --b) hilbert_plane(a0, a1, a2, 1u << b);
+    a1 ^= a0;
+    a2 ^= a1;
+    uint32_t flip = 0;
+    for (int b = nb - 1; b >= 1; --b)
+        if (a2 & (1u << b)) flip ^= (1u << b) - 1;
+    a0 ^= flip;
+    a1 ^= flip;
+    a2 ^= flip;
+    return (spread3(a0) << 2) | (spread3(a1) << 1) | spread3(a2);
+}
+
+// inverse of hilbert_index_bits
+__host__ __device__ inline void hilbert_point_bits(uint64_t h, int nb, uint32_t &x, uint32_t &y, uint32_t &z)
+{
+    uint32_t a0 = gather3(h >> 2), a1 = gather3(h >> 1), a2 = gather3(h);
+    uint32_t t = a2 >> 1;
+    a2 ^= a1;
+    a1 ^= a0;
+    a0 ^= t;
+    for (int b = 1; b < nb; ++b) {
+        const uint32_t q = 1u << b, low = q - 1;
+        if (a2 & q) {
+            a0 ^= low;
+        } else {
+            uint32_t d = (a0 ^ a2) & low;
+            a0 ^= d;
+            a2 ^= d;
+        }
+        if (a1 & q) {
+            a0 ^= low;
+        } else {
+            uint32_t d = (a0 ^ a1) & low;
+            a0 ^= d;
+            a1 ^= d;
+        }
+        if (a0 & q) a0 ^= low;
+    }
+    x = a0;
+    y = a1;
+    z = a2;
+}
+
 // K = 2^(3(l-1)) + H_(l-1)(i,j,k); 0 for coordinates out of range
 __host__ __device__ inline uint64_t oct_key(int32_t i, int32_t j, int32_t k, int32_t l)
 {
@@ -159,9 +209,8 @@ __host__ __device__ inline uint64_t oct_key(int32_t i, int32_t j, int32_t k, int
     const int b = l - 1;
     const int32_t n = 1 << b;
     if (i < 0 || j < 0 || k < 0 || i >= n || j >= n || k >= n) return 0;
-    const int s = kHilbertOrder - b;
-    uint64_t h = hilbert_index20(static_cast<uint32_t>(i) << s, static_cast<uint32_t>(j) << s,
-                                 static_cast<uint32_t>(k) << s) >> (3 * s);
+    const uint64_t h = hilbert_index_bits(static_cast<uint32_t>(i), static_cast<uint32_t>(j),
+                                          static_cast<uint32_t>(k), b);
     return (uint64_t(1) << (3 * b)) + h;
 }
 
@@ -180,13 +229,11 @@ __host__ __device__ inline void key_coords(uint64_t key, int32_t &i, int32_t &j,
 {
     l = key_level(key);
     const int b = l - 1;
-    const int s = kHilbertOrder - b;
-    uint64_t h = key - (uint64_t(1) << (3 * b));
     uint32_t x, y, z;
-    hilbert_point20(h << (3 * s), x, y, z);
-    i = static_cast<int32_t>(x >> s);
-    j = static_cast<int32_t>(y >> s);
-    k = static_cast<int32_t>(z >> s);
+    hilbert_point_bits(key - (uint64_t(1) << (3 * b)), b, x, y, z);
+    i = static_cast<int32_t>(x);
+    j = static_cast<int32_t>(y);
+    k = static_cast<int32_t>(z);
 }
 
 // ---------------------------------------------------------------------------

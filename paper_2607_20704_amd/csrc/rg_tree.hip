@@ -116,33 +116,31 @@ constexpr int kSegLog = 12;
 constexpr int kSegMax = 1 << kSegLog;
 
 struct SegBuild {
-    uint32_t *seg_in, *seg_out, *idx_in, *idx_out;   // [n] each
-    uint32_t *seg_begin, *seg_end;                   // [nseg] each
+    uint32_t *idx;                                   // [n] key indices, bucketed by segment
+    uint32_t *hist;                                  // [nseg][nblk] per-chunk counts, then offsets
+    uint32_t *seg_begin, *seg_end, *seg_tot;         // [nseg] each
     uint32_t *ovf_count;                             // [64] (first used)
     uint32_t *ovf;                                   // [n]
-    void *temp;
-    size_t temp_bytes;
     int seg_log, bits;
-    int64_t nseg;
+    int64_t nseg, nblk;
 };
+
+// keys per bucketing workgroup
+constexpr int kBucketChunk = 4096;
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-int seg_log_for(uint64_t cap)
+int log2_ceil(uint64_t cap)
 {
     int lc = 0;
     while ((uint64_t(1) << lc) < cap) ++lc;
-    return lc < kSegLog ? lc : kSegLog;
+    return lc;
 }
 
-size_t seg_sort_temp(int64_t n, int bits)
+int seg_log_for(uint64_t cap)
 {
-    if (n <= 0 || bits <= 0) return 0;
-    size_t temp = 0;
-    hipcub::DeviceRadixSort::SortPairs(nullptr, temp, static_cast<const uint32_t *>(nullptr),
-                                       static_cast<uint32_t *>(nullptr), static_cast<const uint32_t *>(nullptr),
-                                       static_cast<uint32_t *>(nullptr), static_cast<int>(n), 0, bits);
-    return temp;
+    const int lc = log2_ceil(cap);
+    return lc < kSegLog ? lc : kSegLog;
 }
 
 size_t table_bytes(uint64_t cap) { return align256(sizeof(HashHeader) + cap * (sizeof(uint64_t) + sizeof(int32_t))); }
@@ -152,66 +150,128 @@ SegBuild seg_build_layout(void *ws, int64_t n, uint64_t cap)
 {
     SegBuild b;
     b.seg_log = seg_log_for(cap);
-    int lc = 0;
-    while ((uint64_t(1) << lc) < cap) ++lc;
-    b.bits = lc - b.seg_log;
+    b.bits = log2_ceil(cap) - b.seg_log;
     b.nseg = int64_t(1) << b.bits;
+    b.nblk = n > 0 ? (n + kBucketChunk - 1) / kBucketChunk : 1;
     char *p = static_cast<char *>(ws) + table_bytes(cap);
     const size_t nb = align256(static_cast<size_t>(n) * sizeof(uint32_t));
-    b.seg_in = reinterpret_cast<uint32_t *>(p);
-    p += nb;
-    b.seg_out = reinterpret_cast<uint32_t *>(p);
-    p += nb;
-    b.idx_in = reinterpret_cast<uint32_t *>(p);
-    p += nb;
-    b.idx_out = reinterpret_cast<uint32_t *>(p);
+    b.idx = reinterpret_cast<uint32_t *>(p);
     p += nb;
     b.ovf = reinterpret_cast<uint32_t *>(p);
     p += nb;
+    b.hist = reinterpret_cast<uint32_t *>(p);
+    p += align256(static_cast<size_t>(b.nseg * b.nblk) * sizeof(uint32_t));
     b.seg_begin = reinterpret_cast<uint32_t *>(p);
     b.seg_end = b.seg_begin + b.nseg;
-    b.ovf_count = b.seg_end + b.nseg;
-    p += align256(static_cast<size_t>(2 * b.nseg + 64) * sizeof(uint32_t));
-    b.temp = p;
-    b.temp_bytes = seg_sort_temp(n, b.bits);
+    b.seg_tot = b.seg_end + b.nseg;
+    b.ovf_count = b.seg_tot + b.nseg;
     return b;
 }
 
 size_t seg_build_bytes(int64_t n, uint64_t cap)
 {
-    const int seg_log = seg_log_for(cap);
-    int lc = 0;
-    while ((uint64_t(1) << lc) < cap) ++lc;
-    const int bits = lc - seg_log;
+    const int64_t nn = n < 0 ? 0 : n;
+    const int bits = log2_ceil(cap) - seg_log_for(cap);
     const int64_t nseg = int64_t(1) << bits;
-    const size_t nb = align256(static_cast<size_t>(n < 0 ? 0 : n) * sizeof(uint32_t));
-    return 5 * nb + align256(static_cast<size_t>(2 * nseg + 64) * sizeof(uint32_t)) +
-           align256(seg_sort_temp(n, bits));
+    const int64_t nblk = nn > 0 ? (nn + kBucketChunk - 1) / kBucketChunk : 1;
+    const size_t nb = align256(static_cast<size_t>(nn) * sizeof(uint32_t));
+    return 2 * nb + align256(static_cast<size_t>(nseg * nblk) * sizeof(uint32_t)) +
+           align256(static_cast<size_t>(3 * nseg + 64) * sizeof(uint32_t));
 }
 
-__global__ void k_seg_prepare(const uint64_t *__restrict__ keys, int64_t n, uint64_t mask, int seg_log,
-                              uint32_t *__restrict__ seg_in, uint32_t *__restrict__ idx_in, HashHeader *hdr,
-                              uint64_t cap)
+// per chunk of kBucketChunk keys: how many fall in each segment
+__global__ __launch_bounds__(256) void k_bucket_count(const uint64_t *__restrict__ keys, int64_t n, uint64_t mask,
+                                                      int seg_log, int64_t nseg, uint32_t *__restrict__ hist,
+                                                      HashHeader *hdr, uint64_t cap, uint32_t *ovf_count)
 {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i == 0) {
+    extern __shared__ uint32_t cnt[];
+    const int64_t blk = blockIdx.x, nblk = gridDim.x;
+    if (blk == 0 && threadIdx.x == 0) {
         hdr->cap = cap;
         hdr->n = n;
         hdr->err = 0;
         hdr->bad = -1;
+        *ovf_count = 0;
     }
-    if (i >= n) return;
-    seg_in[i] = static_cast<uint32_t>((fnv1a64(keys[i]) & mask) >> seg_log);
-    idx_in[i] = static_cast<uint32_t>(i);
+    for (int64_t s = threadIdx.x; s < nseg; s += blockDim.x) cnt[s] = 0;
+    __syncthreads();
+    const int64_t b0 = blk * kBucketChunk, b1 = b0 + kBucketChunk < n ? b0 + kBucketChunk : n;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x)
+        atomicAdd(&cnt[(fnv1a64(keys[i]) & mask) >> seg_log], 1u);
+    __syncthreads();
+    for (int64_t s = threadIdx.x; s < nseg; s += blockDim.x) hist[s * nblk + blk] = cnt[s];
 }
 
-__global__ void k_seg_bounds(const uint32_t *__restrict__ seg, int64_t n, uint32_t *seg_begin, uint32_t *seg_end)
+// Per segment (one workgroup each): the exclusive prefix of its per-chunk
+// counts, in place, and its total.
+__global__ __launch_bounds__(256) void k_bucket_scan_seg(uint32_t *__restrict__ hist, int64_t nblk,
+                                                         uint32_t *__restrict__ seg_tot)
 {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t s = seg[i];
-    if (i == 0 || seg[i - 1] != s) seg_begin[s] = static_cast<uint32_t>(i);
-    if (i == n - 1 || seg[i + 1] != s) seg_end[s] = static_cast<uint32_t>(i + 1);
+    __shared__ uint32_t sc[256];
+    uint32_t *row = hist + blockIdx.x * nblk;
+    const int64_t per = (nblk + 255) / 256;
+    const int64_t b0 = threadIdx.x * per, b1 = b0 + per < nblk ? b0 + per : nblk;
+    uint32_t sum = 0;
+    for (int64_t k = b0; k < b1; ++k) sum += row[k];
+    sc[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint32_t v = threadIdx.x >= off ? sc[threadIdx.x - off] : 0u;
+        __syncthreads();
+        sc[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = sc[threadIdx.x] - sum;
+    for (int64_t k = b0; k < b1; ++k) {
+        const uint32_t t = row[k];
+        row[k] = run;
+        run += t;
+    }
+    if (threadIdx.x == 255) seg_tot[blockIdx.x] = sc[255];
+}
+
+// Segment bounds from the segment totals (one workgroup of 1024 threads).
+__global__ __launch_bounds__(1024) void k_bucket_scan_tot(const uint32_t *__restrict__ seg_tot, int64_t nseg,
+                                                          uint32_t *__restrict__ seg_begin,
+                                                          uint32_t *__restrict__ seg_end)
+{
+    __shared__ uint32_t sc[1024];
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < nseg; base += 1024) {
+        const int64_t seg = base + threadIdx.x;
+        const uint32_t tot = seg < nseg ? seg_tot[seg] : 0u;
+        sc[threadIdx.x] = tot;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const uint32_t v = threadIdx.x >= off ? sc[threadIdx.x - off] : 0u;
+            __syncthreads();
+            sc[threadIdx.x] += v;
+            __syncthreads();
+        }
+        if (seg < nseg) {
+            seg_begin[seg] = carry + sc[threadIdx.x] - tot;
+            seg_end[seg] = carry + sc[threadIdx.x];
+        }
+        carry += sc[1023];
+        __syncthreads();
+    }
+}
+
+// key indices into their segment's range (order inside a segment is free)
+__global__ __launch_bounds__(256) void k_bucket_scatter(const uint64_t *__restrict__ keys, int64_t n, uint64_t mask,
+                                                        int seg_log, int64_t nseg, const uint32_t *__restrict__ hist,
+                                                        const uint32_t *__restrict__ seg_begin,
+                                                        uint32_t *__restrict__ idx)
+{
+    extern __shared__ uint32_t cur[];
+    const int64_t blk = blockIdx.x, nblk = gridDim.x;
+    for (int64_t s = threadIdx.x; s < nseg; s += blockDim.x) cur[s] = seg_begin[s] + hist[s * nblk + blk];
+    __syncthreads();
+    const int64_t b0 = blk * kBucketChunk, b1 = b0 + kBucketChunk < n ? b0 + kBucketChunk : n;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
+        const uint32_t pos = atomicAdd(&cur[(fnv1a64(keys[i]) & mask) >> seg_log], 1u);
+        idx[pos] = static_cast<uint32_t>(i);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_seg_build(const uint64_t *__restrict__ keys,
@@ -475,23 +535,22 @@ rg_status rg_hash_build(const uint64_t *d_keys, int64_t n, void *d_ws, size_t ws
     HashView h = hash_view(d_ws, cap);
     hipStream_t s = as_stream(stream);
     SegBuild b = seg_build_layout(d_ws, n, cap);
-    RG_TRY(fill_u32(b.seg_begin, 2 * b.nseg + 64, 0u, s));
-    k_seg_prepare<<<grid_for(n, 256), 256, 0, s>>>(d_keys, n, h.mask, b.seg_log, b.seg_in, b.idx_in, h.hdr, cap);
-    RG_TRY(launch_status("rg_hash_build prepare"));
-    const uint32_t *seg = b.seg_in, *idx = b.idx_in;
-    if (n > 0 && b.bits > 0) {
-        size_t tb = b.temp_bytes;
-        hipError_t e = hipcub::DeviceRadixSort::SortPairs(b.temp, tb, b.seg_in, b.seg_out, b.idx_in, b.idx_out,
-                                                          static_cast<int>(n), 0, b.bits, s);
-        if (e != hipSuccess) return fail(RG_EHIP, "hash bucket sort: %s", hipGetErrorString(e));
-        RG_TRY(launch_status("rg_hash_build sort"));
-        seg = b.seg_out;
-        idx = b.idx_out;
-    }
+    const size_t cnt_bytes = static_cast<size_t>(b.nseg) * sizeof(uint32_t);
+    RG_REQUIRE(cnt_bytes <= 64 * 1024, "table too large for the bucketed build (%lld segments)", (long long)b.nseg);
+    const unsigned nblk = static_cast<unsigned>(b.nblk);
+    k_bucket_count<<<nblk, 256, cnt_bytes, s>>>(d_keys, n, h.mask, b.seg_log, b.nseg, b.hist, h.hdr, cap,
+                                                b.ovf_count);
+    RG_TRY(launch_status("rg_hash_build count"));
+    k_bucket_scan_seg<<<static_cast<unsigned>(b.nseg), 256, 0, s>>>(b.hist, b.nblk, b.seg_tot);
+    RG_TRY(launch_status("rg_hash_build scan"));
+    k_bucket_scan_tot<<<1, 1024, 0, s>>>(b.seg_tot, b.nseg, b.seg_begin, b.seg_end);
+    RG_TRY(launch_status("rg_hash_build bounds"));
     if (n > 0) {
-        k_seg_bounds<<<grid_for(n, 256), 256, 0, s>>>(seg, n, b.seg_begin, b.seg_end);
-        RG_TRY(launch_status("rg_hash_build bounds"));
+        k_bucket_scatter<<<nblk, 256, cnt_bytes, s>>>(d_keys, n, h.mask, b.seg_log, b.nseg, b.hist, b.seg_begin,
+                                                      b.idx);
+        RG_TRY(launch_status("rg_hash_build scatter"));
     }
+    const uint32_t *idx = b.idx;
     k_seg_build<<<static_cast<unsigned>(b.nseg), 256, 0, s>>>(d_keys, b.seg_begin, b.seg_end, idx, h.hdr, h.keys,
                                                               h.vals, h.mask, b.seg_log, b.ovf_count, b.ovf);
     RG_TRY(launch_status("rg_hash_build segments"));

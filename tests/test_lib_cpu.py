@@ -151,13 +151,13 @@ def test_batch_argument_errors_without_a_device():
 def test_workspace_sizes():
     lib = L.lib()
     # the table (256-byte header, capacity = power of two >= 2n slots of 12
-    # bytes) followed by the scratch of the segmented build (five int32 arrays
-    # of n entries, segment bounds, the bucket sort's temporary storage)
+    # bytes) followed by the scratch of the segmented build (two int32 arrays
+    # of n entries, the per-chunk segment counts, the segment bounds)
     def table(cap):
         return (256 + cap * 12 + 255) // 256 * 256
     for n, cap in ((0, 16), (4096, 8192), (4097, 16384), (1 << 21, 1 << 22)):
         b = lib.rg_hash_workspace_bytes(n)
-        assert b >= table(cap) + 5 * 4 * n, (n, b)
+        assert b >= table(cap) + 2 * 4 * n, (n, b)
         assert b % 256 == 0
-        assert b < table(cap) + 5 * 4 * n + 4 * 1024 * 1024 + n * 16, (n, b)
+        assert b < table(cap) + 2 * 4 * n + 2 * n + 64 * 1024, (n, b)
     assert lib.rg_corr_workspace_bytes(10) == 2400

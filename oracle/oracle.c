@@ -29,8 +29,9 @@
  * hash parameters, injection of coarse values into ghost cells, zero-gradient
  * outflow, density/pressure floors, minmod on primitive variables, the
  * primitive-variable Hancock predictor, Davis wave speeds, the symmetric HLLC
- * star state, global time step, coarse-fine flux correction, and the CFL
- * formula.
+ * star state, global time step, coarse-fine flux correction, the CFL
+ * formula, and (for the subcycled driver at the end of the file) the time
+ * step of each level and the coarse values its ghosts take.
  *
  * Every floating-point expression is written in the exact order in which it
  * is evaluated (build with -ffp-contract=off, no fast-math).
@@ -40,7 +41,10 @@
  * (uniform-state preservation, conservation, mirror symmetry, HLLC
  * consistency, exact Sod and Sedov-Taylor within truncation error); the paper
  * prints no per-cell values, so absolute per-cell values are "parity
- * unpinned" beyond those properties.
+ * unpinned" beyond those properties.  The subcycled driver is pinned by its
+ * exact reduction to the global step (one level; a disturbance that stays on
+ * the finest level), conservation, uniform states, symmetry and a brute-force
+ * step size.
  */
 #include <math.h>
 #include <stdint.h>
@@ -626,4 +630,134 @@ void orc_run(int64_t n, const int32_t *ijkl, const int32_t *nbr27, const int32_t
         double dt = orc_step(n, ijkl, nbr27, father_cell, son_mask, u, gamma, cfl);
         if (dts) dts[s] = dt;
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Level subcycling                                                         */
+/* ------------------------------------------------------------------------ */
+
+/* The paper advances the AMR hierarchy level by level with adaptive time
+ * steps (Sec. 2, refinement and time stepping): a level l takes two steps of
+ * half the size of level l-1's step.  Reading used here (the paper gives no
+ * formulas): the coarse step dt_lmin is the CFL limit of every leaf cell
+ * scaled to the coarsest level, min over leaves of 2^(l - lmin) CFL dx_l /
+ * (|u|+|v|+|w|+3c); level l uses dt_lmin / 2^(l - lmin).  Advancing level l:
+ *   1. hydro update of its octs from uold into unew; its coarse ghosts are
+ *      the coarse level's values in uold (the state at the start of the
+ *      coarse step: no interpolation in time); its fluxes owed to coarse
+ *      cells go to corr;
+ *   2. if a finer level exists: twice { advance level l+1; acc += corr of
+ *      the level l+1 octs; uold <- unew for levels l+1 and finer };
+ *   3. the accumulated fine fluxes acc are added to the coarse cells (sides
+ *      in order x-, x+, y-, y+, z-, z+);
+ *   4. level l+1 is restricted into the split cells of level l (unew).
+ * The coarse cell's own flux on a coarse-fine face is zeroed in step 1, so
+ * the fine fluxes of both substeps replace it: mass, momentum and energy are
+ * conserved to round-off. */
+
+typedef struct {
+    orc_tree t;
+    const int32_t *father_cell;
+    int64_t lbeg[ORC_MAX_LEVEL + 2];
+    int lmin, lmax;
+    double *uold, *unew, *corr, *acc;
+    double gamma;
+} sub_ctx;
+
+static void advance_level(sub_ctx *c, int l, double dt)
+{
+    const int64_t ob = c->lbeg[l], oe = c->lbeg[l + 1];
+    for (int64_t o = ob; o < oe; ++o) hydro_oct(&c->t, o, c->uold, c->unew, c->corr, level_dx(l), dt, c->gamma);
+    if (l == c->lmax) return;
+    const int64_t fb = c->lbeg[l + 1], fe = c->lbeg[l + 2];
+    for (int64_t k = 30 * fb; k < 30 * fe; ++k) c->acc[k] = 0.0;
+    for (int sub = 0; sub < 2; ++sub) {
+        advance_level(c, l + 1, 0.5 * dt);
+        for (int64_t k = 30 * fb; k < 30 * fe; ++k) c->acc[k] = c->acc[k] + c->corr[k];
+        memcpy(c->uold + 40 * fb, c->unew + 40 * fb, (size_t)(40 * (c->lbeg[c->lmax + 1] - fb)) * sizeof(double));
+    }
+    for (int side = 0; side < 6; ++side) {
+        int a = side / 2;
+        int fs[3] = {0, 0, 0};
+        fs[a] = (side & 1) ? 1 : -1;
+        int s = nslot(fs[0], fs[1], fs[2]);
+        for (int64_t o = fb; o < fe; ++o) {
+            int32_t e = c->t.nbr27[27 * o + s];
+            if (!(e < 0 && e != ORC_OUTSIDE)) continue;
+            int64_t cc = -1 - (int64_t)e;
+            for (int v = 0; v < 5; ++v) c->unew[5 * cc + v] = c->unew[5 * cc + v] + c->acc[30 * o + 5 * side + v];
+        }
+    }
+    for (int64_t o = fb; o < fe; ++o) {
+        int64_t f = c->father_cell[o];
+        for (int v = 0; v < 5; ++v) {
+            const double *cl = c->unew + 40 * o + v;
+            double sum = ((cl[0] + cl[5]) + (cl[10] + cl[15])) + ((cl[20] + cl[25]) + (cl[30] + cl[35]));
+            c->unew[5 * f + v] = 0.125 * sum;
+        }
+    }
+}
+
+/* Coarse time step of the subcycled scheme (see above). */
+double orc_cfl_dt_subcycled(int64_t n, const int32_t *ijkl, const uint8_t *son_mask, const double *u, double gamma,
+                            double cfl)
+{
+    int lmin = ORC_MAX_LEVEL + 1;
+    for (int64_t o = 0; o < n; ++o)
+        if (ijkl[4 * o + 3] < lmin) lmin = ijkl[4 * o + 3];
+    double best = INFINITY;
+    for (int64_t o = 0; o < n; ++o) {
+        int l = ijkl[4 * o + 3];
+        double dx = level_dx(l);
+        for (int c = 0; c < 8; ++c) {
+            if ((son_mask[o] >> c) & 1) continue;
+            double W[5];
+            orc_prim(u + 5 * (8 * o + c), gamma, W);
+            double cs = sqrt((gamma * W[4]) / W[0]);
+            double sp = ((fabs(W[1]) + fabs(W[2])) + fabs(W[3])) + 3.0 * cs;
+            double d = ldexp(dx / sp, l - lmin);
+            if (d < best) best = d;
+        }
+    }
+    return cfl * best;
+}
+
+/* One coarse step with level subcycling; octs in key order (levels
+ * contiguous, ascending).  Returns the coarse time step. */
+double orc_step_subcycled(int64_t n, const int32_t *ijkl, const int32_t *nbr27, const int32_t *father_cell,
+                          const uint8_t *son_mask, double *u, double gamma, double cfl)
+{
+    sub_ctx c;
+    c.t.n = n;
+    c.t.ijkl = ijkl;
+    c.t.nbr27 = nbr27;
+    c.t.father_cell = father_cell;
+    c.t.son_mask = son_mask;
+    c.father_cell = father_cell;
+    c.gamma = gamma;
+    c.lmin = ORC_MAX_LEVEL + 1;
+    c.lmax = 0;
+    for (int l = 0; l < ORC_MAX_LEVEL + 2; ++l) c.lbeg[l] = 0;
+    for (int64_t o = 0; o < n; ++o) {
+        int l = ijkl[4 * o + 3];
+        if (l < c.lmin) c.lmin = l;
+        if (l > c.lmax) c.lmax = l;
+    }
+    /* levels are contiguous and ascending in key order */
+    for (int l = 0; l < ORC_MAX_LEVEL + 2; ++l) {
+        int64_t b = 0;
+        while (b < n && ijkl[4 * b + 3] < l) ++b;
+        c.lbeg[l] = b;
+    }
+    const double dt = orc_cfl_dt_subcycled(n, ijkl, son_mask, u, gamma, cfl);
+    c.uold = u;
+    c.unew = (double *)malloc((size_t)(40 * (n > 0 ? n : 1)) * sizeof(double));
+    c.corr = (double *)calloc((size_t)(30 * (n > 0 ? n : 1)), sizeof(double));
+    c.acc = (double *)calloc((size_t)(30 * (n > 0 ? n : 1)), sizeof(double));
+    advance_level(&c, c.lmin, dt);
+    memcpy(u, c.unew, (size_t)(40 * n) * sizeof(double));
+    free(c.unew);
+    free(c.corr);
+    free(c.acc);
+    return dt;
 }

@@ -76,6 +76,10 @@ def lib():
         L.orc_step_fixed.argtypes = [i64, P, P, P, P, P, f64, f64]
         L.orc_run.restype = None
         L.orc_run.argtypes = [i64, P, P, P, P, P, f64, f64, i64, P]
+        L.orc_cfl_dt_subcycled.restype = f64
+        L.orc_cfl_dt_subcycled.argtypes = [i64, P, P, P, f64, f64]
+        L.orc_step_subcycled.restype = f64
+        L.orc_step_subcycled.argtypes = [i64, P, P, P, P, P, f64, f64]
         _lib = L
     return _lib
 
@@ -215,3 +219,18 @@ class Tree:
         lib().orc_run(self.n, _p(self.ijkl), _p(self.nbr27), _p(self.father_cell), _p(self.son_mask),
                       _p(u), float(gamma), float(cfl), int(nsteps), _p(dts))
         return dts
+
+    def cfl_dt_subcycled(self, u, gamma, cfl):
+        """Coarse time step of the subcycled scheme."""
+        return lib().orc_cfl_dt_subcycled(self.n, _p(self.ijkl), _p(self.son_mask), _p(_c(u, np.float64)),
+                                          float(gamma), float(cfl))
+
+    def step_subcycled(self, u, gamma, cfl):
+        """One coarse step with level subcycling, in place; returns the coarse dt."""
+        assert u.dtype == np.float64 and u.flags.c_contiguous and u.shape == (8 * self.n, 5)
+        return lib().orc_step_subcycled(self.n, _p(self.ijkl), _p(self.nbr27), _p(self.father_cell),
+                                        _p(self.son_mask), _p(u), float(gamma), float(cfl))
+
+    def run_subcycled(self, u, gamma, cfl, nsteps):
+        """nsteps coarse subcycled steps in place; returns the coarse dts."""
+        return np.array([self.step_subcycled(u, gamma, cfl) for _ in range(nsteps)])

@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define RG_ABI_VERSION 2
+#define RG_ABI_VERSION 3
 #define RG_MAX_LEVEL 21
 #define RG_NBR_OUTSIDE INT32_MIN
 #define RG_RHO_MIN 1e-10
@@ -353,6 +353,34 @@ rg_status rg_prepare_tree(const rg_tree *t, unsigned flags, void *stream);
  * The caller swaps uold and unew afterwards. */
 rg_status rg_step(const rg_tree *t, const double *d_uold, double *d_unew, double gamma, double cfl, int form,
                   unsigned flags, double *d_dt, const rg_tuning *tune, void *stream);
+
+/* One coarse step with level subcycling (Sec. 2: adaptive time steps level
+ * by level, each level taking two steps of half its parent's):
+ *   rg_prepare_tree(t, flags) (flags: RG_STEP_REBUILD, RG_STEP_REKEY or 0);
+ *   d_dt[0] = D = cfl * min over leaf cells of 2^(l - lmin) dx_l /
+ *   (|u|+|v|+|w|+3c), the coarse step; d_dt[1 + k] = D / 2^k, the step of
+ *   level lmin + k (d_dt: device, double[2 + lmax - lmin]);
+ *   advance(lmin, D), where advance(l, dt) is: level l's update with dt (as
+ *   rg_hydro_step_level; its coarse ghost cells take the coarser level's
+ *   values from the start of that level's current step); if l < lmax, twice
+ *   { advance(l + 1, dt / 2); acc += the coarse-side fluxes of level l+1 },
+ *   then acc added to the coarse cells side by side (as
+ *   rg_apply_coarse_corrections) and level l+1 restricted into level l.
+ * The fine fluxes of both substeps replace the coarse flux on a coarse-fine
+ * face, so mass, momentum and energy are conserved to round-off.  With one
+ * level this is rg_step, bit for bit.
+ *
+ * d_u (device, 8 n_oct x 5 doubles, key order) is advanced in place;
+ * d_scratch is a second buffer of the same size whose contents are
+ * overwritten (levels alternate between the two buffers, so no level is
+ * copied between substeps; the coarsest level is copied back at the end).
+ * d_acc: rg_corr_workspace_bytes(n_oct - level_begin[lmin + 1]) bytes, like
+ * t->d_corr; both may be NULL only when lmin == lmax.  form is RG_FP64 or
+ * RG_MIXED; tune as for rg_step (the brick kernel serves the bricks of the
+ * schedule, if t->sched is set).  Asynchronous on `stream`; the host walks
+ * the level recursion, issuing 2^(l - lmin) updates of level l. */
+rg_status rg_step_subcycled(const rg_tree *t, double *d_u, double *d_scratch, double *d_acc, double gamma, double cfl,
+                            int form, unsigned flags, double *d_dt, const rg_tuning *tune, void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Many independent trees in one graph launch                             */

@@ -81,6 +81,8 @@ SIGNATURES = {
                                      P, f64, P, ctypes.c_int, ctypes.POINTER(RgTuning), P]),
     "rg_step": (st, [ctypes.POINTER(RgTree), P, P, f64, f64, ctypes.c_int, ctypes.c_uint, P,
                      ctypes.POINTER(RgTuning), P]),
+    "rg_step_subcycled": (st, [ctypes.POINTER(RgTree), P, P, P, f64, f64, ctypes.c_int, ctypes.c_uint, P,
+                               ctypes.POINTER(RgTuning), P]),
     "rg_batch_create": (st, [ctypes.POINTER(RgBatchTree), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint,
                              ctypes.POINTER(RgTuning), P, P, ctypes.POINTER(P)]),
     "rg_batch_run": (st, [P, P]),

@@ -290,6 +290,31 @@ class DeviceTree:
         return a, dts[:nsteps]
 
 
+    def step_subcycled(self, u, gamma, cfl, form=RG_FP64, rebuild=False, dt=None, tune=None, scratch=None):
+        """One coarse step with level subcycling, advancing u in place.
+        Returns dt: dt[0] the coarse step, dt[1 + k] level lmin + k's step."""
+        if dt is None:
+            dt = torch.empty(self.lmax - self.lmin + 2, dtype=torch.float64, device="cuda")
+        if scratch is None:
+            scratch = torch.empty_like(u)
+        if self.corr is not None and getattr(self, "acc", None) is None:
+            self.acc = torch.empty_like(self.corr)
+        flags = (RG_STEP_REBUILD | L.RG_STEP_REKEY) if rebuild else 0
+        check(L.lib().rg_step_subcycled(ctypes.byref(self._desc), _ptr(u), _ptr(scratch),
+                                        _ptr(self.acc if self.corr is not None else None), float(gamma), float(cfl),
+                                        int(form), flags, _ptr(dt), _tuning(tune), _stream()))
+        return dt
+
+    def run_subcycled(self, u, gamma, cfl, nsteps, form=RG_FP64, rebuild=False, tune=None):
+        """nsteps coarse subcycled steps on a copy of u; returns (state, dts)
+        with dts[s] the coarse step of step s."""
+        a, scratch = u.clone(), torch.empty_like(u)
+        dts = torch.empty((nsteps, self.lmax - self.lmin + 2), dtype=torch.float64, device="cuda")
+        for s in range(nsteps):
+            self.step_subcycled(a, gamma, cfl, form, rebuild, dts[s], tune, scratch)
+        return a, dts[:, 0]
+
+
 # ---------------------------------------------------------------- many trees
 
 class Batch:

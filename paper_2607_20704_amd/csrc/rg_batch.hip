@@ -185,6 +185,7 @@ __global__ __launch_bounds__(kT, sizeof(R) == 8 ? 4 : 6) void k_batch_octs(const
         LevelArgs a;
         a.list = (I.a & 3) == 1 ? T.list : nullptr;
         a.uold = T.u[parity];
+        a.ucoarse = T.u[parity];
         a.unew = T.u[parity ^ 1];
         a.nbr27 = T.nbr27;
         a.son = T.son;

@@ -46,6 +46,7 @@ struct DtArgs {
     double gamma, cfl;
     int64_t n_cell;
     unsigned long long *dt_bits;
+    int sub;   // subcycled: each limit scaled by 2^(l - lmin), the ratio of the coarse step to level l's
 };
 
 __global__ void k_set_u64(unsigned long long *p, unsigned long long v) { *p = v; }
@@ -68,7 +69,7 @@ __global__ __launch_bounds__(256) void k_cfl_dt(DtArgs a)
         prim64(U, a.gamma, W);
         const double cs = sqrt((a.gamma * W[4]) / W[0]);
         const double sp = ((fabs(W[1]) + fabs(W[2])) + fabs(W[3])) + 3.0 * cs;
-        const double d = dx / sp;
+        const double d = a.sub ? ldexp(dx / sp, l - a.lmin) : dx / sp;
         // cfl * min(d) == min(cfl * d): rounding a product by a positive
         // constant is monotone
         const double cd = a.cfl * d;
@@ -152,15 +153,17 @@ __global__ __launch_bounds__(256) void k_cfl_dt_corrected(DtArgs a, const int32_
     }
 }
 
-__global__ void k_restrict(double *__restrict__ u, const int32_t *__restrict__ father, int64_t ob, int64_t oe)
+// children read from src, father cells written in dst (the same buffer in a
+// global step; the two states of a subcycled step can differ)
+__global__ void k_restrict(const double *src, double *dst, const int32_t *__restrict__ father, int64_t ob, int64_t oe)
 {
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t o = ob + t / NV;
     const int v = static_cast<int>(t % NV);
     if (o >= oe) return;
-    const double *c = u + 8 * NV * o + v;
+    const double *c = src + 8 * NV * o + v;
     const double sum = ((c[0] + c[5]) + (c[10] + c[15])) + ((c[20] + c[25]) + (c[30] + c[35]));
-    u[NV * int64_t(father[o]) + v] = 0.125 * sum;
+    dst[NV * int64_t(father[o]) + v] = 0.125 * sum;
 }
 
 // ---------------------------------------------------------------------------
@@ -200,12 +203,13 @@ rg_status hydro_level(const LevelArgs &a, int form, const rg_tuning *tune, hipSt
 rg_status hydro_level_list(const double *uold, double *unew, const int32_t *nbr27, const uint32_t *son,
                            const int32_t *list, int64_t count, double *corr, int64_t corr_base, const double *dt,
                            double dx, double gamma, int form, const rg_tuning *tune, double cfl, double *dt_next,
-                           hipStream_t s, int64_t first)
+                           hipStream_t s, int64_t first, const double *ucoarse)
 {
     if (count <= 0) return RG_OK;
     LevelArgs a;
     a.list = list;
     a.uold = uold;
+    a.ucoarse = ucoarse ? ucoarse : uold;
     a.unew = unew;
     a.nbr27 = nbr27;
     a.son = son;
@@ -219,6 +223,46 @@ rg_status hydro_level_list(const double *uold, double *unew, const int32_t *nbr2
     a.cfl = cfl;
     a.dt_next = reinterpret_cast<unsigned long long *>(dt_next);
     return hydro_level(a, form, tune, s);
+}
+
+// restriction of octs [ob, oe) from src into their father cells in dst
+rg_status restrict_level2(const double *src, double *dst, const int32_t *father, int64_t ob, int64_t oe,
+                          hipStream_t s)
+{
+    if (oe <= ob) return RG_OK;
+    const int64_t items = (oe - ob) * NV;
+    k_restrict<<<grid_for(items, 256), 256, 0, s>>>(src, dst, father, ob, oe);
+    return launch_status("restrict");
+}
+
+// CFL pass; sub = 1 gives the coarse step of the subcycled scheme
+rg_status cfl_dt_pass(const double *d_u, const uint32_t *d_son_mask, const int64_t *h_level_begin, int lmin, int lmax,
+                      double gamma, double cfl, double *d_dt, int sub, void *stream)
+{
+    RG_REQUIRE(d_u && d_son_mask && h_level_begin && d_dt, "null pointer");
+    RG_REQUIRE(lmin >= 1 && lmax >= lmin && lmax <= RG_MAX_LEVEL, "bad level range");
+    RG_REQUIRE(gamma > 1 && cfl > 0, "bad gamma or cfl");
+    RG_REQUIRE(aligned(d_dt, 8), "misaligned dt");
+    DtArgs a;
+    a.u = d_u;
+    a.son = d_son_mask;
+    for (int l = 0; l < RG_MAX_LEVEL + 2; ++l) a.begin[l] = h_level_begin[l];
+    a.lmin = lmin;
+    a.lmax = lmax;
+    a.gamma = gamma;
+    a.cfl = cfl;
+    const int64_t n_oct = h_level_begin[lmax + 1] - h_level_begin[lmin];
+    RG_REQUIRE(h_level_begin[lmin] == 0 && n_oct >= 0, "level ranges must start at 0");
+    a.n_cell = 8 * n_oct;
+    a.sub = sub;
+    a.dt_bits = reinterpret_cast<unsigned long long *>(d_dt);
+    hipStream_t s = as_stream(stream);
+    k_set_u64<<<1, 1, 0, s>>>(a.dt_bits, 0x7ff0000000000000ull);
+    RG_TRY(launch_status("rg_cfl_dt init"));
+    if (a.n_cell == 0) return RG_OK;
+    const unsigned blocks = grid_for(a.n_cell, 256);
+    k_cfl_dt<<<blocks < 2048 ? blocks : 2048, 256, 0, s>>>(a);
+    return launch_status("rg_cfl_dt");
 }
 
 }  // namespace rg
@@ -246,6 +290,7 @@ rg_status rg_hydro_step_level(double dx, const double *d_dt, double gamma, const
     LevelArgs a;
     a.list = nullptr;
     a.uold = d_uold;
+    a.ucoarse = d_uold;
     a.unew = d_unew;
     a.nbr27 = d_nbr27;
     a.son = d_son_mask;
@@ -285,36 +330,14 @@ rg_status rg_restrict_level(double *d_u, const int32_t *d_father_cell, int64_t o
     if (oct_end == oct_begin) return RG_OK;
     RG_REQUIRE(d_u && d_father_cell, "null pointer");
     const int64_t items = (oct_end - oct_begin) * NV;
-    k_restrict<<<grid_for(items, 256), 256, 0, as_stream(stream)>>>(d_u, d_father_cell, oct_begin, oct_end);
+    k_restrict<<<grid_for(items, 256), 256, 0, as_stream(stream)>>>(d_u, d_u, d_father_cell, oct_begin, oct_end);
     return launch_status("rg_restrict_level");
 }
 
 rg_status rg_cfl_dt(const double *d_u, const uint32_t *d_son_mask, const int64_t *h_level_begin, int lmin, int lmax,
                     double gamma, double cfl, double *d_dt, void *stream)
 {
-    RG_REQUIRE(d_u && d_son_mask && h_level_begin && d_dt, "null pointer");
-    RG_REQUIRE(lmin >= 1 && lmax >= lmin && lmax <= RG_MAX_LEVEL, "bad level range");
-    RG_REQUIRE(gamma > 1 && cfl > 0, "bad gamma or cfl");
-    RG_REQUIRE(aligned(d_dt, 8), "misaligned dt");
-    DtArgs a;
-    a.u = d_u;
-    a.son = d_son_mask;
-    for (int l = 0; l < RG_MAX_LEVEL + 2; ++l) a.begin[l] = h_level_begin[l];
-    a.lmin = lmin;
-    a.lmax = lmax;
-    a.gamma = gamma;
-    a.cfl = cfl;
-    const int64_t n_oct = h_level_begin[lmax + 1] - h_level_begin[lmin];
-    RG_REQUIRE(h_level_begin[lmin] == 0 && n_oct >= 0, "level ranges must start at 0");
-    a.n_cell = 8 * n_oct;
-    a.dt_bits = reinterpret_cast<unsigned long long *>(d_dt);
-    hipStream_t s = as_stream(stream);
-    k_set_u64<<<1, 1, 0, s>>>(a.dt_bits, 0x7ff0000000000000ull);
-    RG_TRY(launch_status("rg_cfl_dt init"));
-    if (a.n_cell == 0) return RG_OK;
-    const unsigned blocks = grid_for(a.n_cell, 256);
-    k_cfl_dt<<<blocks < 2048 ? blocks : 2048, 256, 0, s>>>(a);
-    return launch_status("rg_cfl_dt");
+    return cfl_dt_pass(d_u, d_son_mask, h_level_begin, lmin, lmax, gamma, cfl, d_dt, 0, stream);
 }
 
 rg_status rg_cfl_dt_corrected(const double *d_u, const int32_t *d_nbr27, const int64_t *h_level_begin, int lmin,
@@ -334,6 +357,7 @@ rg_status rg_cfl_dt_corrected(const double *d_u, const int32_t *d_nbr27, const i
     a.gamma = gamma;
     a.cfl = cfl;
     a.n_cell = 0;
+    a.sub = 0;
     a.dt_bits = reinterpret_cast<unsigned long long *>(d_dt);
     const int64_t ob = h_level_begin[lmin + 1], oe = h_level_begin[lmax + 1];
     if (oe <= ob) return RG_OK;

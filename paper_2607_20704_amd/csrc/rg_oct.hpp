@@ -90,6 +90,7 @@ __device__ __forceinline__ int slot_of(int x) { return x < 0 ? -1 : (x > 1 ? 1 :
 struct LevelArgs {
     const int32_t *list;  // if set, the octs are list[oct_begin .. oct_end)
     const double *uold;
+    const double *ucoarse;   // coarse ghost cells (the coarser level's state; uold itself in a global step)
     double *unew;
     const int32_t *nbr27;
     const uint32_t *son;
@@ -172,9 +173,10 @@ __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, i
         if (e == RG_NBR_OUTSIDE) e = static_cast<int>(S.oct[g]);
         const int64_t cell = e >= 0 ? 8 * int64_t(e) + ((c[0] & 1) + 2 * (c[1] & 1) + 4 * (c[2] & 1))
                                     : (-1 - int64_t(e));
+        const double *src = e >= 0 ? a.uold : a.ucoarse;
         double U[NV], W[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) U[v] = a.uold[NV * cell + v];
+        for (int v = 0; v < NV; ++v) U[v] = src[NV * cell + v];
         prim64(U, a.gamma, W);
 #pragma unroll
         for (int v = 0; v < NV; ++v) S.w[g][wc][v] = static_cast<R>(W[v]);

@@ -13,7 +13,7 @@ namespace rg {
 rg_status hydro_level_list(const double *uold, double *unew, const int32_t *nbr27, const uint32_t *son,
                            const int32_t *list, int64_t count, double *corr, int64_t corr_base, const double *dt,
                            double dx, double gamma, int form, const rg_tuning *tune, double cfl, double *dt_next,
-                           hipStream_t s, int64_t first = 0);
+                           hipStream_t s, int64_t first = 0, const double *ucoarse = nullptr);
 rg_status hydro_bricks(const double *uold, double *unew, const int32_t *nbr27, const uint32_t *son,
                        const uint64_t *keys, const int32_t *bricks, int64_t nbricks, const double *dt, double dx,
                        double gamma, int outflow, int form, double cfl, double *dt_next, int waves, hipStream_t s);
@@ -24,6 +24,36 @@ using namespace rg;
 namespace {
 constexpr int64_t kBrickOcts = 512;
 }
+
+namespace rg {
+
+// One level of tree t: with a schedule, its bricks by the brick kernel and the
+// rest by the per-oct kernel; without one, the whole level by the per-oct
+// kernel.  Coarse ghost cells are read from ucoarse (bricks have none).
+rg_status hydro_tree_level(const rg_tree *t, const rg_schedule *sc, int level, const double *d_dt, double gamma,
+                           const double *d_uold, const double *d_ucoarse, double *d_unew, double cfl,
+                           double *d_dt_next, int form, const rg_tuning *tune, hipStream_t s)
+{
+    const double dx = ldexp(1.0, -level);
+    const int64_t corr_base = t->level_begin[t->lmin + 1];
+    double *corr = level > t->lmin ? t->d_corr : nullptr;
+    const bool bricks = sc && !(tune && tune->no_bricks);
+    if (bricks) {
+        RG_TRY(hydro_bricks(d_uold, d_unew, t->d_nbr27, t->d_son_mask, t->d_keys, sc->d_list + sc->brick_begin[level],
+                            sc->brick_count[level], d_dt, dx, gamma, t->bc == RG_BC_OUTFLOW, form, cfl, d_dt_next,
+                            tune ? tune->brick_waves : 0, s));
+        RG_TRY(hydro_level_list(d_uold, d_unew, t->d_nbr27, t->d_son_mask, sc->d_list + sc->rest_begin[level],
+                                sc->rest_count[level], corr, corr_base, d_dt, dx, gamma, form, tune, cfl, d_dt_next,
+                                s, 0, d_ucoarse));
+    } else {
+        RG_TRY(hydro_level_list(d_uold, d_unew, t->d_nbr27, t->d_son_mask, nullptr,
+                                t->level_begin[level + 1] - t->level_begin[level], corr, corr_base, d_dt, dx, gamma,
+                                form, tune, cfl, d_dt_next, s, t->level_begin[level], d_ucoarse));
+    }
+    return RG_OK;
+}
+
+}  // namespace rg
 
 extern "C" {
 
@@ -104,24 +134,8 @@ rg_status rg_hydro_step_scheduled(const rg_tree *t, const rg_schedule *sc, int l
     RG_REQUIRE(form == RG_FP64 || form == RG_MIXED, "bad form %d", form);
     RG_REQUIRE(gamma > 1, "bad gamma");
     RG_REQUIRE(!d_dt_next || (cfl > 0 && aligned(d_dt_next, 8)), "bad cfl or misaligned dt_next");
-    hipStream_t s = as_stream(stream);
-    const double dx = ldexp(1.0, -level);
-    const int64_t corr_base = t->level_begin[t->lmin + 1];
-    double *corr = level > t->lmin ? t->d_corr : nullptr;
-    const bool bricks = !(tune && tune->no_bricks);
-    if (bricks) {
-        RG_TRY(hydro_bricks(d_uold, d_unew, t->d_nbr27, t->d_son_mask, t->d_keys, sc->d_list + sc->brick_begin[level],
-                            sc->brick_count[level], d_dt, dx, gamma, t->bc == RG_BC_OUTFLOW, form, cfl, d_dt_next,
-                            tune ? tune->brick_waves : 0, s));
-        RG_TRY(hydro_level_list(d_uold, d_unew, t->d_nbr27, t->d_son_mask, sc->d_list + sc->rest_begin[level],
-                                sc->rest_count[level], corr, corr_base, d_dt, dx, gamma, form, tune, cfl, d_dt_next,
-                                s));
-    } else {
-        RG_TRY(hydro_level_list(d_uold, d_unew, t->d_nbr27, t->d_son_mask, nullptr,
-                                t->level_begin[level + 1] - t->level_begin[level], corr, corr_base, d_dt, dx, gamma,
-                                form, tune, cfl, d_dt_next, s, t->level_begin[level]));
-    }
-    return RG_OK;
+    return hydro_tree_level(t, sc, level, d_dt, gamma, d_uold, d_uold, d_unew, cfl, d_dt_next, form, tune,
+                            as_stream(stream));
 }
 
 }  // extern "C"

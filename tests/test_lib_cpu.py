@@ -148,6 +148,39 @@ def test_batch_argument_errors_without_a_device():
     assert lib.rg_batch_destroy(None) == L.RG_OK
 
 
+def test_subcycled_step_argument_errors_without_a_device():
+    """rg_step_subcycled checks its arguments on the host first."""
+    lib = L.lib()
+    tree = L.RgTree()
+    tree.n_oct, tree.lmin, tree.lmax = 72, 2, 3
+    tree.level_begin[2], tree.level_begin[3], tree.level_begin[4] = 0, 8, 72
+    u, scratch, acc, dt = 256, 512, 768, 1024
+    ok = (ctypes.byref(tree), u, scratch, acc, 1.4, 0.8, 0, 0, dt, None, None)
+
+    def call(**kw):
+        a = list(ok)
+        for k, v in kw.items():
+            a[["t", "u", "scratch", "acc", "gamma", "cfl", "form", "flags", "dt", "tune", "stream"].index(k)] = v
+        return lib.rg_step_subcycled(*a)
+
+    assert call(t=None) == L.RG_EINVAL
+    assert call(dt=None) == L.RG_EINVAL
+    # a multilevel tree needs the correction and accumulation buffers
+    assert call() == L.RG_EINVAL
+    assert b"accumulation" in L.detail().encode()
+    tree.d_corr = 2048
+    assert call(scratch=u) == L.RG_EINVAL
+    assert b"alias" in L.detail().encode()
+    assert call(acc=None) == L.RG_EINVAL
+    assert call(flags=L.RG_STEP_CHAIN_DT) == L.RG_EINVAL
+    assert call(form=9) == L.RG_EINVAL
+    assert call(gamma=1.0) == L.RG_EINVAL
+    assert call(cfl=0.0) == L.RG_EINVAL
+    assert call(u=257) == L.RG_EINVAL
+    tree.level_begin[4] = 71
+    assert call() == L.RG_EINVAL
+
+
 def test_workspace_sizes():
     lib = L.lib()
     # the table (256-byte header, capacity = power of two >= 2n slots of 12

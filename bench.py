@@ -199,7 +199,9 @@ def time_deep_amr(forms, nsteps, api, inputs):
     `nsteps` whole steps per form (dt, every level, corrections,
     restriction; lists prebuilt), and the mixed form's L1 error per
     conserved field against FP64 after those steps (leaf cells, volume
-    weighted)."""
+    weighted).  Also two coarse steps with level subcycling, reported as
+    cell-updates/s and as simulated time advanced per wall second beside
+    the global step's."""
     import numpy as np
     import torch
     w = inputs.deep_amr(nsteps=nsteps)
@@ -216,6 +218,8 @@ def time_deep_amr(forms, nsteps, api, inputs):
            "octs": D.n, "cells": cells,
            "octs_per_level": {str(l): int(D.level_begin[l + 1] - D.level_begin[l]) for l in range(D.lmin, D.lmax + 1)},
            "schedule": {str(l): {"bricks": c[0], "per_oct": c[1]} for l, c in D.schedule_counts().items()}}
+    updates_sub = sum(2 ** (l - D.lmin) * 8 * int(D.level_begin[l + 1] - D.level_begin[l])
+                      for l in range(D.lmin, D.lmax + 1))
     states = {}
     for f in forms:
         form = api.RG_FP64 if f == "fp64" else api.RG_MIXED
@@ -223,12 +227,31 @@ def time_deep_amr(forms, nsteps, api, inputs):
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
-        u, _ = D.run(u0, w.gamma, w.cfl, nsteps, form=form)
+        u, dts = D.run(u0, w.gamma, w.cfl, nsteps, form=form)
         b.record()
         b.synchronize()
         ms = a.elapsed_time(b) / nsteps
         states[f] = u
         out[f] = {"cell_updates_per_s": cells / (ms * 1e-3), "ms_per_step": round(ms, 4)}
+        global_dt = float(dts.mean())
+        # level subcycling: level l takes 2^(l - lmin) steps per coarse step
+        nsub = 2
+        D.run_subcycled(u0, w.gamma, w.cfl, 1, form=form)     # warm-up
+        torch.cuda.synchronize()
+        a.record()
+        _, sdts = D.run_subcycled(u0, w.gamma, w.cfl, nsub, form=form)
+        b.record()
+        b.synchronize()
+        sms = a.elapsed_time(b) / nsub
+        sdt = float(sdts.mean())
+        out[f]["subcycled"] = {
+            "ms_per_coarse_step": round(sms, 3), "coarse_steps": nsub,
+            "cell_updates_per_coarse_step": updates_sub,
+            "cell_updates_per_s": updates_sub / (sms * 1e-3),
+            "coarse_dt": sdt, "global_dt": global_dt,
+            "simulated_time_per_s": sdt / (sms * 1e-3),
+            "global_simulated_time_per_s": global_dt / (ms * 1e-3),
+        }
     if "fp64" in states and "mixed" in states:
         x, y = states["fp64"], states["mixed"]
         num = (vol[:, None] * (x - y).abs()).sum(0)

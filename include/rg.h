@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define RG_ABI_VERSION 3
+#define RG_ABI_VERSION 4
 #define RG_MAX_LEVEL 21
 #define RG_NBR_OUTSIDE INT32_MIN
 #define RG_RHO_MIN 1e-10
@@ -214,6 +214,10 @@ typedef struct rg_schedule {
      * only the slots around the brick are hashed) and the other octs */
     int64_t nbr_brick_begin, nbr_brick_count;
     int64_t nbr_rest_begin, nbr_rest_count;
+    /* coarse-fine corrections: the octs of level l (> lmin) with a coarse
+     * cell across one of their six faces */
+    int64_t border_begin[RG_MAX_LEVEL + 2];
+    int64_t border_count[RG_MAX_LEVEL + 2];
     const int32_t *d_list;
 } rg_schedule;
 
@@ -314,7 +318,7 @@ typedef struct rg_tree {
 } rg_tree;
 
 /* Builds the schedule of tree t (keys, level ranges and neighbour lists must
- * be current) into the caller's d_list (capacity >= 2 n_oct int32 entries).
+ * be current) into the caller's d_list (capacity >= 3 n_oct int32 entries).
  * Reads the keys and neighbour lists back to the host: synchronises.  Once
  * t->sched points to it, rg_prepare_tree builds neighbour lists brick by
  * brick. */
@@ -348,7 +352,8 @@ rg_status rg_prepare_tree(const rg_tree *t, unsigned flags, void *stream);
  *   over the state (so a chain of steps s = 0, 1, ... passes d_dt + s);
  *   every level: rg_hydro_step_scheduled if t->sched is set, else
  *   rg_hydro_step_level over the level (uold -> unew);
- *   rg_apply_coarse_corrections over all levels above lmin;
+ *   rg_apply_coarse_corrections over all levels above lmin (restricted to
+ *   the schedule's border lists when t->sched is set: same bits);
  *   rg_restrict_level from lmax down to lmin + 1 on unew.
  * The caller swaps uold and unew afterwards. */
 rg_status rg_step(const rg_tree *t, const double *d_uold, double *d_unew, double gamma, double cfl, int form,
@@ -363,7 +368,8 @@ rg_status rg_step(const rg_tree *t, const double *d_uold, double *d_unew, double
  *   advance(lmin, D), where advance(l, dt) is: level l's update with dt (as
  *   rg_hydro_step_level; its coarse ghost cells take the coarser level's
  *   values from the start of that level's current step); if l < lmax, twice
- *   { advance(l + 1, dt / 2); acc += the coarse-side fluxes of level l+1 },
+ *   { advance(l + 1, dt / 2) }, with acc = (0 + first substep's coarse-side
+ *   fluxes of level l+1) + second substep's,
  *   then acc added to the coarse cells side by side (as
  *   rg_apply_coarse_corrections) and level l+1 restricted into level l.
  * The fine fluxes of both substeps replace the coarse flux on a coarse-fine
@@ -374,8 +380,9 @@ rg_status rg_step(const rg_tree *t, const double *d_uold, double *d_unew, double
  * d_scratch is a second buffer of the same size whose contents are
  * overwritten (levels alternate between the two buffers, so no level is
  * copied between substeps; the coarsest level is copied back at the end).
- * d_acc: rg_corr_workspace_bytes(n_oct - level_begin[lmin + 1]) bytes, like
- * t->d_corr; both may be NULL only when lmin == lmax.  form is RG_FP64 or
+ * d_acc: rg_corr_workspace_bytes(n_oct - level_begin[lmin + 1]) bytes (the
+ * per-oct kernel sums each level's coarse-side fluxes over the two substeps
+ * into it; t->d_corr is not used); NULL only when lmin == lmax.  form is RG_FP64 or
  * RG_MIXED; tune as for rg_step (the brick kernel serves the bricks of the
  * schedule, if t->sched is set).  Asynchronous on `stream`; the host walks
  * the level recursion, issuing 2^(l - lmin) updates of level l. */

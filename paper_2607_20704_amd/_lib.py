@@ -34,7 +34,8 @@ class RgSchedule(ctypes.Structure):
     _fields_ = [("brick_begin", i64 * (RG_MAX_LEVEL + 2)), ("brick_count", i64 * (RG_MAX_LEVEL + 2)),
                 ("rest_begin", i64 * (RG_MAX_LEVEL + 2)), ("rest_count", i64 * (RG_MAX_LEVEL + 2)),
                 ("nbr_brick_begin", i64), ("nbr_brick_count", i64), ("nbr_rest_begin", i64),
-                ("nbr_rest_count", i64), ("d_list", P)]
+                ("nbr_rest_count", i64), ("border_begin", i64 * (RG_MAX_LEVEL + 2)),
+                ("border_count", i64 * (RG_MAX_LEVEL + 2)), ("d_list", P)]
 
 
 class RgTree(ctypes.Structure):

@@ -205,9 +205,9 @@ class DeviceTree:
         self._desc = self._descriptor()
         self.sched = None
         if schedule:
-            self.sched_list = torch.empty(2 * self.n, dtype=torch.int32, device="cuda")
+            self.sched_list = torch.empty(3 * self.n, dtype=torch.int32, device="cuda")
             self.sched = L.RgSchedule()
-            check(L.lib().rg_schedule_build(ctypes.byref(self._desc), _ptr(self.sched_list), 2 * self.n,
+            check(L.lib().rg_schedule_build(ctypes.byref(self._desc), _ptr(self.sched_list), 3 * self.n,
                                             ctypes.byref(self.sched), _stream()))
             self._desc.sched = ctypes.pointer(self.sched)
 

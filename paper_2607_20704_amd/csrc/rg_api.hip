@@ -38,6 +38,8 @@ rg_status launch_status(const char *what)
 
 struct LevelArgs;
 rg_status hydro_level(const LevelArgs &a, int form, const rg_tuning *tune, hipStream_t s);
+rg_status coarse_corrections_list(double *unew, const double *corr, int64_t corr_base, const int32_t *nbr27,
+                                  const int32_t *list, int64_t count, hipStream_t s);
 
 }  // namespace rg
 
@@ -133,7 +135,15 @@ rg_status rg_step(const rg_tree *t, const double *d_uold, double *d_unew, double
         }
     }
     if (t->lmax > t->lmin) {
-        RG_TRY(rg_apply_coarse_corrections(d_unew, t->d_corr, corr_base, t->d_nbr27, corr_base, t->n_oct, stream));
+        if (t->sched) {
+            // the border lists of all levels above lmin follow each other
+            const rg_schedule *sc = t->sched;
+            const int64_t b = sc->border_begin[t->lmin + 1];
+            const int64_t e = sc->border_begin[t->lmax] + sc->border_count[t->lmax];
+            RG_TRY(coarse_corrections_list(d_unew, t->d_corr, corr_base, t->d_nbr27, sc->d_list + b, e - b, s));
+        } else {
+            RG_TRY(rg_apply_coarse_corrections(d_unew, t->d_corr, corr_base, t->d_nbr27, corr_base, t->n_oct, stream));
+        }
         if (chain)
             RG_TRY(rg_cfl_dt_corrected(d_unew, t->d_nbr27, t->level_begin, t->lmin, t->lmax, gamma, cfl, dt_next,
                                        stream));

@@ -191,6 +191,7 @@ __global__ __launch_bounds__(kT, sizeof(R) == 8 ? 4 : 6) void k_batch_octs(const
         a.son = T.son;
         a.corr = level > T.lmin ? T.corr : nullptr;
         a.corr_base = T.corr_base;
+        a.corr_mode = 0;
         a.oct_begin = I.first;
         a.oct_end = I.first + I.count;
         a.dt = dt + I.tree;

@@ -94,13 +94,16 @@ __global__ __launch_bounds__(256) void k_cfl_dt(DtArgs a)
     }
 }
 
+// octs ob..oe, or list[ob..oe) when a list is given
 __global__ void k_coarse_corr(double *__restrict__ unew, const double *__restrict__ corr, int64_t corr_base,
-                              const int32_t *__restrict__ nbr27, int64_t ob, int64_t oe, int side)
+                              const int32_t *__restrict__ nbr27, const int32_t *__restrict__ list, int64_t ob,
+                              int64_t oe, int side)
 {
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t o = ob + t / NV;
+    const int64_t i = ob + t / NV;
     const int v = static_cast<int>(t % NV);
-    if (o >= oe) return;
+    if (i >= oe) return;
+    const int64_t o = list ? int64_t(list[i]) : i;
     const int ax = side >> 1, hi = side & 1;
     const int slot = nslot(ax == 0 ? (hi ? 1 : -1) : 0, ax == 1 ? (hi ? 1 : -1) : 0, ax == 2 ? (hi ? 1 : -1) : 0);
     const int32_t e = nbr27[27 * o + slot];
@@ -203,10 +206,11 @@ rg_status hydro_level(const LevelArgs &a, int form, const rg_tuning *tune, hipSt
 rg_status hydro_level_list(const double *uold, double *unew, const int32_t *nbr27, const uint32_t *son,
                            const int32_t *list, int64_t count, double *corr, int64_t corr_base, const double *dt,
                            double dx, double gamma, int form, const rg_tuning *tune, double cfl, double *dt_next,
-                           hipStream_t s, int64_t first, const double *ucoarse)
+                           hipStream_t s, int64_t first, const double *ucoarse, int corr_mode)
 {
     if (count <= 0) return RG_OK;
     LevelArgs a;
+    a.corr_mode = corr_mode;
     a.list = list;
     a.uold = uold;
     a.ucoarse = ucoarse ? ucoarse : uold;
@@ -223,6 +227,19 @@ rg_status hydro_level_list(const double *uold, double *unew, const int32_t *nbr2
     a.cfl = cfl;
     a.dt_next = reinterpret_cast<unsigned long long *>(dt_next);
     return hydro_level(a, form, tune, s);
+}
+
+// coarse-fine corrections from the octs list[0..count), side by side
+rg_status coarse_corrections_list(double *unew, const double *corr, int64_t corr_base, const int32_t *nbr27,
+                                  const int32_t *list, int64_t count, hipStream_t s)
+{
+    if (count <= 0) return RG_OK;
+    const int64_t items = count * NV;
+    for (int side = 0; side < 6; ++side) {
+        k_coarse_corr<<<grid_for(items, 256), 256, 0, s>>>(unew, corr, corr_base, nbr27, list, 0, count, side);
+        RG_TRY(launch_status("coarse corrections"));
+    }
+    return RG_OK;
 }
 
 // restriction of octs [ob, oe) from src into their father cells in dst
@@ -288,6 +305,7 @@ rg_status rg_hydro_step_level(double dx, const double *d_dt, double gamma, const
     RG_REQUIRE(!d_corr || corr_base <= oct_begin, "corr_base beyond the oct range");
     RG_REQUIRE(!d_dt_next || (cfl > 0 && aligned(d_dt_next, 8)), "bad cfl or misaligned dt_next");
     LevelArgs a;
+    a.corr_mode = 0;
     a.list = nullptr;
     a.uold = d_uold;
     a.ucoarse = d_uold;
@@ -316,8 +334,8 @@ rg_status rg_apply_coarse_corrections(double *d_unew, const double *d_corr, int6
     hipStream_t s = as_stream(stream);
     const int64_t items = (oct_end - oct_begin) * NV;
     for (int side = 0; side < 6; ++side) {
-        k_coarse_corr<<<grid_for(items, 256), 256, 0, s>>>(d_unew, d_corr, corr_base, d_nbr27, oct_begin, oct_end,
-                                                           side);
+        k_coarse_corr<<<grid_for(items, 256), 256, 0, s>>>(d_unew, d_corr, corr_base, d_nbr27, nullptr, oct_begin,
+                                                           oct_end, side);
         RG_TRY(launch_status("rg_apply_coarse_corrections"));
     }
     return RG_OK;

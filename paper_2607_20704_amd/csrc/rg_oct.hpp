@@ -96,6 +96,7 @@ struct LevelArgs {
     const uint32_t *son;
     double *corr;
     int64_t corr_base;
+    int corr_mode;        // 0: store the owed flux; 1: store 0 + flux; 2: add it (sums over substeps)
     int64_t oct_begin, oct_end;
     const double *dt;     // device scalar
     double dx;
@@ -279,7 +280,9 @@ __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, i
             const double sum = (S.g[g][face_id(ax, c, 0, 0)][v] + S.g[g][face_id(ax, c, 1, 0)][v]) +
                                (S.g[g][face_id(ax, c, 0, 1)][v] + S.g[g][face_id(ax, c, 1, 1)][v]);
             const double d = 0.125 * sum;
-            a.corr[30 * (S.oct[g] - a.corr_base) + k] = hi ? d : -d;
+            const double val = hi ? d : -d;
+            double *dst = a.corr + 30 * (S.oct[g] - a.corr_base) + k;
+            *dst = a.corr_mode == 0 ? val : (a.corr_mode == 1 ? 0.0 : *dst) + val;
         }
     }
 

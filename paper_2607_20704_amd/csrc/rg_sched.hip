@@ -13,7 +13,8 @@ namespace rg {
 rg_status hydro_level_list(const double *uold, double *unew, const int32_t *nbr27, const uint32_t *son,
                            const int32_t *list, int64_t count, double *corr, int64_t corr_base, const double *dt,
                            double dx, double gamma, int form, const rg_tuning *tune, double cfl, double *dt_next,
-                           hipStream_t s, int64_t first = 0, const double *ucoarse = nullptr);
+                           hipStream_t s, int64_t first = 0, const double *ucoarse = nullptr,
+                           int corr_mode = 0);
 rg_status hydro_bricks(const double *uold, double *unew, const int32_t *nbr27, const uint32_t *son,
                        const uint64_t *keys, const int32_t *bricks, int64_t nbricks, const double *dt, double dx,
                        double gamma, int outflow, int form, double cfl, double *dt_next, int waves, hipStream_t s);
@@ -23,20 +24,25 @@ using namespace rg;
 
 namespace {
 constexpr int64_t kBrickOcts = 512;
+// neighbour-list slots (dx+1) + 3 (dy+1) + 9 (dz+1) of the faces x-, x+, y-, y+, z-, z+
+constexpr int kFaceSlot[6] = {12, 14, 10, 16, 4, 22};
 }
 
 namespace rg {
 
 // One level of tree t: with a schedule, its bricks by the brick kernel and the
 // rest by the per-oct kernel; without one, the whole level by the per-oct
-// kernel.  Coarse ghost cells are read from ucoarse (bricks have none).
+// kernel.  Coarse ghost cells are read from ucoarse (bricks have none).  The
+// fluxes owed to coarse cells go to corr (30 doubles per oct from the first
+// oct above lmin): stored (corr_mode 0), stored as 0 + flux (1) or added (2).
 rg_status hydro_tree_level(const rg_tree *t, const rg_schedule *sc, int level, const double *d_dt, double gamma,
                            const double *d_uold, const double *d_ucoarse, double *d_unew, double cfl,
-                           double *d_dt_next, int form, const rg_tuning *tune, hipStream_t s)
+                           double *d_dt_next, int form, const rg_tuning *tune, hipStream_t s, double *d_corr,
+                           int corr_mode)
 {
     const double dx = ldexp(1.0, -level);
     const int64_t corr_base = t->level_begin[t->lmin + 1];
-    double *corr = level > t->lmin ? t->d_corr : nullptr;
+    double *corr = level > t->lmin ? d_corr : nullptr;
     const bool bricks = sc && !(tune && tune->no_bricks);
     if (bricks) {
         RG_TRY(hydro_bricks(d_uold, d_unew, t->d_nbr27, t->d_son_mask, t->d_keys, sc->d_list + sc->brick_begin[level],
@@ -44,11 +50,11 @@ rg_status hydro_tree_level(const rg_tree *t, const rg_schedule *sc, int level, c
                             tune ? tune->brick_waves : 0, s));
         RG_TRY(hydro_level_list(d_uold, d_unew, t->d_nbr27, t->d_son_mask, sc->d_list + sc->rest_begin[level],
                                 sc->rest_count[level], corr, corr_base, d_dt, dx, gamma, form, tune, cfl, d_dt_next,
-                                s, 0, d_ucoarse));
+                                s, 0, d_ucoarse, corr_mode));
     } else {
         RG_TRY(hydro_level_list(d_uold, d_unew, t->d_nbr27, t->d_son_mask, nullptr,
                                 t->level_begin[level + 1] - t->level_begin[level], corr, corr_base, d_dt, dx, gamma,
-                                form, tune, cfl, d_dt_next, s, t->level_begin[level], d_ucoarse));
+                                form, tune, cfl, d_dt_next, s, t->level_begin[level], d_ucoarse, corr_mode));
     }
     return RG_OK;
 }
@@ -60,7 +66,7 @@ extern "C" {
 rg_status rg_schedule_build(const rg_tree *t, int32_t *d_list, int64_t capacity, rg_schedule *out, void *stream)
 {
     RG_REQUIRE(t && d_list && out, "null pointer");
-    RG_REQUIRE(t->n_oct > 0 && capacity >= 2 * t->n_oct, "list capacity below 2 n_oct");
+    RG_REQUIRE(t->n_oct > 0 && capacity >= 3 * t->n_oct, "list capacity below 3 n_oct");
     RG_REQUIRE(t->lmin >= 1 && t->lmax >= t->lmin && t->lmax <= RG_MAX_LEVEL, "bad levels");
     const int64_t n = t->n_oct;
     hipStream_t s = as_stream(stream);
@@ -75,7 +81,8 @@ rg_status rg_schedule_build(const rg_tree *t, int32_t *d_list, int64_t capacity,
     std::vector<int32_t> list, all_bricks, other;
     list.reserve(2 * n);
     for (int l = 0; l < RG_MAX_LEVEL + 2; ++l)
-        out->brick_begin[l] = out->brick_count[l] = out->rest_begin[l] = out->rest_count[l] = 0;
+        out->brick_begin[l] = out->brick_count[l] = out->rest_begin[l] = out->rest_count[l] = out->border_begin[l] =
+            out->border_count[l] = 0;
     for (int l = t->lmin; l <= t->lmax; ++l) {
         const int64_t b = t->level_begin[l], end = t->level_begin[l + 1];
         std::vector<uint8_t> covered(end - b, 0), complete(end - b, 0);
@@ -114,6 +121,19 @@ rg_status rg_schedule_build(const rg_tree *t, int32_t *d_list, int64_t capacity,
     out->nbr_rest_begin = static_cast<int64_t>(list.size());
     out->nbr_rest_count = static_cast<int64_t>(other.size());
     list.insert(list.end(), other.begin(), other.end());
+    // octs above lmin with a coarse cell across a face, level by level
+    for (int l = t->lmin + 1; l <= t->lmax; ++l) {
+        out->border_begin[l] = static_cast<int64_t>(list.size());
+        for (int64_t o = t->level_begin[l]; o < t->level_begin[l + 1]; ++o) {
+            bool coarse = false;
+            for (int side = 0; side < 6; ++side) {
+                const int32_t v = nbr[27 * o + kFaceSlot[side]];
+                coarse = coarse || (v < 0 && v != RG_NBR_OUTSIDE);
+            }
+            if (coarse) list.push_back(static_cast<int32_t>(o));
+        }
+        out->border_count[l] = static_cast<int64_t>(list.size()) - out->border_begin[l];
+    }
     if (static_cast<int64_t>(list.size()) > capacity) return fail(RG_EINVAL, "schedule exceeds list capacity");
     if (!list.empty()) {
         e = hipMemcpyAsync(d_list, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
@@ -135,7 +155,7 @@ rg_status rg_hydro_step_scheduled(const rg_tree *t, const rg_schedule *sc, int l
     RG_REQUIRE(gamma > 1, "bad gamma");
     RG_REQUIRE(!d_dt_next || (cfl > 0 && aligned(d_dt_next, 8)), "bad cfl or misaligned dt_next");
     return hydro_tree_level(t, sc, level, d_dt, gamma, d_uold, d_uold, d_unew, cfl, d_dt_next, form, tune,
-                            as_stream(stream));
+                            as_stream(stream), t->d_corr, 0);
 }
 
 }  // extern "C"

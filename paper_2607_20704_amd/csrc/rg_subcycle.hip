@@ -23,9 +23,12 @@ namespace rg {
 
 rg_status hydro_tree_level(const rg_tree *t, const rg_schedule *sc, int level, const double *d_dt, double gamma,
                            const double *d_uold, const double *d_ucoarse, double *d_unew, double cfl,
-                           double *d_dt_next, int form, const rg_tuning *tune, hipStream_t s);
+                           double *d_dt_next, int form, const rg_tuning *tune, hipStream_t s, double *d_corr,
+                           int corr_mode);
 rg_status restrict_level2(const double *src, double *dst, const int32_t *father, int64_t ob, int64_t oe,
                           hipStream_t s);
+rg_status coarse_corrections_list(double *unew, const double *corr, int64_t corr_base, const int32_t *nbr27,
+                                  const int32_t *list, int64_t count, hipStream_t s);
 rg_status cfl_dt_pass(const double *d_u, const uint32_t *d_son_mask, const int64_t *h_level_begin, int lmin, int lmax,
                       double gamma, double cfl, double *d_dt, int sub, void *stream);
 
@@ -36,14 +39,6 @@ __global__ void k_level_dts(double *dt, int nlev)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0)
         for (int k = 0; k < nlev; ++k) dt[1 + k] = ldexp(dt[0], -k);
-}
-
-// acc = (first ? 0 : acc) + corr over n doubles
-__global__ void k_accumulate(double *__restrict__ acc, const double *__restrict__ corr, int64_t n, int first)
-{
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    acc[i] = (first ? 0.0 : acc[i]) + corr[i];
 }
 
 struct Sub {
@@ -58,7 +53,9 @@ struct Sub {
     hipStream_t s;
 };
 
-rg_status advance(Sub &c, int l)
+// sub: which of its parent's two substeps this is (0 for lmin); the level's
+// fluxes owed to coarse cells are summed over the two into acc
+rg_status advance(Sub &c, int l, int sub)
 {
     const rg_tree *t = c.t;
     const int64_t ob = t->level_begin[l], oe = t->level_begin[l + 1];
@@ -67,21 +64,19 @@ rg_status advance(Sub &c, int l)
     const double *coarse = l > t->lmin ? c.buf[c.cur[l - 1]] : own;
     if (oe > ob)
         RG_TRY(hydro_tree_level(t, t->sched, l, c.dt + 1 + (l - t->lmin), c.gamma, own, coarse, out, 0.0, nullptr,
-                                c.form, c.tune, c.s));
+                                c.form, c.tune, c.s, c.acc, 1 + sub));
     if (l < t->lmax) {
         const int64_t fb = t->level_begin[l + 1], fe = t->level_begin[l + 2];
         const int64_t base = t->level_begin[t->lmin + 1];
-        const int64_t n30 = 30 * (fe - fb);
-        for (int sub = 0; sub < 2; ++sub) {
-            RG_TRY(advance(c, l + 1));
-            if (n30 > 0) {
-                k_accumulate<<<grid_for(n30, 256), 256, 0, c.s>>>(c.acc + 30 * (fb - base), t->d_corr + 30 * (fb - base),
-                                                                  n30, sub == 0);
-                RG_TRY(launch_status("subcycle accumulate"));
-            }
-        }
+        for (int s2 = 0; s2 < 2; ++s2) RG_TRY(advance(c, l + 1, s2));
         if (fe > fb) {
-            RG_TRY(rg_apply_coarse_corrections(out, c.acc, base, t->d_nbr27, fb, fe, c.s));
+            if (t->sched) {
+                const rg_schedule *sc = t->sched;
+                RG_TRY(coarse_corrections_list(out, c.acc, base, t->d_nbr27, sc->d_list + sc->border_begin[l + 1],
+                                               sc->border_count[l + 1], c.s));
+            } else {
+                RG_TRY(rg_apply_coarse_corrections(out, c.acc, base, t->d_nbr27, fb, fe, c.s));
+            }
             RG_TRY(restrict_level2(c.buf[c.cur[l + 1]], out, t->d_father_cell, fb, fe, c.s));
         }
     }
@@ -102,7 +97,7 @@ rg_status rg_step_subcycled(const rg_tree *t, double *d_u, double *d_scratch, do
     RG_REQUIRE(t && d_u && d_scratch && d_dt, "null pointer");
     RG_REQUIRE(t->n_oct > 0 && t->lmin >= 1 && t->lmax >= t->lmin && t->lmax <= RG_MAX_LEVEL, "bad tree");
     RG_REQUIRE(t->level_begin[t->lmin] == 0 && t->level_begin[t->lmax + 1] == t->n_oct, "bad level ranges");
-    RG_REQUIRE(t->lmin == t->lmax || (t->d_corr && d_acc), "a multilevel tree needs correction and accumulation buffers");
+    RG_REQUIRE(t->lmin == t->lmax || d_acc, "a multilevel tree needs an accumulation buffer");
     RG_REQUIRE((flags & ~(RG_STEP_REBUILD | RG_STEP_REKEY)) == 0, "unsupported flags %u", flags);
     RG_REQUIRE(d_u != d_scratch, "state and scratch must not alias");
     RG_REQUIRE(aligned(d_u, 8) && aligned(d_scratch, 8) && aligned(d_dt, 8) && (!d_acc || aligned(d_acc, 8)),
@@ -125,7 +120,7 @@ rg_status rg_step_subcycled(const rg_tree *t, double *d_u, double *d_scratch, do
     c.form = form;
     c.tune = tune;
     c.s = s;
-    RG_TRY(advance(c, t->lmin));
+    RG_TRY(advance(c, t->lmin, 0));
     // level lmin took one step and sits in the scratch buffer; every finer
     // level took an even number and is back in d_u
     const int64_t nb = t->level_begin[t->lmin + 1] - t->level_begin[t->lmin];

@@ -234,6 +234,37 @@ def test_brick_schedule_bit_identical(case, form):
         assert worst <= 1e-12
 
 
+@pytest.mark.parametrize("case", BRICK_CASES[2:], ids=[c[0] for c in BRICK_CASES[2:]])
+def test_border_lists_and_unscheduled_corrections(case):
+    """The schedule's per-level border lists (octs with a coarse cell across
+    a face, which the scheduled step corrects from) equal a brute-force scan
+    of the neighbour lists, and the step without a schedule (corrections
+    over every oct above lmin) gives the same bits."""
+    from paper_2607_20704_amd import api
+    name, mk = case
+    ijkl, bc, state = mk()
+    u_in, gam = state(ijkl)
+    D = api.DeviceTree(ijkl, bc)
+    nbr = D.nbr27.cpu().numpy()
+    lst = D.sched_list.cpu().numpy()
+    face = nbr[:, [12, 14, 10, 16, 4, 22]]
+    border = np.any((face < 0) & (face != O.OUTSIDE), axis=1)
+    total = 0
+    for l in range(D.lmin + 1, D.lmax + 1):
+        b, e = int(D.level_begin[l]), int(D.level_begin[l + 1])
+        want = b + np.nonzero(border[b:e])[0]
+        got = lst[D.sched.border_begin[l]:D.sched.border_begin[l] + D.sched.border_count[l]]
+        assert np.array_equal(got, want), l
+        total += len(want)
+    say("  border octs", total, "of", D.n - int(D.level_begin[D.lmin + 1]))
+    assert total > 0
+    U = api.DeviceTree(ijkl, bc, schedule=False)
+    for form in (0, 1):
+        a = run_device(D, device_state(D, u_in), gam, 0.8, 4, form)[0]
+        c = run_device(U, device_state(U, u_in), gam, 0.8, 4, form)[0]
+        assert np.array_equal(a, c), form
+
+
 CHAIN_CASES = small_trees() + [
     ("sedov_l4_l6", I.sedov_amr(base=4, lmax=6).ijkl, I.PERIODIC, lambda t: (I.sedov_state(t, 1.4), 1.4)),
     ("deep_amr_l4_l7", I.deep_amr(base=4, lmax=7, nclump=60, sigma_a=2.0).ijkl, I.PERIODIC,

@@ -165,13 +165,11 @@ def test_subcycled_step_argument_errors_without_a_device():
 
     assert call(t=None) == L.RG_EINVAL
     assert call(dt=None) == L.RG_EINVAL
-    # a multilevel tree needs the correction and accumulation buffers
-    assert call() == L.RG_EINVAL
+    # a multilevel tree needs the accumulation buffer
+    assert call(acc=None) == L.RG_EINVAL
     assert b"accumulation" in L.detail().encode()
-    tree.d_corr = 2048
     assert call(scratch=u) == L.RG_EINVAL
     assert b"alias" in L.detail().encode()
-    assert call(acc=None) == L.RG_EINVAL
     assert call(flags=L.RG_STEP_CHAIN_DT) == L.RG_EINVAL
     assert call(form=9) == L.RG_EINVAL
     assert call(gamma=1.0) == L.RG_EINVAL

@@ -263,6 +263,25 @@ def time_deep_amr(forms, nsteps, api, inputs):
     return out
 
 
+def copy_ceiling(torch, mib=1024, reps=5):
+    """Practical HBM ceiling: GB/s (read + write) of a plain device copy of
+    `mib` MiB, best of `reps`."""
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b))
+    del src, dst
+    return 2 * n * 8 / (best * 1e-3) / 1e9
+
+
 def cpu_baseline(w, sample_octs):
     """The oracle, as it stands, on the host: its hydro update (tile,
     reconstruction, Riemann, update) of the first `sample_octs` octs in key
@@ -321,6 +340,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    copy_gbs = copy_ceiling(torch)
+    log("plain device copy: %.0f GB/s" % copy_gbs)
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     res = {}
     for f in forms:
@@ -340,6 +361,7 @@ def main():
         achieved = ALG_BYTES_PER_CELL * cells / (r["hydro_kernel_ms"] * 1e-3) / 1e9
         return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(f),
+                "copy_ceiling": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
                 "kernel": "k_hydro_brick", "alg_bytes_per_launch": ALG_BYTES_PER_CELL * cells,
                 "kernel_ms": round(r["hydro_kernel_ms"], 4)}
 

@@ -57,7 +57,7 @@
 #define ORC_OUTSIDE INT32_MIN
 #define ORC_MAX_LEVEL 21
 
-enum { ORC_OK = 0, ORC_EINVAL = 1, ORC_EUNGRADED = 4 };
+enum { ORC_OK = 0, ORC_EINVAL = 1, ORC_EFULL = 2, ORC_EUNGRADED = 4 };
 enum { ORC_PERIODIC = 0, ORC_OUTFLOW = 1 };
 
 int64_t orc_abi_version(void) { return 1; }
@@ -760,4 +760,170 @@ double orc_step_subcycled(int64_t n, const int32_t *ijkl, const int32_t *nbr27, 
     free(c.corr);
     free(c.acc);
     return dt;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Refinement and de-refinement (Sec. 2.2)                                  */
+/* ------------------------------------------------------------------------ */
+
+/* The paper changes the tree every step in four stages: refinement (new octs
+ * under flagged cells), de-refinement (children of split cells that are not
+ * flagged are removed), a sort by level and a Hilbert sort within each level.
+ * It does not state the refinement criterion or how the 2:1 grading is kept;
+ * the readings used here:
+ *   criterion: a cell of level l < lmax_refine is flagged when its density
+ *     exceeds rho_thresh (if rho_thresh > 0) or when, for one of its six face
+ *     neighbours n (same-level cell, else the coarse cell covering it; an
+ *     outflow face gives the cell itself), |rho_n - rho| / (rho_n + rho)
+ *     exceeds grad_thresh (if grad_thresh > 0).  Every cell is tested, split
+ *     cells with their restricted values.
+ *   grading: a flagged cell of level l needs its 26 neighbours and itself to
+ *     exist at level l in the new tree, so the level-(l-1) cells under the
+ *     octs holding them are flagged too; levels are closed from the finest
+ *     down.  (All such cells exist: the current tree is graded.)
+ *   new tree: every oct of the coarsest level, every oct above it whose
+ *     father cell is flagged, and a new oct under every flagged leaf cell.
+ *   new state: kept octs keep their cells; a new oct's 8 cells take its
+ *     father cell's conserved values (injection: conservative); a removed
+ *     oct's father keeps its restricted value.
+ * Octs in key order on input; output in emission order (for each old oct in
+ * key order: the oct if kept, then its new children by cell bit).  crit (may
+ * be NULL) receives the criterion's flags alone, flags the closed ones. */
+
+static int refine_criterion(double rc, const double rn[6], double rho_thresh, double grad_thresh)
+{
+    if (rho_thresh > 0.0 && rc > rho_thresh) return 1;
+    if (grad_thresh > 0.0)
+        for (int s = 0; s < 6; ++s) {
+            double d = fabs(rn[s] - rc) / (rn[s] + rc);
+            if (d > grad_thresh) return 1;
+        }
+    return 0;
+}
+
+/* density of the level-l cell (x,y,z) or of the coarse cell covering it;
+ * *found = 0 if neither exists */
+static double cell_density(const lookup_table *T, const double *u, int l, int32_t x, int32_t y, int32_t z, int *found)
+{
+    int64_t o = table_get(T, x >> 1, y >> 1, z >> 1, l);
+    *found = 1;
+    if (o >= 0) return u[5 * (8 * o + (x & 1) + 2 * (y & 1) + 4 * (z & 1))];
+    int32_t cx = x >> 1, cy = y >> 1, cz = z >> 1;
+    int64_t f = l > 1 ? table_get(T, cx >> 1, cy >> 1, cz >> 1, l - 1) : -1;
+    if (f < 0) {
+        *found = 0;
+        return 0.0;
+    }
+    return u[5 * (8 * f + (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1))];
+}
+
+int orc_refine(int64_t n, const int32_t *ijkl, const uint8_t *son_mask, const double *u, int bc, double rho_thresh,
+               double grad_thresh, int lmax_refine, uint8_t *crit, uint8_t *flags, int64_t capacity, int64_t *m_out,
+               int32_t *new_ijkl, double *new_u)
+{
+    lookup_table T = table_build(n, ijkl);
+    int lmin = ORC_MAX_LEVEL + 1, lmax = 0;
+    for (int64_t o = 0; o < n; ++o) {
+        if (ijkl[4 * o + 3] < lmin) lmin = ijkl[4 * o + 3];
+        if (ijkl[4 * o + 3] > lmax) lmax = ijkl[4 * o + 3];
+        flags[o] = 0;
+    }
+    int status = ORC_OK;
+    /* criterion on every cell below lmax_refine */
+    for (int64_t o = 0; o < n && status == ORC_OK; ++o) {
+        int l = ijkl[4 * o + 3];
+        if (l >= lmax_refine) continue;
+        int32_t N = (int32_t)1 << l;
+        for (int c = 0; c < 8; ++c) {
+            int32_t x = 2 * ijkl[4 * o + 0] + (c & 1), y = 2 * ijkl[4 * o + 1] + ((c >> 1) & 1),
+                    z = 2 * ijkl[4 * o + 2] + ((c >> 2) & 1);
+            double rc = u[5 * (8 * o + c)];
+            double rn[6];
+            for (int s = 0; s < 6; ++s) {
+                int32_t p[3] = {x, y, z};
+                p[s >> 1] += (s & 1) ? 1 : -1;
+                int outside = 0;
+                for (int a = 0; a < 3; ++a) {
+                    if (bc == ORC_PERIODIC) p[a] = (p[a] + N) % N;
+                    else if (p[a] < 0 || p[a] >= N) outside = 1;
+                }
+                int found = 1;
+                rn[s] = outside ? rc : cell_density(&T, u, l, p[0], p[1], p[2], &found);
+                if (!found) status = ORC_EUNGRADED;
+            }
+            if (refine_criterion(rc, rn, rho_thresh, grad_thresh)) flags[o] |= (uint8_t)(1u << c);
+        }
+    }
+    if (crit)
+        for (int64_t o = 0; o < n; ++o) crit[o] = flags[o];
+    /* grading closure, finest level first */
+    for (int l = lmax; l > lmin && status == ORC_OK; --l) {
+        int32_t N = (int32_t)1 << l;
+        for (int64_t o = 0; o < n; ++o) {
+            if (ijkl[4 * o + 3] != l || !flags[o]) continue;
+            for (int c = 0; c < 8; ++c) {
+                if (!((flags[o] >> c) & 1)) continue;
+                int32_t x = 2 * ijkl[4 * o + 0] + (c & 1), y = 2 * ijkl[4 * o + 1] + ((c >> 1) & 1),
+                        z = 2 * ijkl[4 * o + 2] + ((c >> 2) & 1);
+                for (int dz = -1; dz <= 1; ++dz)
+                    for (int dy = -1; dy <= 1; ++dy)
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            int32_t p[3] = {x + dx, y + dy, z + dz};
+                            int outside = 0;
+                            for (int a = 0; a < 3; ++a) {
+                                if (bc == ORC_PERIODIC) p[a] = (p[a] + N) % N;
+                                else if (p[a] < 0 || p[a] >= N) outside = 1;
+                            }
+                            if (outside) continue;
+                            /* the level-(l-1) cell under the level-l oct holding p */
+                            int32_t fx = p[0] >> 2, fy = p[1] >> 2, fz = p[2] >> 2;
+                            int64_t f = table_get(&T, fx, fy, fz, l - 1);
+                            if (f < 0) {
+                                status = ORC_EUNGRADED;
+                                continue;
+                            }
+                            int bit = ((p[0] >> 1) & 1) + 2 * ((p[1] >> 1) & 1) + 4 * ((p[2] >> 1) & 1);
+                            flags[f] |= (uint8_t)(1u << bit);
+                        }
+            }
+        }
+    }
+    /* the new tree and its state */
+    int64_t m = 0;
+    for (int64_t o = 0; o < n && status == ORC_OK; ++o) {
+        int32_t i = ijkl[4 * o + 0], j = ijkl[4 * o + 1], k = ijkl[4 * o + 2], l = ijkl[4 * o + 3];
+        int keep = l == lmin;
+        if (!keep) {
+            int64_t f = table_get(&T, i >> 1, j >> 1, k >> 1, l - 1);
+            int bit = (i & 1) + 2 * (j & 1) + 4 * (k & 1);
+            keep = f >= 0 && ((flags[f] >> bit) & 1);
+        }
+        if (!keep) continue;
+        if (m >= capacity) {
+            status = ORC_EFULL;
+            break;
+        }
+        new_ijkl[4 * m + 0] = i;
+        new_ijkl[4 * m + 1] = j;
+        new_ijkl[4 * m + 2] = k;
+        new_ijkl[4 * m + 3] = l;
+        memcpy(new_u + 40 * m, u + 40 * o, 40 * sizeof(double));
+        ++m;
+        for (int c = 0; c < 8; ++c) {
+            if (!((flags[o] >> c) & 1) || ((son_mask[o] >> c) & 1)) continue;
+            if (m >= capacity) {
+                status = ORC_EFULL;
+                break;
+            }
+            new_ijkl[4 * m + 0] = 2 * i + (c & 1);
+            new_ijkl[4 * m + 1] = 2 * j + ((c >> 1) & 1);
+            new_ijkl[4 * m + 2] = 2 * k + ((c >> 2) & 1);
+            new_ijkl[4 * m + 3] = l + 1;
+            for (int q = 0; q < 8; ++q) memcpy(new_u + 40 * m + 5 * q, u + 5 * (8 * o + c), 5 * sizeof(double));
+            ++m;
+        }
+    }
+    *m_out = m;
+    free(T.t);
+    return status;
 }

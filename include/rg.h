@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define RG_ABI_VERSION 4
+#define RG_ABI_VERSION 5
 #define RG_MAX_LEVEL 21
 #define RG_NBR_OUTSIDE INT32_MIN
 #define RG_RHO_MIN 1e-10
@@ -308,13 +308,15 @@ typedef struct rg_tree {
     uint32_t *d_son_mask;                     /* [n_oct] */
     double *d_corr;                           /* 30 doubles per oct of levels > lmin; NULL if lmin == lmax */
     /* used by RG_STEP_REKEY only (may be NULL otherwise): */
-    const int32_t *d_ijkl;                    /* key-ordered oct coordinates [n_oct][4] */
+    int32_t *d_ijkl;                          /* key-ordered oct coordinates [n_oct][4] */
     uint64_t *d_keys_scratch;                 /* [n_oct] unsorted keys */
     int32_t *d_perm;                          /* [n_oct] sort permutation (identity for a static tree) */
     void *d_sort_ws;                          /* rg_sort_workspace_bytes(n_oct) */
     size_t sort_ws_bytes;
     int64_t *d_level_begin;                   /* device level ranges [RG_MAX_LEVEL + 2] */
     const rg_schedule *sched;                 /* optional kernel schedule (NULL: per-oct kernel) */
+    int64_t capacity;                         /* octs every per-oct buffer can hold (ngridmax, Sec. 2);
+                                                 0: n_oct.  rg_refine may grow the tree up to it. */
 } rg_tree;
 
 /* Builds the schedule of tree t (keys, level ranges and neighbour lists must
@@ -388,6 +390,57 @@ rg_status rg_step(const rg_tree *t, const double *d_uold, double *d_unew, double
  * the level recursion, issuing 2^(l - lmin) updates of level l. */
 rg_status rg_step_subcycled(const rg_tree *t, double *d_u, double *d_scratch, double *d_acc, double gamma, double cfl,
                             int form, unsigned flags, double *d_dt, const rg_tuning *tune, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Refinement and de-refinement                                           */
+/* ---------------------------------------------------------------------- */
+
+/* Refinement criterion (the paper does not state one for its hydro tests):
+ * a cell of level l < lmax is flagged when rho > rho_thresh (rho_thresh > 0)
+ * or when, for one of its six face neighbours n, |rho_n - rho| / (rho_n +
+ * rho) > grad_thresh (grad_thresh > 0); n is the same-level cell, else the
+ * coarse cell under the missing oct, and on an outflow face the cell itself.
+ * Split cells are tested with their restricted values. */
+typedef struct rg_refine_params {
+    double rho_thresh;
+    double grad_thresh;
+    int32_t lmax;        /* finest level allowed: cells of level >= lmax are never flagged */
+    int32_t pad;
+} rg_refine_params;
+
+/* Bytes of the workspace rg_refine needs for a tree of `capacity` octs. */
+size_t rg_refine_workspace_bytes(int64_t capacity);
+
+/* The flags rg_refine acts on, into d_flags[n_oct] (bit c of an oct's word
+ * = its cell c): the criterion alone (closure 0) or closed for grading
+ * (closure 1): a flagged cell of level l needs its 26 neighbours and itself
+ * at level l, so the level-(l-1) cells under the octs holding them are
+ * flagged, levels taken from the finest down.  Reads d_u (key order). */
+rg_status rg_refine_flags(const rg_tree *t, const double *d_u, const rg_refine_params *p, int closure,
+                          uint32_t *d_flags, void *stream);
+
+/* One refinement / de-refinement of tree t (Sec. 2.2: refine, de-refine,
+ * sort by level, Hilbert order inside a level), on the device:
+ *   flags as rg_refine_flags(closure = 1);
+ *   new tree: every oct of level lmin, every oct above whose father cell is
+ *   flagged, and a new oct under every flagged cell that has none; octs under
+ *   unflagged cells are dropped (their fathers hold the restricted values);
+ *   new state in d_u_new (key order of the new tree): kept octs copy their
+ *   cells, a new oct's 8 cells take its father cell's values (injection, so
+ *   leaf sums of volume * U are unchanged);
+ *   keys, one radix sort, level ranges, hash table and neighbour lists of the
+ *   new tree, written into t's buffers; t->n_oct, t->lmax and
+ *   t->level_begin are updated and t->sched is set to NULL (rebuild a
+ *   schedule with rg_schedule_build if wanted).
+ * Every per-oct buffer of t (keys, scratch keys, permutation, coordinates,
+ * neighbour lists, father cells, son masks, correction buffer) and the hash
+ * and sort workspaces must be sized for t->capacity octs (0: n_oct);
+ * RG_EFULL, with t unchanged, if the new tree would not fit.  d_u and
+ * d_u_new are 8 x capacity x 5 doubles and must not alias; d_ws is
+ * rg_refine_workspace_bytes(capacity) bytes, 256-byte aligned.  Synchronises
+ * `stream` twice (the new oct count and the level ranges are read back). */
+rg_status rg_refine(rg_tree *t, const double *d_u, double *d_u_new, const rg_refine_params *p, void *d_ws,
+                    size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Many independent trees in one graph launch                             */

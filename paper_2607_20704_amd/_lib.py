@@ -44,7 +44,11 @@ class RgTree(ctypes.Structure):
                 ("d_keys", P), ("d_hash_ws", P), ("hash_ws_bytes", sz),
                 ("d_nbr27", P), ("d_father_cell", P), ("d_son_mask", P), ("d_corr", P),
                 ("d_ijkl", P), ("d_keys_scratch", P), ("d_perm", P), ("d_sort_ws", P), ("sort_ws_bytes", sz),
-                ("d_level_begin", P), ("sched", ctypes.POINTER(RgSchedule))]
+                ("d_level_begin", P), ("sched", ctypes.POINTER(RgSchedule)), ("capacity", i64)]
+
+
+class RgRefineParams(ctypes.Structure):
+    _fields_ = [("rho_thresh", ctypes.c_double), ("grad_thresh", ctypes.c_double), ("lmax", i32), ("pad", i32)]
 
 
 class RgBatchTree(ctypes.Structure):
@@ -84,6 +88,9 @@ SIGNATURES = {
                      ctypes.POINTER(RgTuning), P]),
     "rg_step_subcycled": (st, [ctypes.POINTER(RgTree), P, P, P, f64, f64, ctypes.c_int, ctypes.c_uint, P,
                                ctypes.POINTER(RgTuning), P]),
+    "rg_refine_workspace_bytes": (sz, [i64]),
+    "rg_refine_flags": (st, [ctypes.POINTER(RgTree), P, ctypes.POINTER(RgRefineParams), ctypes.c_int, P, P]),
+    "rg_refine": (st, [ctypes.POINTER(RgTree), P, P, ctypes.POINTER(RgRefineParams), P, sz, P]),
     "rg_batch_create": (st, [ctypes.POINTER(RgBatchTree), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint,
                              ctypes.POINTER(RgTuning), P, P, ctypes.POINTER(P)]),
     "rg_batch_run": (st, [P, P]),

@@ -175,41 +175,107 @@ class DeviceTree:
     lists and the coarse-fine correction buffer, built from oct coordinates
     by the library (encode, radix sort, level ranges, hash, neighbours)."""
 
-    def __init__(self, ijkl, bc, schedule=True):
+    def __init__(self, ijkl, bc, schedule=True, capacity=None):
         ijkl_d = torch.as_tensor(np.ascontiguousarray(ijkl, dtype=np.int32)).to("cuda")
         self.bc = int(bc)
-        self.n = int(ijkl_d.shape[0])
+        n = int(ijkl_d.shape[0])
+        cap = int(capacity) if capacity else n
+        if cap < n:
+            raise ValueError("capacity %d below the oct count %d" % (cap, n))
+        self.capacity = cap
         keys_in = encode_keys(ijkl_d)
-        self.keys, self.perm = sort_keys(keys_in)
-        begin = level_ranges(self.keys).cpu().numpy()
-        self.level_begin = begin
-        present = [l for l in range(1, RG_MAX_LEVEL + 1) if begin[l + 1] > begin[l]]
-        self.lmin, self.lmax = min(present), max(present)
-        self.hash_ws = torch.empty(hash_workspace_bytes(self.n), dtype=torch.uint8, device="cuda")
-        self.nbr27 = torch.empty((self.n, 27), dtype=torch.int32, device="cuda")
-        self.father_cell = torch.empty(self.n, dtype=torch.int32, device="cuda")
-        self.son_mask = torch.empty(self.n, dtype=torch.int32, device="cuda")
-        self.corr_base = int(begin[self.lmin + 1])
-        nfine = self.n - self.corr_base
-        self.corr = torch.empty(max(nfine, 1) * 30, dtype=torch.float64, device="cuda") if nfine > 0 else None
-        # key-ordered coordinates and scratch for re-keying inside a step
-        self.ijkl_sorted = decode_keys(self.keys)
-        self.keys_scratch = torch.empty_like(self.keys)
-        self.perm_scratch = torch.empty(self.n, dtype=torch.int32, device="cuda")
-        self.sort_ws = _u8(L.lib().rg_sort_workspace_bytes(self.n))
+        keys, self.perm = sort_keys(keys_in)
+        # every per-oct buffer holds `capacity` octs; the attributes below are
+        # views of the first n_oct rows (re-cut after a refinement)
+        self._keys = torch.empty(cap, dtype=torch.uint64, device="cuda")
+        self._keys[:n] = keys
+        self.hash_ws = torch.empty(hash_workspace_bytes(cap), dtype=torch.uint8, device="cuda")
+        self._nbr27 = torch.empty((cap, 27), dtype=torch.int32, device="cuda")
+        self._father_cell = torch.empty(cap, dtype=torch.int32, device="cuda")
+        self._son_mask = torch.empty(cap, dtype=torch.int32, device="cuda")
+        self._ijkl = torch.empty((cap, 4), dtype=torch.int32, device="cuda")
+        self._ijkl[:n] = decode_keys(keys)
+        self.keys_scratch = torch.empty(cap, dtype=torch.uint64, device="cuda")
+        self.perm_scratch = torch.empty(cap, dtype=torch.int32, device="cuda")
+        self.sort_ws = _u8(L.lib().rg_sort_workspace_bytes(cap))
         self.level_begin_dev = torch.empty(RG_MAX_LEVEL + 2, dtype=torch.int64, device="cuda")
+        self._set_size(n, level_ranges(keys).cpu().numpy())
+        self._corr = None
+        if capacity or self.lmax > self.lmin:
+            self._corr = torch.empty(cap * 30, dtype=torch.float64, device="cuda")
         self.rebuild()
         st, bad = check_ws(self.hash_ws)
         if st != L.RG_OK:
             raise RgError(st, "tree build failed (%s) at index %d" % (L.lib().rg_status_string(st).decode(), bad))
         self._desc = self._descriptor()
         self.sched = None
+        self._want_schedule = schedule
         if schedule:
-            self.sched_list = torch.empty(3 * self.n, dtype=torch.int32, device="cuda")
-            self.sched = L.RgSchedule()
-            check(L.lib().rg_schedule_build(ctypes.byref(self._desc), _ptr(self.sched_list), 3 * self.n,
-                                            ctypes.byref(self.sched), _stream()))
-            self._desc.sched = ctypes.pointer(self.sched)
+            self.build_schedule()
+
+    def _set_size(self, n, begin):
+        self.n = int(n)
+        self.level_begin = np.asarray(begin, dtype=np.int64).copy()
+        present = [l for l in range(1, RG_MAX_LEVEL + 1) if self.level_begin[l + 1] > self.level_begin[l]]
+        self.lmin, self.lmax = min(present), max(present)
+        self.keys = self._keys[:self.n]
+        self.nbr27 = self._nbr27[:self.n]
+        self.father_cell = self._father_cell[:self.n]
+        self.son_mask = self._son_mask[:self.n]
+        self.ijkl_sorted = self._ijkl[:self.n]
+        self.corr_base = int(self.level_begin[self.lmin + 1])
+
+    @property
+    def corr(self):
+        """Coarse-fine correction buffer (30 doubles per oct above lmin), or
+        None for a single-level tree."""
+        if self._corr is None or self.n == self.corr_base:
+            return None
+        return self._corr
+
+    def build_schedule(self):
+        """(Re)build the kernel schedule from the current keys and lists."""
+        if not hasattr(self, "sched_list") or self.sched_list.numel() < 3 * self.n:
+            self.sched_list = torch.empty(3 * self.capacity, dtype=torch.int32, device="cuda")
+        self.sched = L.RgSchedule()
+        check(L.lib().rg_schedule_build(ctypes.byref(self._desc), _ptr(self.sched_list), self.sched_list.numel(),
+                                        ctypes.byref(self.sched), _stream()))
+        self._desc.sched = ctypes.pointer(self.sched)
+
+    def refine(self, u, rho_thresh=0.0, grad_thresh=0.0, lmax=None, out=None, schedule=None):
+        """One refinement / de-refinement of the tree from state u (key
+        order): the tree is rebuilt in place and the new state, in the new
+        key order, is returned (a view of `out`, 8 x capacity x 5 doubles).
+        The schedule is rebuilt when the tree was built with one (or when
+        schedule=True)."""
+        p = L.RgRefineParams()
+        p.rho_thresh, p.grad_thresh = float(rho_thresh), float(grad_thresh)
+        p.lmax = int(lmax if lmax is not None else self.lmax)
+        if out is None:
+            out = torch.empty((8 * self.capacity, 5), dtype=torch.float64, device="cuda")
+        if not hasattr(self, "refine_ws"):
+            self.refine_ws = _u8(L.lib().rg_refine_workspace_bytes(self.capacity))
+        check(L.lib().rg_refine(ctypes.byref(self._desc), _ptr(u), _ptr(out), ctypes.byref(p), _ptr(self.refine_ws),
+                                self.refine_ws.numel(), _stream()))
+        d = self._desc
+        self._set_size(d.n_oct, [d.level_begin[l] for l in range(RG_MAX_LEVEL + 2)])
+        if self._corr is None and self.lmax > self.lmin:
+            self._corr = torch.empty(self.capacity * 30, dtype=torch.float64, device="cuda")
+            self._desc.d_corr = self._corr.data_ptr()
+        self.sched = None
+        if schedule if schedule is not None else self._want_schedule:
+            self.build_schedule()
+        return out[:8 * self.n]
+
+    def refine_flags(self, u, rho_thresh=0.0, grad_thresh=0.0, lmax=None, closure=True):
+        """The flags a refinement would act on (uint32 per oct, bit c = cell c)."""
+        p = L.RgRefineParams()
+        p.rho_thresh, p.grad_thresh = float(rho_thresh), float(grad_thresh)
+        p.lmax = int(lmax if lmax is not None else self.lmax)
+        flags = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        check(L.lib().rg_refine_flags(ctypes.byref(self._desc), _ptr(u), ctypes.byref(p), int(bool(closure)),
+                                      _ptr(flags), _stream()))
+        return flags
 
     def schedule_counts(self):
         """{level: (bricks, per-oct)} of the kernel schedule."""
@@ -245,13 +311,14 @@ class DeviceTree:
         t.d_nbr27 = self.nbr27.data_ptr()
         t.d_father_cell = self.father_cell.data_ptr()
         t.d_son_mask = self.son_mask.data_ptr()
-        t.d_corr = self.corr.data_ptr() if self.corr is not None else None
+        t.d_corr = self._corr.data_ptr() if self._corr is not None else None
         t.d_ijkl = self.ijkl_sorted.data_ptr()
         t.d_keys_scratch = self.keys_scratch.data_ptr()
         t.d_perm = self.perm_scratch.data_ptr()
         t.d_sort_ws = self.sort_ws.data_ptr()
         t.sort_ws_bytes = self.sort_ws.numel()
         t.d_level_begin = self.level_begin_dev.data_ptr()
+        t.capacity = self.capacity
         return t
 
     def prepare(self, flags=L.RG_STEP_REKEY | RG_STEP_REBUILD):

@@ -1,0 +1,154 @@
+"""GPU parity of refinement / de-refinement (Sec. 2.2) against the oracle:
+flags (criterion alone and closed), the new tree's keys, neighbour lists,
+father cells and son masks, and its state, all bit for bit; a dynamic run
+(hydro step, then refinement, repeated) against the oracle doing the same;
+convergence to the static sphere tree; a full tree reported as RG_EFULL."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import parity_metric, say
+from oracle import oracle as O
+from paper_2607_20704_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _random_amr(seed, bc=I.PERIODIC):
+    centre = (0.45, 0.5, 0.55) if bc == I.PERIODIC else (0.2, 0.3, 0.75)
+    ijkl = I.sphere_tree(3, 6, centre, 0.2, bc)
+    gam = 5.0 / 3.0
+    f = I.random_fields_grid(8, seed, gamma=gam)
+    return ijkl, bc, I.grid_to_tree_state(ijkl, 3, f, gam), gam
+
+
+CASES = [
+    ("periodic_rho", lambda: _random_amr(51), (1.3, 0.0, 7)),
+    ("periodic_grad", lambda: _random_amr(52), (0.0, 0.1, 6)),
+    ("outflow_both", lambda: _random_amr(53, I.OUTFLOW), (1.5, 0.15, 7)),
+    ("sedov_shrink", lambda: (lambda w: (w.ijkl, w.bc, w.u, w.gamma))(I.sedov_amr(base=4, lmax=6, radius=0.15)),
+     (0.0, 0.1, 7)),
+]
+
+
+def _device_tree(ijkl, bc, capacity=None):
+    from paper_2607_20704_amd import api
+    return api.DeviceTree(ijkl, bc, capacity=capacity)
+
+
+def _check_tree_equal(D, T2):
+    assert D.n == T2.n
+    assert np.array_equal(D.keys.cpu().numpy(), T2.keys)
+    assert np.array_equal(D.nbr27.cpu().numpy(), T2.nbr27)
+    assert np.array_equal(D.father_cell.cpu().numpy(), T2.father_cell)
+    assert np.array_equal(D.son_mask.cpu().numpy(), T2.son_mask.astype(np.int32))
+    assert (D.lmin, D.lmax) == (T2.lmin, T2.lmax)
+    assert all(int(D.level_begin[l]) == T2.level_begin[l] for l in range(T2.lmin, T2.lmax + 2))
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_refine_parity(case):
+    name, mk, params = case
+    ijkl, bc, u_in, gam = mk()
+    say("refine:", name, params)
+    T = O.Tree(ijkl, bc)
+    D = _device_tree(ijkl, bc, capacity=9 * len(ijkl))
+    u = D.to_key_order(u_in)
+    ref = T.permute_cells(u_in)
+    assert np.array_equal(u.cpu().numpy(), ref)
+    flags, ni, nu = T.refine(ref, *params)
+    got_crit = D.refine_flags(u, *params, closure=False).cpu().numpy()
+    got_flags = D.refine_flags(u, *params, closure=True).cpu().numpy()
+    assert np.array_equal(got_crit, T.last_crit.astype(np.int32))
+    assert np.array_equal(got_flags, flags.astype(np.int32))
+    u2 = D.refine(u, *params)
+    torch.cuda.synchronize()
+    T2 = O.Tree(ni, bc)
+    say("  octs %d -> %d, levels %d-%d" % (T.n, T2.n, T2.lmin, T2.lmax))
+    _check_tree_equal(D, T2)
+    assert np.array_equal(u2.cpu().numpy(), T2.permute_cells(nu))
+
+
+def test_dynamic_sedov_parity():
+    """Sedov blast: hydro step, then refinement on the density jump, ten times;
+    the device and the oracle follow the same trees and states."""
+    from paper_2607_20704_amd import api
+    w = I.sedov_amr(base=4, lmax=6, radius=0.15)
+    params = (0.0, 0.08, 7)
+    T = O.Tree(w.ijkl, w.bc)
+    D = _device_tree(w.ijkl, w.bc, capacity=60000)
+    u = D.to_key_order(w.u)
+    ref = T.permute_cells(w.u)
+    for s in range(10):
+        a = torch.empty_like(u)
+        dt = D.step(u, a, w.gamma, w.cfl, api.RG_FP64)
+        ref_dt = T.step(ref, w.gamma, w.cfl)
+        assert float(dt.cpu()[0]) == ref_dt
+        flags, ni, nu = T.refine(ref, *params)
+        T = O.Tree(ni, w.bc)
+        ref = T.permute_cells(nu)
+        u = D.refine(a, *params).clone()
+        torch.cuda.synchronize()
+        say("  step %d: octs %d, levels %d-%d" % (s, T.n, T.lmin, T.lmax))
+        _check_tree_equal(D, T)
+        worst, dmax = parity_metric(u.cpu().numpy(), ref)
+        assert worst <= 1e-12, (s, worst)
+    assert T.lmax == 7
+
+
+def _sphere_state(ijkl, centre, radius):
+    cen, _ = I.cell_centres(ijkl)
+    d = cen - np.asarray(centre)[None, None, :]
+    d = d - np.round(d)
+    inside = (d * d).sum(-1) < radius * radius
+    z = np.zeros(cen.shape[:2])
+    return I.conserved(np.where(inside, 2.0, 1.0), z, z, z, 1.0 + z, 1.4).reshape(-1, 5)
+
+
+def test_converges_to_static_sphere_tree():
+    centre, radius, lmax = (0.4, 0.55, 0.5), 0.22, 6
+    D = _device_tree(I.uniform_tree(3), I.PERIODIC, capacity=40000)
+    for it in range(2 * lmax):
+        n0, keys0 = D.n, D.keys.clone()
+        u = torch.as_tensor(np.ascontiguousarray(_sphere_state(D.ijkl_sorted.cpu().numpy(), centre, radius))).cuda()
+        D.refine(u, 1.5, 0.0, lmax)
+        if D.n == n0 and torch.equal(D.keys, keys0):
+            break
+    else:
+        raise AssertionError("did not converge")
+    want = O.Tree(I.sphere_tree(3, lmax, centre, radius, I.PERIODIC), I.PERIODIC)
+    assert np.array_equal(D.keys.cpu().numpy(), want.keys)
+
+
+def test_full_tree_is_reported_and_left_unchanged():
+    from paper_2607_20704_amd import api, _lib as L
+    ijkl, bc, u_in, gam = _random_amr(54)
+    D = _device_tree(ijkl, bc, capacity=len(ijkl) + 8)
+    u = D.to_key_order(u_in)
+    keys = D.keys.clone()
+    with pytest.raises(api.RgError) as e:
+        D.refine(u, 1.0, 0.0, 7)
+    assert e.value.status == L.RG_EFULL
+    assert torch.equal(D.keys, keys)
+    # the tree still steps
+    T = O.Tree(ijkl, bc)
+    a = torch.empty_like(u)
+    D.step(u, a, gam, 0.8, api.RG_FP64)
+    ref = T.permute_cells(u_in)
+    T.step(ref, gam, 0.8)
+    assert parity_metric(a.cpu().numpy(), ref)[0] <= 1e-12
+
+
+def test_schedule_rebuilt_after_refine():
+    """A refined tree with its schedule rebuilt steps to the same bits as
+    without one."""
+    from paper_2607_20704_amd import api
+    w = I.sedov_amr(base=5, lmax=6, radius=0.2)
+    D = _device_tree(w.ijkl, w.bc, capacity=60000)
+    u = D.refine(D.to_key_order(w.u), 0.0, 0.05, 7).clone()
+    assert D.sched is not None and sum(c[0] for c in D.schedule_counts().values()) > 0
+    a, _ = D.run(u, w.gamma, w.cfl, 3)
+    U = api.DeviceTree(D.ijkl_sorted.cpu().numpy(), w.bc, schedule=False)
+    b, _ = U.run(u, w.gamma, w.cfl, 3)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)

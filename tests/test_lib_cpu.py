@@ -179,6 +179,41 @@ def test_subcycled_step_argument_errors_without_a_device():
     assert call() == L.RG_EINVAL
 
 
+def test_refine_argument_errors_without_a_device():
+    """rg_refine and rg_refine_flags check the tree, the parameters, the
+    buffers and the capacity on the host before any device call."""
+    lib = L.lib()
+    tree = L.RgTree()
+    tree.n_oct, tree.lmin, tree.lmax = 72, 2, 3
+    tree.level_begin[2], tree.level_begin[3], tree.level_begin[4] = 0, 8, 72
+    tree.d_nbr27, tree.d_father_cell, tree.d_son_mask = 256, 512, 768
+    p = L.RgRefineParams()
+    p.rho_thresh, p.grad_thresh, p.lmax = 1.0, 0.0, 5
+    u, u2, ws = 1024, 2048, 4096
+    assert lib.rg_refine_flags(None, u, ctypes.byref(p), 1, ws, None) == L.RG_EINVAL
+    assert lib.rg_refine_flags(ctypes.byref(tree), None, ctypes.byref(p), 1, ws, None) == L.RG_EINVAL
+    p.lmax = 1
+    assert lib.rg_refine_flags(ctypes.byref(tree), u, ctypes.byref(p), 1, ws, None) == L.RG_EINVAL
+    p.lmax = 5
+    need = lib.rg_refine_workspace_bytes(72)
+    assert need > 72 * 4 * 5
+    assert lib.rg_refine(ctypes.byref(tree), u, u, ctypes.byref(p), ws, need, None) == L.RG_EINVAL
+    # no coordinates / scratch / sort workspace
+    assert lib.rg_refine(ctypes.byref(tree), u, u2, ctypes.byref(p), ws, need, None) == L.RG_EINVAL
+    tree.d_ijkl, tree.d_keys_scratch, tree.d_perm, tree.d_sort_ws = 8192, 16384, 32768, 65536
+    tree.d_level_begin, tree.d_hash_ws = 131072, 262144
+    tree.sort_ws_bytes = lib.rg_sort_workspace_bytes(72)
+    tree.hash_ws_bytes = lib.rg_hash_workspace_bytes(72)
+    tree.capacity = 64       # below n_oct
+    assert lib.rg_refine(ctypes.byref(tree), u, u2, ctypes.byref(p), ws, need, None) == L.RG_EINVAL
+    assert b"capacity" in L.detail().encode()
+    tree.capacity = 200      # workspaces sized for 72 octs only
+    assert lib.rg_refine(ctypes.byref(tree), u, u2, ctypes.byref(p), ws, need, None) == L.RG_EINVAL
+    tree.capacity = 0
+    assert lib.rg_refine(ctypes.byref(tree), u, u2, ctypes.byref(p), ws, need - 256, None) == L.RG_EINVAL
+    assert lib.rg_refine(ctypes.byref(tree), u, u2, ctypes.byref(p), ws + 8, need, None) == L.RG_EINVAL
+
+
 def test_workspace_sizes():
     lib = L.lib()
     # the table (256-byte header, capacity = power of two >= 2n slots of 12

@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define RG_ABI_VERSION 5
+#define RG_ABI_VERSION 6
 #define RG_MAX_LEVEL 21
 #define RG_NBR_OUTSIDE INT32_MIN
 #define RG_RHO_MIN 1e-10
@@ -325,6 +325,19 @@ typedef struct rg_tree {
  * t->sched points to it, rg_prepare_tree builds neighbour lists brick by
  * brick. */
 rg_status rg_schedule_build(const rg_tree *t, int32_t *d_list, int64_t capacity, rg_schedule *out, void *stream);
+
+/* Bytes of the workspace rg_schedule_build_device needs for n_oct octs. */
+size_t rg_schedule_workspace_bytes(int64_t n_oct);
+
+/* The same schedule built on the device (no copy of the tree to the host;
+ * synchronises once to read the list lengths back): per level the same
+ * brick, per-oct and border lists, in key order, laid out as all levels'
+ * bricks, then all levels' per-oct octs, the neighbour-build lists, and the
+ * border lists (offsets in *out).  d_list capacity >= 3 n_oct; d_ws is
+ * rg_schedule_workspace_bytes(n_oct) bytes, 256-byte aligned.  For trees
+ * that change every step (rg_refine). */
+rg_status rg_schedule_build_device(const rg_tree *t, int32_t *d_list, int64_t capacity, void *d_ws, size_t ws_bytes,
+                                   rg_schedule *out, void *stream);
 
 /* One level's update following a schedule: the level's bricks with the
  * brick kernel, its other octs with the per-oct kernel (which also records

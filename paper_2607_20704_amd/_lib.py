@@ -88,6 +88,8 @@ SIGNATURES = {
                      ctypes.POINTER(RgTuning), P]),
     "rg_step_subcycled": (st, [ctypes.POINTER(RgTree), P, P, P, f64, f64, ctypes.c_int, ctypes.c_uint, P,
                                ctypes.POINTER(RgTuning), P]),
+    "rg_schedule_workspace_bytes": (sz, [i64]),
+    "rg_schedule_build_device": (st, [ctypes.POINTER(RgTree), P, i64, P, sz, ctypes.POINTER(RgSchedule), P]),
     "rg_refine_workspace_bytes": (sz, [i64]),
     "rg_refine_flags": (st, [ctypes.POINTER(RgTree), P, ctypes.POINTER(RgRefineParams), ctypes.c_int, P, P]),
     "rg_refine": (st, [ctypes.POINTER(RgTree), P, P, ctypes.POINTER(RgRefineParams), P, sz, P]),

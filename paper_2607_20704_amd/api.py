@@ -233,14 +233,37 @@ class DeviceTree:
             return None
         return self._corr
 
-    def build_schedule(self):
-        """(Re)build the kernel schedule from the current keys and lists."""
+    def build_schedule(self, on_host=False):
+        """(Re)build the kernel schedule from the current keys and lists, on
+        the device (default) or on the host (rg_schedule_build)."""
         if not hasattr(self, "sched_list") or self.sched_list.numel() < 3 * self.n:
             self.sched_list = torch.empty(3 * self.capacity, dtype=torch.int32, device="cuda")
+        self._desc.sched = None
         self.sched = L.RgSchedule()
-        check(L.lib().rg_schedule_build(ctypes.byref(self._desc), _ptr(self.sched_list), self.sched_list.numel(),
-                                        ctypes.byref(self.sched), _stream()))
+        if on_host:
+            check(L.lib().rg_schedule_build(ctypes.byref(self._desc), _ptr(self.sched_list),
+                                            self.sched_list.numel(), ctypes.byref(self.sched), _stream()))
+        else:
+            if not hasattr(self, "sched_ws"):
+                self.sched_ws = _u8(L.lib().rg_schedule_workspace_bytes(self.capacity))
+            check(L.lib().rg_schedule_build_device(ctypes.byref(self._desc), _ptr(self.sched_list),
+                                                   self.sched_list.numel(), _ptr(self.sched_ws), self.sched_ws.numel(),
+                                                   ctypes.byref(self.sched), _stream()))
         self._desc.sched = ctypes.pointer(self.sched)
+
+    def schedule_lists(self):
+        """{level: (bricks, per-oct octs, border octs)} as numpy arrays, plus
+        the neighbour-build lists under key "nbr"."""
+        lst = self.sched_list.cpu().numpy()
+        sc = self.sched
+        out = {}
+        for l in range(self.lmin, self.lmax + 1):
+            out[l] = tuple(lst[b:b + c].copy() for b, c in ((sc.brick_begin[l], sc.brick_count[l]),
+                                                           (sc.rest_begin[l], sc.rest_count[l]),
+                                                           (sc.border_begin[l], sc.border_count[l])))
+        out["nbr"] = (lst[sc.nbr_brick_begin:sc.nbr_brick_begin + sc.nbr_brick_count].copy(),
+                      lst[sc.nbr_rest_begin:sc.nbr_rest_begin + sc.nbr_rest_count].copy())
+        return out
 
     def refine(self, u, rho_thresh=0.0, grad_thresh=0.0, lmax=None, out=None, schedule=None):
         """One refinement / de-refinement of the tree from state u (key

@@ -152,3 +152,27 @@ def test_schedule_rebuilt_after_refine():
     b, _ = U.run(u, w.gamma, w.cfl, 3)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+SCHED_TREES = [
+    ("uniform_l5", lambda: (I.uniform_tree(5), I.PERIODIC)),
+    ("sedov_l4_l6", lambda: (I.sedov_amr(base=4, lmax=6).ijkl, I.PERIODIC)),
+    ("sphere_5_6_outflow", lambda: (I.sphere_tree(5, 6, (0.3, 0.6, 0.55), 0.2, I.OUTFLOW), I.OUTFLOW)),
+    ("deep_amr_l4_l7", lambda: (I.deep_amr(base=4, lmax=7, nclump=60, sigma_a=2.0).ijkl, I.PERIODIC)),
+]
+
+
+@pytest.mark.parametrize("case", SCHED_TREES, ids=[c[0] for c in SCHED_TREES])
+def test_device_schedule_equals_host(case):
+    from paper_2607_20704_amd import api
+    name, mk = case
+    ijkl, bc = mk()
+    D = api.DeviceTree(ijkl, bc)
+    dev = D.schedule_lists()
+    D.build_schedule(on_host=True)
+    host = D.schedule_lists()
+    assert dev.keys() == host.keys()
+    for k in dev:
+        for a, b in zip(dev[k], host[k]):
+            assert np.array_equal(a, b), (name, k)
+    say("  %s: bricks %d" % (name, sum(len(v[0]) for k, v in dev.items() if k != "nbr")))

@@ -20,6 +20,12 @@
 #include "rg_internal.hpp"
 
 namespace rg {
+
+size_t nbr_lists_ws_bytes(int64_t n);
+rg_status nbr_lists_device(const uint64_t *d_keys, int64_t n, const int64_t *h_level_begin, int lmin, int lmax,
+                           void *d_ws, size_t ws_bytes, const int32_t **list, int64_t *nbricks, int64_t *nrest,
+                           hipStream_t s);
+
 namespace {
 
 constexpr int NVR = 5;   // conserved variables per cell
@@ -86,30 +92,38 @@ __global__ void k_zero_u32(uint32_t *p, int64_t n)
     if (i < n) p[i] = 0;
 }
 
-// one thread per (oct, cell) of one level: a flagged cell marks the father
-// cell of every level-l oct that holds one of its 26 neighbours or itself
+// one thread per oct of one level: a flagged cell marks the father cell of
+// every level-l oct holding one of its 26 neighbours or itself.  A cell with
+// in-oct position c reaches, along each axis, its own oct and the neighbour
+// oct on its side (offset -1 for c = 0, +1 for c = 1), so the oct's flagged
+// cells need at most 27 neighbour octs; each target bit is set by an atomic
+// only if a plain read does not already show it (many octs mark the same
+// coarse cells).
 __global__ void k_refine_closure(const int32_t *__restrict__ nbr27, const int32_t *__restrict__ father,
                                  int64_t ob, int64_t oe, uint32_t *flags)
 {
-    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t o = ob + (t >> 3);
+    const int64_t o = ob + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (o >= oe) return;
-    const int c = static_cast<int>(t & 7);
-    if (!((flags[o] >> c) & 1u)) return;
-    const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
-    for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int px = cx + dx, py = cy + dy, pz = cz + dz;
-                const int sx = px < 0 ? -1 : (px > 1 ? 1 : 0);
-                const int sy = py < 0 ? -1 : (py > 1 ? 1 : 0);
-                const int sz = pz < 0 ? -1 : (pz > 1 ? 1 : 0);
-                const int32_t e = nbr27[27 * o + (sx + 1) + 3 * (sy + 1) + 9 * (sz + 1)];
-                if (e == RG_NBR_OUTSIDE) continue;
-                const int64_t fc = e >= 0 ? int64_t(father[e]) : (-1 - int64_t(e));
-                if (fc < 0) continue;   // coarsest level: nothing to mark
-                atomicOr(&flags[fc >> 3], 1u << (fc & 7));
-            }
+    const uint32_t m = flags[o] & 0xffu;
+    if (!m) return;
+    uint32_t need = 0;   // bit (sx+1) + 3(sy+1) + 9(sz+1): neighbour oct offsets needed
+    for (int c = 0; c < 8; ++c) {
+        if (!((m >> c) & 1u)) continue;
+        const int ox = (c & 1) ? 1 : -1, oy = ((c >> 1) & 1) ? 1 : -1, oz = (c >> 2) ? 1 : -1;
+        for (int b = 0; b < 8; ++b) {
+            const int sx = (b & 1) ? ox : 0, sy = ((b >> 1) & 1) ? oy : 0, sz = (b >> 2) ? oz : 0;
+            need |= 1u << ((sx + 1) + 3 * (sy + 1) + 9 * (sz + 1));
+        }
+    }
+    for (int slot = 0; slot < 27; ++slot) {
+        if (!((need >> slot) & 1u)) continue;
+        const int32_t e = nbr27[27 * o + slot];
+        if (e == RG_NBR_OUTSIDE) continue;
+        const int64_t fc = e >= 0 ? int64_t(father[e]) : (-1 - int64_t(e));
+        if (fc < 0) continue;   // coarsest level: nothing to mark
+        const uint32_t bit = 1u << (fc & 7);
+        if (!(flags[fc >> 3] & bit)) atomicOr(&flags[fc >> 3], bit);
+    }
 }
 
 __device__ __forceinline__ bool kept(const uint32_t *flags, const int32_t *father, int64_t o, bool coarsest)
@@ -246,7 +260,7 @@ rg_status flags_pass(const rg_tree *t, const double *d_u, const rg_refine_params
         for (int l = t->lmax; l > t->lmin; --l) {
             const int64_t ob = t->level_begin[l], oe = t->level_begin[l + 1];
             if (oe <= ob) continue;
-            k_refine_closure<<<grid_for(8 * (oe - ob), 256), 256, 0, s>>>(t->d_nbr27, t->d_father_cell, ob, oe, flags);
+            k_refine_closure<<<grid_for(oe - ob, 256), 256, 0, s>>>(t->d_nbr27, t->d_father_cell, ob, oe, flags);
             RG_TRY(launch_status("refine closure"));
         }
     }
@@ -263,7 +277,8 @@ extern "C" {
 size_t rg_refine_workspace_bytes(int64_t capacity)
 {
     const int64_t cap = capacity > 0 ? capacity : 1;
-    return 4 * al256(4 * cap) + al256(16 * cap) + 256 + al256(scan_temp_bytes(cap)) + 256;
+    const size_t core = 4 * al256(4 * cap) + al256(16 * cap) + 256 + al256(scan_temp_bytes(cap)) + 256;
+    return core + al256(nbr_lists_ws_bytes(cap));
 }
 
 rg_status rg_refine_flags(const rg_tree *t, const double *d_u, const rg_refine_params *p, int closure,
@@ -331,8 +346,14 @@ rg_status rg_refine(rg_tree *t, const double *d_u, double *d_u_new, const rg_ref
     t->lmax = lmax;
     t->sched = nullptr;
     RG_TRY(rg_hash_build(t->d_keys, m, t->d_hash_ws, t->hash_ws_bytes, stream));
-    return rg_build_neighbours(t->d_hash_ws, t->d_keys, m, t->lmin, t->bc, t->d_nbr27, t->d_father_cell,
-                               t->d_son_mask, stream);
+    // neighbour lists brick by brick: the complete bricks follow from the keys
+    const size_t core = 4 * al256(4 * cap) + al256(16 * cap) + 256 + al256(scan_temp_bytes(cap)) + 256;
+    const int32_t *lst = nullptr;
+    int64_t nb = 0, nr = 0;
+    RG_TRY(nbr_lists_device(t->d_keys, m, t->level_begin, t->lmin, t->lmax, static_cast<char *>(d_ws) + core,
+                            ws_bytes - core, &lst, &nb, &nr, s));
+    return neighbours_scheduled(t->d_hash_ws, t->d_keys, m, t->lmin, t->bc, lst, nb, lst + nb, nr, t->d_nbr27,
+                                t->d_father_cell, t->d_son_mask, s);
 }
 
 }  // extern "C"

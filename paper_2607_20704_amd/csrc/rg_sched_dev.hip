@@ -115,6 +115,26 @@ __global__ void k_sched_scatter(int64_t n, const int32_t *__restrict__ pred, con
         if (pred[int64_t(k) * n + o]) list[b.base[k] + pos[int64_t(k) * n + o]] = static_cast<int32_t>(o);
 }
 
+// keys only: first octs of complete bricks (pred[0]) and octs outside
+// complete bricks (pred[1]), for the brick-wise neighbour build
+__global__ void k_nbr_pred(SchedArgs a, int32_t *pred)
+{
+    const int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (o >= a.n) return;
+    const int64_t f = brick_first(a, o, level_of(a, o));
+    pred[o] = f >= 0 && f == o;
+    pred[a.n + o] = f < 0;
+}
+
+__global__ void k_nbr_scatter(int64_t n, const int32_t *__restrict__ pred, const int32_t *__restrict__ pos,
+                              int64_t base1, int32_t *list)
+{
+    const int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (o >= n) return;
+    if (pred[o]) list[pos[o]] = static_cast<int32_t>(o);
+    if (pred[n + o]) list[base1 + pos[n + o]] = static_cast<int32_t>(o);
+}
+
 size_t al(size_t b) { return (b + 255) & ~size_t(255); }
 
 size_t scan_bytes(int64_t n)
@@ -126,6 +146,59 @@ size_t scan_bytes(int64_t n)
 }
 
 }  // namespace
+
+size_t nbr_lists_ws_bytes(int64_t n)
+{
+    n = n > 0 ? n : 1;
+    return 2 * al(8 * n) + al(4 * n + 4 * (n / kBrick) + 4) + al(scan_bytes(n)) + 256;
+}
+
+// The neighbour-build lists of a tree from its keys and level ranges alone
+// (complete bricks, then the other octs, in key order) into the workspace;
+// *list points at them.  Synchronises once for the two lengths.
+rg_status nbr_lists_device(const uint64_t *d_keys, int64_t n, const int64_t *h_level_begin, int lmin, int lmax,
+                           void *d_ws, size_t ws_bytes, const int32_t **list, int64_t *nbricks, int64_t *nrest,
+                           hipStream_t s)
+{
+    RG_REQUIRE(ws_bytes >= nbr_lists_ws_bytes(n) && aligned(d_ws, 256), "neighbour-list workspace too small");
+    char *p = static_cast<char *>(d_ws);
+    int32_t *pred = reinterpret_cast<int32_t *>(p);
+    p += al(8 * n);
+    int32_t *pos = reinterpret_cast<int32_t *>(p);
+    p += al(8 * n);
+    int32_t *lst = reinterpret_cast<int32_t *>(p);
+    p += al(4 * n + 4 * (n / kBrick) + 4);
+    void *temp = p;
+    SchedArgs a;
+    a.keys = d_keys;
+    a.nbr27 = nullptr;
+    a.n = n;
+    for (int l = 0; l < kLB; ++l) a.begin[l] = h_level_begin[l];
+    for (int l = lmax + 1; l < kLB; ++l) a.begin[l] = n;
+    a.lmin = lmin;
+    k_nbr_pred<<<grid_for(n, 256), 256, 0, s>>>(a, pred);
+    RG_TRY(launch_status("neighbour lists"));
+    for (int k = 0; k < 2; ++k) {
+        size_t tb = al(scan_bytes(n));
+        if (hipcub::DeviceScan::ExclusiveSum(temp, tb, pred + k * n, pos + k * n, static_cast<int>(n), s) !=
+            hipSuccess)
+            return fail(RG_EHIP, "neighbour-list scan");
+    }
+    int32_t h[4];
+    if (hipMemcpyAsync(&h[0], pos + (n - 1), 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&h[1], pred + (n - 1), 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&h[2], pos + (2 * n - 1), 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&h[3], pred + (2 * n - 1), 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(RG_EHIP, "neighbour-list readback");
+    *nbricks = int64_t(h[0]) + h[1];
+    *nrest = int64_t(h[2]) + h[3];
+    k_nbr_scatter<<<grid_for(n, 256), 256, 0, s>>>(n, pred, pos, *nbricks, lst);
+    RG_TRY(launch_status("neighbour-list scatter"));
+    *list = lst;
+    return RG_OK;
+}
+
 }  // namespace rg
 
 using namespace rg;

@@ -263,6 +263,83 @@ def time_deep_amr(forms, nsteps, api, inputs):
     return out
 
 
+def time_dynamic(api, inputs):
+    """Tree changes on the device (refinement, de-refinement, sort, hash and
+    neighbour rebuild: rg_refine; kernel schedule: rg_schedule_build_device).
+    Deep AMR: refinement passes with the criterion the tree was built with
+    (rho > 8 mean rho, finest level 12) beside one FP64 hydro step of the
+    same tree.  Sedov (base 6, up to level 8): every step a hydro step, then
+    refinement on the density jump (> 0.08), then the schedule; wall time per
+    step with its parts."""
+    import torch
+
+    def wall(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t0) * 1e3
+
+    out = {}
+    w = inputs.deep_amr()
+    n = len(w.ijkl)
+    D = api.DeviceTree(w.ijkl, w.bc, capacity=int(1.25 * n))
+    thr = 8.0 * w.meta["mean_rho"]
+    bufs = [D.to_key_order(w.u), torch.empty((8 * D.capacity, 5), dtype=torch.float64, device="cuda")]
+    full = torch.empty((8 * D.capacity, 5), dtype=torch.float64, device="cuda")
+    full[:8 * D.n] = bufs[0]
+    bufs[0] = full
+    cur = 0
+    refine_ms, sched_ms, octs = [], [], []
+    for it in range(4):
+        _, ms = wall(lambda: D.refine(bufs[cur][:8 * D.n], thr, 0.0, 12, out=bufs[cur ^ 1], schedule=False))
+        cur ^= 1
+        _, ms2 = wall(lambda: D.build_schedule())
+        if it:
+            refine_ms.append(ms)
+            sched_ms.append(ms2)
+        octs.append(D.n)
+    _, host_sched_ms = wall(lambda: D.build_schedule(on_host=True))
+    D.build_schedule()
+    u = bufs[cur][:8 * D.n]
+    a = torch.empty_like(u)
+    D.step(u, a, w.gamma, w.cfl, api.RG_FP64)
+    _, step_ms = wall(lambda: D.step(u, a, w.gamma, w.cfl, api.RG_FP64))
+    out["deep_amr_refine"] = {
+        "octs_per_pass": octs, "refine_ms": round(min(refine_ms), 3), "schedule_ms": round(min(sched_ms), 3),
+        "host_schedule_ms": round(host_sched_ms, 1), "hydro_step_ms": round(step_ms, 3),
+        "note": "refine = flags, closure, new oct list, key sort, state gather, level ranges, hash, neighbours"}
+    del bufs, full, u, a, D
+    torch.cuda.empty_cache()
+
+    w = inputs.sedov_amr()
+    D = api.DeviceTree(w.ijkl, w.bc, capacity=400000)
+    u = torch.empty((8 * D.capacity, 5), dtype=torch.float64, device="cuda")
+    v = torch.empty_like(u)
+    u[:8 * D.n] = D.to_key_order(w.u)
+    parts = {"step": 0.0, "refine": 0.0, "schedule": 0.0}
+    cells = 0
+    nsteps, warm = 20, 5
+    for s in range(warm + nsteps):
+        n8 = 8 * D.n
+        _, t1 = wall(lambda: D.step(u[:n8], v[:n8], w.gamma, w.cfl, api.RG_FP64))
+        _, t2 = wall(lambda: D.refine(v[:n8], 0.0, 0.08, 8, out=u, schedule=False))
+        _, t3 = wall(lambda: D.build_schedule())
+        if s >= warm:
+            parts["step"] += t1
+            parts["refine"] += t2
+            parts["schedule"] += t3
+            cells += n8
+    total = sum(parts.values())
+    out["sedov_dynamic"] = {
+        "workload": "Sedov blast, base level 6, refined on |rho_n - rho| / (rho_n + rho) > 0.08 up to level 8, "
+                    "FP64, refinement every step",
+        "steps": nsteps, "octs_at_end": D.n, "ms_per_step": round(total / nsteps, 3),
+        "parts_ms_per_step": {k: round(v_ / nsteps, 3) for k, v_ in parts.items()},
+        "cell_updates_per_s": cells / (total * 1e-3)}
+    return out
+
+
 def copy_ceiling(torch, mib=1024, reps=5):
     """Practical HBM ceiling: GB/s (read + write) of a plain device copy of
     `mib` MiB, best of `reps`."""
@@ -315,6 +392,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-box batched workload")
     ap.add_argument("--no-tune", action="store_true", help="library default kernels instead of autotuned ones")
     ap.add_argument("--no-deep-amr", action="store_true", help="skip the clumpy-gas deep-AMR workload")
+    ap.add_argument("--no-dynamic", action="store_true", help="skip the refinement (dynamic tree) measurements")
+    ap.add_argument("--leg", choices=["all", "deep_amr", "dynamic"], default="all",
+                    help="run one workload only and print its JSON (for profiling it); 'all' is the benchmark line")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -326,6 +406,11 @@ def main():
 
     from paper_2607_20704_amd import api, autotune, inputs
     torch.cuda.set_device(0)
+    if args.leg != "all":
+        forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+        leg = time_deep_amr(forms, 10, api, inputs) if args.leg == "deep_amr" else time_dynamic(api, inputs)
+        print(json.dumps({args.leg: leg}), flush=True)
+        return
     log("generating the 256^3 random-field box")
     w = inputs.random_uniform()
     D = api.DeviceTree(w.ijkl, w.bc)
@@ -407,6 +492,10 @@ def main():
     if not args.no_deep_amr:
         log("deep-AMR workload: generating")
         out["deep_amr"] = time_deep_amr(forms, 10, api, inputs)
+        torch.cuda.empty_cache()
+    if not args.no_dynamic:
+        log("dynamic trees: refinement on the device")
+        out["dynamic"] = time_dynamic(api, inputs)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("oracle CPU baseline on a bounded sample")

@@ -14,3 +14,11 @@ if HERE not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (run on the GPU box)")
     config.addinivalue_line("markers", "slow: long CPU test")
+
+
+@pytest.fixture(scope="session")
+def deep_full():
+    """The full clumpy-gas deep-AMR workload (base 7 to level 12, about 3.5 M
+    octs), generated once per session."""
+    from paper_2607_20704_amd import inputs
+    return inputs.deep_amr()

@@ -50,13 +50,13 @@ def test_small_deep_amr_mixed_l1():
     assert np.all(mom <= 1e-5), mom
 
 
-def test_full_deep_amr_sampled():
+def test_full_deep_amr_sampled(deep_full):
     """28 M cells, 3.5 M octs on levels 7-12: one FP64 update of every level
     (the launches the benchmark times) against the oracle's update of 1500
     sampled octs, including the fluxes they owe to coarse neighbours."""
     from paper_2607_20704_amd import api
     say("deep amr full: generating")
-    w = I.deep_amr()
+    w = deep_full
     say("  octs", len(w.ijkl), "levels", np.bincount(w.ijkl[:, 3])[7:].tolist())
     D = api.DeviceTree(w.ijkl, w.bc)
     T = O.Tree(w.ijkl, w.bc)

@@ -176,3 +176,67 @@ def test_device_schedule_equals_host(case):
         for a, b in zip(dev[k], host[k]):
             assert np.array_equal(a, b), (name, k)
     say("  %s: bricks %d" % (name, sum(len(v[0]) for k, v in dev.items() if k != "nbr")))
+
+
+def _leaf_totals_dev(D, u):
+    """Leaf sums of volume * U on the device (float64)."""
+    lv = D.ijkl_sorted[:, 3].to(torch.float64)
+    bits = torch.arange(8, device="cuda", dtype=torch.int32)
+    leaf = ((D.son_mask[:, None] >> bits[None, :]) & 1) == 0
+    vol = torch.pow(2.0, -3.0 * lv)[:, None] * leaf
+    w = vol.reshape(-1, 1)
+    return (w * u).sum(0).cpu().numpy(), (w * u.abs()).sum(0).cpu().numpy()
+
+
+def test_full_deep_amr_refine_properties(deep_full):
+    """The 3.5 M-oct clumpy tree refined with the criterion it was built
+    with, in the configuration the benchmark times: the new tree is graded,
+    kept octs carry their cells unchanged and children exactly where the
+    closed flags are, new octs hold their father's values, the criterion's
+    flags are among the closed ones, and leaf sums are unchanged."""
+    from paper_2607_20704_amd import api, _lib as L
+    w = deep_full
+    n = len(w.ijkl)
+    thr = 8.0 * w.meta["mean_rho"]
+    D = api.DeviceTree(w.ijkl, w.bc, capacity=int(1.25 * n))
+    u = torch.empty((8 * D.capacity, 5), dtype=torch.float64, device="cuda")
+    u[:8 * n] = D.to_key_order(w.u)
+    u = u[:8 * n]
+    crit = D.refine_flags(u, thr, 0.0, 12, closure=False).cpu().numpy()
+    flags = D.refine_flags(u, thr, 0.0, 12, closure=True).cpu().numpy()
+    assert np.all((crit & ~flags) == 0) and crit.any()
+    tot0, abs0 = _leaf_totals_dev(D, u)
+    keys0 = D.keys.cpu().numpy()
+    father0 = D.father_cell.cpu().numpy()
+    lv0 = D.ijkl_sorted[:, 3].cpu().numpy()
+    u_old = u.cpu().numpy().reshape(-1, 8, 5)
+    u2 = D.refine(u, thr, 0.0, 12)
+    st, bad = api.check_ws(D.hash_ws)
+    assert st == L.RG_OK, (st, bad)
+    keys1 = D.keys.cpu().numpy()
+    ijkl1 = D.ijkl_sorted.cpu().numpy()
+    son1 = D.son_mask.cpu().numpy()
+    u_new = u2.cpu().numpy().reshape(-1, 8, 5)
+    say("  octs %d -> %d" % (n, D.n))
+    # kept octs
+    kept = lv0 == lv0.min()
+    nf = father0 >= 0
+    kept[nf] = ((flags[father0[nf] >> 3] >> (father0[nf] & 7)) & 1) == 1
+    pos = np.searchsorted(keys1, keys0)
+    pos = np.minimum(pos, len(keys1) - 1)
+    present = keys1[pos] == keys0
+    assert np.array_equal(present, kept)
+    assert np.array_equal(u_new[pos[kept]], u_old[kept])
+    assert np.array_equal(son1[pos[kept]], flags[kept] & 0xff)
+    # new octs: father cell's values in all eight cells
+    fresh = np.ones(len(keys1), bool)
+    fresh[pos[kept]] = False
+    fk = keys1[fresh] >> np.uint64(3)
+    fo = np.searchsorted(keys0, fk)
+    assert np.array_equal(keys0[fo], fk)
+    c = ijkl1[fresh]
+    cell = (c[:, 0] & 1) + 2 * (c[:, 1] & 1) + 4 * (c[:, 2] & 1)
+    src = u_old[fo, cell]
+    assert np.array_equal(u_new[fresh], np.repeat(src[:, None, :], 8, axis=1))
+    tot1, abs1 = _leaf_totals_dev(D, u2)
+    assert np.all(np.abs(tot1 - tot0) <= 1e-12 * np.maximum(abs0, abs1))

@@ -384,6 +384,96 @@ typedef struct {
 static int slot_of(int x) { return x < 0 ? -1 : (x > 1 ? 1 : 0); }
 static int nslot(int sx, int sy, int sz) { return (sx + 1) + 3 * (sy + 1) + 9 * (sz + 1); }
 
+/* Coarse ghost values (Sec. 2.3 creates ghost zones where a neighbour oct
+ * does not exist; the paper does not say how they are filled).  Mode 0
+ * (default): injection, every fine position takes the coarse cell's values.
+ * Mode 1: minmod-limited linear interpolation of the conserved variables
+ * inside the coarse cell C (the RAMSES option): with the one-sided
+ * differences to C's face neighbours along each axis, slope_a =
+ * minmod(U_C - U_a-, U_a+ - U_C), and a fine cell at sub-position s in C
+ * gets ((U_C + q_x slope_x) + q_y slope_y) + q_z slope_z, q = -1/4 for s = 0,
+ * +1/4 for s = 1 (its centre lies a quarter of C's width from C's).  C's
+ * neighbour across a face is the same-level cell (in C's oct or the
+ * neighbouring oct), else the coarser cell covering it, and C itself on an
+ * outflow boundary. */
+static int g_ghost_mode = 0;
+
+void orc_set_ghost_mode(int mode) { g_ghost_mode = mode; }
+int orc_get_ghost_mode(void) { return g_ghost_mode; }
+
+static int64_t cell_across(const orc_tree *t, int64_t c, int a, int d)
+{
+    const int64_t P = c >> 3;
+    const int q = (int)(c & 7);
+    const int qa = (q >> a) & 1;
+    if ((d > 0 && qa == 0) || (d < 0 && qa == 1)) return 8 * P + (q ^ (1 << a));
+    int fs[3] = {0, 0, 0};
+    fs[a] = d;
+    const int32_t e = t->nbr27[27 * P + nslot(fs[0], fs[1], fs[2])];
+    if (e == ORC_OUTSIDE) return c;
+    if (e >= 0) return 8 * (int64_t)e + (q ^ (1 << a));
+    return -1 - (int64_t)e;
+}
+
+static void coarse_ghost(const orc_tree *t, const double *uold, int64_t C, const int sub[3], double *out)
+{
+    const double *uc = uold + 5 * C;
+    for (int v = 0; v < 5; ++v) out[v] = uc[v];
+    if (g_ghost_mode != 1) return;
+    for (int a = 0; a < 3; ++a) {
+        const double *ul = uold + 5 * cell_across(t, C, a, -1);
+        const double *ur = uold + 5 * cell_across(t, C, a, +1);
+        const double q = sub[a] ? 0.25 : -0.25;
+        for (int v = 0; v < 5; ++v) out[v] = out[v] + q * orc_minmod(uc[v] - ul[v], ur[v] - uc[v]);
+    }
+}
+
+/* The 6x6x6 tile of oct o (Sec. 3): same-level neighbours give their cells;
+ * a missing neighbour gives coarse ghost values (above); an outside position
+ * copies the nearest cell inside the domain.  split marks split cells. */
+static void build_tile(const orc_tree *t, int64_t o, const double *uold, double U[6][6][6][5], int split[6][6][6])
+{
+    const int32_t *nb = t->nbr27 + 27 * o;
+    for (int z = -2; z <= 3; ++z)
+        for (int y = -2; y <= 3; ++y)
+            for (int x = -2; x <= 3; ++x) {
+                int c[3] = {x, y, z};
+                int s[3] = {slot_of(x), slot_of(y), slot_of(z)};
+                for (int a = 0; a < 3; ++a) {
+                    int fs[3] = {0, 0, 0};
+                    fs[a] = s[a];
+                    if (s[a] != 0 && nb[nslot(fs[0], fs[1], fs[2])] == ORC_OUTSIDE) {
+                        c[a] = s[a] > 0 ? 1 : 0;
+                        s[a] = 0;
+                    }
+                }
+                int32_t e = nb[nslot(s[0], s[1], s[2])];
+                int is_split = 0;
+                double *dst = U[TI(z)][TI(y)][TI(x)];
+                if (e >= 0) {
+                    int bit = (c[0] & 1) + 2 * (c[1] & 1) + 4 * (c[2] & 1);
+                    int64_t cell = 8 * (int64_t)e + bit;
+                    /* a clamped position is a ghost copy, never split */
+                    if (c[0] == x && c[1] == y && c[2] == z)
+                        is_split = (t->son_mask[e] >> bit) & 1;
+                    for (int v = 0; v < 5; ++v) dst[v] = uold[5 * cell + v];
+                } else {
+                    int sub[3] = {c[0] & 1, c[1] & 1, c[2] & 1};
+                    coarse_ghost(t, uold, -1 - (int64_t)e, sub, dst);
+                }
+                split[TI(z)][TI(y)][TI(x)] = is_split;
+            }
+}
+
+/* The tile of oct o, [z][y][x][var] over -2..3 (test access). */
+void orc_oct_tile(int64_t n, const int32_t *ijkl, const int32_t *nbr27, const uint8_t *son_mask, const double *u,
+                  int64_t o, double *tile)
+{
+    orc_tree t = {n, ijkl, nbr27, NULL, son_mask};
+    static int split[6][6][6];
+    build_tile(&t, o, u, (double(*)[6][6][5])tile, split);
+}
+
 /* Update the 8 cells of oct o from uold into unew, and record, for each of
  * the oct's six sides that borders a coarse ghost, the flux it sends to that
  * coarse cell (corr[30*o + 5*side + var], side = 2*axis + (high ? 1 : 0)). */
@@ -399,37 +489,8 @@ static void hydro_oct(const orc_tree *t, int64_t o, const double *uold, double *
     static double Gf[3][6][6][6][5];
     const int32_t *nb = t->nbr27 + 27 * o;
 
-    /* 1. tile: same-level neighbours give their cells; a missing neighbour
-     *    gives its covering coarse cell to all 8 positions (injection); an
-     *    outside position copies the nearest cell inside the domain. */
-    for (int z = -2; z <= 3; ++z)
-        for (int y = -2; y <= 3; ++y)
-            for (int x = -2; x <= 3; ++x) {
-                int c[3] = {x, y, z};
-                int s[3] = {slot_of(x), slot_of(y), slot_of(z)};
-                for (int a = 0; a < 3; ++a) {
-                    int fs[3] = {0, 0, 0};
-                    fs[a] = s[a];
-                    if (s[a] != 0 && nb[nslot(fs[0], fs[1], fs[2])] == ORC_OUTSIDE) {
-                        c[a] = s[a] > 0 ? 1 : 0;
-                        s[a] = 0;
-                    }
-                }
-                int32_t e = nb[nslot(s[0], s[1], s[2])];
-                int64_t cell;
-                int is_split = 0;
-                if (e >= 0) {
-                    int bit = (c[0] & 1) + 2 * (c[1] & 1) + 4 * (c[2] & 1);
-                    cell = 8 * (int64_t)e + bit;
-                    /* a clamped position is a ghost copy, never split */
-                    if (c[0] == x && c[1] == y && c[2] == z)
-                        is_split = (t->son_mask[e] >> bit) & 1;
-                } else {
-                    cell = -1 - (int64_t)e;
-                }
-                for (int v = 0; v < 5; ++v) U[TI(z)][TI(y)][TI(x)][v] = uold[5 * cell + v];
-                split[TI(z)][TI(y)][TI(x)] = is_split;
-            }
+    /* 1. the tile */
+    build_tile(t, o, uold, U, split);
 
     /* 2. primitive variables on the whole tile */
     for (int z = 0; z < 6; ++z)

@@ -78,6 +78,12 @@ def lib():
         L.orc_run.argtypes = [i64, P, P, P, P, P, f64, f64, i64, P]
         L.orc_cfl_dt_subcycled.restype = f64
         L.orc_cfl_dt_subcycled.argtypes = [i64, P, P, P, f64, f64]
+        L.orc_set_ghost_mode.restype = None
+        L.orc_set_ghost_mode.argtypes = [ctypes.c_int]
+        L.orc_get_ghost_mode.restype = ctypes.c_int
+        L.orc_get_ghost_mode.argtypes = []
+        L.orc_oct_tile.restype = None
+        L.orc_oct_tile.argtypes = [i64, P, P, P, P, i64, P]
         L.orc_refine.restype = ctypes.c_int
         L.orc_refine.argtypes = [i64, P, P, P, ctypes.c_int, f64, f64, ctypes.c_int, P, P, i64, P, P, P]
         L.orc_step_subcycled.restype = f64
@@ -165,8 +171,18 @@ def cfl_dt(ijkl, son_mask, u, gamma, cfl):
     return lib().orc_cfl_dt(len(sm), _p(ijkl), _p(sm), _p(u), float(gamma), float(cfl))
 
 
-def hydro_octs(ijkl, nbr27, son_mask, ob, oe, uold, unew, corr, dt, gamma):
+GHOST_INJECT, GHOST_LINEAR = 0, 1
+
+
+def set_ghost_mode(mode):
+    """Coarse ghost values for the module-level calls: GHOST_INJECT or
+    GHOST_LINEAR (minmod-limited linear interpolation)."""
+    lib().orc_set_ghost_mode(int(mode))
+
+
+def hydro_octs(ijkl, nbr27, son_mask, ob, oe, uold, unew, corr, dt, gamma, ghost=GHOST_INJECT):
     """Hydro update of octs [ob, oe) into unew / corr (arrays modified in place)."""
+    set_ghost_mode(ghost)
     ijkl = _c(ijkl, np.int32)
     nbr27 = _c(nbr27, np.int32)
     sm = _c(son_mask, np.uint8)
@@ -178,9 +194,11 @@ def hydro_octs(ijkl, nbr27, son_mask, ob, oe, uold, unew, corr, dt, gamma):
 
 
 class Tree:
-    """A key-ordered tree with the oracle's own neighbour lists."""
+    """A key-ordered tree with the oracle's own neighbour lists; `ghost`
+    selects how coarse ghost cells are filled (GHOST_INJECT, GHOST_LINEAR)."""
 
-    def __init__(self, ijkl, bc):
+    def __init__(self, ijkl, bc, ghost=GHOST_INJECT):
+        self.ghost = int(ghost)
         ijkl = _c(ijkl, np.int32).reshape(-1, 4)
         self.perm = tree_order(ijkl)
         self.ijkl = np.ascontiguousarray(ijkl[self.perm])
@@ -204,18 +222,21 @@ class Tree:
 
     def step(self, u, gamma, cfl):
         """One global-dt step, in place; returns dt."""
+        set_ghost_mode(self.ghost)
         assert u.dtype == np.float64 and u.flags.c_contiguous and u.shape == (8 * self.n, 5)
         return lib().orc_step(self.n, _p(self.ijkl), _p(self.nbr27), _p(self.father_cell), _p(self.son_mask),
                               _p(u), float(gamma), float(cfl))
 
     def step_fixed(self, u, gamma, dt):
         """One step with the given dt, in place."""
+        set_ghost_mode(self.ghost)
         assert u.dtype == np.float64 and u.flags.c_contiguous and u.shape == (8 * self.n, 5)
         return lib().orc_step_fixed(self.n, _p(self.ijkl), _p(self.nbr27), _p(self.father_cell),
                                     _p(self.son_mask), _p(u), float(gamma), float(dt))
 
     def run(self, u, gamma, cfl, nsteps):
         """nsteps steps in place; returns the array of dts."""
+        set_ghost_mode(self.ghost)
         assert u.dtype == np.float64 and u.flags.c_contiguous and u.shape == (8 * self.n, 5)
         dts = np.zeros(nsteps)
         lib().orc_run(self.n, _p(self.ijkl), _p(self.nbr27), _p(self.father_cell), _p(self.son_mask),
@@ -229,6 +250,7 @@ class Tree:
 
     def step_subcycled(self, u, gamma, cfl):
         """One coarse step with level subcycling, in place; returns the coarse dt."""
+        set_ghost_mode(self.ghost)
         assert u.dtype == np.float64 and u.flags.c_contiguous and u.shape == (8 * self.n, 5)
         return lib().orc_step_subcycled(self.n, _p(self.ijkl), _p(self.nbr27), _p(self.father_cell),
                                         _p(self.son_mask), _p(u), float(gamma), float(cfl))
@@ -257,3 +279,11 @@ class Tree:
         m = m.value
         self.last_crit = crit
         return flags, new_ijkl[:m].copy(), new_u[:8 * m].copy()
+
+    def tile(self, u, o):
+        """The 6x6x6 tile of oct o, [z][y][x][var] for tile coordinates -2..3."""
+        set_ghost_mode(self.ghost)
+        t = np.zeros((6, 6, 6, 5))
+        lib().orc_oct_tile(self.n, _p(self.ijkl), _p(self.nbr27), _p(self.son_mask), _p(_c(u, np.float64)), int(o),
+                           _p(t))
+        return t

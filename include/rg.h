@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define RG_ABI_VERSION 6
+#define RG_ABI_VERSION 7
 #define RG_MAX_LEVEL 21
 #define RG_NBR_OUTSIDE INT32_MIN
 #define RG_RHO_MIN 1e-10
@@ -73,6 +73,17 @@ typedef enum rg_status {
 } rg_status;
 
 enum { RG_BC_PERIODIC = 0, RG_BC_OUTFLOW = 1 };
+
+/* Coarse ghost cells (Sec. 2.3: ghost zones where a neighbour oct is
+ * missing; the paper does not say how they are filled).  INJECT: every fine
+ * position takes the coarse cell's values.  LINEAR: minmod-limited linear
+ * interpolation of the conserved variables inside the coarse cell C: slope_a
+ * = minmod(U_C - U_a-, U_a+ - U_C) from C's face neighbours (same-level
+ * cells, else the coarser cell covering them, C itself across an outflow
+ * face), and a fine cell at sub-position s gets ((U_C + q_x slope_x) + q_y
+ * slope_y) + q_z slope_z, q = -1/4 for s = 0 and +1/4 for s = 1.  Selected
+ * per tree (rg_tree.ghost); rg_hydro_step_level, which has no tree, injects. */
+enum { RG_GHOST_INJECT = 0, RG_GHOST_LINEAR = 1 };
 
 /* Precision forms of the hydro update:
  *   RG_FP64  every step in double precision.
@@ -298,7 +309,7 @@ typedef struct rg_tree {
     int64_t n_oct;
     int32_t lmin, lmax;                       /* levels present */
     int32_t bc;                               /* RG_BC_* */
-    int32_t pad0;
+    int32_t ghost;                            /* coarse ghost cells: RG_GHOST_INJECT or RG_GHOST_LINEAR */
     int64_t level_begin[RG_MAX_LEVEL + 2];    /* host copy of the level ranges */
     uint64_t *d_keys;                         /* sorted keys [n_oct] */
     void *d_hash_ws;                          /* rg_hash_workspace_bytes(n_oct) */

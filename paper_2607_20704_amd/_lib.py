@@ -17,6 +17,7 @@ RG_NBR_OUTSIDE = -(2 ** 31)
 RG_STEP_REBUILD = 1
 RG_STEP_REKEY = 2
 RG_STEP_CHAIN_DT = 4
+RG_GHOST_INJECT, RG_GHOST_LINEAR = 0, 1
 
 # every symbol include/rg.h declares, with (restype, argtypes)
 P = ctypes.c_void_p
@@ -39,7 +40,7 @@ class RgSchedule(ctypes.Structure):
 
 
 class RgTree(ctypes.Structure):
-    _fields_ = [("n_oct", i64), ("lmin", i32), ("lmax", i32), ("bc", i32), ("pad0", i32),
+    _fields_ = [("n_oct", i64), ("lmin", i32), ("lmax", i32), ("bc", i32), ("ghost", i32),
                 ("level_begin", i64 * (RG_MAX_LEVEL + 2)),
                 ("d_keys", P), ("d_hash_ws", P), ("hash_ws_bytes", sz),
                 ("d_nbr27", P), ("d_father_cell", P), ("d_son_mask", P), ("d_corr", P),

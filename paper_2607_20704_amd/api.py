@@ -175,9 +175,10 @@ class DeviceTree:
     lists and the coarse-fine correction buffer, built from oct coordinates
     by the library (encode, radix sort, level ranges, hash, neighbours)."""
 
-    def __init__(self, ijkl, bc, schedule=True, capacity=None):
+    def __init__(self, ijkl, bc, schedule=True, capacity=None, ghost=0):
         ijkl_d = torch.as_tensor(np.ascontiguousarray(ijkl, dtype=np.int32)).to("cuda")
         self.bc = int(bc)
+        self.ghost = int(ghost)
         n = int(ijkl_d.shape[0])
         cap = int(capacity) if capacity else n
         if cap < n:
@@ -326,6 +327,7 @@ class DeviceTree:
     def _descriptor(self):
         t = RgTree()
         t.n_oct, t.lmin, t.lmax, t.bc = self.n, self.lmin, self.lmax, self.bc
+        t.ghost = self.ghost
         for l in range(RG_MAX_LEVEL + 2):
             t.level_begin[l] = int(self.level_begin[l])
         t.d_keys = self.keys.data_ptr()

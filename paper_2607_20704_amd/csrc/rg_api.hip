@@ -111,6 +111,7 @@ rg_status rg_step(const rg_tree *t, const double *d_uold, double *d_unew, double
     RG_REQUIRE(t->lmin == t->lmax || t->d_corr, "a multilevel tree needs a correction buffer");
     RG_REQUIRE((flags & ~(RG_STEP_REBUILD | RG_STEP_REKEY | RG_STEP_CHAIN_DT)) == 0, "unknown flags %u", flags);
     RG_REQUIRE(gamma > 1 && cfl > 0, "bad gamma or cfl");
+    RG_REQUIRE(t->ghost == RG_GHOST_INJECT || t->ghost == RG_GHOST_LINEAR, "bad ghost mode %d", t->ghost);
     hipStream_t s = as_stream(stream);
     const unsigned prep = flags & (RG_STEP_REBUILD | RG_STEP_REKEY);
     if (prep) RG_TRY(rg_prepare_tree(t, prep, stream));

@@ -35,7 +35,7 @@ struct BTree {
     int32_t *hvals;
     uint64_t hmask;
     double gamma, cfl;
-    int32_t lmin, lmax, bc, pad;
+    int32_t lmin, lmax, bc, ghost;
     int64_t n_oct;
     int64_t level_begin[RG_MAX_LEVEL + 2];
 };
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(BT, sizeof(R) == 8 ? 2 : 4) void k_batch_bricks(con
     }
 }
 
-template <typename R, int G, bool P>
+template <typename R, int G, bool P, bool GH>
 __global__ __launch_bounds__(kT, sizeof(R) == 8 ? 4 : 6) void k_batch_octs(const BTree *__restrict__ trees,
                                                                           const Item *__restrict__ items,
                                                                           int64_t nitems, int parity,
@@ -192,6 +192,8 @@ __global__ __launch_bounds__(kT, sizeof(R) == 8 ? 4 : 6) void k_batch_octs(const
         a.corr = level > T.lmin ? T.corr : nullptr;
         a.corr_base = T.corr_base;
         a.corr_mode = 0;
+        a.ghost = T.ghost;
+        a.ucoarse2 = T.u[parity];
         a.oct_begin = I.first;
         a.oct_end = I.first + I.count;
         a.dt = dt + I.tree;
@@ -199,7 +201,7 @@ __global__ __launch_bounds__(kT, sizeof(R) == 8 ? 4 : 6) void k_batch_octs(const
         a.gamma = T.gamma;
         a.cfl = T.cfl;
         a.dt_next = reinterpret_cast<unsigned long long *>(dt_next + I.tree);
-        hydro_group<R, G, kT>(a, I.first, static_cast<int>(I.count), S);
+        hydro_group<R, G, kT, GH>(a, I.first, static_cast<int>(I.count), S);
         __syncthreads();
     }
 }
@@ -405,27 +407,32 @@ rg_status launch_bricks(bool persistent, const BTree *trees, const Phase &p, int
     return launch_status("batched bricks");
 }
 
-template <typename R, int G>
+template <typename R, int G, bool GH>
 rg_status launch_octs(bool persistent, const BTree *trees, const Phase &p, int parity, const double *dt,
                       double *dt_next, hipStream_t s)
 {
     if (p.n == 0) return RG_OK;
     if (persistent) {
-        const int grid = persistent_grid(reinterpret_cast<const void *>(&k_batch_octs<R, G, true>), kT, p.n);
-        k_batch_octs<R, G, true><<<grid, kT, 0, s>>>(trees, p.d_items, p.n, parity, dt, dt_next);
+        const int grid = persistent_grid(reinterpret_cast<const void *>(&k_batch_octs<R, G, true, GH>), kT, p.n);
+        k_batch_octs<R, G, true, GH><<<grid, kT, 0, s>>>(trees, p.d_items, p.n, parity, dt, dt_next);
     } else {
-        k_batch_octs<R, G, false><<<one_shot_grid(p.n), kT, 0, s>>>(trees, p.d_items, p.n, parity, dt, dt_next);
+        k_batch_octs<R, G, false, GH><<<one_shot_grid(p.n), kT, 0, s>>>(trees, p.d_items, p.n, parity, dt, dt_next);
     }
     return launch_status("batched oct groups");
 }
 
 template <typename R>
-rg_status launch_octs_g(int g, bool persistent, const BTree *trees, const Phase &p, int parity, const double *dt,
-                        double *dt_next, hipStream_t s)
+rg_status launch_octs_g(int g, bool gh, bool persistent, const BTree *trees, const Phase &p, int parity,
+                        const double *dt, double *dt_next, hipStream_t s)
 {
-    if (g == 2) return launch_octs<R, 2>(persistent, trees, p, parity, dt, dt_next, s);
-    if (g == 8) return launch_octs<R, 8>(persistent, trees, p, parity, dt, dt_next, s);
-    return launch_octs<R, 4>(persistent, trees, p, parity, dt, dt_next, s);
+    if (gh) {
+        if (g == 2) return launch_octs<R, 2, true>(persistent, trees, p, parity, dt, dt_next, s);
+        if (g == 8) return launch_octs<R, 8, true>(persistent, trees, p, parity, dt, dt_next, s);
+        return launch_octs<R, 4, true>(persistent, trees, p, parity, dt, dt_next, s);
+    }
+    if (g == 2) return launch_octs<R, 2, false>(persistent, trees, p, parity, dt, dt_next, s);
+    if (g == 8) return launch_octs<R, 8, false>(persistent, trees, p, parity, dt, dt_next, s);
+    return launch_octs<R, 4, false>(persistent, trees, p, parity, dt, dt_next, s);
 }
 
 unsigned small_grid(int64_t n)
@@ -453,6 +460,8 @@ rg_status rg_batch_create(const rg_batch_tree *trees, int ntree, int form, int n
     RG_REQUIRE(g == 2 || g == 4 || g == 8, "batched kernel has no %d-oct groups", g);
     const bool bricks = !(tune && tune->no_bricks);
     const bool persistent = tune && tune->persistent;
+    bool gh = false;   // some tree interpolates its coarse ghosts
+    for (int t = 0; t < ntree; ++t) gh = gh || (trees[t].tree && trees[t].tree->ghost == RG_GHOST_LINEAR);
     *out = nullptr;
     hipStream_t s = as_stream(stream);
 
@@ -467,6 +476,7 @@ rg_status rg_batch_create(const rg_batch_tree *trees, int ntree, int form, int n
         RG_REQUIRE(T->n_oct > 0 && T->lmin >= 1 && T->lmax >= T->lmin && T->lmax <= RG_MAX_LEVEL, "tree %d levels", t);
         RG_REQUIRE(T->level_begin[T->lmin] == 0 && T->level_begin[T->lmax + 1] == T->n_oct, "tree %d level ranges", t);
         RG_REQUIRE(T->lmin == T->lmax || T->d_corr, "tree %d needs a correction buffer", t);
+        RG_REQUIRE(T->ghost == RG_GHOST_INJECT || T->ghost == RG_GHOST_LINEAR, "tree %d ghost mode", t);
         RG_REQUIRE(T->d_keys && T->d_hash_ws && T->d_nbr27 && T->d_father_cell && T->d_son_mask, "tree %d buffers", t);
         RG_REQUIRE(trees[t].gamma > 1 && trees[t].cfl > 0, "tree %d gamma/cfl", t);
         const rg_schedule *sc = T->sched;
@@ -491,7 +501,7 @@ rg_status rg_batch_create(const rg_batch_tree *trees, int ntree, int form, int n
         b.lmin = T->lmin;
         b.lmax = T->lmax;
         b.bc = T->bc;
-        b.pad = 0;
+        b.ghost = T->ghost;
         b.n_oct = T->n_oct;
         for (int l = 0; l < RG_MAX_LEVEL + 2; ++l) b.level_begin[l] = T->level_begin[l];
 
@@ -622,9 +632,9 @@ rg_status rg_batch_create(const rg_batch_tree *trees, int ntree, int form, int n
         if (st != RG_OK) break;
         hipStream_t so = fork ? cs2 : cs;
         if (form == RG_FP64)
-            st = launch_octs_g<double>(g, persistent, d_trees, ph_octs, parity, dt, dt_next, so);
+            st = launch_octs_g<double>(g, gh, persistent, d_trees, ph_octs, parity, dt, dt_next, so);
         else
-            st = launch_octs_g<float>(g, persistent, d_trees, ph_octs, parity, dt, dt_next, so);
+            st = launch_octs_g<float>(g, gh, persistent, d_trees, ph_octs, parity, dt, dt_next, so);
         if (st != RG_OK) break;
         if (fork) {
             e = hipEventRecord(ev_join, cs2);

@@ -24,14 +24,14 @@
 namespace rg {
 namespace {
 
-template <typename R, int G, int NT>
+template <typename R, int G, int NT, bool GH>
 __global__ __launch_bounds__(NT) void k_hydro_level(LevelArgs a)
 {
     __shared__ Smem<R, G> S;
     const int64_t first = a.oct_begin + int64_t(blockIdx.x) * G;
     const int64_t left = a.oct_end - first;
     const int count = left < G ? static_cast<int>(left) : G;
-    hydro_group<R, G, NT>(a, first, count, S);
+    hydro_group<R, G, NT, GH>(a, first, count, S);
 }
 
 // ---------------------------------------------------------------------------
@@ -177,7 +177,10 @@ template <typename R, int G, int NT> rg_status launch_level(const LevelArgs &a, 
 {
     const int64_t n = a.oct_end - a.oct_begin;
     const unsigned blocks = static_cast<unsigned>((n + G - 1) / G);
-    k_hydro_level<R, G, NT><<<blocks, NT, 0, s>>>(a);
+    if (a.ghost)
+        k_hydro_level<R, G, NT, true><<<blocks, NT, 0, s>>>(a);
+    else
+        k_hydro_level<R, G, NT, false><<<blocks, NT, 0, s>>>(a);
     return launch_status("rg_hydro_step_level");
 }
 
@@ -206,11 +209,14 @@ rg_status hydro_level(const LevelArgs &a, int form, const rg_tuning *tune, hipSt
 rg_status hydro_level_list(const double *uold, double *unew, const int32_t *nbr27, const uint32_t *son,
                            const int32_t *list, int64_t count, double *corr, int64_t corr_base, const double *dt,
                            double dx, double gamma, int form, const rg_tuning *tune, double cfl, double *dt_next,
-                           hipStream_t s, int64_t first, const double *ucoarse, int corr_mode)
+                           hipStream_t s, int64_t first, const double *ucoarse, int corr_mode, int ghost,
+                           const double *ucoarse2)
 {
     if (count <= 0) return RG_OK;
     LevelArgs a;
     a.corr_mode = corr_mode;
+    a.ghost = ghost;
+    a.ucoarse2 = ucoarse2 ? ucoarse2 : (ucoarse ? ucoarse : uold);
     a.list = list;
     a.uold = uold;
     a.ucoarse = ucoarse ? ucoarse : uold;
@@ -306,6 +312,8 @@ rg_status rg_hydro_step_level(double dx, const double *d_dt, double gamma, const
     RG_REQUIRE(!d_dt_next || (cfl > 0 && aligned(d_dt_next, 8)), "bad cfl or misaligned dt_next");
     LevelArgs a;
     a.corr_mode = 0;
+    a.ghost = RG_GHOST_INJECT;
+    a.ucoarse2 = d_uold;
     a.list = nullptr;
     a.uold = d_uold;
     a.ucoarse = d_uold;

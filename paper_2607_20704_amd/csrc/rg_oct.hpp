@@ -97,6 +97,8 @@ struct LevelArgs {
     double *corr;
     int64_t corr_base;
     int corr_mode;        // 0: store the owed flux; 1: store 0 + flux; 2: add it (sums over substeps)
+    int ghost;            // coarse ghost cells: 0 injection, 1 minmod-limited linear interpolation
+    const double *ucoarse2;   // cells two levels down (neighbours of a coarse ghost cell's own coarse cell)
     int64_t oct_begin, oct_end;
     const double *dt;     // device scalar
     double dx;
@@ -104,6 +106,51 @@ struct LevelArgs {
     double cfl;
     unsigned long long *dt_next;   // if set: CFL limit of the new state folded in (bits of a positive double)
 };
+
+// Values of the fine position at sub-cell (sx, sy, sz) of coarse cell C:
+// C's own (injection), or with ghost = 1 C's values plus a quarter of each
+// minmod slope, toward the position, taken from C's face neighbours (in C's
+// oct, in the neighbouring oct, the coarser cell covering it, or C itself
+// outside the domain).
+__device__ __forceinline__ void coarse_ghost(const LevelArgs &a, int64_t C, int sx, int sy, int sz, double *U)
+{
+    double uc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) uc[v] = a.ucoarse[NV * C + v];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) U[v] = uc[v];
+    if (!a.ghost) return;
+    const int64_t P = C >> 3;
+    const int q = static_cast<int>(C & 7);
+    const int sub[3] = {sx, sy, sz};
+    for (int ax = 0; ax < 3; ++ax) {
+        double un[2][NV];
+        for (int d = 0; d < 2; ++d) {   // 0: low neighbour, 1: high
+            const int qa = (q >> ax) & 1;
+            const double *src = a.ucoarse;
+            int64_t cell;
+            if (qa != d) {
+                cell = 8 * P + (q ^ (1 << ax));
+            } else {
+                const int slot = nslot(ax == 0 ? (d ? 1 : -1) : 0, ax == 1 ? (d ? 1 : -1) : 0, ax == 2 ? (d ? 1 : -1) : 0);
+                const int32_t e2 = a.nbr27[27 * P + slot];
+                if (e2 == RG_NBR_OUTSIDE) {
+                    cell = C;
+                } else if (e2 >= 0) {
+                    cell = 8 * int64_t(e2) + (q ^ (1 << ax));
+                } else {
+                    cell = -1 - int64_t(e2);
+                    src = a.ucoarse2;
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) un[d][v] = src[NV * cell + v];
+        }
+        const double qq = sub[ax] ? 0.25 : -0.25;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) U[v] = U[v] + qq * minmod<double>(uc[v] - un[0][v], un[1][v] - uc[v]);
+    }
+}
 
 template <typename R, int G> struct Smem {
     int64_t oct[G];
@@ -116,7 +163,9 @@ template <typename R, int G> struct Smem {
     double red[8];              // block minimum of the fused CFL limit (one per wave)
 };
 
-template <typename R, int G, int NT>
+// GH: compiled with the interpolating coarse-ghost path (whose registers
+// would otherwise lower every launch's occupancy); a.ghost then selects it
+template <typename R, int G, int NT, bool GH = false>
 __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, int count, Smem<R, G> &S)
 {
     const int tid = threadIdx.x;
@@ -174,10 +223,16 @@ __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, i
         if (e == RG_NBR_OUTSIDE) e = static_cast<int>(S.oct[g]);
         const int64_t cell = e >= 0 ? 8 * int64_t(e) + ((c[0] & 1) + 2 * (c[1] & 1) + 4 * (c[2] & 1))
                                     : (-1 - int64_t(e));
-        const double *src = e >= 0 ? a.uold : a.ucoarse;
         double U[NV], W[NV];
+        if (e >= 0) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) U[v] = src[NV * cell + v];
+            for (int v = 0; v < NV; ++v) U[v] = a.uold[NV * cell + v];
+        } else if constexpr (GH) {
+            coarse_ghost(a, cell, c[0] & 1, c[1] & 1, c[2] & 1, U);
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) U[v] = a.ucoarse[NV * cell + v];
+        }
         prim64(U, a.gamma, W);
 #pragma unroll
         for (int v = 0; v < NV; ++v) S.w[g][wc][v] = static_cast<R>(W[v]);

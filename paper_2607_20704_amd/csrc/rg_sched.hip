@@ -14,7 +14,7 @@ rg_status hydro_level_list(const double *uold, double *unew, const int32_t *nbr2
                            const int32_t *list, int64_t count, double *corr, int64_t corr_base, const double *dt,
                            double dx, double gamma, int form, const rg_tuning *tune, double cfl, double *dt_next,
                            hipStream_t s, int64_t first = 0, const double *ucoarse = nullptr,
-                           int corr_mode = 0);
+                           int corr_mode = 0, int ghost = 0, const double *ucoarse2 = nullptr);
 rg_status hydro_bricks(const double *uold, double *unew, const int32_t *nbr27, const uint32_t *son,
                        const uint64_t *keys, const int32_t *bricks, int64_t nbricks, const double *dt, double dx,
                        double gamma, int outflow, int form, double cfl, double *dt_next, int waves, hipStream_t s);
@@ -38,8 +38,9 @@ namespace rg {
 rg_status hydro_tree_level(const rg_tree *t, const rg_schedule *sc, int level, const double *d_dt, double gamma,
                            const double *d_uold, const double *d_ucoarse, double *d_unew, double cfl,
                            double *d_dt_next, int form, const rg_tuning *tune, hipStream_t s, double *d_corr,
-                           int corr_mode)
+                           int corr_mode, const double *d_ucoarse2)
 {
+    RG_REQUIRE(t->ghost == RG_GHOST_INJECT || t->ghost == RG_GHOST_LINEAR, "bad ghost mode %d", t->ghost);
     const double dx = ldexp(1.0, -level);
     const int64_t corr_base = t->level_begin[t->lmin + 1];
     double *corr = level > t->lmin ? d_corr : nullptr;
@@ -50,11 +51,12 @@ rg_status hydro_tree_level(const rg_tree *t, const rg_schedule *sc, int level, c
                             tune ? tune->brick_waves : 0, s));
         RG_TRY(hydro_level_list(d_uold, d_unew, t->d_nbr27, t->d_son_mask, sc->d_list + sc->rest_begin[level],
                                 sc->rest_count[level], corr, corr_base, d_dt, dx, gamma, form, tune, cfl, d_dt_next,
-                                s, 0, d_ucoarse, corr_mode));
+                                s, 0, d_ucoarse, corr_mode, t->ghost, d_ucoarse2));
     } else {
         RG_TRY(hydro_level_list(d_uold, d_unew, t->d_nbr27, t->d_son_mask, nullptr,
                                 t->level_begin[level + 1] - t->level_begin[level], corr, corr_base, d_dt, dx, gamma,
-                                form, tune, cfl, d_dt_next, s, t->level_begin[level], d_ucoarse, corr_mode));
+                                form, tune, cfl, d_dt_next, s, t->level_begin[level], d_ucoarse, corr_mode, t->ghost,
+                                d_ucoarse2));
     }
     return RG_OK;
 }
@@ -155,7 +157,7 @@ rg_status rg_hydro_step_scheduled(const rg_tree *t, const rg_schedule *sc, int l
     RG_REQUIRE(gamma > 1, "bad gamma");
     RG_REQUIRE(!d_dt_next || (cfl > 0 && aligned(d_dt_next, 8)), "bad cfl or misaligned dt_next");
     return hydro_tree_level(t, sc, level, d_dt, gamma, d_uold, d_uold, d_unew, cfl, d_dt_next, form, tune,
-                            as_stream(stream), t->d_corr, 0);
+                            as_stream(stream), t->d_corr, 0, d_uold);
 }
 
 }  // extern "C"

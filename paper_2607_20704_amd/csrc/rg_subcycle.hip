@@ -24,7 +24,7 @@ namespace rg {
 rg_status hydro_tree_level(const rg_tree *t, const rg_schedule *sc, int level, const double *d_dt, double gamma,
                            const double *d_uold, const double *d_ucoarse, double *d_unew, double cfl,
                            double *d_dt_next, int form, const rg_tuning *tune, hipStream_t s, double *d_corr,
-                           int corr_mode);
+                           int corr_mode, const double *d_ucoarse2);
 rg_status restrict_level2(const double *src, double *dst, const int32_t *father, int64_t ob, int64_t oe,
                           hipStream_t s);
 rg_status coarse_corrections_list(double *unew, const double *corr, int64_t corr_base, const int32_t *nbr27,
@@ -62,9 +62,10 @@ rg_status advance(Sub &c, int l, int sub)
     const double *own = c.buf[c.cur[l]];
     double *out = c.buf[c.cur[l] ^ 1];
     const double *coarse = l > t->lmin ? c.buf[c.cur[l - 1]] : own;
+    const double *coarse2 = l > t->lmin + 1 ? c.buf[c.cur[l - 2]] : coarse;
     if (oe > ob)
         RG_TRY(hydro_tree_level(t, t->sched, l, c.dt + 1 + (l - t->lmin), c.gamma, own, coarse, out, 0.0, nullptr,
-                                c.form, c.tune, c.s, c.acc, 1 + sub));
+                                c.form, c.tune, c.s, c.acc, 1 + sub, coarse2));
     if (l < t->lmax) {
         const int64_t fb = t->level_begin[l + 1], fe = t->level_begin[l + 2];
         const int64_t base = t->level_begin[t->lmin + 1];

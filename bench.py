@@ -312,31 +312,37 @@ def time_dynamic(api, inputs):
     del bufs, full, u, a, D
     torch.cuda.empty_cache()
 
-    w = inputs.sedov_amr()
-    D = api.DeviceTree(w.ijkl, w.bc, capacity=400000)
-    u = torch.empty((8 * D.capacity, 5), dtype=torch.float64, device="cuda")
-    v = torch.empty_like(u)
-    u[:8 * D.n] = D.to_key_order(w.u)
-    parts = {"step": 0.0, "refine": 0.0, "schedule": 0.0}
-    cells = 0
-    nsteps, warm = 20, 5
-    for s in range(warm + nsteps):
-        n8 = 8 * D.n
-        _, t1 = wall(lambda: D.step(u[:n8], v[:n8], w.gamma, w.cfl, api.RG_FP64))
-        _, t2 = wall(lambda: D.refine(v[:n8], 0.0, 0.08, 8, out=u, schedule=False))
-        _, t3 = wall(lambda: D.build_schedule())
-        if s >= warm:
-            parts["step"] += t1
-            parts["refine"] += t2
-            parts["schedule"] += t3
-            cells += n8
-    total = sum(parts.values())
-    out["sedov_dynamic"] = {
-        "workload": "Sedov blast, base level 6, refined on |rho_n - rho| / (rho_n + rho) > 0.08 up to level 8, "
-                    "FP64, refinement every step",
-        "steps": nsteps, "octs_at_end": D.n, "ms_per_step": round(total / nsteps, 3),
-        "parts_ms_per_step": {k: round(v_ / nsteps, 3) for k, v_ in parts.items()},
-        "cell_updates_per_s": cells / (total * 1e-3)}
+    def sedov(nsubgrid):
+        w = inputs.sedov_amr()
+        D = api.DeviceTree(w.ijkl, w.bc, capacity=400000)
+        u = torch.empty((8 * D.capacity, 5), dtype=torch.float64, device="cuda")
+        v = torch.empty_like(u)
+        u[:8 * D.n] = D.to_key_order(w.u)
+        parts = {"step": 0.0, "refine": 0.0, "schedule": 0.0}
+        cells = 0
+        nsteps, warm = 20, 5
+        for s in range(warm + nsteps):
+            n8 = 8 * D.n
+            _, t1 = wall(lambda: D.step(u[:n8], v[:n8], w.gamma, w.cfl, api.RG_FP64))
+            _, t2 = wall(lambda: D.refine(v[:n8], 0.0, 0.08, 8, out=u, schedule=False, nsubgrid=nsubgrid))
+            _, t3 = wall(lambda: D.build_schedule())
+            if s >= warm:
+                parts["step"] += t1
+                parts["refine"] += t2
+                parts["schedule"] += t3
+                cells += n8
+        total = sum(parts.values())
+        return {
+            "workload": "Sedov blast, base level 6, refined on |rho_n - rho| / (rho_n + rho) > 0.08 up to level 8, "
+                        "FP64, refinement every step, nsubgrid %d" % nsubgrid,
+            "steps": nsteps, "octs_at_end": D.n,
+            "bricks_at_end": sum(c[0] for c in D.schedule_counts().values()),
+            "ms_per_step": round(total / nsteps, 3),
+            "parts_ms_per_step": {k: round(v_ / nsteps, 3) for k, v_ in parts.items()},
+            "cell_updates_per_s": cells / (total * 1e-3)}
+
+    out["sedov_dynamic"] = sedov(2)
+    out["sedov_dynamic_blocks"] = sedov(4)
     return out
 
 

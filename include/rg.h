@@ -429,7 +429,9 @@ typedef struct rg_refine_params {
     double rho_thresh;
     double grad_thresh;
     int32_t lmax;        /* finest level allowed: cells of level >= lmax are never flagged */
-    int32_t pad;
+    int32_t nsubgrid;    /* 2 (or 0): cell by cell; 4: every flag, of the criterion or the closure, is
+                            widened to all 8 cells of its oct, so octs come in complete sibling groups
+                            (4^3-cell blocks, the paper's nsubgrid = 4 grids, Sec. 2) */
 } rg_refine_params;
 
 /* Bytes of the workspace rg_refine needs for a tree of `capacity` octs. */

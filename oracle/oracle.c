@@ -847,6 +847,10 @@ double orc_step_subcycled(int64_t n, const int32_t *ijkl, const int32_t *nbr27, 
  *   new state: kept octs keep their cells; a new oct's 8 cells take its
  *     father cell's conserved values (injection: conservative); a removed
  *     oct's father keeps its restricted value.
+ * Block refinement (nsubgrid = 4; the paper's 4^3-cell blocks, Sec. 2 and
+ * Sec. 3): every flag, from the criterion or the closure, is widened to all
+ * 8 cells of its oct, so octs are created and removed in complete sibling
+ * groups; nsubgrid = 2 (or 0) is the cell-by-cell tree.
  * Octs in key order on input; output in emission order (for each old oct in
  * key order: the oct if kept, then its new children by cell bit).  crit (may
  * be NULL) receives the criterion's flags alone, flags the closed ones. */
@@ -879,8 +883,8 @@ static double cell_density(const lookup_table *T, const double *u, int l, int32_
 }
 
 int orc_refine(int64_t n, const int32_t *ijkl, const uint8_t *son_mask, const double *u, int bc, double rho_thresh,
-               double grad_thresh, int lmax_refine, uint8_t *crit, uint8_t *flags, int64_t capacity, int64_t *m_out,
-               int32_t *new_ijkl, double *new_u)
+               double grad_thresh, int lmax_refine, int nsubgrid, uint8_t *crit, uint8_t *flags, int64_t capacity,
+               int64_t *m_out, int32_t *new_ijkl, double *new_u)
 {
     lookup_table T = table_build(n, ijkl);
     int lmin = ORC_MAX_LEVEL + 1, lmax = 0;
@@ -914,6 +918,7 @@ int orc_refine(int64_t n, const int32_t *ijkl, const uint8_t *son_mask, const do
             }
             if (refine_criterion(rc, rn, rho_thresh, grad_thresh)) flags[o] |= (uint8_t)(1u << c);
         }
+        if (nsubgrid == 4 && flags[o]) flags[o] = 0xff;
     }
     if (crit)
         for (int64_t o = 0; o < n; ++o) crit[o] = flags[o];
@@ -944,7 +949,7 @@ int orc_refine(int64_t n, const int32_t *ijkl, const uint8_t *son_mask, const do
                                 continue;
                             }
                             int bit = ((p[0] >> 1) & 1) + 2 * ((p[1] >> 1) & 1) + 4 * ((p[2] >> 1) & 1);
-                            flags[f] |= (uint8_t)(1u << bit);
+                            flags[f] |= nsubgrid == 4 ? (uint8_t)0xff : (uint8_t)(1u << bit);
                         }
             }
         }

@@ -85,7 +85,7 @@ def lib():
         L.orc_oct_tile.restype = None
         L.orc_oct_tile.argtypes = [i64, P, P, P, P, i64, P]
         L.orc_refine.restype = ctypes.c_int
-        L.orc_refine.argtypes = [i64, P, P, P, ctypes.c_int, f64, f64, ctypes.c_int, P, P, i64, P, P, P]
+        L.orc_refine.argtypes = [i64, P, P, P, ctypes.c_int, f64, f64, ctypes.c_int, ctypes.c_int, P, P, i64, P, P, P]
         L.orc_step_subcycled.restype = f64
         L.orc_step_subcycled.argtypes = [i64, P, P, P, P, P, f64, f64]
         _lib = L
@@ -259,11 +259,12 @@ class Tree:
         """nsteps coarse subcycled steps in place; returns the coarse dts."""
         return np.array([self.step_subcycled(u, gamma, cfl) for _ in range(nsteps)])
 
-    def refine(self, u, rho_thresh, grad_thresh, lmax_refine):
+    def refine(self, u, rho_thresh, grad_thresh, lmax_refine, nsubgrid=2):
         """Flags (per oct, key order, criterion + grading closure) and the
         refined / de-refined tree: (flags, new_ijkl, new_u), the new octs in
         emission order (pass new_ijkl to Tree and new_u to its
-        permute_cells).  The criterion's own flags are kept in self.last_crit."""
+        permute_cells).  The criterion's own flags (widened to whole octs when
+        nsubgrid = 4) are kept in self.last_crit."""
         assert u.dtype == np.float64 and u.flags.c_contiguous and u.shape == (8 * self.n, 5)
         cap = 9 * self.n
         flags = np.zeros(self.n, np.uint8)
@@ -272,7 +273,8 @@ class Tree:
         new_ijkl = np.zeros((cap, 4), np.int32)
         new_u = np.zeros((8 * cap, 5))
         st = lib().orc_refine(self.n, _p(self.ijkl), _p(self.son_mask), _p(u), int(self.bc), float(rho_thresh),
-                              float(grad_thresh), int(lmax_refine), _p(crit), _p(flags), cap, ctypes.byref(m),
+                              float(grad_thresh), int(lmax_refine), int(nsubgrid), _p(crit), _p(flags), cap,
+                              ctypes.byref(m),
                               _p(new_ijkl), _p(new_u))
         if st != OK:
             raise ValueError("refine failed with status %d" % st)

@@ -49,7 +49,7 @@ class RgTree(ctypes.Structure):
 
 
 class RgRefineParams(ctypes.Structure):
-    _fields_ = [("rho_thresh", ctypes.c_double), ("grad_thresh", ctypes.c_double), ("lmax", i32), ("pad", i32)]
+    _fields_ = [("rho_thresh", ctypes.c_double), ("grad_thresh", ctypes.c_double), ("lmax", i32), ("nsubgrid", i32)]
 
 
 class RgBatchTree(ctypes.Structure):

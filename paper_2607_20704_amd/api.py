@@ -266,7 +266,7 @@ class DeviceTree:
                       lst[sc.nbr_rest_begin:sc.nbr_rest_begin + sc.nbr_rest_count].copy())
         return out
 
-    def refine(self, u, rho_thresh=0.0, grad_thresh=0.0, lmax=None, out=None, schedule=None):
+    def refine(self, u, rho_thresh=0.0, grad_thresh=0.0, lmax=None, out=None, schedule=None, nsubgrid=2):
         """One refinement / de-refinement of the tree from state u (key
         order): the tree is rebuilt in place and the new state, in the new
         key order, is returned (a view of `out`, 8 x capacity x 5 doubles).
@@ -275,6 +275,7 @@ class DeviceTree:
         p = L.RgRefineParams()
         p.rho_thresh, p.grad_thresh = float(rho_thresh), float(grad_thresh)
         p.lmax = int(lmax if lmax is not None else self.lmax)
+        p.nsubgrid = int(nsubgrid)
         if out is None:
             out = torch.empty((8 * self.capacity, 5), dtype=torch.float64, device="cuda")
         if not hasattr(self, "refine_ws"):
@@ -291,11 +292,12 @@ class DeviceTree:
             self.build_schedule()
         return out[:8 * self.n]
 
-    def refine_flags(self, u, rho_thresh=0.0, grad_thresh=0.0, lmax=None, closure=True):
+    def refine_flags(self, u, rho_thresh=0.0, grad_thresh=0.0, lmax=None, closure=True, nsubgrid=2):
         """The flags a refinement would act on (uint32 per oct, bit c = cell c)."""
         p = L.RgRefineParams()
         p.rho_thresh, p.grad_thresh = float(rho_thresh), float(grad_thresh)
         p.lmax = int(lmax if lmax is not None else self.lmax)
+        p.nsubgrid = int(nsubgrid)
         flags = torch.empty(self.n, dtype=torch.int32, device="cuda")
         check(L.lib().rg_refine_flags(ctypes.byref(self._desc), _ptr(u), ctypes.byref(p), int(bool(closure)),
                                       _ptr(flags), _stream()))

@@ -42,6 +42,7 @@ struct CritArgs {
     int64_t ob, oe;       // octs of the levels that may be flagged
     double rho_thresh, grad_thresh;
     uint32_t *flags;
+    int whole;            // widen a flag to all 8 cells of its oct (4^3-cell blocks)
 };
 
 // one thread per cell: the criterion on the cell's density and its six face
@@ -83,7 +84,9 @@ __global__ void k_refine_criterion(CritArgs a)
     // the eight lanes of an oct are eight consecutive lanes of one wave
     const uint64_t votes = __ballot(flag);
     const int lane = threadIdx.x & 63;
-    if (c == 0) a.flags[o] = static_cast<uint32_t>((votes >> (lane & ~7)) & 0xffu);
+    uint32_t m = static_cast<uint32_t>((votes >> (lane & ~7)) & 0xffu);
+    if (a.whole && m) m = 0xffu;
+    if (c == 0) a.flags[o] = m;
 }
 
 __global__ void k_zero_u32(uint32_t *p, int64_t n)
@@ -100,7 +103,7 @@ __global__ void k_zero_u32(uint32_t *p, int64_t n)
 // only if a plain read does not already show it (many octs mark the same
 // coarse cells).
 __global__ void k_refine_closure(const int32_t *__restrict__ nbr27, const int32_t *__restrict__ father,
-                                 int64_t ob, int64_t oe, uint32_t *flags)
+                                 int64_t ob, int64_t oe, uint32_t *flags, int whole)
 {
     const int64_t o = ob + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (o >= oe) return;
@@ -121,8 +124,8 @@ __global__ void k_refine_closure(const int32_t *__restrict__ nbr27, const int32_
         if (e == RG_NBR_OUTSIDE) continue;
         const int64_t fc = e >= 0 ? int64_t(father[e]) : (-1 - int64_t(e));
         if (fc < 0) continue;   // coarsest level: nothing to mark
-        const uint32_t bit = 1u << (fc & 7);
-        if (!(flags[fc >> 3] & bit)) atomicOr(&flags[fc >> 3], bit);
+        const uint32_t bit = whole ? 0xffu : 1u << (fc & 7);
+        if ((flags[fc >> 3] & bit) != bit) atomicOr(&flags[fc >> 3], bit);
     }
 }
 
@@ -232,6 +235,7 @@ rg_status check_tree(const rg_tree *t, const rg_refine_params *pr)
     RG_REQUIRE(t->level_begin[t->lmin] == 0 && t->level_begin[t->lmax + 1] == t->n_oct, "bad level ranges");
     RG_REQUIRE(t->d_nbr27 && t->d_father_cell && t->d_son_mask, "tree without neighbour lists");
     RG_REQUIRE(pr->lmax >= t->lmin && pr->lmax <= RG_MAX_LEVEL, "refinement level limit %d out of range", pr->lmax);
+    RG_REQUIRE(pr->nsubgrid == 0 || pr->nsubgrid == 2 || pr->nsubgrid == 4, "nsubgrid %d not 2 or 4", pr->nsubgrid);
     return RG_OK;
 }
 
@@ -251,6 +255,7 @@ rg_status flags_pass(const rg_tree *t, const double *d_u, const rg_refine_params
         a.rho_thresh = pr->rho_thresh;
         a.grad_thresh = pr->grad_thresh;
         a.flags = flags;
+        a.whole = pr->nsubgrid == 4;
         if (a.oe > 0) {
             k_refine_criterion<<<grid_for(8 * a.oe, 256), 256, 0, s>>>(a);
             RG_TRY(launch_status("refine criterion"));
@@ -260,7 +265,8 @@ rg_status flags_pass(const rg_tree *t, const double *d_u, const rg_refine_params
         for (int l = t->lmax; l > t->lmin; --l) {
             const int64_t ob = t->level_begin[l], oe = t->level_begin[l + 1];
             if (oe <= ob) continue;
-            k_refine_closure<<<grid_for(oe - ob, 256), 256, 0, s>>>(t->d_nbr27, t->d_father_cell, ob, oe, flags);
+            k_refine_closure<<<grid_for(oe - ob, 256), 256, 0, s>>>(t->d_nbr27, t->d_father_cell, ob, oe, flags,
+                                                                    pr->nsubgrid == 4);
             RG_TRY(launch_status("refine closure"));
         }
     }

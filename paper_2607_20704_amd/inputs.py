@@ -84,12 +84,26 @@ def uniform_tree(level):
     return _levels_to_ijkl({level: np.arange(N ** 3, dtype=np.int64)})
 
 
-def refined_tree(base, lmax, flag, bc, max_passes=8):
+def _siblings(levels, base):
+    """Every oct above `base` brings its 7 siblings (4^3-cell blocks)."""
+    for l in sorted(levels):
+        if l <= base or len(levels[l]) == 0:
+            continue
+        i, j, k = _decode(levels[l], 1 << (l - 1))
+        kids = [_code(2 * (i >> 1) + a, 2 * (j >> 1) + b, 2 * (k >> 1) + c, 1 << (l - 1))
+                for a in (0, 1) for b in (0, 1) for c in (0, 1)]
+        levels[l] = np.unique(np.concatenate([levels[l]] + kids))
+    return levels
+
+
+def refined_tree(base, lmax, flag, bc, max_passes=8, blocks=False):
     """Base level complete; a cell of level l < lmax is refined when
     ``flag(l, centres[m,3]) -> bool[m]`` says so and its oct exists; graded
-    closure is applied and flagging repeated until nothing changes."""
+    closure is applied and flagging repeated until nothing changes.  With
+    blocks=True an oct's cells are refined together (a flag on one flags all
+    eight) and every oct comes with its siblings."""
     levels = {base: np.arange((1 << (base - 1)) ** 3, dtype=np.int64)}
-    for _ in range(max_passes):
+    for _ in range(max_passes if not blocks else 4 * max_passes):
         before = {l: len(v) for l, v in levels.items()}
         for l in range(base, lmax):
             octs = levels.get(l)
@@ -98,6 +112,8 @@ def refined_tree(base, lmax, flag, bc, max_passes=8):
             i, j, k = _decode(octs, 1 << (l - 1))
             cen = _cell_centres(l, np.stack([i, j, k], 1))
             f = flag(l, cen.reshape(-1, 3)).reshape(-1, 8)
+            if blocks:
+                f = np.repeat(f.any(1, keepdims=True), 8, axis=1)
             oo, cc = np.nonzero(f)
             ci = 2 * i[oo] + (cc & 1)
             cj = 2 * j[oo] + ((cc >> 1) & 1)
@@ -105,12 +121,14 @@ def refined_tree(base, lmax, flag, bc, max_passes=8):
             new = _code(ci, cj, ck, 1 << l)
             levels[l + 1] = np.unique(np.concatenate([levels.get(l + 1, np.zeros(0, np.int64)), new]))
         levels = _close(levels, base, bc)
+        if blocks:
+            levels = _siblings(levels, base)
         if {l: len(v) for l, v in levels.items()} == before:
             break
     return _levels_to_ijkl({l: v for l, v in levels.items() if len(v)})
 
 
-def sphere_tree(base, lmax, centre, radius, bc):
+def sphere_tree(base, lmax, centre, radius, bc, blocks=False):
     """Refine every cell whose centre lies within `radius` of `centre`
     (minimum-image distance for periodic boxes) up to level lmax."""
     c = np.asarray(centre, np.float64).reshape(1, 3)
@@ -121,7 +139,7 @@ def sphere_tree(base, lmax, centre, radius, bc):
             d = d - np.round(d)
         return (d * d).sum(1) < radius * radius
 
-    return refined_tree(base, lmax, flag, bc)
+    return refined_tree(base, lmax, flag, bc, blocks=blocks)
 
 
 def split_info(ijkl):

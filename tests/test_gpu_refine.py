@@ -46,22 +46,23 @@ def _check_tree_equal(D, T2):
     assert all(int(D.level_begin[l]) == T2.level_begin[l] for l in range(T2.lmin, T2.lmax + 2))
 
 
+@pytest.mark.parametrize("nsubgrid", [2, 4])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
-def test_refine_parity(case):
+def test_refine_parity(case, nsubgrid):
     name, mk, params = case
     ijkl, bc, u_in, gam = mk()
-    say("refine:", name, params)
+    say("refine:", name, params, "nsubgrid", nsubgrid)
     T = O.Tree(ijkl, bc)
     D = _device_tree(ijkl, bc, capacity=9 * len(ijkl))
     u = D.to_key_order(u_in)
     ref = T.permute_cells(u_in)
     assert np.array_equal(u.cpu().numpy(), ref)
-    flags, ni, nu = T.refine(ref, *params)
-    got_crit = D.refine_flags(u, *params, closure=False).cpu().numpy()
-    got_flags = D.refine_flags(u, *params, closure=True).cpu().numpy()
+    flags, ni, nu = T.refine(ref, *params, nsubgrid=nsubgrid)
+    got_crit = D.refine_flags(u, *params, closure=False, nsubgrid=nsubgrid).cpu().numpy()
+    got_flags = D.refine_flags(u, *params, closure=True, nsubgrid=nsubgrid).cpu().numpy()
     assert np.array_equal(got_crit, T.last_crit.astype(np.int32))
     assert np.array_equal(got_flags, flags.astype(np.int32))
-    u2 = D.refine(u, *params)
+    u2 = D.refine(u, *params, nsubgrid=nsubgrid)
     torch.cuda.synchronize()
     T2 = O.Tree(ni, bc)
     say("  octs %d -> %d, levels %d-%d" % (T.n, T2.n, T2.lmin, T2.lmax))

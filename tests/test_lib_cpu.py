@@ -195,6 +195,9 @@ def test_refine_argument_errors_without_a_device():
     p.lmax = 1
     assert lib.rg_refine_flags(ctypes.byref(tree), u, ctypes.byref(p), 1, ws, None) == L.RG_EINVAL
     p.lmax = 5
+    p.nsubgrid = 3
+    assert lib.rg_refine_flags(ctypes.byref(tree), u, ctypes.byref(p), 1, ws, None) == L.RG_EINVAL
+    p.nsubgrid = 4
     need = lib.rg_refine_workspace_bytes(72)
     assert need > 72 * 4 * 5
     assert lib.rg_refine(ctypes.byref(tree), u, u, ctypes.byref(p), ws, need, None) == L.RG_EINVAL

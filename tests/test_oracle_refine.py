@@ -165,3 +165,42 @@ def test_converges_to_the_static_sphere_tree(start, centre, radius):
         raise AssertionError("did not converge")
     want = O.Tree(I.sphere_tree(3, lmax, centre, radius, I.PERIODIC), I.PERIODIC)
     assert np.array_equal(want.keys, T.keys)
+
+
+@pytest.mark.parametrize("params", [(1.3, 0.0, 7), (0.0, 0.1, 6)])
+def test_block_refinement_keeps_sibling_groups(params):
+    """nsubgrid = 4: octs above the coarsest level come in complete sibling
+    groups (every split cell's oct is split in all 8 cells), the new tree is
+    graded, the criterion's cells are split, and leaf sums are kept."""
+    T, u = _amr_case(45)
+    flags, ni, nu = T.refine(u, *params, nsubgrid=4)
+    assert np.all((flags == 0) | (flags == 0xff))
+    T2 = O.Tree(ni, T.bc)
+    assert np.all((T2.son_mask == 0) | (T2.son_mask == 0xff))
+    old, new = _octs(T), _octs(T2)
+    for key, o in old.items():
+        if key in new:
+            assert int(T2.son_mask[new[key]]) == int(flags[o])
+    # each removed oct leaves its father's restricted mean: one rounding each
+    a, abs_a = leaf_totals(T, u)
+    b, abs_b = leaf_totals(T2, T2.permute_cells(nu))
+    assert np.all(np.abs(a - b) <= 1e-12 * np.maximum(abs_a, abs_b))
+
+
+def test_block_refinement_converges_to_the_static_block_tree():
+    """Repeated block refinement on a sphere-shaped density reaches the
+    block-structured sphere tree the input module builds independently."""
+    centre, radius, lmax = (0.4, 0.55, 0.5), 0.22, 6
+    ijkl = I.uniform_tree(3)
+    for it in range(3 * lmax):
+        T = O.Tree(ijkl, I.PERIODIC)
+        u = np.ascontiguousarray(_sphere_state(T.ijkl, centre, radius))
+        _, ni, _ = T.refine(u, 1.5, 0.0, lmax, nsubgrid=4)
+        if len(ni) == T.n and set(map(tuple, ni.tolist())) == set(map(tuple, T.ijkl.tolist())):
+            break
+        ijkl = ni
+    else:
+        raise AssertionError("did not converge")
+    want = O.Tree(I.sphere_tree(3, lmax, centre, radius, I.PERIODIC, blocks=True), I.PERIODIC)
+    assert np.all((want.son_mask == 0) | (want.son_mask == 0xff))
+    assert np.array_equal(want.keys, T.keys)

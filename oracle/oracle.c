@@ -993,3 +993,151 @@ int orc_refine(int64_t n, const int32_t *ijkl, const uint8_t *son_mask, const do
     free(T.t);
     return status;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Multigrid Poisson solver (Sec. 5) on a uniform periodic grid             */
+/* ------------------------------------------------------------------------ */
+
+/* The paper's self-gravity solver: V-cycles over a hierarchy of levels,
+ * red-black Gauss-Seidel smoothing with the colours given by the parity of
+ * a cell's coordinates inside its oct, residual restriction averaging the 8
+ * children (factor 1/8), prolongation of the correction by trilinear
+ * interpolation with weights 27, 9, 3, 1 (/64) from the 8 coarse cells
+ * nearest the fine cell.  Readings taken here: the equation is Lap phi = f
+ * with the 7-point Laplacian, (sum of the six neighbours - 6 phi) / h^2; a
+ * uniform periodic grid of N^3 cells (N = 2^L; f must have zero mean); a
+ * V-cycle on level l does nu1 sweeps, computes the residual, restricts it
+ * into the right-hand side of level l-1, solves there for a correction that
+ * starts at zero (recursively; on the coarsest level ncoarse sweeps), adds
+ * the prolongated correction and does nu2 sweeps; a sweep is a red pass
+ * (even coordinate sum) then a black pass.  Each value is computed in the
+ * order written below.  The grid is dense, [z][y][x], and deliberately
+ * unrelated to the oct layout of the library. */
+
+#define MG_AT(a, N, i, j, k) (a)[((size_t)(((k) + (N)) % (N)) * (N) + (size_t)(((j) + (N)) % (N))) * (N) + (size_t)(((i) + (N)) % (N))]
+
+static double mg_sum6(const double *p, int N, int i, int j, int k)
+{
+    return ((((MG_AT(p, N, i - 1, j, k) + MG_AT(p, N, i + 1, j, k)) + MG_AT(p, N, i, j - 1, k)) + MG_AT(p, N, i, j + 1, k)) +
+            MG_AT(p, N, i, j, k - 1)) + MG_AT(p, N, i, j, k + 1);
+}
+
+static void mg_smooth(double *phi, const double *f, int N, double h, int sweeps)
+{
+    const double h2 = h * h;
+    for (int s = 0; s < sweeps; ++s)
+        for (int colour = 0; colour < 2; ++colour)
+            for (int k = 0; k < N; ++k)
+                for (int j = 0; j < N; ++j)
+                    for (int i = 0; i < N; ++i) {
+                        if (((i + j + k) & 1) != colour) continue;
+                        MG_AT(phi, N, i, j, k) = (mg_sum6(phi, N, i, j, k) - h2 * MG_AT(f, N, i, j, k)) / 6.0;
+                    }
+}
+
+static void mg_residual(const double *phi, const double *f, double *r, int N, double h)
+{
+    const double h2 = h * h;
+    for (int k = 0; k < N; ++k)
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) {
+                const double lap = (mg_sum6(phi, N, i, j, k) - 6.0 * MG_AT(phi, N, i, j, k)) / h2;
+                MG_AT(r, N, i, j, k) = MG_AT(f, N, i, j, k) - lap;
+            }
+}
+
+/* coarse right-hand side: the mean of the 8 fine residuals, summed in the
+ * children's cell order (x fastest) pairwise */
+static void mg_restrict(const double *r, double *fc, int Nc)
+{
+    const int N = 2 * Nc;
+    for (int K = 0; K < Nc; ++K)
+        for (int J = 0; J < Nc; ++J)
+            for (int I = 0; I < Nc; ++I) {
+                double c[8];
+                for (int q = 0; q < 8; ++q) c[q] = MG_AT(r, N, 2 * I + (q & 1), 2 * J + ((q >> 1) & 1), 2 * K + (q >> 2));
+                MG_AT(fc, Nc, I, J, K) = 0.125 * (((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7])));
+            }
+}
+
+/* phi += trilinear interpolation of the coarse correction e: the fine cell
+ * lies in coarse cell C, a quarter of C's width from its centre toward the
+ * side s = (-1 or +1 per axis); weights 27 (C), 9 (one step along s), 3
+ * (two steps), 1 (three steps), over 64 */
+static void mg_prolong_add(const double *e, double *phi, int Nc)
+{
+    const int N = 2 * Nc;
+    for (int k = 0; k < N; ++k)
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) {
+                const int I = i >> 1, J = j >> 1, K = k >> 1;
+                const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
+                const double w = ((((((27.0 * MG_AT(e, Nc, I, J, K) + 9.0 * MG_AT(e, Nc, I + sx, J, K)) +
+                                      9.0 * MG_AT(e, Nc, I, J + sy, K)) + 9.0 * MG_AT(e, Nc, I, J, K + sz)) +
+                                    3.0 * MG_AT(e, Nc, I + sx, J + sy, K)) + 3.0 * MG_AT(e, Nc, I + sx, J, K + sz)) +
+                                  3.0 * MG_AT(e, Nc, I, J + sy, K + sz)) + MG_AT(e, Nc, I + sx, J + sy, K + sz);
+                MG_AT(phi, N, i, j, k) = MG_AT(phi, N, i, j, k) + 0.015625 * w;
+            }
+}
+
+static void mg_vcycle(double **phi, double **f, double **r, int l, int lcoarse, int nu1, int nu2, int ncoarse)
+{
+    const int N = 1 << l;
+    const double h = ldexp(1.0, -l);
+    if (l == lcoarse) {
+        mg_smooth(phi[l], f[l], N, h, ncoarse);
+        return;
+    }
+    mg_smooth(phi[l], f[l], N, h, nu1);
+    mg_residual(phi[l], f[l], r[l], N, h);
+    mg_restrict(r[l], f[l - 1], N / 2);
+    const size_t nc = (size_t)(N / 2) * (N / 2) * (N / 2);
+    for (size_t q = 0; q < nc; ++q) phi[l - 1][q] = 0.0;
+    mg_vcycle(phi, f, r, l - 1, lcoarse, nu1, nu2, ncoarse);
+    mg_prolong_add(phi[l - 1], phi[l], N / 2);
+    mg_smooth(phi[l], f[l], N, h, nu2);
+}
+
+/* ncycles V-cycles on level L (N = 2^L cells per side) from phi (in/out)
+ * with right-hand side f; res[c] = L2 norm (root mean square) of the
+ * residual after cycle c (may be NULL). */
+void orc_mg_vcycles(int L, int lcoarse, int nu1, int nu2, int ncoarse, int ncycles, double *phi_io, const double *f_in,
+                    double *res)
+{
+    double *phi[ORC_MAX_LEVEL + 1], *f[ORC_MAX_LEVEL + 1], *r[ORC_MAX_LEVEL + 1];
+    for (int l = lcoarse; l <= L; ++l) {
+        const size_t n = (size_t)1 << (3 * l);
+        phi[l] = (double *)calloc(n, sizeof(double));
+        f[l] = (double *)calloc(n, sizeof(double));
+        r[l] = (double *)calloc(n, sizeof(double));
+    }
+    const size_t n = (size_t)1 << (3 * L);
+    memcpy(phi[L], phi_io, n * sizeof(double));
+    memcpy(f[L], f_in, n * sizeof(double));
+    for (int c = 0; c < ncycles; ++c) {
+        mg_vcycle(phi, f, r, L, lcoarse, nu1, nu2, ncoarse);
+        if (res) {
+            mg_residual(phi[L], f[L], r[L], 1 << L, ldexp(1.0, -L));
+            double s = 0.0;
+            for (size_t q = 0; q < n; ++q) s += r[L][q] * r[L][q];
+            res[c] = sqrt(s / (double)n);
+        }
+    }
+    memcpy(phi_io, phi[L], n * sizeof(double));
+    for (int l = lcoarse; l <= L; ++l) {
+        free(phi[l]);
+        free(f[l]);
+        free(r[l]);
+    }
+}
+
+/* one building block at a time, for the pins: residual and prolongation on
+ * dense grids */
+void orc_mg_residual(int L, const double *phi, const double *f, double *r)
+{
+    mg_residual(phi, f, r, 1 << L, ldexp(1.0, -L));
+}
+
+void orc_mg_prolong_add(int Lc, const double *e, double *phi) { mg_prolong_add(e, phi, 1 << Lc); }
+
+void orc_mg_smooth(int L, double *phi, const double *f, int sweeps) { mg_smooth(phi, f, 1 << L, ldexp(1.0, -L), sweeps); }

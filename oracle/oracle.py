@@ -84,6 +84,14 @@ def lib():
         L.orc_get_ghost_mode.argtypes = []
         L.orc_oct_tile.restype = None
         L.orc_oct_tile.argtypes = [i64, P, P, P, P, i64, P]
+        L.orc_mg_vcycles.restype = None
+        L.orc_mg_vcycles.argtypes = [ctypes.c_int] * 6 + [P, P, P]
+        L.orc_mg_residual.restype = None
+        L.orc_mg_residual.argtypes = [ctypes.c_int, P, P, P]
+        L.orc_mg_prolong_add.restype = None
+        L.orc_mg_prolong_add.argtypes = [ctypes.c_int, P, P]
+        L.orc_mg_smooth.restype = None
+        L.orc_mg_smooth.argtypes = [ctypes.c_int, P, P, ctypes.c_int]
         L.orc_refine.restype = ctypes.c_int
         L.orc_refine.argtypes = [i64, P, P, P, ctypes.c_int, f64, f64, ctypes.c_int, ctypes.c_int, P, P, i64, P, P, P]
         L.orc_step_subcycled.restype = f64
@@ -289,3 +297,41 @@ class Tree:
         lib().orc_oct_tile(self.n, _p(self.ijkl), _p(self.nbr27), _p(self.son_mask), _p(_c(u, np.float64)), int(o),
                            _p(t))
         return t
+
+
+# ------------------------------------------------------------ multigrid Poisson
+
+def mg_vcycles(phi, f, ncycles, lcoarse=1, nu1=2, nu2=2, ncoarse=50):
+    """V-cycles for Lap phi = f on a periodic N^3 grid ([z][y][x], N = 2^L);
+    returns (phi after the cycles, RMS residual after each cycle)."""
+    phi = np.ascontiguousarray(phi, dtype=np.float64).copy()
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    N = phi.shape[0]
+    L = int(round(np.log2(N)))
+    assert phi.shape == (N, N, N) == f.shape and 1 << L == N
+    res = np.zeros(ncycles)
+    lib().orc_mg_vcycles(L, int(lcoarse), int(nu1), int(nu2), int(ncoarse), int(ncycles), _p(phi), _p(f), _p(res))
+    return phi, res
+
+
+def mg_residual(phi, f):
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    L = int(round(np.log2(phi.shape[0])))
+    r = np.zeros_like(phi)
+    lib().orc_mg_residual(L, _p(phi), _p(f), _p(r))
+    return r
+
+
+def mg_prolong_add(e, phi):
+    e = np.ascontiguousarray(e, dtype=np.float64)
+    phi = np.ascontiguousarray(phi, dtype=np.float64).copy()
+    lib().orc_mg_prolong_add(int(round(np.log2(e.shape[0]))), _p(e), _p(phi))
+    return phi
+
+
+def mg_smooth(phi, f, sweeps):
+    phi = np.ascontiguousarray(phi, dtype=np.float64).copy()
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    lib().orc_mg_smooth(int(round(np.log2(phi.shape[0]))), _p(phi), _p(f), int(sweeps))
+    return phi

@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define RG_ABI_VERSION 7
+#define RG_ABI_VERSION 8
 #define RG_MAX_LEVEL 21
 #define RG_NBR_OUTSIDE INT32_MIN
 #define RG_RHO_MIN 1e-10
@@ -467,6 +467,31 @@ rg_status rg_refine_flags(const rg_tree *t, const double *d_u, const rg_refine_p
  * `stream` twice (the new oct count and the level ranges are read back). */
 rg_status rg_refine(rg_tree *t, const double *d_u, double *d_u_new, const rg_refine_params *p, void *d_ws,
                     size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Multigrid Poisson solver                                               */
+/* ---------------------------------------------------------------------- */
+
+/* V-cycles for Lap phi = f (Sec. 5), 7-point Laplacian with cell width
+ * h_l = 2^-l, on a hierarchy held by tree t: levels lcoarse .. lfine all
+ * complete (every cell below lfine split, 8^(l-1) octs on level l),
+ * periodic.  d_phi, d_f, d_r are per-cell arrays over the whole tree (8
+ * n_oct doubles, key order).  On entry d_phi and d_f hold the initial guess
+ * and the right-hand side on level lfine (f must have zero mean); the other
+ * levels' entries are overwritten.  A V-cycle on level l: nu1 red-black
+ * Gauss-Seidel sweeps (a red pass over the cells whose coordinates sum to an
+ * even number, then a black pass; phi = (sum of the six neighbours - h^2 f)
+ * / 6), the residual r = f - Lap phi, restricted into level l-1's f as the
+ * mean of a cell's 8 children, a correction on level l-1 from zero
+ * (recursively; ncoarse sweeps on lcoarse), added to phi by trilinear
+ * interpolation (weights 27, 9, 3, 1 over 64 from the 8 coarse cells around
+ * the fine cell), then nu2 sweeps.  ncycles cycles are run. */
+rg_status rg_mg_vcycles(const rg_tree *t, double *d_phi, double *d_f, double *d_r, int lfine, int lcoarse, int nu1,
+                        int nu2, int ncoarse, int ncycles, void *stream);
+
+/* r = f - Lap phi on one complete periodic level of t (as in a V-cycle). */
+rg_status rg_mg_residual(const rg_tree *t, const double *d_phi, const double *d_f, double *d_r, int level,
+                         void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Many independent trees in one graph launch                             */

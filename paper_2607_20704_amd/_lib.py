@@ -91,6 +91,8 @@ SIGNATURES = {
                                ctypes.POINTER(RgTuning), P]),
     "rg_schedule_workspace_bytes": (sz, [i64]),
     "rg_schedule_build_device": (st, [ctypes.POINTER(RgTree), P, i64, P, sz, ctypes.POINTER(RgSchedule), P]),
+    "rg_mg_vcycles": (st, [ctypes.POINTER(RgTree), P, P, P] + [ctypes.c_int] * 6 + [P]),
+    "rg_mg_residual": (st, [ctypes.POINTER(RgTree), P, P, P, ctypes.c_int, P]),
     "rg_refine_workspace_bytes": (sz, [i64]),
     "rg_refine_flags": (st, [ctypes.POINTER(RgTree), P, ctypes.POINTER(RgRefineParams), ctypes.c_int, P, P]),
     "rg_refine": (st, [ctypes.POINTER(RgTree), P, P, ctypes.POINTER(RgRefineParams), P, sz, P]),

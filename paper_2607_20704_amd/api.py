@@ -409,6 +409,45 @@ class DeviceTree:
         return a, dts[:, 0]
 
 
+# ---------------------------------------------------------------- multigrid
+
+class Multigrid:
+    """Multigrid Poisson V-cycles (rg_mg_vcycles) on a periodic unigrid of
+    level `lfine`: the hierarchy is the complete tree of levels 1..lfine,
+    built once on the device (keys, hash, neighbour lists)."""
+
+    def __init__(self, lfine, lcoarse=1):
+        from . import inputs
+        self.lfine, self.lcoarse = int(lfine), int(lcoarse)
+        self.tree = DeviceTree(inputs.full_tree(self.lfine), 0, schedule=False)
+        n8 = 8 * self.tree.n
+        self.phi = torch.zeros((n8,), dtype=torch.float64, device="cuda")
+        self.f = torch.zeros_like(self.phi)
+        self.r = torch.zeros_like(self.phi)
+        lb = self.tree.level_begin
+        self.fine = slice(8 * int(lb[self.lfine]), 8 * int(lb[self.lfine + 1]))
+
+    def fine_cells_ijk(self):
+        """[m, 3] global cell coordinates of the fine level's cells, in array order."""
+        ijkl = self.tree.ijkl_sorted[int(self.tree.level_begin[self.lfine]):].cpu().numpy()
+        c = np.arange(8)
+        out = np.empty((len(ijkl), 8, 3), np.int64)
+        out[..., 0] = 2 * ijkl[:, :1] + (c & 1)
+        out[..., 1] = 2 * ijkl[:, 1:2] + ((c >> 1) & 1)
+        out[..., 2] = 2 * ijkl[:, 2:3] + (c >> 2)
+        return out.reshape(-1, 3)
+
+    def vcycles(self, ncycles, nu1=2, nu2=2, ncoarse=50):
+        check(L.lib().rg_mg_vcycles(ctypes.byref(self.tree._desc), _ptr(self.phi), _ptr(self.f), _ptr(self.r),
+                                    self.lfine, self.lcoarse, int(nu1), int(nu2), int(ncoarse), int(ncycles),
+                                    _stream()))
+
+    def residual(self):
+        check(L.lib().rg_mg_residual(ctypes.byref(self.tree._desc), _ptr(self.phi), _ptr(self.f), _ptr(self.r),
+                                     self.lfine, _stream()))
+        return self.r[self.fine]
+
+
 # ---------------------------------------------------------------- many trees
 
 class Batch:

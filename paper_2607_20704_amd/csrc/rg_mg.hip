@@ -1,0 +1,223 @@
+// rg_mg.hip -- multigrid Poisson V-cycles on the oct tree.
+//
+// Paper Sec. 5: the self-gravity solver runs V-cycles over a hierarchy of
+// levels built from the octs, with the 27-entry neighbour list replacing
+// hash lookups inside the kernels; red-black Gauss-Seidel with the colours
+// given by the parity of a cell's position inside its oct; the residual
+// restricted by averaging the 8 children; the correction prolongated by
+// trilinear interpolation with weights 27, 9, 3, 1 (/64) from the parent
+// cell's neighbourhood.  Here the hierarchy is a tree whose levels lcoarse
+// .. lfine are all complete (every cell below lfine split), periodic: the
+// unigrid problem of the paper's measurements.  The equation is Lap phi = f
+// with the 7-point Laplacian; every value is formed in the same order as in
+// the serial reference so that the results agree bit for bit.
+#include "rg_internal.hpp"
+
+namespace rg {
+namespace {
+
+// the six face-neighbour cells of cell c of oct o, in the order x-, x+, y-,
+// y+, z-, z+ (same oct, else the neighbouring oct through the list)
+__device__ __forceinline__ void face_cells(const int32_t *__restrict__ nbr27, int64_t o, int c, int64_t *nb)
+{
+    const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
+#pragma unroll
+    for (int side = 0; side < 6; ++side) {
+        const int ax = side >> 1, d = (side & 1) ? 1 : -1;
+        int p[3] = {cx, cy, cz};
+        p[ax] += d;
+        if (p[ax] >= 0 && p[ax] <= 1) {
+            nb[side] = 8 * o + (p[0] + 2 * p[1] + 4 * p[2]);
+        } else {
+            const int slot = 13 + (ax == 0 ? d : ax == 1 ? 3 * d : 9 * d);
+            const int32_t e = nbr27[27 * o + slot];
+            nb[side] = 8 * int64_t(e) + ((p[0] & 1) + 2 * (p[1] & 1) + 4 * (p[2] & 1));
+        }
+    }
+}
+
+__device__ __forceinline__ double sum6(const double *__restrict__ phi, const int64_t *nb)
+{
+    return ((((phi[nb[0]] + phi[nb[1]]) + phi[nb[2]]) + phi[nb[3]]) + phi[nb[4]]) + phi[nb[5]];
+}
+
+// cells of one colour: even (0, 3, 5, 6) or odd (1, 2, 4, 7) coordinate sum
+__constant__ int c_colour[2][4] = {{0, 3, 5, 6}, {1, 2, 4, 7}};
+
+// one colour pass of Gauss-Seidel over the octs [ob, oe): four cells per oct
+__global__ void k_mg_smooth(double *phi, const double *__restrict__ f, const int32_t *__restrict__ nbr27, int64_t ob,
+                            int64_t oe, double h2, int colour)
+{
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t o = ob + (t >> 2);
+    if (o >= oe) return;
+    const int c = c_colour[colour][t & 3];
+    int64_t nb[6];
+    face_cells(nbr27, o, c, nb);
+    const int64_t cell = 8 * o + c;
+    phi[cell] = (sum6(phi, nb) - h2 * f[cell]) / 6.0;
+}
+
+__global__ void k_mg_residual(const double *__restrict__ phi, const double *__restrict__ f, double *__restrict__ r,
+                              const int32_t *__restrict__ nbr27, int64_t ob, int64_t oe, double h2)
+{
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t o = ob + (t >> 3);
+    if (o >= oe) return;
+    const int c = static_cast<int>(t & 7);
+    int64_t nb[6];
+    face_cells(nbr27, o, c, nb);
+    const int64_t cell = 8 * o + c;
+    const double lap = (sum6(phi, nb) - 6.0 * phi[cell]) / h2;
+    r[cell] = f[cell] - lap;
+}
+
+// coarse right-hand side at each fine oct's father cell: the mean of the 8
+// fine residuals, summed pairwise in cell order
+__global__ void k_mg_restrict(const double *__restrict__ r, double *__restrict__ f, const int32_t *__restrict__ father,
+                              int64_t ob, int64_t oe)
+{
+    const int64_t o = ob + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (o >= oe) return;
+    const double *c = r + 8 * o;
+    f[father[o]] = 0.125 * (((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7])));
+}
+
+__global__ void k_mg_zero(double *p, int64_t b, int64_t e)
+{
+    const int64_t i = b + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < e) p[i] = 0.0;
+}
+
+// phi of each fine cell += trilinear interpolation of the coarse correction:
+// the fine cell sits a quarter of its father cell C's width from C's centre
+// toward side s per axis; the 8 coarse cells C + {0, s_x} x {0, s_y} x {0,
+// s_z} weigh 27, 9, 3, 1 by the number of steps
+__global__ void k_mg_prolong(double *phi, const int32_t *__restrict__ nbr27, const int32_t *__restrict__ father,
+                             int64_t ob, int64_t oe)
+{
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t o = ob + (t >> 3);
+    if (o >= oe) return;
+    const int c = static_cast<int>(t & 7);
+    const int64_t C = father[o];
+    const int64_t P = C >> 3;
+    const int q = static_cast<int>(C & 7);
+    const int q3[3] = {q & 1, (q >> 1) & 1, q >> 2};
+    const int s3[3] = {(c & 1) ? 1 : -1, ((c >> 1) & 1) ? 1 : -1, (c >> 2) ? 1 : -1};
+    double e[8];   // index b: bit a set = one step along axis a
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        int p[3], sl[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            p[a] = q3[a] + (((b >> a) & 1) ? s3[a] : 0);
+            sl[a] = p[a] < 0 ? -1 : (p[a] > 1 ? 1 : 0);
+        }
+        int64_t cell;
+        if (sl[0] == 0 && sl[1] == 0 && sl[2] == 0) {
+            cell = 8 * P + (p[0] + 2 * p[1] + 4 * p[2]);
+        } else {
+            const int32_t n = nbr27[27 * P + (sl[0] + 1) + 3 * (sl[1] + 1) + 9 * (sl[2] + 1)];
+            cell = 8 * int64_t(n) + ((p[0] & 1) + 2 * (p[1] & 1) + 4 * (p[2] & 1));
+        }
+        e[b] = phi[cell];
+    }
+    const double w = ((((((27.0 * e[0] + 9.0 * e[1]) + 9.0 * e[2]) + 9.0 * e[4]) + 3.0 * e[3]) + 3.0 * e[5]) +
+                      3.0 * e[6]) + e[7];
+    const int64_t cell = 8 * o + c;
+    phi[cell] = phi[cell] + 0.015625 * w;
+}
+
+struct Mg {
+    const rg_tree *t;
+    double *phi, *f, *r;
+    int lcoarse, nu1, nu2, ncoarse;
+    hipStream_t s;
+};
+
+rg_status smooth(const Mg &m, int l, int sweeps)
+{
+    const int64_t ob = m.t->level_begin[l], oe = m.t->level_begin[l + 1];
+    const double h2 = ldexp(1.0, -2 * l);
+    for (int sw = 0; sw < sweeps; ++sw)
+        for (int colour = 0; colour < 2; ++colour) {
+            k_mg_smooth<<<grid_for(4 * (oe - ob), 256), 256, 0, m.s>>>(m.phi, m.f, m.t->d_nbr27, ob, oe, h2, colour);
+            RG_TRY(launch_status("multigrid smooth"));
+        }
+    return RG_OK;
+}
+
+rg_status residual(const rg_tree *t, const double *phi, const double *f, double *r, int l, hipStream_t s)
+{
+    const int64_t ob = t->level_begin[l], oe = t->level_begin[l + 1];
+    k_mg_residual<<<grid_for(8 * (oe - ob), 256), 256, 0, s>>>(phi, f, r, t->d_nbr27, ob, oe, ldexp(1.0, -2 * l));
+    return launch_status("multigrid residual");
+}
+
+rg_status vcycle(const Mg &m, int l)
+{
+    if (l == m.lcoarse) return smooth(m, l, m.ncoarse);
+    const rg_tree *t = m.t;
+    RG_TRY(smooth(m, l, m.nu1));
+    RG_TRY(residual(t, m.phi, m.f, m.r, l, m.s));
+    const int64_t ob = t->level_begin[l], oe = t->level_begin[l + 1];
+    k_mg_restrict<<<grid_for(oe - ob, 256), 256, 0, m.s>>>(m.r, m.f, t->d_father_cell, ob, oe);
+    RG_TRY(launch_status("multigrid restrict"));
+    const int64_t cb = 8 * t->level_begin[l - 1], ce = 8 * t->level_begin[l];
+    k_mg_zero<<<grid_for(ce - cb, 256), 256, 0, m.s>>>(m.phi, cb, ce);
+    RG_TRY(launch_status("multigrid zero"));
+    RG_TRY(vcycle(m, l - 1));
+    k_mg_prolong<<<grid_for(8 * (oe - ob), 256), 256, 0, m.s>>>(m.phi, t->d_nbr27, t->d_father_cell, ob, oe);
+    RG_TRY(launch_status("multigrid prolong"));
+    return smooth(m, l, m.nu2);
+}
+
+rg_status check_hierarchy(const rg_tree *t, int lfine, int lcoarse)
+{
+    RG_REQUIRE(t && t->d_nbr27 && t->d_father_cell, "tree without neighbour lists");
+    RG_REQUIRE(t->bc == RG_BC_PERIODIC, "the multigrid hierarchy must be periodic");
+    RG_REQUIRE(lcoarse >= 1 && lcoarse <= lfine && lfine <= t->lmax && lcoarse >= t->lmin && lfine <= 10,
+               "levels %d..%d not in the tree", lcoarse, lfine);
+    for (int l = lcoarse; l <= lfine; ++l)
+        RG_REQUIRE(t->level_begin[l + 1] - t->level_begin[l] == (int64_t(1) << (3 * (l - 1))),
+                   "level %d is not complete", l);
+    return RG_OK;
+}
+
+}  // namespace
+}  // namespace rg
+
+using namespace rg;
+
+extern "C" {
+
+rg_status rg_mg_residual(const rg_tree *t, const double *d_phi, const double *d_f, double *d_r, int level,
+                         void *stream)
+{
+    RG_TRY(check_hierarchy(t, level, level));
+    RG_REQUIRE(d_phi && d_f && d_r, "null pointer");
+    return residual(t, d_phi, d_f, d_r, level, as_stream(stream));
+}
+
+rg_status rg_mg_vcycles(const rg_tree *t, double *d_phi, double *d_f, double *d_r, int lfine, int lcoarse, int nu1,
+                        int nu2, int ncoarse, int ncycles, void *stream)
+{
+    RG_TRY(check_hierarchy(t, lfine, lcoarse));
+    RG_REQUIRE(d_phi && d_f && d_r, "null pointer");
+    RG_REQUIRE(nu1 >= 0 && nu2 >= 0 && ncoarse >= 0 && ncycles >= 0, "negative sweep or cycle count");
+    Mg m;
+    m.t = t;
+    m.phi = d_phi;
+    m.f = d_f;
+    m.r = d_r;
+    m.lcoarse = lcoarse;
+    m.nu1 = nu1;
+    m.nu2 = nu2;
+    m.ncoarse = ncoarse;
+    m.s = as_stream(stream);
+    for (int c = 0; c < ncycles; ++c) RG_TRY(vcycle(m, lfine));
+    return RG_OK;
+}
+
+}  // extern "C"

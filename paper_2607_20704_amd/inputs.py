@@ -84,6 +84,12 @@ def uniform_tree(level):
     return _levels_to_ijkl({level: np.arange(N ** 3, dtype=np.int64)})
 
 
+def full_tree(level):
+    """Every oct of levels 1..level (each cell below `level` split): the
+    hierarchy of a multigrid solver on a level-`level` unigrid."""
+    return _levels_to_ijkl({l: np.arange(8 ** (l - 1), dtype=np.int64) for l in range(1, level + 1)})
+
+
 def _siblings(levels, base):
     """Every oct above `base` brings its 7 siblings (4^3-cell blocks)."""
     for l in sorted(levels):

@@ -217,6 +217,29 @@ def test_refine_argument_errors_without_a_device():
     assert lib.rg_refine(ctypes.byref(tree), u, u2, ctypes.byref(p), ws + 8, need, None) == L.RG_EINVAL
 
 
+def test_multigrid_argument_errors_without_a_device():
+    """rg_mg_vcycles checks the hierarchy on the host: periodic, levels
+    present and complete, sane counts."""
+    lib = L.lib()
+    tree = L.RgTree()
+    tree.n_oct, tree.lmin, tree.lmax, tree.bc = 73, 1, 3, 0
+    for l, b in ((1, 0), (2, 1), (3, 9), (4, 73)):
+        tree.level_begin[l] = b
+    tree.d_nbr27, tree.d_father_cell = 256, 512
+    a = (256, 512, 768)
+    assert lib.rg_mg_vcycles(ctypes.byref(tree), *a, 3, 1, 2, 2, 10, 0, None) == L.RG_OK   # zero cycles
+    assert lib.rg_mg_vcycles(ctypes.byref(tree), *a, 4, 1, 2, 2, 10, 1, None) == L.RG_EINVAL
+    assert lib.rg_mg_vcycles(ctypes.byref(tree), *a, 3, 0, 2, 2, 10, 1, None) == L.RG_EINVAL
+    assert lib.rg_mg_vcycles(ctypes.byref(tree), *a, 3, 1, -1, 2, 10, 1, None) == L.RG_EINVAL
+    assert lib.rg_mg_vcycles(ctypes.byref(tree), None, 512, 768, 3, 1, 2, 2, 10, 1, None) == L.RG_EINVAL
+    tree.level_begin[3] = 8      # level 2 incomplete
+    assert lib.rg_mg_vcycles(ctypes.byref(tree), *a, 3, 1, 2, 2, 10, 1, None) == L.RG_EINVAL
+    tree.level_begin[3] = 9
+    tree.bc = 1
+    assert lib.rg_mg_vcycles(ctypes.byref(tree), *a, 3, 1, 2, 2, 10, 1, None) == L.RG_EINVAL
+    assert b"periodic" in L.detail().encode()
+
+
 def test_workspace_sizes():
     lib = L.lib()
     # the table (256-byte header, capacity = power of two >= 2n slots of 12

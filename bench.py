@@ -346,6 +346,39 @@ def time_dynamic(api, inputs):
     return out
 
 
+def time_mg(api, level=8, ncycles=5):
+    """Multigrid Poisson V-cycles (Sec. 5) on the periodic level-`level`
+    unigrid (256^3 by default): Lap phi = f with a seeded zero-mean random
+    f, 2 + 2 red-black sweeps per level, down to level 1 with 50 sweeps
+    there.  Reports cell-updates per second per V-cycle (fine cells over the
+    cycle's time, the paper's unit) and the residual reduction per cycle."""
+    import numpy as np
+    import torch
+    M = api.Multigrid(level)
+    N = 1 << level
+    rng = np.random.default_rng(20704)
+    f = rng.standard_normal(N ** 3)
+    f -= f.mean()
+    M.f[M.fine] = torch.as_tensor(f).cuda()
+    r0 = float(torch.sqrt((M.residual() ** 2).mean()))
+    M.vcycles(1)
+    r1 = float(torch.sqrt((M.residual() ** 2).mean()))
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    M.vcycles(ncycles)
+    b.record()
+    b.synchronize()
+    ms = a.elapsed_time(b) / ncycles
+    r2 = float(torch.sqrt((M.residual() ** 2).mean()))
+    cells = N ** 3
+    return {"workload": "Poisson Lap phi = f on a %d^3 periodic unigrid, seeded zero-mean random f, V(2,2) cycles "
+                        "to level 1" % N,
+            "ms_per_vcycle": round(ms, 4), "cell_updates_per_s_per_vcycle": cells / (ms * 1e-3),
+            "residual_rms": [r0, r1, r2], "residual_factor_per_cycle": (r2 / r1) ** (1.0 / ncycles),
+            "octs_in_hierarchy": M.tree.n}
+
+
 def copy_ceiling(torch, mib=1024, reps=5):
     """Practical HBM ceiling: GB/s (read + write) of a plain device copy of
     `mib` MiB, best of `reps`."""
@@ -399,7 +432,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="library default kernels instead of autotuned ones")
     ap.add_argument("--no-deep-amr", action="store_true", help="skip the clumpy-gas deep-AMR workload")
     ap.add_argument("--no-dynamic", action="store_true", help="skip the refinement (dynamic tree) measurements")
-    ap.add_argument("--leg", choices=["all", "deep_amr", "dynamic"], default="all",
+    ap.add_argument("--no-mg", action="store_true", help="skip the multigrid Poisson measurement")
+    ap.add_argument("--leg", choices=["all", "deep_amr", "dynamic", "mg_poisson"], default="all",
                     help="run one workload only and print its JSON (for profiling it); 'all' is the benchmark line")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (reference for HBM byte counters)")
@@ -414,7 +448,8 @@ def main():
     torch.cuda.set_device(0)
     if args.leg != "all":
         forms = [f.strip() for f in args.forms.split(",") if f.strip()]
-        leg = time_deep_amr(forms, 10, api, inputs) if args.leg == "deep_amr" else time_dynamic(api, inputs)
+        leg = (time_deep_amr(forms, 10, api, inputs) if args.leg == "deep_amr" else
+               time_dynamic(api, inputs) if args.leg == "dynamic" else time_mg(api))
         print(json.dumps({args.leg: leg}), flush=True)
         return
     log("generating the 256^3 random-field box")
@@ -498,6 +533,10 @@ def main():
     if not args.no_deep_amr:
         log("deep-AMR workload: generating")
         out["deep_amr"] = time_deep_amr(forms, 10, api, inputs)
+        torch.cuda.empty_cache()
+    if not args.no_mg:
+        log("multigrid Poisson V-cycles")
+        out["mg_poisson"] = time_mg(api)
         torch.cuda.empty_cache()
     if not args.no_dynamic:
         log("dynamic trees: refinement on the device")

@@ -194,7 +194,7 @@ def time_batched(forms, nsteps, reps, api, inputs, autotune):
     return out
 
 
-def time_deep_amr(forms, nsteps, api, inputs):
+def time_deep_amr(forms, nsteps, api, inputs, autotune=None):
     """The clumpy-gas deep tree (base 7 up to level 12, about 28 M cells):
     `nsteps` whole steps per form (dt, every level, corrections,
     restriction; lists prebuilt), and the mixed form's L1 error per
@@ -223,23 +223,25 @@ def time_deep_amr(forms, nsteps, api, inputs):
     states = {}
     for f in forms:
         form = api.RG_FP64 if f == "fp64" else api.RG_MIXED
-        D.run(u0, w.gamma, w.cfl, 1, form=form)       # warm-up
+        tune = autotune.tune_tree(D, u0, w.gamma, form)[0] if autotune else None
+        D.run(u0, w.gamma, w.cfl, 1, form=form, tune=tune)       # warm-up
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
-        u, dts = D.run(u0, w.gamma, w.cfl, nsteps, form=form)
+        u, dts = D.run(u0, w.gamma, w.cfl, nsteps, form=form, tune=tune)
         b.record()
         b.synchronize()
         ms = a.elapsed_time(b) / nsteps
         states[f] = u
-        out[f] = {"cell_updates_per_s": cells / (ms * 1e-3), "ms_per_step": round(ms, 4)}
+        out[f] = {"cell_updates_per_s": cells / (ms * 1e-3), "ms_per_step": round(ms, 4),
+                  "tune": list(tune) if tune else None}
         global_dt = float(dts.mean())
         # level subcycling: level l takes 2^(l - lmin) steps per coarse step
         nsub = 2
-        D.run_subcycled(u0, w.gamma, w.cfl, 1, form=form)     # warm-up
+        D.run_subcycled(u0, w.gamma, w.cfl, 1, form=form, tune=tune)     # warm-up
         torch.cuda.synchronize()
         a.record()
-        _, sdts = D.run_subcycled(u0, w.gamma, w.cfl, nsub, form=form)
+        _, sdts = D.run_subcycled(u0, w.gamma, w.cfl, nsub, form=form, tune=tune)
         b.record()
         b.synchronize()
         sms = a.elapsed_time(b) / nsub
@@ -448,7 +450,7 @@ def main():
     torch.cuda.set_device(0)
     if args.leg != "all":
         forms = [f.strip() for f in args.forms.split(",") if f.strip()]
-        leg = (time_deep_amr(forms, 10, api, inputs) if args.leg == "deep_amr" else
+        leg = (time_deep_amr(forms, 10, api, inputs, None if args.no_tune else autotune) if args.leg == "deep_amr" else
                time_dynamic(api, inputs) if args.leg == "dynamic" else time_mg(api))
         print(json.dumps({args.leg: leg}), flush=True)
         return
@@ -532,7 +534,7 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_deep_amr:
         log("deep-AMR workload: generating")
-        out["deep_amr"] = time_deep_amr(forms, 10, api, inputs)
+        out["deep_amr"] = time_deep_amr(forms, 10, api, inputs, None if args.no_tune else autotune)
         torch.cuda.empty_cache()
     if not args.no_mg:
         log("multigrid Poisson V-cycles")

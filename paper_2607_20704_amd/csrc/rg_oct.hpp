@@ -157,9 +157,13 @@ template <typename R, int G> struct Smem {
     int32_t nb[G][27];
     uint32_t sm[G][7];          // son masks: own, then sides x-, x+, y-, y+, z-, z+
     double u[G][8][NV];         // uold of the oct's own cells
-    R w[G][80][NV];             // primitive variables of the stencil cells
+    // the stencil's primitives are dead once the face states exist (phase
+    // B), before the fluxes are written (phase C): one LDS region serves both
+    union {
+        R w[G][80][NV];         // primitive variables of the stencil cells
+        double g[G][36][NV];    // G = F dt/dx per face
+    };
     R fs[G][36][2][NV];         // face states: [face][0] left of the face, [1] right
-    double g[G][36][NV];        // G = F dt/dx per face
     double red[8];              // block minimum of the fused CFL limit (one per wave)
 };
 

@@ -399,6 +399,27 @@ class DeviceTree:
                                         int(form), flags, _ptr(dt), _tuning(tune), _stream()))
         return dt
 
+    def capture_subcycled(self, u, gamma, cfl, nsteps=1, form=RG_FP64, tune=None):
+        """A captured HIP graph of `nsteps` subcycled coarse steps advancing
+        u in place (for trees small enough that launching the level
+        recursion costs more than the work).  Returns (graph, dts); each
+        graph.replay() runs the steps and writes dts[s] (coarse step s's
+        time steps).  The tree must not change while the graph is used."""
+        nlev = self.lmax - self.lmin + 2
+        dts = torch.empty((nsteps, nlev), dtype=torch.float64, device="cuda")
+        scratch = torch.empty_like(u)
+        if self.corr is not None and getattr(self, "acc", None) is None:
+            self.acc = torch.empty_like(self.corr)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            for k in range(nsteps):
+                self.step_subcycled(u, gamma, cfl, form, False, dts[k], tune, scratch)
+        torch.cuda.current_stream().wait_stream(side)
+        self._graph_buffers = (scratch,)
+        return g, dts
+
     def run_subcycled(self, u, gamma, cfl, nsteps, form=RG_FP64, rebuild=False, tune=None):
         """nsteps coarse subcycled steps on a copy of u; returns (state, dts)
         with dts[s] the coarse step of step s."""

@@ -241,3 +241,31 @@ def test_full_deep_amr_refine_properties(deep_full):
     assert np.array_equal(u_new[fresh], np.repeat(src[:, None, :], 8, axis=1))
     tot1, abs1 = _leaf_totals_dev(D, u2)
     assert np.all(np.abs(tot1 - tot0) <= 1e-12 * np.maximum(abs0, abs1))
+
+
+def test_dynamic_subcycled_parity():
+    """Subcycled coarse steps with refinement after each one (Sedov blast,
+    linear coarse ghosts, 4^3-cell blocks): the device follows the oracle's
+    trees, time steps and states bit for bit."""
+    from paper_2607_20704_amd import api
+    w = I.sedov_amr(base=4, lmax=6, radius=0.15)
+    params = (0.0, 0.08, 7)
+    T = O.Tree(w.ijkl, w.bc, ghost=O.GHOST_LINEAR)
+    D = api.DeviceTree(w.ijkl, w.bc, capacity=60000, ghost=api.L.RG_GHOST_LINEAR)
+    ref = T.permute_cells(w.u)
+    u = torch.empty((8 * D.capacity, 5), dtype=torch.float64, device="cuda")
+    u[:8 * D.n] = D.to_key_order(w.u)
+    for s in range(4):
+        n8 = 8 * D.n
+        dt = D.step_subcycled(u[:n8], w.gamma, w.cfl)
+        ref_dt = T.step_subcycled(ref, w.gamma, w.cfl)
+        assert float(dt[0].cpu()) == ref_dt
+        flags, ni, nu = T.refine(ref, *params, nsubgrid=4)
+        T = O.Tree(ni, w.bc, ghost=O.GHOST_LINEAR)
+        ref = T.permute_cells(nu)
+        u = D.refine(u[:n8], *params, nsubgrid=4).clone()
+        u = torch.cat([u, torch.empty((8 * D.capacity - u.shape[0], 5), dtype=torch.float64, device="cuda")])
+        torch.cuda.synchronize()
+        say("  coarse step %d: octs %d, levels %d-%d" % (s, T.n, T.lmin, T.lmax))
+        _check_tree_equal(D, T)
+        assert np.array_equal(u[:8 * D.n].cpu().numpy(), ref)

@@ -189,3 +189,32 @@ def test_full_deep_amr_subcycled(deep_full):
     l1 = torch.cat([num[:1] / den[:1], num[1:4] / den[0], num[4:] / den[4:]]).cpu().numpy()
     say("  mixed vs fp64 L1", l1)
     assert np.all(l1 <= 1e-5)
+
+
+def test_captured_subcycled_step_replays_exactly():
+    """A coarse step captured in a HIP graph, replayed three times with
+    eager work and synchronisations in between: every replay equals the
+    eager step from the same state, state and time steps."""
+    from paper_2607_20704_amd import api
+    w = I.sedov_amr(base=4, lmax=6, radius=0.15)
+    D = api.DeviceTree(w.ijkl, w.bc)
+    u0 = D.to_key_order(w.u)
+    # eager reference: three coarse steps
+    eager, e_dts = [], []
+    a = u0.clone()
+    for s in range(3):
+        e_dts.append(D.step_subcycled(a, w.gamma, w.cfl).clone())
+        eager.append(a.clone())
+    ug = u0.clone()
+    g, dts = D.capture_subcycled(ug, w.gamma, w.cfl)
+    torch.cuda.synchronize()
+    assert torch.equal(ug, u0)            # capture runs nothing
+    for s in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(ug, eager[s]), s
+        assert torch.equal(dts[0], e_dts[s]), s
+        # eager work between replays, on other buffers
+        other, _ = D.run(u0, w.gamma, w.cfl, 1)
+        torch.cuda.synchronize()
+        del other

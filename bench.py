@@ -265,6 +265,21 @@ def time_deep_amr(forms, nsteps, api, inputs, autotune=None):
             "simulated_time_per_s": sdt / (sms * 1e-3),
             "global_simulated_time_per_s": global_dt / (ms * 1e-3),
         }
+    # coarse ghost cells by linear interpolation (the per-oct kernel's second
+    # instantiation; bricks have no coarse ghosts)
+    if "fp64" in forms:
+        tune = out["fp64"]["tune"]
+        DL = api.DeviceTree(w.ijkl, w.bc, ghost=api.L.RG_GHOST_LINEAR)
+        DL.run(u0, w.gamma, w.cfl, 1, form=api.RG_FP64, tune=tune)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        DL.run(u0, w.gamma, w.cfl, nsteps, form=api.RG_FP64, tune=tune)
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b) / nsteps
+        out["fp64"]["linear_ghosts"] = {"ms_per_step": round(ms, 4), "cell_updates_per_s": cells / (ms * 1e-3)}
+        del DL
     if "fp64" in states and "mixed" in states:
         x, y = states["fp64"], states["mixed"]
         num = (vol[:, None] * (x - y).abs()).sum(0)

@@ -228,7 +228,7 @@ def time_deep_amr(forms, nsteps, api, inputs, autotune=None):
                        "gamma 5/3, periodic; %d steps" % (w.meta["sigma_a"], nsteps),
            "octs": D.n, "cells": cells,
            "octs_per_level": {str(l): int(D.level_begin[l + 1] - D.level_begin[l]) for l in range(D.lmin, D.lmax + 1)},
-           "schedule": {str(l): {"bricks": c[0], "per_oct": c[1]} for l, c in D.schedule_counts().items()}}
+           "schedule": {str(l): {"bricks": c[0], "per_oct": c[1], "sibling_groups": c[2]} for l, c in D.schedule_counts().items()}}
     updates_sub = sum(2 ** (l - D.lmin) * 8 * int(D.level_begin[l + 1] - D.level_begin[l])
                       for l in range(D.lmin, D.lmax + 1))
     states = {}
@@ -247,6 +247,15 @@ def time_deep_amr(forms, nsteps, api, inputs, autotune=None):
         out[f] = {"cell_updates_per_s": cells / (ms * 1e-3), "ms_per_step": round(ms, 4),
                   "tune": list(tune) if tune else None}
         global_dt = float(dts.mean())
+        # the same steps with the sibling groups left to the per-oct kernel
+        base = list(tune[:5]) if tune else [4, 256, 0, 0, 0]
+        ng = tuple(base + [0] * (5 - len(base)) + [1, 0])
+        D.run(u0, w.gamma, w.cfl, 1, form=form, tune=ng)
+        a.record()
+        D.run(u0, w.gamma, w.cfl, nsteps, form=form, tune=ng)
+        b.record()
+        b.synchronize()
+        out[f]["ms_per_step_without_sibling_groups"] = round(a.elapsed_time(b) / nsteps, 4)
         # level subcycling: level l takes 2^(l - lmin) steps per coarse step
         nsub = 2
         D.run_subcycled(u0, w.gamma, w.cfl, 1, form=form, tune=tune)     # warm-up
@@ -556,7 +565,7 @@ def main():
     out["config"] = {"workload": "random_uniform_l8: 256^3 periodic box, lognormal rho (sigma_ln 0.5), k^-2 "
                                  "velocities at rms Mach 2, p=1, gamma 5/3, CFL 0.8, seed 20704",
                      "octs": D.n, "cells": cells, "levels": [D.lmin, D.lmax], "form": primary,
-                     "schedule": {str(l): {"bricks": c[0], "per_oct": c[1]} for l, c in D.schedule_counts().items()},
+                     "schedule": {str(l): {"bricks": c[0], "per_oct": c[1], "sibling_groups": c[2]} for l, c in D.schedule_counts().items()},
                      "step": "hash rebuild + neighbour lists + hydro with the next dt folded in (+ corrections "
                              "+ corrected cells' dt + restriction)"}
     out["roofline"] = s["roofline"]

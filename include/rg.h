@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define RG_ABI_VERSION 8
+#define RG_ABI_VERSION 9
 #define RG_MAX_LEVEL 21
 #define RG_NBR_OUTSIDE INT32_MIN
 #define RG_RHO_MIN 1e-10
@@ -203,7 +203,9 @@ typedef struct rg_tuning {
                                  0 = one workgroup per work item */
     int32_t brick_waves;      /* brick kernel register budget: waves per SIMD it is compiled for
                                  (FP64: 2 or 3, mixed: 3 or 4; 0 = default: 2 for FP64, 4 mixed) */
-    int32_t reserved[3];
+    int32_t no_groups;        /* 1: scheduled updates leave complete sibling groups to the per-oct kernel */
+    int32_t group_threads;    /* sibling-group kernel workgroup size: 256, 320 or 384 (0 = default) */
+    int32_t reserved[1];
 } rg_tuning;
 
 /* Kernel schedule of a tree.  A brick is a Hilbert-aligned cube of 8x8x8
@@ -211,11 +213,15 @@ typedef struct rg_tuning {
  * a complete brick none of whose octs borders a coarse ghost is updated by
  * the brick kernel, which marches the brick plane by plane and shares the
  * stencil of all its octs (the paper's larger-block idea, Sec. 3); all other
- * octs use the per-oct kernel.  For level l, d_list holds
- * [brick_begin[l], +brick_count[l]) first octs of bricks and
- * [rest_begin[l], +rest_count[l]) octs for the per-oct kernel.  The schedule
- * depends only on the keys and neighbour lists: rebuild it when the tree
- * changes. */
+ * octs are updated one at a time, or eight at a time where they form a
+ * complete sibling group (the 8 children of one oct, keys 8 P .. 8 P + 7,
+ * consecutive in memory), whose 4^3 cells share one stencil tile.  For level
+ * l, d_list holds [brick_begin[l], +brick_count[l]) first octs of bricks,
+ * [rest_begin[l], +rest_count[l]) every oct outside them, and that set split
+ * into [group_begin[l], +group_count[l]) first octs of complete sibling
+ * groups (levels above lmin) and [single_begin[l], +single_count[l]) the
+ * other octs.  The schedule depends only on the keys and neighbour lists:
+ * rebuild it when the tree changes. */
 typedef struct rg_schedule {
     int64_t brick_begin[RG_MAX_LEVEL + 2];
     int64_t brick_count[RG_MAX_LEVEL + 2];
@@ -229,6 +235,10 @@ typedef struct rg_schedule {
      * cell across one of their six faces */
     int64_t border_begin[RG_MAX_LEVEL + 2];
     int64_t border_count[RG_MAX_LEVEL + 2];
+    int64_t group_begin[RG_MAX_LEVEL + 2];
+    int64_t group_count[RG_MAX_LEVEL + 2];
+    int64_t single_begin[RG_MAX_LEVEL + 2];
+    int64_t single_count[RG_MAX_LEVEL + 2];
     const int32_t *d_list;
 } rg_schedule;
 
@@ -331,7 +341,7 @@ typedef struct rg_tree {
 } rg_tree;
 
 /* Builds the schedule of tree t (keys, level ranges and neighbour lists must
- * be current) into the caller's d_list (capacity >= 3 n_oct int32 entries).
+ * be current) into the caller's d_list (capacity >= 4 n_oct int32 entries).
  * Reads the keys and neighbour lists back to the host: synchronises.  Once
  * t->sched points to it, rg_prepare_tree builds neighbour lists brick by
  * brick. */
@@ -342,16 +352,17 @@ size_t rg_schedule_workspace_bytes(int64_t n_oct);
 
 /* The same schedule built on the device (no copy of the tree to the host;
  * synchronises once to read the list lengths back): per level the same
- * brick, per-oct and border lists, in key order, laid out as all levels'
- * bricks, then all levels' per-oct octs, the neighbour-build lists, and the
- * border lists (offsets in *out).  d_list capacity >= 3 n_oct; d_ws is
+ * brick, per-oct, border, sibling-group and single-oct lists, in key order,
+ * list by list (offsets in *out).  d_list capacity >= 4 n_oct; d_ws is
  * rg_schedule_workspace_bytes(n_oct) bytes, 256-byte aligned.  For trees
  * that change every step (rg_refine). */
 rg_status rg_schedule_build_device(const rg_tree *t, int32_t *d_list, int64_t capacity, void *d_ws, size_t ws_bytes,
                                    rg_schedule *out, void *stream);
 
 /* One level's update following a schedule: the level's bricks with the
- * brick kernel, its other octs with the per-oct kernel (which also records
+ * brick kernel, its complete sibling groups with the sibling-group kernel
+ * (one 8x8x8 tile per group; tune->no_groups 1 leaves them to the per-oct
+ * kernel), its other octs with the per-oct kernel (the last two also record
  * the coarse-side fluxes in t->d_corr).  Same results, bit for bit, as
  * rg_hydro_step_level over the whole level. */
 rg_status rg_hydro_step_scheduled(const rg_tree *t, const rg_schedule *sched, int level, const double *d_dt,

@@ -28,7 +28,7 @@ st = ctypes.c_int
 
 class RgTuning(ctypes.Structure):
     _fields_ = [("octs_per_group", i32), ("threads", i32), ("no_bricks", i32), ("persistent", i32),
-                ("brick_waves", i32), ("reserved", i32 * 3)]
+                ("brick_waves", i32), ("no_groups", i32), ("group_threads", i32), ("reserved", i32 * 1)]
 
 
 class RgSchedule(ctypes.Structure):
@@ -36,7 +36,10 @@ class RgSchedule(ctypes.Structure):
                 ("rest_begin", i64 * (RG_MAX_LEVEL + 2)), ("rest_count", i64 * (RG_MAX_LEVEL + 2)),
                 ("nbr_brick_begin", i64), ("nbr_brick_count", i64), ("nbr_rest_begin", i64),
                 ("nbr_rest_count", i64), ("border_begin", i64 * (RG_MAX_LEVEL + 2)),
-                ("border_count", i64 * (RG_MAX_LEVEL + 2)), ("d_list", P)]
+                ("border_count", i64 * (RG_MAX_LEVEL + 2)),
+                ("group_begin", i64 * (RG_MAX_LEVEL + 2)), ("group_count", i64 * (RG_MAX_LEVEL + 2)),
+                ("single_begin", i64 * (RG_MAX_LEVEL + 2)), ("single_count", i64 * (RG_MAX_LEVEL + 2)),
+                ("d_list", P)]
 
 
 class RgTree(ctypes.Structure):

@@ -30,7 +30,8 @@ def _ptr(t):
 
 
 def _tuning(tune):
-    """tune: None or (octs_per_group, threads[, no_bricks[, persistent[, brick_waves]]])."""
+    """tune: None or (octs_per_group, threads[, no_bricks[, persistent[, brick_waves[, no_groups[,
+    group_threads]]]]])."""
     if tune is None:
         return None
     t = RgTuning()
@@ -38,6 +39,8 @@ def _tuning(tune):
     t.no_bricks = int(tune[2]) if len(tune) > 2 else 0
     t.persistent = int(tune[3]) if len(tune) > 3 else 0
     t.brick_waves = int(tune[4]) if len(tune) > 4 else 0
+    t.no_groups = int(tune[5]) if len(tune) > 5 else 0
+    t.group_threads = int(tune[6]) if len(tune) > 6 else 0
     return ctypes.byref(t)
 
 
@@ -237,8 +240,8 @@ class DeviceTree:
     def build_schedule(self, on_host=False):
         """(Re)build the kernel schedule from the current keys and lists, on
         the device (default) or on the host (rg_schedule_build)."""
-        if not hasattr(self, "sched_list") or self.sched_list.numel() < 3 * self.n:
-            self.sched_list = torch.empty(3 * self.capacity, dtype=torch.int32, device="cuda")
+        if not hasattr(self, "sched_list") or self.sched_list.numel() < 4 * self.n:
+            self.sched_list = torch.empty(4 * self.capacity, dtype=torch.int32, device="cuda")
         self._desc.sched = None
         self.sched = L.RgSchedule()
         if on_host:
@@ -253,15 +256,18 @@ class DeviceTree:
         self._desc.sched = ctypes.pointer(self.sched)
 
     def schedule_lists(self):
-        """{level: (bricks, per-oct octs, border octs)} as numpy arrays, plus
-        the neighbour-build lists under key "nbr"."""
+        """{level: (bricks, per-oct octs, border octs, sibling groups, single
+        octs)} as numpy arrays, plus the neighbour-build lists under key
+        "nbr"."""
         lst = self.sched_list.cpu().numpy()
         sc = self.sched
         out = {}
         for l in range(self.lmin, self.lmax + 1):
             out[l] = tuple(lst[b:b + c].copy() for b, c in ((sc.brick_begin[l], sc.brick_count[l]),
                                                            (sc.rest_begin[l], sc.rest_count[l]),
-                                                           (sc.border_begin[l], sc.border_count[l])))
+                                                           (sc.border_begin[l], sc.border_count[l]),
+                                                           (sc.group_begin[l], sc.group_count[l]),
+                                                           (sc.single_begin[l], sc.single_count[l])))
         out["nbr"] = (lst[sc.nbr_brick_begin:sc.nbr_brick_begin + sc.nbr_brick_count].copy(),
                       lst[sc.nbr_rest_begin:sc.nbr_rest_begin + sc.nbr_rest_count].copy())
         return out
@@ -304,10 +310,11 @@ class DeviceTree:
         return flags
 
     def schedule_counts(self):
-        """{level: (bricks, per-oct)} of the kernel schedule."""
+        """{level: (bricks, octs outside bricks, sibling groups among them)}
+        of the kernel schedule."""
         if self.sched is None:
             return {}
-        return {l: (int(self.sched.brick_count[l]), int(self.sched.rest_count[l]))
+        return {l: (int(self.sched.brick_count[l]), int(self.sched.rest_count[l]), int(self.sched.group_count[l]))
                 for l in range(self.lmin, self.lmax + 1)}
 
     def hydro_level(self, level, dt, gamma, uold, unew, form=RG_FP64, tune=None, cfl=0.0, dt_next=None):

@@ -1,9 +1,10 @@
 """Kernel-variant selection by measurement.
 
 Every variant the library offers for a workload (octs per workgroup of the
-per-oct kernel, bricks on or off, the brick kernel's register budget,
-persistent or one-item-per-workgroup batched grids) computes the same bits -- the GPU tests check this -- so the
-choice only changes speed.  The tuner times each candidate with HIP events
+per-oct kernel, bricks on or off, sibling groups on or off and their
+workgroup size, the brick kernel's register budget, persistent or
+one-item-per-workgroup batched grids) computes the same bits -- the GPU
+tests check this -- so the choice only changes speed.  The tuner times each candidate with HIP events
 on the caller's device and keeps the fastest in a JSON cache keyed by device
 name, form and a coarse workload signature, so later runs reuse it.
 
@@ -18,10 +19,11 @@ import torch
 
 from . import api
 
-# (octs_per_group, threads, no_bricks, persistent, brick_waves): per-oct
-# workgroup shapes, bricks off, and the brick kernel's register budgets
+# (octs_per_group, threads, no_bricks, persistent, brick_waves, no_groups,
+# group_threads): per-oct workgroup shapes, bricks off, sibling groups off
+# or on other workgroup sizes, and the brick kernel's register budgets
 TREE_CANDIDATES = [(4, 256, 0, 0, 0), (2, 128, 0, 0, 0), (8, 256, 0, 0, 0), (7, 256, 0, 0, 0), (3, 128, 0, 0, 0),
-                   (4, 256, 1, 0, 0)]
+                   (4, 256, 1, 0, 0), (4, 256, 0, 0, 0, 1, 0), (4, 256, 0, 0, 0, 0, 256), (4, 256, 0, 0, 0, 0, 384)]
 BRICK_WAVES = {api.RG_FP64: (2, 3), api.RG_MIXED: (3, 4)}
 
 
@@ -91,8 +93,10 @@ def _time(fn, reps):
 
 
 def tree_signature(D):
-    bricks = sum(c[0] for c in D.schedule_counts().values())
-    return "n%d_l%d-%d_b%d" % (_bucket(D.n), D.lmin, D.lmax, _bucket(512 * bricks + 1))
+    counts = D.schedule_counts().values()
+    bricks = sum(c[0] for c in counts)
+    groups = sum(c[2] for c in counts)
+    return "n%d_l%d-%d_b%d_g%d" % (_bucket(D.n), D.lmin, D.lmax, _bucket(512 * bricks + 1), _bucket(8 * groups + 1))
 
 
 def tune_tree(D, u, gamma, form, reps=5, use_cache=True, candidates=None):

@@ -20,6 +20,7 @@
 #include "rg_internal.hpp"
 #include "rg_math.hpp"
 #include "rg_oct.hpp"
+#include "rg_sib.hpp"
 
 namespace rg {
 namespace {
@@ -32,6 +33,15 @@ __global__ __launch_bounds__(NT) void k_hydro_level(LevelArgs a)
     const int64_t left = a.oct_end - first;
     const int count = left < G ? static_cast<int>(left) : G;
     hydro_group<R, G, NT, GH>(a, first, count, S);
+}
+
+// one complete sibling group per workgroup: list[oct_begin + block] is the
+// group's first oct
+template <typename R, int NT, bool GH>
+__global__ __launch_bounds__(NT) void k_hydro_sib(LevelArgs a, const int32_t *__restrict__ father)
+{
+    __shared__ SibSmem<R> S;
+    hydro_sib<R, NT, GH>(a, father, a.list[a.oct_begin + blockIdx.x], S);
 }
 
 // ---------------------------------------------------------------------------
@@ -196,23 +206,31 @@ template <typename R> rg_status launch_form(const LevelArgs &a, const rg_tuning 
     return fail(RG_ENOTSUP, "no hydro kernel for %d octs per group and %d threads", g, nt);
 }
 
-}  // namespace
-
-rg_status hydro_level(const LevelArgs &a, int form, const rg_tuning *tune, hipStream_t s)
+template <typename R, int NT> rg_status launch_sib(const LevelArgs &a, const int32_t *father, hipStream_t s)
 {
-    if (a.oct_end <= a.oct_begin) return RG_OK;
-    if (form == RG_FP64) return launch_form<double>(a, tune, s);
-    return launch_form<float>(a, tune, s);
+    const unsigned blocks = static_cast<unsigned>(a.oct_end - a.oct_begin);
+    if (a.ghost)
+        k_hydro_sib<R, NT, true><<<blocks, NT, 0, s>>>(a, father);
+    else
+        k_hydro_sib<R, NT, false><<<blocks, NT, 0, s>>>(a, father);
+    return launch_status("sibling-group hydro");
 }
 
-// octs list[0..count) (or first..first+count when list is null)
-rg_status hydro_level_list(const double *uold, double *unew, const int32_t *nbr27, const uint32_t *son,
-                           const int32_t *list, int64_t count, double *corr, int64_t corr_base, const double *dt,
-                           double dx, double gamma, int form, const rg_tuning *tune, double cfl, double *dt_next,
-                           hipStream_t s, int64_t first, const double *ucoarse, int corr_mode, int ghost,
-                           const double *ucoarse2)
+template <typename R> rg_status launch_sib_form(const LevelArgs &a, const int32_t *father, const rg_tuning *tune,
+                                                hipStream_t s)
 {
-    if (count <= 0) return RG_OK;
+    const int nt = tune && tune->group_threads ? tune->group_threads : 320;
+    if (nt == 320) return launch_sib<R, 320>(a, father, s);
+    if (nt == 256) return launch_sib<R, 256>(a, father, s);
+    if (nt == 384) return launch_sib<R, 384>(a, father, s);
+    return fail(RG_ENOTSUP, "no sibling-group kernel for %d threads", nt);
+}
+
+LevelArgs level_args(const double *uold, double *unew, const int32_t *nbr27, const uint32_t *son,
+                     const int32_t *list, int64_t count, double *corr, int64_t corr_base, const double *dt, double dx,
+                     double gamma, double cfl, double *dt_next, int64_t first, const double *ucoarse, int corr_mode,
+                     int ghost, const double *ucoarse2)
+{
     LevelArgs a;
     a.corr_mode = corr_mode;
     a.ghost = ghost;
@@ -232,7 +250,44 @@ rg_status hydro_level_list(const double *uold, double *unew, const int32_t *nbr2
     a.gamma = gamma;
     a.cfl = cfl;
     a.dt_next = reinterpret_cast<unsigned long long *>(dt_next);
+    return a;
+}
+
+}  // namespace
+
+rg_status hydro_level(const LevelArgs &a, int form, const rg_tuning *tune, hipStream_t s)
+{
+    if (a.oct_end <= a.oct_begin) return RG_OK;
+    if (form == RG_FP64) return launch_form<double>(a, tune, s);
+    return launch_form<float>(a, tune, s);
+}
+
+// octs list[0..count) (or first..first+count when list is null)
+rg_status hydro_level_list(const double *uold, double *unew, const int32_t *nbr27, const uint32_t *son,
+                           const int32_t *list, int64_t count, double *corr, int64_t corr_base, const double *dt,
+                           double dx, double gamma, int form, const rg_tuning *tune, double cfl, double *dt_next,
+                           hipStream_t s, int64_t first, const double *ucoarse, int corr_mode, int ghost,
+                           const double *ucoarse2)
+{
+    if (count <= 0) return RG_OK;
+    const LevelArgs a = level_args(uold, unew, nbr27, son, list, count, corr, corr_base, dt, dx, gamma, cfl, dt_next,
+                                   first, ucoarse, corr_mode, ghost, ucoarse2);
     return hydro_level(a, form, tune, s);
+}
+
+// complete sibling groups whose first octs are list[0..count): octs
+// list[i] .. list[i] + 7, placed in the group by their father cells
+rg_status hydro_groups_list(const double *uold, double *unew, const int32_t *nbr27, const uint32_t *son,
+                            const int32_t *father, const int32_t *list, int64_t count, double *corr,
+                            int64_t corr_base, const double *dt, double dx, double gamma, int form,
+                            const rg_tuning *tune, double cfl, double *dt_next, hipStream_t s, const double *ucoarse,
+                            int corr_mode, int ghost, const double *ucoarse2)
+{
+    if (count <= 0) return RG_OK;
+    const LevelArgs a = level_args(uold, unew, nbr27, son, list, count, corr, corr_base, dt, dx, gamma, cfl, dt_next,
+                                   0, ucoarse, corr_mode, ghost, ucoarse2);
+    if (form == RG_FP64) return launch_sib_form<double>(a, father, tune, s);
+    return launch_sib_form<float>(a, father, tune, s);
 }
 
 // coarse-fine corrections from the octs list[0..count), side by side

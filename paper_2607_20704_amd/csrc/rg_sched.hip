@@ -4,7 +4,9 @@
 // stencil and removes redundant ghost-cell work; in a cell-by-cell tree only
 // some regions are covered by complete blocks.  The schedule finds, per
 // level, the complete Hilbert-aligned 8^3-oct bricks that border no coarse
-// ghost, and lists every other oct for the per-oct kernel.
+// ghost, then among the other octs the complete sibling groups (8 octs of
+// one father, consecutive keys), and lists the remaining octs for the
+// per-oct kernel.
 #include <vector>
 
 #include "rg_internal.hpp"
@@ -15,6 +17,11 @@ rg_status hydro_level_list(const double *uold, double *unew, const int32_t *nbr2
                            double dx, double gamma, int form, const rg_tuning *tune, double cfl, double *dt_next,
                            hipStream_t s, int64_t first = 0, const double *ucoarse = nullptr,
                            int corr_mode = 0, int ghost = 0, const double *ucoarse2 = nullptr);
+rg_status hydro_groups_list(const double *uold, double *unew, const int32_t *nbr27, const uint32_t *son,
+                            const int32_t *father, const int32_t *list, int64_t count, double *corr,
+                            int64_t corr_base, const double *dt, double dx, double gamma, int form,
+                            const rg_tuning *tune, double cfl, double *dt_next, hipStream_t s, const double *ucoarse,
+                            int corr_mode, int ghost, const double *ucoarse2);
 rg_status hydro_bricks(const double *uold, double *unew, const int32_t *nbr27, const uint32_t *son,
                        const uint64_t *keys, const int32_t *bricks, int64_t nbricks, const double *dt, double dx,
                        double gamma, int outflow, int form, double cfl, double *dt_next, int waves, hipStream_t s);
@@ -24,17 +31,19 @@ using namespace rg;
 
 namespace {
 constexpr int64_t kBrickOcts = 512;
+constexpr int64_t kGroupOcts = 8;
 // neighbour-list slots (dx+1) + 3 (dy+1) + 9 (dz+1) of the faces x-, x+, y-, y+, z-, z+
 constexpr int kFaceSlot[6] = {12, 14, 10, 16, 4, 22};
 }
 
 namespace rg {
 
-// One level of tree t: with a schedule, its bricks by the brick kernel and the
-// rest by the per-oct kernel; without one, the whole level by the per-oct
-// kernel.  Coarse ghost cells are read from ucoarse (bricks have none).  The
-// fluxes owed to coarse cells go to corr (30 doubles per oct from the first
-// oct above lmin): stored (corr_mode 0), stored as 0 + flux (1) or added (2).
+// One level of tree t: with a schedule, its bricks by the brick kernel, its
+// complete sibling groups by the group kernel and the rest by the per-oct
+// kernel; without one, the whole level by the per-oct kernel.  Coarse ghost
+// cells are read from ucoarse (bricks have none).  The fluxes owed to coarse
+// cells go to corr (30 doubles per oct from the first oct above lmin):
+// stored (corr_mode 0), stored as 0 + flux (1) or added (2).
 rg_status hydro_tree_level(const rg_tree *t, const rg_schedule *sc, int level, const double *d_dt, double gamma,
                            const double *d_uold, const double *d_ucoarse, double *d_unew, double cfl,
                            double *d_dt_next, int form, const rg_tuning *tune, hipStream_t s, double *d_corr,
@@ -49,9 +58,19 @@ rg_status hydro_tree_level(const rg_tree *t, const rg_schedule *sc, int level, c
         RG_TRY(hydro_bricks(d_uold, d_unew, t->d_nbr27, t->d_son_mask, t->d_keys, sc->d_list + sc->brick_begin[level],
                             sc->brick_count[level], d_dt, dx, gamma, t->bc == RG_BC_OUTFLOW, form, cfl, d_dt_next,
                             tune ? tune->brick_waves : 0, s));
-        RG_TRY(hydro_level_list(d_uold, d_unew, t->d_nbr27, t->d_son_mask, sc->d_list + sc->rest_begin[level],
-                                sc->rest_count[level], corr, corr_base, d_dt, dx, gamma, form, tune, cfl, d_dt_next,
-                                s, 0, d_ucoarse, corr_mode, t->ghost, d_ucoarse2));
+        if (tune && tune->no_groups) {
+            RG_TRY(hydro_level_list(d_uold, d_unew, t->d_nbr27, t->d_son_mask, sc->d_list + sc->rest_begin[level],
+                                    sc->rest_count[level], corr, corr_base, d_dt, dx, gamma, form, tune, cfl,
+                                    d_dt_next, s, 0, d_ucoarse, corr_mode, t->ghost, d_ucoarse2));
+        } else {
+            RG_TRY(hydro_groups_list(d_uold, d_unew, t->d_nbr27, t->d_son_mask, t->d_father_cell,
+                                     sc->d_list + sc->group_begin[level], sc->group_count[level], corr, corr_base,
+                                     d_dt, dx, gamma, form, tune, cfl, d_dt_next, s, d_ucoarse, corr_mode, t->ghost,
+                                     d_ucoarse2));
+            RG_TRY(hydro_level_list(d_uold, d_unew, t->d_nbr27, t->d_son_mask, sc->d_list + sc->single_begin[level],
+                                    sc->single_count[level], corr, corr_base, d_dt, dx, gamma, form, tune, cfl,
+                                    d_dt_next, s, 0, d_ucoarse, corr_mode, t->ghost, d_ucoarse2));
+        }
     } else {
         RG_TRY(hydro_level_list(d_uold, d_unew, t->d_nbr27, t->d_son_mask, nullptr,
                                 t->level_begin[level + 1] - t->level_begin[level], corr, corr_base, d_dt, dx, gamma,
@@ -68,7 +87,7 @@ extern "C" {
 rg_status rg_schedule_build(const rg_tree *t, int32_t *d_list, int64_t capacity, rg_schedule *out, void *stream)
 {
     RG_REQUIRE(t && d_list && out, "null pointer");
-    RG_REQUIRE(t->n_oct > 0 && capacity >= 3 * t->n_oct, "list capacity below 3 n_oct");
+    RG_REQUIRE(t->n_oct > 0 && capacity >= 4 * t->n_oct, "list capacity below 4 n_oct");
     RG_REQUIRE(t->lmin >= 1 && t->lmax >= t->lmin && t->lmax <= RG_MAX_LEVEL, "bad levels");
     const int64_t n = t->n_oct;
     hipStream_t s = as_stream(stream);
@@ -81,10 +100,12 @@ rg_status rg_schedule_build(const rg_tree *t, int32_t *d_list, int64_t capacity,
     if (e != hipSuccess) return fail(RG_EHIP, "schedule readback: %s", hipGetErrorString(e));
 
     std::vector<int32_t> list, all_bricks, other;
+    std::vector<std::vector<int32_t>> groups(RG_MAX_LEVEL + 2), singles(RG_MAX_LEVEL + 2);
     list.reserve(2 * n);
     for (int l = 0; l < RG_MAX_LEVEL + 2; ++l)
         out->brick_begin[l] = out->brick_count[l] = out->rest_begin[l] = out->rest_count[l] = out->border_begin[l] =
-            out->border_count[l] = 0;
+            out->border_count[l] = out->group_begin[l] = out->group_count[l] = out->single_begin[l] =
+                out->single_count[l] = 0;
     for (int l = t->lmin; l <= t->lmax; ++l) {
         const int64_t b = t->level_begin[l], end = t->level_begin[l + 1];
         std::vector<uint8_t> covered(end - b, 0), complete(end - b, 0);
@@ -116,6 +137,19 @@ rg_status rg_schedule_build(const rg_tree *t, int32_t *d_list, int64_t capacity,
         out->rest_count[l] = static_cast<int64_t>(list.size()) - out->rest_begin[l];
         for (int64_t o = b; o < end; ++o)
             if (!complete[o - b]) other.push_back(static_cast<int32_t>(o));
+        // complete sibling groups outside the bricks (a brick holds whole
+        // groups); their father cells exist above lmin only
+        std::vector<uint8_t> grouped(end - b, 0);
+        if (l > t->lmin)
+            for (int64_t o = b; o + kGroupOcts <= end; ++o) {
+                const uint64_t k = keys[o];
+                if (!covered[o - b] && (k & (kGroupOcts - 1)) == 0 && keys[o + kGroupOcts - 1] == k + kGroupOcts - 1) {
+                    groups[l].push_back(static_cast<int32_t>(o));
+                    for (int64_t q = o; q < o + kGroupOcts; ++q) grouped[q - b] = 1;
+                }
+            }
+        for (int64_t o = b; o < end; ++o)
+            if (!covered[o - b] && !grouped[o - b]) singles[l].push_back(static_cast<int32_t>(o));
     }
     out->nbr_brick_begin = static_cast<int64_t>(list.size());
     out->nbr_brick_count = static_cast<int64_t>(all_bricks.size());
@@ -135,6 +169,16 @@ rg_status rg_schedule_build(const rg_tree *t, int32_t *d_list, int64_t capacity,
             if (coarse) list.push_back(static_cast<int32_t>(o));
         }
         out->border_count[l] = static_cast<int64_t>(list.size()) - out->border_begin[l];
+    }
+    for (int l = t->lmin; l <= t->lmax; ++l) {
+        out->group_begin[l] = static_cast<int64_t>(list.size());
+        out->group_count[l] = static_cast<int64_t>(groups[l].size());
+        list.insert(list.end(), groups[l].begin(), groups[l].end());
+    }
+    for (int l = t->lmin; l <= t->lmax; ++l) {
+        out->single_begin[l] = static_cast<int64_t>(list.size());
+        out->single_count[l] = static_cast<int64_t>(singles[l].size());
+        list.insert(list.end(), singles[l].begin(), singles[l].end());
     }
     if (static_cast<int64_t>(list.size()) > capacity) return fail(RG_EINVAL, "schedule exceeds list capacity");
     if (!list.empty()) {

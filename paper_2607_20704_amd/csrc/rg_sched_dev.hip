@@ -3,12 +3,14 @@
 // Same lists as rg_schedule_build (per level: complete Hilbert-aligned
 // 8^3-oct bricks that border no coarse cell, the other octs; every complete
 // brick and the other octs for the neighbour build; per level above lmin the
-// octs with a coarse cell across a face), found without copying the tree to
-// the host: one pass marks complete bricks and the bricks that touch a coarse
-// cell, a second pass evaluates the five membership tests per oct, five
-// scans give every oct its place, and a scatter writes the lists in key
-// order.  The host reads back only the per-level list lengths.  A tree that
-// changes every step (refinement) keeps its brick kernel this way.
+// octs with a coarse cell across a face; per level the complete sibling
+// groups outside the bricks and the octs outside bricks and groups), found
+// without copying the tree to the host: one pass marks complete bricks and
+// the bricks that touch a coarse cell, a second pass evaluates the seven
+// membership tests per oct, seven scans give every oct its place, and a
+// scatter writes the lists in key order.  The host reads back only the
+// per-level list lengths.  A tree that changes every step (refinement) keeps
+// its brick kernel this way.
 #include <hipcub/hipcub.hpp>
 
 #include "rg_internal.hpp"
@@ -16,8 +18,11 @@
 namespace rg {
 namespace {
 
-constexpr int kLists = 5;            // bricks, per-oct, all complete bricks, octs outside them, border octs
+// bricks, per-oct, all complete bricks, octs outside them, border octs,
+// sibling groups, octs outside bricks and groups
+constexpr int kLists = 7;
 constexpr int64_t kBrick = 512;      // octs per brick
+constexpr int64_t kGroup = 8;        // octs per sibling group
 constexpr int kLB = RG_MAX_LEVEL + 2;
 
 struct SchedArgs {
@@ -43,6 +48,18 @@ __device__ __forceinline__ int64_t brick_first(const SchedArgs &a, int64_t o, in
     const int64_t f = o - r;
     if (f < a.begin[l] || f + kBrick - 1 >= a.begin[l + 1]) return -1;
     if (a.keys[f] != k - uint64_t(r) || a.keys[f + kBrick - 1] != k - uint64_t(r) + uint64_t(kBrick - 1)) return -1;
+    return f;
+}
+
+// first oct of the complete sibling group holding o (levels above lmin), or -1
+__device__ __forceinline__ int64_t group_first(const SchedArgs &a, int64_t o, int l)
+{
+    if (l <= a.lmin) return -1;
+    const uint64_t k = a.keys[o];
+    const int64_t r = static_cast<int64_t>(k & uint64_t(kGroup - 1));
+    const int64_t f = o - r;
+    if (f < a.begin[l] || f + kGroup - 1 >= a.begin[l + 1]) return -1;
+    if (a.keys[f] != k - uint64_t(r) || a.keys[f + kGroup - 1] != k - uint64_t(r) + uint64_t(kGroup - 1)) return -1;
     return f;
 }
 
@@ -85,6 +102,9 @@ __global__ void k_sched_pred(SchedArgs a, const uint32_t *__restrict__ bad, int3
     pred[2 * a.n + o] = complete && f == o;
     pred[3 * a.n + o] = !complete;
     pred[4 * a.n + o] = border;
+    const int64_t g = covered ? -1 : group_first(a, o, l);
+    pred[5 * a.n + o] = g >= 0 && g == o;
+    pred[6 * a.n + o] = !covered && g < 0;
 }
 
 // per list and level boundary: the number of list members before the
@@ -215,8 +235,8 @@ rg_status rg_schedule_build_device(const rg_tree *t, int32_t *d_list, int64_t ca
                                    rg_schedule *out, void *stream)
 {
     RG_REQUIRE(t && d_list && out && d_ws, "null pointer");
-    RG_REQUIRE(t->n_oct > 0 && t->n_oct <= (int64_t(1) << 28) && capacity >= 3 * t->n_oct,
-               "list capacity below 3 n_oct");
+    RG_REQUIRE(t->n_oct > 0 && t->n_oct <= (int64_t(1) << 28) && capacity >= 4 * t->n_oct,
+               "list capacity below 4 n_oct");
     RG_REQUIRE(t->lmin >= 1 && t->lmax >= t->lmin && t->lmax <= RG_MAX_LEVEL, "bad levels");
     RG_REQUIRE(t->level_begin[t->lmin] == 0 && t->level_begin[t->lmax + 1] == t->n_oct, "bad level ranges");
     RG_REQUIRE(t->d_keys && t->d_nbr27, "tree without keys or neighbour lists");
@@ -254,7 +274,8 @@ rg_status rg_schedule_build_device(const rg_tree *t, int32_t *d_list, int64_t ca
             hipSuccess)
             return fail(RG_EHIP, "schedule scan");
     }
-    k_sched_bounds<<<1, 128, 0, s>>>(a, pred, pos, bounds);
+    static_assert(kLists * kLB <= 256, "one thread per list and level");
+    k_sched_bounds<<<1, 256, 0, s>>>(a, pred, pos, bounds);
     RG_TRY(launch_status("schedule bounds"));
     int64_t h[kLists * kLB];
     if (hipMemcpyAsync(h, bounds, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -272,7 +293,8 @@ rg_status rg_schedule_build_device(const rg_tree *t, int32_t *d_list, int64_t ca
     RG_TRY(launch_status("schedule scatter"));
     for (int l = 0; l < kLB; ++l)
         out->brick_begin[l] = out->brick_count[l] = out->rest_begin[l] = out->rest_count[l] = out->border_begin[l] =
-            out->border_count[l] = 0;
+            out->border_count[l] = out->group_begin[l] = out->group_count[l] = out->single_begin[l] =
+                out->single_count[l] = 0;
     for (int l = t->lmin; l <= t->lmax; ++l) {
         out->brick_begin[l] = b.base[0] + at(0, l);
         out->brick_count[l] = at(0, l + 1) - at(0, l);
@@ -282,6 +304,10 @@ rg_status rg_schedule_build_device(const rg_tree *t, int32_t *d_list, int64_t ca
             out->border_begin[l] = b.base[4] + at(4, l);
             out->border_count[l] = at(4, l + 1) - at(4, l);
         }
+        out->group_begin[l] = b.base[5] + at(5, l);
+        out->group_count[l] = at(5, l + 1) - at(5, l);
+        out->single_begin[l] = b.base[6] + at(6, l);
+        out->single_count[l] = at(6, l + 1) - at(6, l);
     }
     out->nbr_brick_begin = b.base[2];
     out->nbr_brick_count = at(2, kLB - 1);

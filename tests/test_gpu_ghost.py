@@ -80,7 +80,7 @@ def test_variants_and_batch_linear_ghosts():
     T, D = _both(w.ijkl, w.bc)
     u0 = D.to_key_order(w.u)
     base, _ = D.run(u0, w.gamma, w.cfl, 4)
-    for tune in [(2, 128), (8, 256), (4, 256, 1)]:
+    for tune in [(2, 128), (8, 256), (4, 256, 1), (4, 256, 0, 0, 0, 1)]:
         other, _ = D.run(u0, w.gamma, w.cfl, 4, tune=tune)
         assert torch.equal(base, other), tune
     U = api.DeviceTree(w.ijkl, w.bc, schedule=False, ghost=api.L.RG_GHOST_LINEAR)

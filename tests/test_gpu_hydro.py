@@ -226,12 +226,43 @@ def test_brick_schedule_bit_identical(case, form):
     for waves in ((2, 3) if form == 0 else (3, 4)):
         c = run_device(D, u0, gam, 0.8, 5, form, tune=(4, 256, 0, 0, waves))[0]
         assert np.array_equal(a, c), waves
+    # sibling groups left to the per-oct kernel, or on other workgroup sizes
+    for t in ((4, 256, 0, 0, 0, 1), (4, 256, 0, 0, 0, 0, 256), (4, 256, 0, 0, 0, 0, 384)):
+        c = run_device(D, u0, gam, 0.8, 5, form, tune=t)[0]
+        assert np.array_equal(a, c), t
     if form == 0:
         ref = T.permute_cells(u_in)
         T.run(ref, gam, 0.8, 5)
         worst, dmax = parity_metric(a, ref)
         say("  vs oracle: worst ratio %.3g, max |diff| %.3g" % (worst, dmax))
         assert worst <= 1e-12
+
+
+@pytest.mark.parametrize("case", BRICK_CASES[2:], ids=[c[0] for c in BRICK_CASES[2:]])
+def test_sibling_group_lists(case):
+    """Per level above lmin, the group list holds exactly the octs outside
+    bricks whose key ends in 0 (binary 000) and whose 7 following keys are
+    its siblings; the single list the other octs outside bricks."""
+    from paper_2607_20704_amd import api
+    name, mk = case
+    ijkl, bc, _ = mk()
+    D = api.DeviceTree(ijkl, bc)
+    keys = D.keys.cpu().numpy()
+    lists = D.schedule_lists()
+    total = 0
+    for l in range(D.lmin, D.lmax + 1):
+        bricks, rest, border, groups, singles = lists[l]
+        e = int(D.level_begin[l + 1])
+        want = [o for o in rest if l > D.lmin and keys[o] % 8 == 0 and o + 7 < e and keys[o + 7] == keys[o] + 7]
+        assert np.array_equal(groups, np.array(want, dtype=groups.dtype)), l
+        grouped = np.zeros(D.n, bool)
+        for o in want:
+            grouped[o:o + 8] = True
+        assert grouped[rest].sum() == 8 * len(want)
+        assert np.array_equal(singles, rest[~grouped[rest]]), l
+        total += len(want)
+    say("  %s: sibling groups %d" % (name, total))
+    assert total > 0
 
 
 @pytest.mark.parametrize("case", BRICK_CASES[2:], ids=[c[0] for c in BRICK_CASES[2:]])

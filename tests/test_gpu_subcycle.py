@@ -102,7 +102,7 @@ def test_sedov_amr_config_fp64_parity():
     assert worst <= 1e-12
 
 
-VARIANTS = [None, (2, 128), (8, 256), (4, 256, 1), (4, 256, 0, 0, 3)]
+VARIANTS = [None, (2, 128), (8, 256), (4, 256, 1), (4, 256, 0, 0, 3), (4, 256, 0, 0, 0, 1), (4, 256, 0, 0, 0, 0, 256)]
 
 
 def test_variants_and_unscheduled_path_bit_identical():

@@ -535,8 +535,9 @@ rg_status rg_mg_residual(const rg_tree *t, const double *d_phi, const double *d_
  * rg_tree and rg_batch_tree structs are read during this call only; the
  * device buffers they point to are used by every rg_batch_run.
  * tune: octs_per_group 2, 4 (default) or 8; no_bricks 1 runs every oct
- * through the per-oct body; persistent selects persistent grids.  Every
- * choice gives the same bits.  Allocates one device table (work lists and
+ * through the per-oct body; no_groups 1 leaves complete sibling groups to
+ * the per-oct body (the batched group kernel runs 256 threads); persistent
+ * selects persistent grids.  Every choice gives the same bits.  Allocates one device table (work lists and
  * tree descriptors) and the graph; synchronises `stream` once. */
 typedef struct rg_batch_tree {
     const rg_tree *tree;

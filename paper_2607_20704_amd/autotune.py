@@ -34,8 +34,9 @@ def tree_candidates(form):
     return out
 
 
-# (octs_per_group, threads, no_bricks, persistent)
-BATCH_CANDIDATES = [(g, 256, nb, p) for g in (2, 4, 8) for nb in (0, 1) for p in (0, 1)]
+# (octs_per_group, threads, no_bricks, persistent[, brick_waves, no_groups])
+BATCH_CANDIDATES = ([(g, 256, nb, p) for g in (2, 4, 8) for nb in (0, 1) for p in (0, 1)] +
+                    [(g, 256, 0, p, 0, 1) for g in (2, 4, 8) for p in (0, 1)])
 
 
 def _cache_path():

@@ -6,8 +6,9 @@
 // items spanning all trees; the phases of all steps are captured once into
 // a HIP graph, so a whole run is one hipGraphLaunch.  Each tree keeps its
 // own time step (dt is a per-tree device slot).  The per-item work is the
-// same device code as the single-tree kernels (rg_oct.hpp, rg_brick.hpp,
-// rg_nbr.hpp), so a tree gives the same bits whether run alone or in a batch.
+// same device code as the single-tree kernels (rg_oct.hpp, rg_sib.hpp,
+// rg_brick.hpp, rg_nbr.hpp), so a tree gives the same bits whether run alone
+// or in a batch.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -17,6 +18,7 @@
 #include "rg_math.hpp"
 #include "rg_nbr.hpp"
 #include "rg_oct.hpp"
+#include "rg_sib.hpp"
 
 namespace rg {
 namespace {
@@ -202,6 +204,42 @@ __global__ __launch_bounds__(kT, sizeof(R) == 8 ? 4 : 6) void k_batch_octs(const
         a.cfl = T.cfl;
         a.dt_next = reinterpret_cast<unsigned long long *>(dt_next + I.tree);
         hydro_group<R, G, kT, GH>(a, I.first, static_cast<int>(I.count), S);
+        __syncthreads();
+    }
+}
+
+// complete sibling groups: item = one group, `first` its entry in the tree's
+// schedule list
+template <typename R, bool P, bool GH>
+__global__ __launch_bounds__(kT) void k_batch_groups(const BTree *__restrict__ trees, const Item *__restrict__ items,
+                                                     int64_t nitems, int parity, const double *dt, double *dt_next)
+{
+    __shared__ SibSmem<R> S;
+    const ItemRange r = P ? xcd_items(nitems) : xcd_item(nitems);
+    for (int64_t it = r.begin; it < r.end; it += r.stride) {
+        const Item I = items[it];
+        const BTree &T = trees[I.tree];
+        const int level = I.a >> 2;
+        LevelArgs a;
+        a.list = T.list;
+        a.uold = T.u[parity];
+        a.ucoarse = T.u[parity];
+        a.unew = T.u[parity ^ 1];
+        a.nbr27 = T.nbr27;
+        a.son = T.son;
+        a.corr = level > T.lmin ? T.corr : nullptr;
+        a.corr_base = T.corr_base;
+        a.corr_mode = 0;
+        a.ghost = T.ghost;
+        a.ucoarse2 = T.u[parity];
+        a.oct_begin = I.first;
+        a.oct_end = I.first + 1;
+        a.dt = dt + I.tree;
+        a.dx = ldexp(1.0, -level);
+        a.gamma = T.gamma;
+        a.cfl = T.cfl;
+        a.dt_next = reinterpret_cast<unsigned long long *>(dt_next + I.tree);
+        hydro_sib<R, kT, GH>(a, T.father, T.list[I.first], S);
         __syncthreads();
     }
 }
@@ -435,6 +473,27 @@ rg_status launch_octs_g(int g, bool gh, bool persistent, const BTree *trees, con
     return launch_octs<R, 4, false>(persistent, trees, p, parity, dt, dt_next, s);
 }
 
+template <typename R>
+rg_status launch_groups(bool gh, bool persistent, const BTree *trees, const Phase &p, int parity, const double *dt,
+                        double *dt_next, hipStream_t s)
+{
+    if (p.n == 0) return RG_OK;
+    if (persistent) {
+        if (gh) {
+            const int grid = persistent_grid(reinterpret_cast<const void *>(&k_batch_groups<R, true, true>), kT, p.n);
+            k_batch_groups<R, true, true><<<grid, kT, 0, s>>>(trees, p.d_items, p.n, parity, dt, dt_next);
+        } else {
+            const int grid = persistent_grid(reinterpret_cast<const void *>(&k_batch_groups<R, true, false>), kT, p.n);
+            k_batch_groups<R, true, false><<<grid, kT, 0, s>>>(trees, p.d_items, p.n, parity, dt, dt_next);
+        }
+    } else if (gh) {
+        k_batch_groups<R, false, true><<<one_shot_grid(p.n), kT, 0, s>>>(trees, p.d_items, p.n, parity, dt, dt_next);
+    } else {
+        k_batch_groups<R, false, false><<<one_shot_grid(p.n), kT, 0, s>>>(trees, p.d_items, p.n, parity, dt, dt_next);
+    }
+    return launch_status("batched sibling groups");
+}
+
 unsigned small_grid(int64_t n)
 {
     const int64_t want = std::min<int64_t>(n, 4 * device_cus());
@@ -459,6 +518,7 @@ rg_status rg_batch_create(const rg_batch_tree *trees, int ntree, int form, int n
     const int g = tune && tune->octs_per_group ? tune->octs_per_group : 4;
     RG_REQUIRE(g == 2 || g == 4 || g == 8, "batched kernel has no %d-oct groups", g);
     const bool bricks = !(tune && tune->no_bricks);
+    const bool groups = bricks && !(tune && tune->no_groups);
     const bool persistent = tune && tune->persistent;
     bool gh = false;   // some tree interpolates its coarse ghosts
     for (int t = 0; t < ntree; ++t) gh = gh || (trees[t].tree && trees[t].tree->ghost == RG_GHOST_LINEAR);
@@ -466,7 +526,7 @@ rg_status rg_batch_create(const rg_batch_tree *trees, int ntree, int form, int n
     hipStream_t s = as_stream(stream);
 
     std::vector<BTree> bt(ntree);
-    std::vector<Item> it_bricks, it_octs, it_dt, it_corr, it_clear, it_insert, it_nbr;
+    std::vector<Item> it_bricks, it_octs, it_groups, it_dt, it_corr, it_clear, it_insert, it_nbr;
     std::vector<std::vector<Item>> it_restrict;
     int maxdepth = 0;
     for (int t = 0; t < ntree; ++t) {
@@ -506,7 +566,13 @@ rg_status rg_batch_create(const rg_batch_tree *trees, int ntree, int form, int n
         for (int l = 0; l < RG_MAX_LEVEL + 2; ++l) b.level_begin[l] = T->level_begin[l];
 
         for (int l = T->lmin; l <= T->lmax; ++l) {
-            if (bricks) {
+            if (groups) {
+                for (int64_t k = 0; k < sc->brick_count[l]; ++k)
+                    it_bricks.push_back(Item{t, 4 * l, sc->brick_begin[l] + k, 1});
+                for (int64_t k = 0; k < sc->group_count[l]; ++k)
+                    it_groups.push_back(Item{t, 4 * l + 3, sc->group_begin[l] + k, 1});
+                chunk(it_octs, t, 4 * l + 1, sc->single_begin[l], sc->single_count[l], g);
+            } else if (bricks) {
                 for (int64_t k = 0; k < sc->brick_count[l]; ++k)
                     it_bricks.push_back(Item{t, 4 * l, sc->brick_begin[l] + k, 1});
                 chunk(it_octs, t, 4 * l + 1, sc->rest_begin[l], sc->rest_count[l], g);
@@ -533,7 +599,7 @@ rg_status rg_batch_create(const rg_batch_tree *trees, int ntree, int form, int n
         }
     // one device allocation: tree table then item lists
     std::vector<const std::vector<Item> *> lists = {&it_bricks, &it_octs, &it_dt, &it_corr,
-                                                      &it_clear, &it_insert, &it_nbr};
+                                                      &it_clear, &it_insert, &it_nbr, &it_groups};
     for (auto &v : it_restrict) lists.push_back(&v);
     size_t bytes = (sizeof(BTree) * ntree + 255) & ~size_t(255);
     for (auto *v : lists) bytes += (v->size() * sizeof(Item) + 255) & ~size_t(255);
@@ -566,10 +632,10 @@ rg_status rg_batch_create(const rg_batch_tree *trees, int ntree, int form, int n
         delete B;
         return fail(RG_EHIP, "batch upload: %s", hipGetErrorString(e));
     }
-    enum { P_BRICKS, P_OCTS, P_DT, P_CORR, P_CLEAR, P_INSERT, P_NBR, P_RESTRICT };
+    enum { P_BRICKS, P_OCTS, P_DT, P_CORR, P_CLEAR, P_INSERT, P_NBR, P_GROUPS, P_RESTRICT };
     const Phase &ph_bricks = phases[P_BRICKS], &ph_octs = phases[P_OCTS], &ph_dt = phases[P_DT],
                 &ph_corr = phases[P_CORR], &ph_clear = phases[P_CLEAR], &ph_insert = phases[P_INSERT],
-                &ph_nbr = phases[P_NBR];
+                &ph_nbr = phases[P_NBR], &ph_groups = phases[P_GROUPS];
     const unsigned g_dt = small_grid(ph_dt.n), g_corr = small_grid(ph_corr.n), g_clear = small_grid(ph_clear.n),
                    g_insert = small_grid(ph_insert.n), g_nbr = small_grid(ph_nbr.n);
     std::vector<unsigned> g_restrict(maxdepth);
@@ -577,8 +643,9 @@ rg_status rg_batch_create(const rg_batch_tree *trees, int ntree, int form, int n
     // warm the occupancy queries outside the capture
     (void)persistent_grid(reinterpret_cast<const void *>(&k_batch_bricks<double, true>), BT, 1);
 
-    // capture all steps into one graph; within a step the bricks and the oct
-    // groups (disjoint outputs) are two branches that may run concurrently
+    // capture all steps into one graph; within a step the bricks and the
+    // other octs (sibling groups, then single octs; disjoint outputs) are two
+    // branches that may run concurrently
     hipStream_t cs = nullptr, cs2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
@@ -616,7 +683,7 @@ rg_status rg_batch_create(const rg_batch_tree *trees, int ntree, int form, int n
             k_batch_dt<<<g_dt, kT, 0, cs>>>(d_trees, ph_dt.d_items, ph_dt.n, parity, dt);
         }
         k_batch_dt_init<<<(ntree + 255) / 256, 256, 0, cs>>>(dt_next, ntree);
-        const bool fork = ph_bricks.n > 0 && ph_octs.n > 0;
+        const bool fork = ph_bricks.n > 0 && (ph_octs.n > 0 || ph_groups.n > 0);
         if (fork) {
             e = hipEventRecord(ev_fork, cs);
             if (e == hipSuccess) e = hipStreamWaitEvent(cs2, ev_fork, 0);
@@ -631,6 +698,11 @@ rg_status rg_batch_create(const rg_batch_tree *trees, int ntree, int form, int n
             st = launch_bricks<float>(persistent, d_trees, ph_bricks, parity, dt, dt_next, cs);
         if (st != RG_OK) break;
         hipStream_t so = fork ? cs2 : cs;
+        if (form == RG_FP64)
+            st = launch_groups<double>(gh, persistent, d_trees, ph_groups, parity, dt, dt_next, so);
+        else
+            st = launch_groups<float>(gh, persistent, d_trees, ph_groups, parity, dt, dt_next, so);
+        if (st != RG_OK) break;
         if (form == RG_FP64)
             st = launch_octs_g<double>(g, gh, persistent, d_trees, ph_octs, parity, dt, dt_next, so);
         else

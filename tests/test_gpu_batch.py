@@ -14,8 +14,9 @@ from paper_2607_20704_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-# (octs_per_group, threads, no_bricks, persistent)
-BATCH_TUNINGS = [(4, 256, 0, 0), (4, 256, 0, 1), (2, 256, 0, 0), (8, 256, 0, 1), (4, 256, 1, 0)]
+# (octs_per_group, threads, no_bricks, persistent[, brick_waves, no_groups])
+BATCH_TUNINGS = [(4, 256, 0, 0), (4, 256, 0, 1), (2, 256, 0, 0), (8, 256, 0, 1), (4, 256, 1, 0),
+                 (4, 256, 0, 1, 0, 1)]
 
 
 def small_boxes(nsteps):
@@ -38,7 +39,8 @@ def alone(D, u0, box, nsteps, form, rebuild):
 
 
 @pytest.mark.parametrize("form", ["fp64", "mixed"])
-@pytest.mark.parametrize("tune", BATCH_TUNINGS, ids=["g%d_nb%d_p%d" % (t[0], t[2], t[3]) for t in BATCH_TUNINGS])
+@pytest.mark.parametrize("tune", BATCH_TUNINGS, ids=["g%d_nb%d_p%d_ng%d" % (t[0], t[2], t[3], t[5] if len(t) > 5 else 0)
+                                                     for t in BATCH_TUNINGS])
 def test_batch_equals_alone(form, tune):
     from paper_2607_20704_amd import api
     nsteps = 4

@@ -95,3 +95,36 @@ def test_full_deep_amr_sampled(deep_full):
     say("  coarse sides compared:", int(coarse.sum()))
     assert coarse.sum() > 0
     assert np.array_equal(dc[s2 - cb][coarse], want[coarse])
+
+
+def test_full_deep_amr_kernels_agree(deep_full):
+    """On the full tree, in both forms: bricks, sibling groups and single
+    octs give the same bits as bricks with the groups left to the per-oct
+    kernel, and as the per-oct kernel alone -- new state, fluxes owed to
+    coarse cells and the folded next time step."""
+    from paper_2607_20704_amd import api
+    w = deep_full
+    D = api.DeviceTree(w.ijkl, w.bc)
+    counts = D.schedule_counts()
+    say("  schedule", counts)
+    assert sum(c[2] for c in counts.values()) > 0
+    u0 = D.to_key_order(w.u)
+    dt = api.cfl_dt(u0, D.son_mask, D.level_begin, D.lmin, D.lmax, w.gamma, w.cfl)
+    for form in (api.RG_FP64, api.RG_MIXED):
+        first = None
+        for tune in (None, (4, 256, 0, 0, 0, 1), (4, 256, 1)):
+            u1 = torch.zeros_like(u0)
+            dn = torch.full((1,), float("inf"), dtype=torch.float64, device="cuda")
+            D.corr.zero_()
+            for l in range(D.lmin, D.lmax + 1):
+                D.hydro_level(l, dt, w.gamma, u0, u1, form, tune, cfl=w.cfl, dt_next=dn)
+            torch.cuda.synchronize()
+            got = (u1, D.corr.clone(), dn)
+            if first is None:
+                first = got
+                continue
+            say("  form %d tune %s: max |diff| %.3g" % (form, tune, float((u1 - first[0]).abs().max())))
+            assert torch.equal(got[0], first[0]), (form, tune)
+            assert torch.equal(got[1], first[1]), (form, tune)
+            assert torch.equal(got[2], first[2]), (form, tune)
+        del first

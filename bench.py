@@ -471,7 +471,14 @@ def cpu_baseline(w, sample_octs):
     t0 = time.perf_counter()
     O.hydro_octs(T.ijkl, T.nbr27, T.son_mask, 0, n, u, unew, corr, dt, w.gamma)
     sec = time.perf_counter() - t0
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": 8 * n / sec, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "host_cpus": len(os.sched_getaffinity(0)), "cpu_model": model,
             "sample": "hydro update (stencil, MUSCL-Hancock, HLLC, update) of the first %d octs (%d cells, a "
                       "Hilbert-contiguous %s of the box) of the same 256^3 state; serial FP64, %.1f s"
                       % (n, 8 * n, "half" if 2 * n == T.n else "part", sec)}

@@ -141,7 +141,9 @@ __device__ __forceinline__ ItemRange xcd_item(int64_t nitems)
 // octs first .. first+count-1) are separate kernels, so that each keeps the
 // register allocation of its single-tree twin.
 // With P the grid is persistent and loops over the items; without, each
-// workgroup takes one item (no loop-carried registers).
+// workgroup takes one item (no loop-carried registers).  As in the
+// single-tree kernels, FP64 bricks keep each column's state in registers
+// (two waves per SIMD) and mixed bricks read it again (four waves).
 template <typename R, bool P>
 __global__ __launch_bounds__(BT, sizeof(R) == 8 ? 2 : 4) void k_batch_bricks(const BTree *__restrict__ trees,
                                                                             const Item *__restrict__ items,
@@ -167,7 +169,7 @@ __global__ __launch_bounds__(BT, sizeof(R) == 8 ? 2 : 4) void k_batch_bricks(con
         a.outflow = T.bc == RG_BC_OUTFLOW;
         a.cfl = T.cfl;
         a.dt_next = reinterpret_cast<unsigned long long *>(dt_next + I.tree);
-        brick_body<R>(a, T.list[I.first], I.first, S);
+        brick_body<R, sizeof(R) == 8>(a, T.list[I.first], I.first, S);
         __syncthreads();
     }
 }

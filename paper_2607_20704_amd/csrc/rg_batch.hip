@@ -174,11 +174,11 @@ __global__ __launch_bounds__(BT, sizeof(R) == 8 ? 2 : 4) void k_batch_bricks(con
     }
 }
 
+// registers as the compiler sees fit: a forced occupancy made the loop
+// spill (up to 45 registers in the mixed form)
 template <typename R, int G, bool P, bool GH>
-__global__ __launch_bounds__(kT, sizeof(R) == 8 ? 4 : 6) void k_batch_octs(const BTree *__restrict__ trees,
-                                                                          const Item *__restrict__ items,
-                                                                          int64_t nitems, int parity,
-                                                                          const double *dt, double *dt_next)
+__global__ __launch_bounds__(kT) void k_batch_octs(const BTree *__restrict__ trees, const Item *__restrict__ items,
+                                                   int64_t nitems, int parity, const double *dt, double *dt_next)
 {
     __shared__ Smem<R, G> S;
     const ItemRange r = P ? xcd_items(nitems) : xcd_item(nitems);

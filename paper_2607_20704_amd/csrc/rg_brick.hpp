@@ -33,27 +33,47 @@ struct BrickArgs {
     unsigned long long *dt_next;   // if set: CFL limit of the new state folded in (bits of a positive double)
 };
 
-template <typename R> struct BrickSmem {
+// Face states, written by the reconstruction; each is read by exactly one
+// thread in the flux pass, which then overwrites it with the flux of that
+// face, so states and fluxes share the storage without a barrier.
+template <typename R> union BrickFaces {
+    struct {
+        R sxp[BC + 1][BC][NV];  // [x][y]: x+ state of cell x-1 (x = 0..16 -> cells -1..15)
+        R syp[BC + 1][BC][NV];  // [y][x]: y+ state of cell y-1
+        R sxm_hi[BC][NV];       // x- state of the ghost cell x = 16
+        R sym_hi[BC][NV];
+    } st;
+    struct {                    // fluxes F (zero on faces touching split cells)
+        R fx[BC + 1][BC][NV];   // [x][y]: face (x-1 | x), in place of sxp[x][y]
+        R fy[BC + 1][BC][NV];   // [y][x]: face (y-1 | y), in place of syp[y][x]
+    } fl;
+    R row[2 * (BC + 1) * BC + 2 * BC][NV];   // the face states as one list of rows (st's layout)
+};
+static_assert(sizeof(BrickFaces<double>) == sizeof(double) * (2 * (BC + 1) * BC + 2 * BC) * NV,
+              "the row list spans the face states");
+
+// Row of the face state that ghost-ring lane (side q, position k) writes:
+// q = 0 sxp[0][k], 1 sxm_hi[k], 2 syp[0][k], 3 sym_hi[k].  Plain arithmetic:
+// a pointer chosen per lane through branches (one pointer per side) was
+// compiled wrongly for the two-buffer layout -- the lanes of the last side
+// stored through the pointer of the third.
+__host__ __device__ __forceinline__ int ring_row(int q, int k)
+{
+    const int hi = q & 1, ax = q >> 1;
+    return k + hi * (2 * (BC + 1) * BC + ax * BC) + (1 - hi) * ax * ((BC + 1) * BC);
+}
+
+// NB = 2: two face buffers and two split-flag planes (planes of even and odd
+// z), which saves one barrier per plane (see brick_body) for 23 KB more LDS
+// in FP64 -- free at two workgroups per CU, which the FP64 kernel's registers
+// allow anyway; NB = 1 for variants that fit more workgroups.
+template <typename R, int NB = 1> struct BrickSmem {
+    BrickFaces<R> u_[NB];           // face states and fluxes (NB = 2: planes of even / odd z)
     int32_t slot[HS * HS * HS];     // oct slots -1..8 around the brick: oct index inside, neighbour entry outside
     uint8_t son[HS * HS * HS];      // son mask of same-level slot octs, 0 otherwise
     R w[PW * PW][NV];               // primitive variables of the current plane
     R hw[3][4 * BC][NV];            // primitive variables of the reconstructed ghost ring, planes r-1, r, r+1
-    // Face states, written by the reconstruction; each is read by exactly
-    // one thread in the flux pass, which then overwrites it with the flux of
-    // that face, so states and fluxes share the storage without a barrier.
-    union {
-        struct {
-            R sxp[BC + 1][BC][NV];  // [x][y]: x+ state of cell x-1 (x = 0..16 -> cells -1..15)
-            R syp[BC + 1][BC][NV];  // [y][x]: y+ state of cell y-1
-            R sxm_hi[BC][NV];       // x- state of the ghost cell x = 16
-            R sym_hi[BC][NV];
-        } st;
-        struct {                    // fluxes F (zero on faces touching split cells)
-            R fx[BC + 1][BC][NV];   // [x][y]: face (x-1 | x), in place of sxp[x][y]
-            R fy[BC + 1][BC][NV];   // [y][x]: face (y-1 | y), in place of syp[y][x]
-        } fl;
-    } u_;
-    uint8_t split[PW * PW];         // split flag of the current plane's cells
+    uint8_t split[NB][PW * PW];     // split flags of the current plane's cells
     double red[8];                  // block minimum of the fused CFL limit, one per wave
     // mixed form: each column's partial update of the previous plane (its own
     // slot, no sharing), kept here rather than in registers
@@ -73,8 +93,9 @@ __device__ __forceinline__ int slot_index(int sa, int sb, int sc) { return (sa +
 // id, and whether it is a split cell.  Outside the domain (outflow) the
 // position takes the nearest cell inside (zero gradient) and counts as not
 // split; a missing same-level oct gives its coarse cell (injection).
-template <typename R>
-__device__ __forceinline__ int64_t source_cell(const BrickSmem<R> &S, const Geom &g, int x, int y, int z, bool &split)
+template <typename R, int NB>
+__device__ __forceinline__ int64_t source_cell(const BrickSmem<R, NB> &S, const Geom &g, int x, int y, int z,
+                                               bool &split)
 {
     bool clamped = false;
     if (g.outflow) {
@@ -153,8 +174,8 @@ __device__ __forceinline__ void face_F(const R *L, const R *Rt, int dir, R gamma
 // KU: keep each column's conserved state of the current plane in registers
 // until the update instead of reading it again (10 more registers, one
 // 40-byte read per cell less).
-template <typename R, bool KU = false>
-__device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int64_t b, BrickSmem<R> &S)
+template <typename R, bool KU = false, int NB = 1>
+__device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int64_t b, BrickSmem<R, NB> &S)
 {
     const int tid = threadIdx.x;
 
@@ -256,8 +277,16 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
         if (do_face) load_u(a.uold, source_cell(S, g, hx, hy, 0, sdummy), Upf);
         if (ring_role) load_u(a.uold, source_cell(S, g, rx, ry, 0, sdummy), Upf);
     }
-    // partial update (uold + x and y flux differences) of plane rz-1: in
-    // registers for FP64, in the column's own LDS slot for the mixed form
+    // DB (NB = 2): planes alternate between two face buffers and split-flag
+    // planes, so the fluxes of plane rz are read -- and plane rz is updated --
+    // after the first barrier of the next iteration instead of after a third
+    // barrier of their own; nothing written before a barrier of iteration
+    // rz+1 is still being read from iteration rz-1 (the second barrier of
+    // iteration rz separates them).  With one buffer the third barrier stays.
+    constexpr bool DB = NB == 2;
+    double Ucp[NV];   // DB with KU: conserved state of plane rz-1, own column
+    // partial update (uold + x and y flux differences) of plane rz-1 (mixed
+    // form): in the column's own LDS slot
     constexpr bool ACC_LDS = sizeof(R) == 4;
     double acc_prev[NV], gz_prev[NV];
     R zp_prev[NV];
@@ -270,6 +299,9 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
 
     for (int rz = -1; rz <= BC; ++rz) {
         const bool inner = rz >= 0 && rz < BC;      // plane with x/y faces
+        const int fb = DB ? (rz & 1) : 0;           // this plane's face buffer and split flags
+        BrickFaces<R> &FB = S.u_[fb];
+        uint8_t *spl = S.split[fb];
         double Un[NV];                               // conserved variables of plane rz+1, own column
         sp_next = false;
         load_u(a.uold, source_cell(S, g, x, y, rz + 1, sp_next), Un);
@@ -294,11 +326,11 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
         // 2. plane rz into LDS: W and split flags
         {
             copy5(S.w[(x + 2) + PW * (y + 2)], W0);
-            S.split[(x + 2) + PW * (y + 2)] = sp_cur;
+            spl[(x + 2) + PW * (y + 2)] = sp_cur;
         }
         if (do_face) {
             copy5(S.w[(hx + 2) + PW * (hy + 2)], S.hw[(rz + 3) % 3][lane]);
-            S.split[(hx + 2) + PW * (hy + 2)] = hsplit;
+            spl[(hx + 2) + PW * (hy + 2)] = hsplit;
         }
         if (ring_role && inner) {
             R Wr[NV];
@@ -322,19 +354,10 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
             const int c = (hx + 2) + PW * (hy + 2);
             reconstruct<R>(S.hw[(rz + 3) % 3][lane], S.w[c - 1], S.w[c + 1], S.w[c - PW], S.w[c + PW],
                            S.hw[(rz + 2) % 3][lane], S.hw[(rz + 4) % 3][lane], h, gam, dW, Wq);
-            if (hq == 0) {            // x = -1: its x+ state feeds face (-1|0)
-                face_state<R>(Wq, dW[0], true, st);
-                copy5(S.u_.st.sxp[0][hk], st);
-            } else if (hq == 1) {     // x = 16: x- state feeds face (15|16)
-                face_state<R>(Wq, dW[0], false, st);
-                copy5(S.u_.st.sxm_hi[hk], st);
-            } else if (hq == 2) {     // y = -1
-                face_state<R>(Wq, dW[1], true, st);
-                copy5(S.u_.st.syp[0][hk], st);
-            } else {                  // y = 16
-                face_state<R>(Wq, dW[1], false, st);
-                copy5(S.u_.st.sym_hi[hk], st);
-            }
+            // x = -1 / y = -1 feed their high-side state to face (-1|0), x = 16
+            // / y = 16 their low-side state to face (15|16)
+            face_state<R>(Wq, hq < 2 ? dW[0] : dW[1], (hq & 1) == 0, st);
+            copy5(FB.row[ring_row(hq, hk)], st);
         }
         R sxm[NV], sym[NV];
         double gz[NV];
@@ -342,19 +365,55 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
             to_prim(Un, a.gamma, Wp);
             R dW[3][NV], Wq[NV], st[NV], szm[NV];
             const int c = (x + 2) + PW * (y + 2);
-            nxy_cur = S.split[c - 1] || S.split[c + 1] || S.split[c - PW] || S.split[c + PW];
+            nxy_cur = spl[c - 1] || spl[c + 1] || spl[c - PW] || spl[c + PW];
             reconstruct<R>(W0, S.w[c - 1], S.w[c + 1], S.w[c - PW], S.w[c + PW], Wm, Wp, h, gam, dW, Wq);
             if (inner) {
                 face_state<R>(Wq, dW[0], true, st);
-                copy5(S.u_.st.sxp[x + 1][y], st);
+                copy5(FB.st.sxp[x + 1][y], st);
                 face_state<R>(Wq, dW[1], true, st);
-                copy5(S.u_.st.syp[y + 1][x], st);
+                copy5(FB.st.syp[y + 1][x], st);
                 face_state<R>(Wq, dW[0], false, sxm);
                 face_state<R>(Wq, dW[1], false, sym);
             }
             face_state<R>(Wq, dW[2], false, szm);
             if (rz >= 0) face_flux<R>(zp_prev, szm, 2, gam, g1, r, sp_prev || sp_cur, gz);
             face_state<R>(Wq, dW[2], true, zp_prev);
+        }
+        // DB: plane rz-1 is complete: its x/y fluxes have been in the other
+        // buffer since the barrier above, and its upper z face was just
+        // evaluated
+        if constexpr (DB) {
+            if (rz >= 1) {
+                const BrickFaces<R> &PB = S.u_[(rz - 1) & 1];
+                double Ucur[NV], out[NV];
+                if constexpr (KU) {
+                    copy5(Ucur, Ucp);
+                } else {
+                    bool sdummy;
+                    load_u(a.uold, source_cell(S, g, x, y, rz - 1, sdummy), Ucur);
+                }
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const double gxm = static_cast<double>(PB.fl.fx[x][y][v]) * r;
+                    const double gxp = static_cast<double>(PB.fl.fx[x + 1][y][v]) * r;
+                    const double gym = static_cast<double>(PB.fl.fy[y][x][v]) * r;
+                    const double gyp = static_cast<double>(PB.fl.fy[y + 1][x][v]) * r;
+                    const double acc = (Ucur[v] + (gxm - gxp)) + (gym - gyp);
+                    out[v] = acc + (gz_prev[v] - gz[v]);
+                }
+                bool sdummy;
+                const int64_t cell = source_cell(S, g, x, y, rz - 1, sdummy);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) a.unew[NV * cell + v] = out[v];
+                if (a.dt_next && !sp_prev && !(nxy_prev || sp_prev2 || sp_cur)) {
+                    double Wn[NV];
+                    prim64(out, a.gamma, Wn);
+                    const double cs = sqrt((a.gamma * Wn[4]) / Wn[0]);
+                    const double sp = ((fabs(Wn[1]) + fabs(Wn[2])) + fabs(Wn[3])) + 3.0 * cs;
+                    const double cd = a.cfl * (a.dx / sp);
+                    dt_min = cd < dt_min ? cd : dt_min;
+                }
+            }
         }
         __syncthreads();
 
@@ -364,27 +423,28 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
         if (inner) {
             R F[NV];
             {
-                face_F<R>(S.u_.st.sxp[x][y], sxm, 0, gam, g1, S.split[(x + 1) + PW * (y + 2)] || sp_cur, F);
-                copy5(S.u_.fl.fx[x][y], F);
-                face_F<R>(S.u_.st.syp[y][x], sym, 1, gam, g1, S.split[(x + 2) + PW * (y + 1)] || sp_cur, F);
-                copy5(S.u_.fl.fy[y][x], F);
+                face_F<R>(FB.st.sxp[x][y], sxm, 0, gam, g1, spl[(x + 1) + PW * (y + 2)] || sp_cur, F);
+                copy5(FB.fl.fx[x][y], F);
+                face_F<R>(FB.st.syp[y][x], sym, 1, gam, g1, spl[(x + 2) + PW * (y + 1)] || sp_cur, F);
+                copy5(FB.fl.fy[y][x], F);
             }
             if (extra_faces) {
                 if (lane < BC) {
-                    const bool z2 = S.split[(BC + 1) + PW * (hk + 2)] || S.split[(BC + 2) + PW * (hk + 2)];
-                    face_F<R>(S.u_.st.sxp[BC][hk], S.u_.st.sxm_hi[hk], 0, gam, g1, z2, F);
-                    copy5(S.u_.fl.fx[BC][hk], F);
+                    const bool z2 = spl[(BC + 1) + PW * (hk + 2)] || spl[(BC + 2) + PW * (hk + 2)];
+                    face_F<R>(FB.st.sxp[BC][hk], FB.st.sxm_hi[hk], 0, gam, g1, z2, F);
+                    copy5(FB.fl.fx[BC][hk], F);
                 } else {
-                    const bool z2 = S.split[(hk + 2) + PW * (BC + 1)] || S.split[(hk + 2) + PW * (BC + 2)];
-                    face_F<R>(S.u_.st.syp[BC][hk], S.u_.st.sym_hi[hk], 1, gam, g1, z2, F);
-                    copy5(S.u_.fl.fy[BC][hk], F);
+                    const bool z2 = spl[(hk + 2) + PW * (BC + 1)] || spl[(hk + 2) + PW * (BC + 2)];
+                    face_F<R>(FB.st.syp[BC][hk], FB.st.sym_hi[hk], 1, gam, g1, z2, F);
+                    copy5(FB.fl.fy[BC][hk], F);
                 }
             }
         }
-        __syncthreads();
+        // DB: the fluxes are read after the next iteration's first barrier
+        if constexpr (!DB) __syncthreads();
 
         // 5. update: plane rz-1 is complete; x/y part of plane rz
-        if (rz >= 1) {
+        if (!DB && rz >= 1) {
             double out[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v)
@@ -402,7 +462,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
                 dt_min = cd < dt_min ? cd : dt_min;
             }
         }
-        if (inner) {
+        if (!DB && inner) {
             double Ucur[NV];
             if constexpr (KU) {
                 copy5(Ucur, Uc);
@@ -412,10 +472,10 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
             }
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const double gxm = static_cast<double>(S.u_.fl.fx[x][y][v]) * r;
-                const double gxp = static_cast<double>(S.u_.fl.fx[x + 1][y][v]) * r;
-                const double gym = static_cast<double>(S.u_.fl.fy[y][x][v]) * r;
-                const double gyp = static_cast<double>(S.u_.fl.fy[y + 1][x][v]) * r;
+                const double gxm = static_cast<double>(FB.fl.fx[x][y][v]) * r;
+                const double gxp = static_cast<double>(FB.fl.fx[x + 1][y][v]) * r;
+                const double gym = static_cast<double>(FB.fl.fy[y][x][v]) * r;
+                const double gyp = static_cast<double>(FB.fl.fy[y + 1][x][v]) * r;
                 const double acc = (Ucur[v] + (gxm - gxp)) + (gym - gyp);
                 if constexpr (ACC_LDS)
                     S.acc[tid][v] = acc;
@@ -431,7 +491,10 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
                 Wm[v] = W0[v];
                 W0[v] = Wp[v];
             }
-            if constexpr (KU) copy5(Uc, Un);
+            if constexpr (KU) {
+                if constexpr (DB) copy5(Ucp, Uc);
+                copy5(Uc, Un);
+            }
         }
         sp_prev2 = sp_prev;
         sp_prev = sp_cur;

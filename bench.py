@@ -43,10 +43,16 @@ def log(*a):
 
 
 def kernel_source_digest():
+    """Digest of the brick kernel's code (its sources without comments and
+    blank lines, so that a comment edit keeps the counter summary valid)."""
     h = hashlib.sha256()
     for f in ("rg_brick.hip", "rg_brick.hpp", "rg_math.hpp", "rg_internal.hpp"):
-        with open(os.path.join(ROOT, "paper_2607_20704_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2607_20704_amd", "csrc", f)) as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        for line in text.splitlines():
+            code = line.split("//", 1)[0].strip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -285,8 +285,8 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
     // iteration rz separates them).  With one buffer the third barrier stays.
     constexpr bool DB = NB == 2;
     double Ucp[NV];   // DB with KU: conserved state of plane rz-1, own column
-    // partial update (uold + x and y flux differences) of plane rz-1 (mixed
-    // form): in the column's own LDS slot
+    // one buffer: partial update (uold + x and y flux differences) of plane
+    // rz-1, in registers (FP64) or in the column's own LDS slot (mixed)
     constexpr bool ACC_LDS = sizeof(R) == 4;
     double acc_prev[NV], gz_prev[NV];
     R zp_prev[NV];

@@ -150,7 +150,7 @@ __global__ __launch_bounds__(BT, sizeof(R) == 8 ? 2 : 4) void k_batch_bricks(con
                                                                             int64_t nitems, int parity,
                                                                             const double *dt, double *dt_next)
 {
-    __shared__ BrickSmem<R, sizeof(R) == 8 ? 2 : 1> S;
+    __shared__ BrickSmem<R, 2> S;
     const ItemRange r = P ? xcd_items(nitems) : xcd_item(nitems);
     for (int64_t it = r.begin; it < r.end; it += r.stride) {
         const Item I = items[it];

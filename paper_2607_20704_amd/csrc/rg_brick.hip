@@ -37,8 +37,9 @@ __global__ __launch_bounds__(BT, W) void k_hydro_brick(BrickArgs a)
 {
     // two face buffers (one barrier per plane less) where the LDS still holds
     // as many workgroups as the registers allow: FP64 at two waves per SIMD
-    // (76 KB), mixed at three (51 KB)
-    __shared__ BrickSmem<R, ((sizeof(R) == 8 && W == 2) || (sizeof(R) == 4 && W == 3)) ? 2 : 1> S;
+    // (76 KB), mixed at four (40 KB: its partial updates then need no LDS
+    // slot) or three
+    __shared__ BrickSmem<R, ((sizeof(R) == 8 && W == 2) || sizeof(R) == 4) ? 2 : 1> S;
     // consecutive bricks on one XCD: workgroups are dealt round-robin to the
     // eight XCDs, so give each XCD a contiguous Hilbert range of bricks
     const int64_t per_xcd = (a.nbricks + 7) / 8;

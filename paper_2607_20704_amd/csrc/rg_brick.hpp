@@ -75,9 +75,10 @@ template <typename R, int NB = 1> struct BrickSmem {
     R hw[3][4 * BC][NV];            // primitive variables of the reconstructed ghost ring, planes r-1, r, r+1
     uint8_t split[NB][PW * PW];     // split flags of the current plane's cells
     double red[8];                  // block minimum of the fused CFL limit, one per wave
-    // mixed form: each column's partial update of the previous plane (its own
-    // slot, no sharing), kept here rather than in registers
-    double acc[sizeof(R) == 4 ? BT : 1][NV];
+    // mixed form with one buffer: each column's partial update of the
+    // previous plane (its own slot, no sharing), kept here rather than in
+    // registers
+    double acc[(sizeof(R) == 4 && NB == 1) ? BT : 1][NV];
 };
 
 struct Geom {

@@ -102,15 +102,19 @@ __device__ __forceinline__ void nbr_octs_body(const NbrTable &T, const int32_t *
 
 // Neighbour lists of one complete brick (8^3 octs, keys 512 P .. 512 P + 511,
 // consecutive in memory).  Inside the brick every neighbour follows from the
-// decoded positions; only the 488 oct slots around the brick are looked up
-// in the hash table (with the coarse-cell fallback), and each sibling
-// group's father is looked up once.  Every child of the brick's fathers lies
-// in the brick, so their son masks are complete (all 8 bits) and are stored
-// directly.
+// decoded positions.  The 488 oct slots around the brick lie in the 26
+// neighbouring brick-sized cubes; a cube whose first and last keys are both
+// in the hash table, 511 entries apart, is complete, and its octs are found
+// by key offset from its first one -- two lookups per cube instead of one
+// per slot.  Slots in other cubes are looked up one by one (with the
+// coarse-cell fallback).  Each sibling group's father is looked up once.
+// Every child of the brick's fathers lies in the brick, so their son masks
+// are complete (all 8 bits) and are stored directly.
 struct NbrBrick {
     int32_t slot[10 * 10 * 10];
     int16_t pos[512];         // local position of the k-th oct in key order
     int32_t father[64];       // father oct of each sibling group
+    int32_t cube[27];         // first oct of each complete neighbouring cube, else -1
 };
 
 __device__ __forceinline__ void nbr_brick_body(const NbrTable &T, int64_t base, NbrBrick &S)
@@ -130,6 +134,27 @@ __device__ __forceinline__ void nbr_brick_body(const NbrTable &T, int64_t base, 
         S.slot[((p & 7) + 1) + HS * (((p >> 3) & 7) + 1) + HS * HS * ((p >> 6) + 1)] = static_cast<int32_t>(base + k);
     }
     const int32_t N = 1 << (l - 1);
+    if (tid < 27) {
+        const int dx = tid % 3 - 1, dy = (tid / 3) % 3 - 1, dz = tid / 9 - 1;
+        int32_t bi = i0 + BO * dx, bj = j0 + BO * dy, bk = k0 + BO * dz;
+        bool inside = true;
+        if (T.bc == RG_BC_PERIODIC) {
+            bi &= N - 1;
+            bj &= N - 1;
+            bk &= N - 1;
+        } else {
+            inside = bi >= 0 && bj >= 0 && bk >= 0 && bi < N && bj < N && bk < N;
+        }
+        int32_t first = -1;
+        if (inside) {
+            const uint64_t kb = oct_key(bi, bj, bk, l) & ~uint64_t(BO * BO * BO - 1);
+            const int32_t f = hash_probe(T.keys, T.vals, T.mask, kb);
+            if (f >= 0 && hash_probe(T.keys, T.vals, T.mask, kb + (BO * BO * BO - 1)) == f + (BO * BO * BO - 1))
+                first = f;
+        }
+        S.cube[tid] = first;
+    }
+    __syncthreads();
     for (int sidx = tid; sidx < HS * HS * HS; sidx += 256) {
         const int sa = sidx % HS - 1, sb = (sidx / HS) % HS - 1, sc = sidx / (HS * HS) - 1;
         if (sa >= 0 && sa < BO && sb >= 0 && sb < BO && sc >= 0 && sc < BO) continue;
@@ -143,7 +168,11 @@ __device__ __forceinline__ void nbr_brick_body(const NbrTable &T, int64_t base, 
             continue;
         }
         const uint64_t kn = oct_key(ni, nj, nk, l);
-        int32_t e = hash_probe(T.keys, T.vals, T.mask, kn);
+        const int cube = (sa < 0 ? 0 : (sa >= BO ? 2 : 1)) + 3 * (sb < 0 ? 0 : (sb >= BO ? 2 : 1)) +
+                         9 * (sc < 0 ? 0 : (sc >= BO ? 2 : 1));
+        const int32_t first = S.cube[cube];
+        int32_t e = first >= 0 ? first + static_cast<int32_t>(kn & uint64_t(BO * BO * BO - 1))
+                               : hash_probe(T.keys, T.vals, T.mask, kn);
         if (e < 0) {
             const int32_t f = (l > 1) ? hash_probe(T.keys, T.vals, T.mask, kn >> 3) : -1;
             if (f < 0) {

@@ -213,7 +213,8 @@ def deep_workload(inputs):
 
 def time_deep_amr(forms, nsteps, api, inputs, autotune=None):
     """The clumpy-gas deep tree (base 7 up to level 12, about 28 M cells):
-    `nsteps` whole steps per form (dt, every level, corrections,
+    `nsteps` whole steps per form (dt folded into the previous step's
+    update as in the main workload, every level, corrections,
     restriction; lists prebuilt), and the mixed form's L1 error per
     conserved field against FP64 after those steps (leaf cells, volume
     weighted).  Also two coarse steps with level subcycling, reported as
@@ -241,11 +242,11 @@ def time_deep_amr(forms, nsteps, api, inputs, autotune=None):
     for f in forms:
         form = api.RG_FP64 if f == "fp64" else api.RG_MIXED
         tune = autotune.tune_tree(D, u0, w.gamma, form)[0] if autotune else None
-        D.run(u0, w.gamma, w.cfl, 1, form=form, tune=tune)       # warm-up
+        D.run(u0, w.gamma, w.cfl, 1, form=form, tune=tune, chain=True)       # warm-up
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
-        u, dts = D.run(u0, w.gamma, w.cfl, nsteps, form=form, tune=tune)
+        u, dts = D.run(u0, w.gamma, w.cfl, nsteps, form=form, tune=tune, chain=True)
         b.record()
         b.synchronize()
         ms = a.elapsed_time(b) / nsteps
@@ -256,9 +257,9 @@ def time_deep_amr(forms, nsteps, api, inputs, autotune=None):
         # the same steps with the sibling groups left to the per-oct kernel
         base = list(tune[:5]) if tune else [4, 256, 0, 0, 0]
         ng = tuple(base + [0] * (5 - len(base)) + [1, 0])
-        D.run(u0, w.gamma, w.cfl, 1, form=form, tune=ng)
+        D.run(u0, w.gamma, w.cfl, 1, form=form, tune=ng, chain=True)
         a.record()
-        D.run(u0, w.gamma, w.cfl, nsteps, form=form, tune=ng)
+        D.run(u0, w.gamma, w.cfl, nsteps, form=form, tune=ng, chain=True)
         b.record()
         b.synchronize()
         out[f]["ms_per_step_without_sibling_groups"] = round(a.elapsed_time(b) / nsteps, 4)
@@ -285,11 +286,11 @@ def time_deep_amr(forms, nsteps, api, inputs, autotune=None):
     if "fp64" in forms:
         tune = out["fp64"]["tune"]
         DL = api.DeviceTree(w.ijkl, w.bc, ghost=api.L.RG_GHOST_LINEAR)
-        DL.run(u0, w.gamma, w.cfl, 1, form=api.RG_FP64, tune=tune)
+        DL.run(u0, w.gamma, w.cfl, 1, form=api.RG_FP64, tune=tune, chain=True)
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
-        DL.run(u0, w.gamma, w.cfl, nsteps, form=api.RG_FP64, tune=tune)
+        DL.run(u0, w.gamma, w.cfl, nsteps, form=api.RG_FP64, tune=tune, chain=True)
         b.record()
         b.synchronize()
         ms = a.elapsed_time(b) / nsteps

@@ -79,7 +79,7 @@ __global__ void k_batch_dt_init(double *dt, int ntree)
     if (t < ntree) reinterpret_cast<unsigned long long *>(dt)[t] = 0x7ff0000000000000ull;
 }
 
-// cells [first, first+count) of one tree; one atomicMin per item
+// cells [first, first+count) of one tree; one fold of the minimum per item
 __global__ __launch_bounds__(kT) void k_batch_dt(const BTree *__restrict__ trees, const Item *__restrict__ items,
                                                   int64_t nitems, int parity, double *dt)
 {
@@ -116,9 +116,7 @@ __global__ __launch_bounds__(kT) void k_batch_dt(const BTree *__restrict__ trees
         if (threadIdx.x == 0) {
             double m = s_min[0];
             for (int k = 1; k < kT / 64; ++k) m = s_min[k] < m ? s_min[k] : m;
-            if (m < __longlong_as_double(0x7ff0000000000000ll))
-                atomicMin(reinterpret_cast<unsigned long long *>(dt + I.tree),
-                          static_cast<unsigned long long>(__double_as_longlong(m)));
+            fold_min(reinterpret_cast<unsigned long long *>(dt + I.tree), m);
         }
         __syncthreads();
     }
@@ -311,9 +309,7 @@ __global__ __launch_bounds__(kT) void k_batch_corr_dt(const BTree *__restrict__ 
         if (threadIdx.x == 0) {
             double m = s_min[0];
             for (int k = 1; k < kT / 64; ++k) m = s_min[k] < m ? s_min[k] : m;
-            if (m < __longlong_as_double(0x7ff0000000000000ll))
-                atomicMin(reinterpret_cast<unsigned long long *>(dt_next + I.tree),
-                          static_cast<unsigned long long>(__double_as_longlong(m)));
+            fold_min(reinterpret_cast<unsigned long long *>(dt_next + I.tree), m);
         }
         __syncthreads();
     }

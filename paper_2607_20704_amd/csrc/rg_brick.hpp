@@ -513,8 +513,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
         if (tid == 0) {
             double m = S.red[0];
             for (int k = 1; k < BT / 64; ++k) m = S.red[k] < m ? S.red[k] : m;
-            if (m < __longlong_as_double(0x7ff0000000000000ll))
-                atomicMin(a.dt_next, static_cast<unsigned long long>(__double_as_longlong(m)));
+            fold_min(a.dt_next, m);
         }
     }
 }

@@ -98,9 +98,7 @@ __global__ __launch_bounds__(256) void k_cfl_dt(DtArgs a)
     if (threadIdx.x == 0) {
         double m = s_min[0];
         for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = s_min[k] < m ? s_min[k] : m;
-        // positive doubles order like their bit patterns; NaN never wins
-        if (m < __longlong_as_double(0x7ff0000000000000ll))
-            atomicMin(a.dt_bits, static_cast<unsigned long long>(__double_as_longlong(m)));
+        fold_min(a.dt_bits, m);
     }
 }
 
@@ -161,8 +159,7 @@ __global__ __launch_bounds__(256) void k_cfl_dt_corrected(DtArgs a, const int32_
     if (threadIdx.x == 0) {
         double m = s_min[0];
         for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = s_min[k] < m ? s_min[k] : m;
-        if (m < __longlong_as_double(0x7ff0000000000000ll))
-            atomicMin(a.dt_bits, static_cast<unsigned long long>(__double_as_longlong(m)));
+        fold_min(a.dt_bits, m);
     }
 }
 

@@ -37,6 +37,19 @@ rg_status launch_status(const char *what);
 
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Folds a limit m into *p, the bits of a positive double (+inf at first):
+// positive doubles order like their bit patterns, so a 64-bit atomic minimum
+// gives the exact minimum in any order.  The stored value is read first and
+// the atomic skipped when m cannot lower it -- the value only decreases, so a
+// stale read is never below it -- which spares one atomic per workgroup on a
+// single address.  m = +inf or NaN folds nothing.
+__device__ __forceinline__ void fold_min(unsigned long long *p, double m)
+{
+    if (!(m < __longlong_as_double(0x7ff0000000000000ll))) return;
+    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(m));
+    if (b < *reinterpret_cast<volatile unsigned long long *>(p)) atomicMin(p, b);
+}
+
 inline bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
 inline unsigned grid_for(int64_t items, int threads)

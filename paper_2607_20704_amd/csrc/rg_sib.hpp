@@ -29,6 +29,12 @@ struct SibTables {
     int8_t wpos[kSibW][3];   // group-relative positions -2..5 (own cells first: x + 4y + 16z)
     int8_t wsib[kSibW];      // sibling (x + 2y + 4z of its place in the group) whose tile holds the cell
     int16_t tile2w[512];     // (x+2) + 8(y+2) + 64(z+2) -> index into wpos, -1 if unused
+    // the same, packed so that a thread reads one word per item:
+    // stencil cell: (x+2) | (y+2) << 3 | (z+2) << 6 | sibling << 9
+    uint32_t wcode[kSibW];
+    // reconstructed cell: its neighbours' indices x-, x+, y-, y+, z-, z+
+    // (9 bits each), then x+2, y+2, z+2 (3 bits each) from bit 54
+    uint64_t rcode[kSibR];
 };
 
 constexpr int sib_tile(int x, int y, int z) { return (x + 2) + 8 * (y + 2) + 64 * (z + 2); }
@@ -77,6 +83,19 @@ constexpr SibTables make_sib_tables()
             p[v] = (q >> 3) & 1 ? 4 : -1;
             sib_add(t, n, p[0], p[1], p[2]);
         }
+    for (int i = 0; i < kSibW; ++i)
+        t.wcode[i] = static_cast<uint32_t>((t.wpos[i][0] + 2) | (t.wpos[i][1] + 2) << 3 | (t.wpos[i][2] + 2) << 6 |
+                                           t.wsib[i] << 9);
+    for (int i = 0; i < kSibR; ++i) {
+        const int x = t.wpos[i][0], y = t.wpos[i][1], z = t.wpos[i][2];
+        const int nb[6] = {t.tile2w[sib_tile(x - 1, y, z)], t.tile2w[sib_tile(x + 1, y, z)],
+                           t.tile2w[sib_tile(x, y - 1, z)], t.tile2w[sib_tile(x, y + 1, z)],
+                           t.tile2w[sib_tile(x, y, z - 1)], t.tile2w[sib_tile(x, y, z + 1)]};
+        uint64_t c = 0;
+        for (int k = 0; k < 6; ++k) c |= static_cast<uint64_t>(nb[k]) << (9 * k);
+        c |= static_cast<uint64_t>(x + 2) << 54 | static_cast<uint64_t>(y + 2) << 57 | static_cast<uint64_t>(z + 2) << 60;
+        t.rcode[i] = c;
+    }
     return t;
 }
 
@@ -165,9 +184,10 @@ __device__ __forceinline__ void hydro_sib(const LevelArgs &a, const int32_t *__r
 
     // A: gather uold for the stencil cells, primitive variables
     for (int it = tid; it < kSibW; it += NT) {
-        const int sib = c_sib.wsib[it];
-        int c[3] = {c_sib.wpos[it][0] - 2 * (sib & 1), c_sib.wpos[it][1] - 2 * ((sib >> 1) & 1),
-                    c_sib.wpos[it][2] - 2 * (sib >> 2)};
+        const uint32_t code = c_sib.wcode[it];
+        const int sib = static_cast<int>(code >> 9);
+        int c[3] = {static_cast<int>(code & 7) - 2 - 2 * (sib & 1), static_cast<int>((code >> 3) & 7) - 2 - 2 * ((sib >> 1) & 1),
+                    static_cast<int>((code >> 6) & 7) - 2 - 2 * (sib >> 2)};
         int s[3] = {slot_of(c[0]), slot_of(c[1]), slot_of(c[2])};
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
@@ -205,12 +225,12 @@ __device__ __forceinline__ void hydro_sib(const LevelArgs &a, const int32_t *__r
 
     // B: slopes, predictor and face states of the own and face-layer cells
     for (int it = tid; it < kSibR; it += NT) {
-        const int x = c_sib.wpos[it][0], y = c_sib.wpos[it][1], z = c_sib.wpos[it][2];
+        const uint64_t code = c_sib.rcode[it];
+        const int x = static_cast<int>((code >> 54) & 7) - 2, y = static_cast<int>((code >> 57) & 7) - 2,
+                  z = static_cast<int>((code >> 60) & 7) - 2;
         R dW[3][NV], Wp[NV];
-        reconstruct<R>(S.w[it], S.w[c_sib.tile2w[sib_tile(x - 1, y, z)]], S.w[c_sib.tile2w[sib_tile(x + 1, y, z)]],
-                       S.w[c_sib.tile2w[sib_tile(x, y - 1, z)]], S.w[c_sib.tile2w[sib_tile(x, y + 1, z)]],
-                       S.w[c_sib.tile2w[sib_tile(x, y, z - 1)]], S.w[c_sib.tile2w[sib_tile(x, y, z + 1)]], h, gam,
-                       dW, Wp);
+        reconstruct<R>(S.w[it], S.w[code & 511], S.w[(code >> 9) & 511], S.w[(code >> 18) & 511],
+                       S.w[(code >> 27) & 511], S.w[(code >> 36) & 511], S.w[(code >> 45) & 511], h, gam, dW, Wp);
         const int p[3] = {x, y, z};
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {

@@ -20,6 +20,12 @@ struct StencilTables {
     int8_t wpos[80][3];    // cells whose primitive variables are needed
     int8_t rpos[32][3];    // cells that are reconstructed (8 own + 24 face layer)
     int8_t tile2w[216];    // (x+2) + 6(y+2) + 36(z+2) -> index into wpos, -1 if unused
+    // packed so that a thread reads one word per item: stencil cell
+    // (x+2) | (y+2) << 3 | (z+2) << 6; reconstructed cell: the indices of
+    // itself and of its neighbours x-, x+, y-, y+, z-, z+ (7 bits each), then
+    // x+2, y+2, z+2 (3 bits each) from bit 49
+    uint16_t wcode[80];
+    uint64_t rcode[32];
 };
 
 constexpr int tile_index(int x, int y, int z) { return (x + 2) + 6 * (y + 2) + 36 * (z + 2); }
@@ -70,6 +76,19 @@ constexpr StencilTables make_tables()
             t.tile2w[tile_index(p[0], p[1], p[2])] = static_cast<int8_t>(nw);
             ++nw;
         }
+    for (int i = 0; i < 80; ++i)
+        t.wcode[i] = static_cast<uint16_t>((t.wpos[i][0] + 2) | (t.wpos[i][1] + 2) << 3 | (t.wpos[i][2] + 2) << 6);
+    for (int i = 0; i < 32; ++i) {
+        const int x = t.rpos[i][0], y = t.rpos[i][1], z = t.rpos[i][2];
+        const int nb[7] = {t.tile2w[tile_index(x, y, z)],     t.tile2w[tile_index(x - 1, y, z)],
+                           t.tile2w[tile_index(x + 1, y, z)], t.tile2w[tile_index(x, y - 1, z)],
+                           t.tile2w[tile_index(x, y + 1, z)], t.tile2w[tile_index(x, y, z - 1)],
+                           t.tile2w[tile_index(x, y, z + 1)]};
+        uint64_t c = 0;
+        for (int k = 0; k < 7; ++k) c |= static_cast<uint64_t>(nb[k]) << (7 * k);
+        c |= static_cast<uint64_t>(x + 2) << 49 | static_cast<uint64_t>(y + 2) << 52 | static_cast<uint64_t>(z + 2) << 55;
+        t.rcode[i] = c;
+    }
     return t;
 }
 
@@ -209,7 +228,8 @@ __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, i
     for (int it = tid; it < G * 80; it += NT) {
         int g = it / 80, wc = it - 80 * g;
         if (g >= count) continue;
-        int c[3] = {c_tab.wpos[wc][0], c_tab.wpos[wc][1], c_tab.wpos[wc][2]};
+        const int code = c_tab.wcode[wc];
+        int c[3] = {(code & 7) - 2, ((code >> 3) & 7) - 2, ((code >> 6) & 7) - 2};
         int s[3] = {slot_of(c[0]), slot_of(c[1]), slot_of(c[2])};
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
@@ -251,12 +271,13 @@ __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, i
     for (int it = tid; it < G * 32; it += NT) {
         int g = it / 32, rc = it - 32 * g;
         if (g >= count) continue;
-        const int x = c_tab.rpos[rc][0], y = c_tab.rpos[rc][1], z = c_tab.rpos[rc][2];
-        const R *w0 = S.w[g][c_tab.tile2w[tile_index(x, y, z)]];
+        const uint64_t code = c_tab.rcode[rc];
+        const int x = static_cast<int>((code >> 49) & 7) - 2, y = static_cast<int>((code >> 52) & 7) - 2,
+                  z = static_cast<int>((code >> 55) & 7) - 2;
+        const R *w0 = S.w[g][code & 127];
         R dW[3][NV], Wp[NV];
-        reconstruct<R>(w0, S.w[g][c_tab.tile2w[tile_index(x - 1, y, z)]], S.w[g][c_tab.tile2w[tile_index(x + 1, y, z)]],
-                       S.w[g][c_tab.tile2w[tile_index(x, y - 1, z)]], S.w[g][c_tab.tile2w[tile_index(x, y + 1, z)]],
-                       S.w[g][c_tab.tile2w[tile_index(x, y, z - 1)]], S.w[g][c_tab.tile2w[tile_index(x, y, z + 1)]], h,
+        reconstruct<R>(w0, S.w[g][(code >> 7) & 127], S.w[g][(code >> 14) & 127], S.w[g][(code >> 21) & 127],
+                       S.w[g][(code >> 28) & 127], S.w[g][(code >> 35) & 127], S.w[g][(code >> 42) & 127], h,
                        gam, dW, Wp);
         const int p[3] = {x, y, z};
 #pragma unroll

@@ -44,6 +44,12 @@
  * - father_cell[o]: global id of the level-(l-1) cell that oct o refines,
  *   -1 on the coarsest level.  son_mask[o]: bit c set iff cell c of oct o has
  *   a child oct (32-bit word per oct, low 8 bits used).
+ * - Empty inputs: a call given a zero count or an empty oct range does
+ *   nothing and returns RG_OK, and its device pointers may then be null.
+ *   Exceptions: rg_hash_build with n = 0 still writes an empty table (its
+ *   workspace must be valid; every lookup then returns -1), rg_level_ranges
+ *   with n = 0 writes zeros, and rg_cfl_dt over levels that hold no octs
+ *   writes +inf (its pointers must still be valid).
  */
 #ifndef RG_H
 #define RG_H

@@ -95,7 +95,8 @@ def level_ranges(sorted_keys):
 def permute_rows(x, perm):
     out = torch.empty_like(x)
     rows = perm.shape[0]
-    check(L.lib().rg_permute_rows(_ptr(x), _ptr(perm), rows, x.numel() // max(rows, 1), _ptr(out), _stream()))
+    row_doubles = x.numel() // rows if rows else 1   # a row is everything of one permuted item
+    check(L.lib().rg_permute_rows(_ptr(x), _ptr(perm), rows, row_doubles, _ptr(out), _stream()))
     return out
 
 

@@ -178,3 +178,59 @@ def test_hash_build_probe_runs_leave_their_segment():
     ws2 = api.hash_build(torch.as_tensor(dup.view(np.int64)).cuda().view(torch.uint64))
     st, bad = api.check_ws(ws2)
     assert st == L.RG_EDUPKEY and bad in (first, n)
+
+
+def test_empty_inputs():
+    """Zero counts and empty oct ranges return RG_OK and write nothing; an
+    empty hash table answers -1; the time step over no octs is +inf."""
+    from paper_2607_20704_amd import api
+    say("empty inputs")
+    ijkl = torch.empty((0, 4), dtype=torch.int32, device="cuda")
+    keys = api.encode_keys(ijkl)
+    assert keys.shape == (0,)
+    assert api.decode_keys(keys).shape == (0, 4)
+    skeys, perm = api.sort_keys(keys)
+    assert skeys.shape == (0,) and perm.shape == (0,)
+    assert not api.level_ranges(skeys).cpu().numpy().any()
+    ws = api.hash_build(keys)
+    assert api.check_ws(ws) == (0, -1)
+    q = torch.as_tensor(O.keys(I.uniform_tree(2)).astype(np.int64)).cuda().view(torch.uint64)
+    assert np.all(api.hash_lookup(ws, q).cpu().numpy() == -1)
+    assert api.hash_lookup(ws, keys).shape == (0,)
+    nbr27, father, son = api.build_neighbours(ws, keys, 1, api.RG_BC_PERIODIC)
+    assert nbr27.shape == (0, 27) and father.shape == (0,) and son.shape == (0,)
+    x = torch.empty((0, 5), dtype=torch.float64, device="cuda")
+    assert api.permute_rows(x, perm).shape == (0, 5)
+    # empty oct ranges: no pointer is read, nothing is written
+    for form in (api.RG_FP64, api.RG_MIXED):
+        api.hydro_step_level(0.5, None, 1.4, None, None, None, None, 3, 3, form=form)
+    api.apply_coarse_corrections(None, None, 0, None, 5, 5)
+    api.restrict_level(None, None, 7, 7)
+    u = torch.full((16, 5), 7.0, dtype=torch.float64, device="cuda")
+    un = u.clone()
+    dt = torch.full((1,), 0.25, dtype=torch.float64, device="cuda")
+    nb = torch.zeros((2, 27), dtype=torch.int32, device="cuda")
+    sm = torch.zeros(2, dtype=torch.int32, device="cuda")
+    api.hydro_step_level(0.5, dt, 1.4, u, un, nb, sm, 1, 1, cfl=0.8, dt_next=dt)
+    torch.cuda.synchronize()
+    assert torch.equal(un, u) and dt.item() == 0.25
+    # the time step over levels that hold no octs
+    d = api.cfl_dt(u, sm, np.zeros(api.RG_MAX_LEVEL + 2, np.int64), 1, 3, 1.4, 0.8)
+    assert d.item() == float("inf")
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 8, 9])
+def test_hash_tiny_tables(n):
+    """Tables below one segment (capacity 16 and 32): every key found at its
+    index, absent keys answer -1."""
+    from paper_2607_20704_amd import api
+    from paper_2607_20704_amd import _lib as L
+    hk = O.keys(I.uniform_tree(3)).astype(np.int64)
+    say("hash: %d keys" % n)
+    sel = hk[np.random.default_rng(n).permutation(len(hk))[:n]]
+    keys = torch.as_tensor(sel).cuda().view(torch.uint64)
+    ws = api.hash_build(keys)
+    assert api.check_ws(ws) == (L.RG_OK, -1)
+    assert np.array_equal(api.hash_lookup(ws, keys).cpu().numpy(), np.arange(n))
+    rest = torch.as_tensor(np.setdiff1d(hk, sel)).cuda().view(torch.uint64)
+    assert np.all(api.hash_lookup(ws, rest).cpu().numpy() == -1)

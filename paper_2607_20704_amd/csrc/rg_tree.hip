@@ -127,6 +127,7 @@ struct SegBuild {
 
 // keys per bucketing workgroup
 constexpr int kBucketChunk = 4096;
+constexpr int kBucketThreads = 1024;   // per chunk: four keys per thread
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -180,7 +181,7 @@ size_t seg_build_bytes(int64_t n, uint64_t cap)
 }
 
 // per chunk of kBucketChunk keys: how many fall in each segment
-__global__ __launch_bounds__(256) void k_bucket_count(const uint64_t *__restrict__ keys, int64_t n, uint64_t mask,
+__global__ __launch_bounds__(kBucketThreads) void k_bucket_count(const uint64_t *__restrict__ keys, int64_t n, uint64_t mask,
                                                       int seg_log, int64_t nseg, uint32_t *__restrict__ hist,
                                                       HashHeader *hdr, uint64_t cap, uint32_t *ovf_count)
 {
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(1024) void k_bucket_scan_tot(const uint32_t *__rest
 }
 
 // key indices into their segment's range (order inside a segment is free)
-__global__ __launch_bounds__(256) void k_bucket_scatter(const uint64_t *__restrict__ keys, int64_t n, uint64_t mask,
+__global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(const uint64_t *__restrict__ keys, int64_t n, uint64_t mask,
                                                         int seg_log, int64_t nseg, const uint32_t *__restrict__ hist,
                                                         const uint32_t *__restrict__ seg_begin,
                                                         uint32_t *__restrict__ idx)
@@ -538,7 +539,7 @@ rg_status rg_hash_build(const uint64_t *d_keys, int64_t n, void *d_ws, size_t ws
     const size_t cnt_bytes = static_cast<size_t>(b.nseg) * sizeof(uint32_t);
     RG_REQUIRE(cnt_bytes <= 64 * 1024, "table too large for the bucketed build (%lld segments)", (long long)b.nseg);
     const unsigned nblk = static_cast<unsigned>(b.nblk);
-    k_bucket_count<<<nblk, 256, cnt_bytes, s>>>(d_keys, n, h.mask, b.seg_log, b.nseg, b.hist, h.hdr, cap,
+    k_bucket_count<<<nblk, kBucketThreads, cnt_bytes, s>>>(d_keys, n, h.mask, b.seg_log, b.nseg, b.hist, h.hdr, cap,
                                                 b.ovf_count);
     RG_TRY(launch_status("rg_hash_build count"));
     k_bucket_scan_seg<<<static_cast<unsigned>(b.nseg), 256, 0, s>>>(b.hist, b.nblk, b.seg_tot);
@@ -546,7 +547,7 @@ rg_status rg_hash_build(const uint64_t *d_keys, int64_t n, void *d_ws, size_t ws
     k_bucket_scan_tot<<<1, 1024, 0, s>>>(b.seg_tot, b.nseg, b.seg_begin, b.seg_end);
     RG_TRY(launch_status("rg_hash_build bounds"));
     if (n > 0) {
-        k_bucket_scatter<<<nblk, 256, cnt_bytes, s>>>(d_keys, n, h.mask, b.seg_log, b.nseg, b.hist, b.seg_begin,
+        k_bucket_scatter<<<nblk, kBucketThreads, cnt_bytes, s>>>(d_keys, n, h.mask, b.seg_log, b.nseg, b.hist, b.seg_begin,
                                                       b.idx);
         RG_TRY(launch_status("rg_hash_build scatter"));
     }

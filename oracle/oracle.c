@@ -36,6 +36,18 @@
  * Every floating-point expression is written in the exact order in which it
  * is evaluated (build with -ffp-contract=off, no fast-math).
  *
+ * The same source builds serially and with OpenMP (-fopenmp).  Only loops
+ * whose iterations write disjoint data run in parallel: the per-oct update
+ * of a level (each oct writes its own cells and correction slots, from a
+ * thread-local tile) and the CFL minimum (each thread's minimum, then the
+ * minimum of those: the minimum is exact, so the order does not matter).
+ * The coarse-fine corrections and the restriction stay serial.  Both builds
+ * therefore give the same bits.
+ *
+ * Floor counters: every activation of the density or pressure floor, in the
+ * primitive variables and in the face states, is counted (orc_floor_counts)
+ * so that a run can show whether the floors ever acted.
+ *
  * Parity status: the per-cell values of this particular second-order scheme
  * are pinned only through exact properties and reference solutions
  * (uniform-state preservation, conservation, mirror symmetry, HLLC
@@ -50,6 +62,12 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* per-thread scratch of the per-oct update (one copy per OpenMP thread) */
+#define ORC_TLS __thread
 
 #define ORC_RHO_MIN 1e-10
 #define ORC_P_MIN 1e-20
@@ -61,6 +79,39 @@ enum { ORC_OK = 0, ORC_EINVAL = 1, ORC_EFULL = 2, ORC_EUNGRADED = 4 };
 enum { ORC_PERIODIC = 0, ORC_OUTFLOW = 1 };
 
 int64_t orc_abi_version(void) { return 1; }
+
+/* threads the parallel loops use (1 in the serial build) */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* floor activations: [0] density floor of a primitive state, [1] pressure
+ * floor of a primitive state, [2] density floor of a face state, [3]
+ * pressure floor of a face state */
+static int64_t g_floor_count[4];
+
+static void count_floor(int k)
+{
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+    g_floor_count[k] += 1;
+}
+
+void orc_floor_counts(int64_t *out)
+{
+    for (int k = 0; k < 4; ++k) out[k] = g_floor_count[k];
+}
+
+void orc_floor_reset(void)
+{
+    for (int k = 0; k < 4; ++k) g_floor_count[k] = 0;
+}
 
 /* ------------------------------------------------------------------------ */
 /* Hilbert index, Skilling (2004): axes -> transposed index -> interleave.   */
@@ -280,6 +331,7 @@ int orc_neighbours(int64_t n, const int32_t *ijkl, int bc, int32_t *nbr27,
  * the floor). */
 void orc_prim(const double *U, double gamma, double *W)
 {
+    if (!(U[0] >= ORC_RHO_MIN)) count_floor(0);
     double rho = fmax(U[0], ORC_RHO_MIN);
     double inv = 1.0 / rho;
     double u = U[1] * inv;
@@ -287,7 +339,9 @@ void orc_prim(const double *U, double gamma, double *W)
     double w = U[3] * inv;
     double q = (u * u + v * v) + w * w;
     double ek = 0.5 * rho * q;
-    double p = fmax((gamma - 1.0) * (U[4] - ek), ORC_P_MIN);
+    double p0 = (gamma - 1.0) * (U[4] - ek);
+    if (!(p0 >= ORC_P_MIN)) count_floor(1);
+    double p = fmax(p0, ORC_P_MIN);
     W[0] = rho; W[1] = u; W[2] = v; W[3] = w; W[4] = p;
 }
 
@@ -470,23 +524,26 @@ void orc_oct_tile(int64_t n, const int32_t *ijkl, const int32_t *nbr27, const ui
                   int64_t o, double *tile)
 {
     orc_tree t = {n, ijkl, nbr27, NULL, son_mask};
-    static int split[6][6][6];
+    static ORC_TLS int split[6][6][6];
     build_tile(&t, o, u, (double(*)[6][6][5])tile, split);
 }
 
 /* Update the 8 cells of oct o from uold into unew, and record, for each of
  * the oct's six sides that borders a coarse ghost, the flux it sends to that
  * coarse cell (corr[30*o + 5*side + var], side = 2*axis + (high ? 1 : 0)). */
+/* if set, hydro_oct copies its face states here (test access) */
+static ORC_TLS double *g_face_out = NULL;
+
 static void hydro_oct(const orc_tree *t, int64_t o, const double *uold, double *unew,
                       double *corr, double dx, double dt, double gamma)
 {
-    static double U[6][6][6][5], W[6][6][6][5];
-    static int split[6][6][6];
+    static ORC_TLS double U[6][6][6][5], W[6][6][6][5];
+    static ORC_TLS int split[6][6][6];
     /* face states: S[axis][side][x][y][z][var], side 0 = low face, 1 = high */
-    static double S[3][2][6][6][6][5];
+    static ORC_TLS double S[3][2][6][6][6][5];
     /* fluxes G on faces normal to `axis`, indexed by the cell on their high
      * side: Gf[axis][x][y][z] is the face between (x,y,z)-e_axis and (x,y,z) */
-    static double Gf[3][6][6][6][5];
+    static ORC_TLS double Gf[3][6][6][6][5];
     const int32_t *nb = t->nbr27 + 27 * o;
 
     /* 1. the tile */
@@ -517,10 +574,13 @@ static void hydro_oct(const orc_tree *t, int64_t o, const double *uold, double *
                         double *st = S[a][side][TI(z)][TI(y)][TI(x)];
                         for (int v = 0; v < 5; ++v)
                             st[v] = side ? (Wp[v] + 0.5 * dW[a][v]) : (Wp[v] - 0.5 * dW[a][v]);
+                        if (!(st[0] >= ORC_RHO_MIN)) count_floor(2);
+                        if (!(st[4] >= ORC_P_MIN)) count_floor(3);
                         st[0] = fmax(st[0], ORC_RHO_MIN);
                         st[4] = fmax(st[4], ORC_P_MIN);
                     }
             }
+    if (g_face_out) memcpy(g_face_out, S, sizeof(S));
 
     /* 4. fluxes on the faces of the oct's cells: faces normal to axis a at
      *    positions between c-1 and c for c in 0..2 along a, 0..1 across */
@@ -592,17 +652,30 @@ double orc_cfl_dt(int64_t n, const int32_t *ijkl, const uint8_t *son_mask, const
                   double gamma, double cfl)
 {
     double best = INFINITY;
-    for (int64_t o = 0; o < n; ++o) {
-        double dx = level_dx(ijkl[4 * o + 3]);
-        for (int c = 0; c < 8; ++c) {
-            if ((son_mask[o] >> c) & 1) continue;
-            double W[5];
-            orc_prim(u + 5 * (8 * o + c), gamma, W);
-            double cs = sqrt((gamma * W[4]) / W[0]);
-            double sp = ((fabs(W[1]) + fabs(W[2])) + fabs(W[3])) + 3.0 * cs;
-            double d = dx / sp;
-            if (d < best) best = d;
+#ifdef _OPENMP
+#pragma omp parallel
+#endif
+    {
+        double mine = INFINITY;
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+        for (int64_t o = 0; o < n; ++o) {
+            double dx = level_dx(ijkl[4 * o + 3]);
+            for (int c = 0; c < 8; ++c) {
+                if ((son_mask[o] >> c) & 1) continue;
+                double W[5];
+                orc_prim(u + 5 * (8 * o + c), gamma, W);
+                double cs = sqrt((gamma * W[4]) / W[0]);
+                double sp = ((fabs(W[1]) + fabs(W[2])) + fabs(W[3])) + 3.0 * cs;
+                double d = dx / sp;
+                if (d < mine) mine = d;
+            }
         }
+#ifdef _OPENMP
+#pragma omp critical(orc_min)
+#endif
+        if (mine < best) best = mine;
     }
     return cfl * best;
 }
@@ -615,7 +688,27 @@ void orc_hydro_octs(int64_t n, const int32_t *ijkl, const int32_t *nbr27, const 
                     double dt, double gamma)
 {
     orc_tree t = {n, ijkl, nbr27, NULL, son_mask};
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
     for (int64_t o = ob; o < oe; ++o) hydro_oct(&t, o, uold, unew, corr, level_dx(ijkl[4 * o + 3]), dt, gamma);
+}
+
+/* The face states of oct o's update with time step dt (test access):
+ * out[axis][side][z][y][x][var] over tile coordinates -2..3 (only the inner
+ * 4x4x4 is written), side 0 = low face of the cell, 1 = high face. */
+void orc_oct_face_states(int64_t n, const int32_t *ijkl, const int32_t *nbr27, const uint8_t *son_mask,
+                         const double *u, int64_t o, double dt, double gamma, double *out)
+{
+    orc_tree t = {n, ijkl, nbr27, NULL, son_mask};
+    double *unew = (double *)malloc((size_t)(40 * n) * sizeof(double));
+    double *corr = (double *)calloc((size_t)(30 * n), sizeof(double));
+    memset(out, 0, sizeof(double) * 3 * 2 * 216 * 5);
+    g_face_out = out;
+    hydro_oct(&t, o, u, unew, corr, level_dx(ijkl[4 * o + 3]), dt, gamma);
+    g_face_out = NULL;
+    free(unew);
+    free(corr);
 }
 
 /* One step with a global dt (no subcycling):
@@ -636,6 +729,9 @@ static double step_with(int64_t n, const int32_t *ijkl, const int32_t *nbr27, co
         if (l > lmax) lmax = l;
     }
     orc_tree t = {n, ijkl, nbr27, father_cell, son_mask};
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
     for (int64_t o = 0; o < n; ++o) hydro_oct(&t, o, u, unew, corr, level_dx(ijkl[4 * o + 3]), dt, gamma);
 
     for (int side = 0; side < 6; ++side) {
@@ -728,6 +824,9 @@ typedef struct {
 static void advance_level(sub_ctx *c, int l, double dt)
 {
     const int64_t ob = c->lbeg[l], oe = c->lbeg[l + 1];
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
     for (int64_t o = ob; o < oe; ++o) hydro_oct(&c->t, o, c->uold, c->unew, c->corr, level_dx(l), dt, c->gamma);
     if (l == c->lmax) return;
     const int64_t fb = c->lbeg[l + 1], fe = c->lbeg[l + 2];

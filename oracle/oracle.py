@@ -19,33 +19,67 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_LIB_OMP_PATH = os.path.join(_HERE, "liboracle_omp.so")
 
 OUTSIDE = -(2 ** 31)
 PERIODIC, OUTFLOW = 0, 1
 OK, EUNGRADED = 0, 4
 
 
-def build(force=True):
-    """Compile oracle.c with gcc: serial, -O2, no FMA contraction, no fast-math."""
-    if not force and os.path.exists(_LIB_PATH):
-        return _LIB_PATH
-    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-           "-o", tmp, _SRC, "-lm"]
+def _compile(out, extra):
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"] + extra + \
+          ["-o", tmp, _SRC, "-lm"]
     subprocess.check_call(cmd)
-    os.replace(tmp, _LIB_PATH)
+    os.replace(tmp, out)
+
+
+def build(force=True):
+    """Compile oracle.c with gcc, -O2, no FMA contraction, no fast-math:
+    liboracle.so (serial) and liboracle_omp.so (the same source with OpenMP
+    over the octs of a level; same bits)."""
+    if force or not os.path.exists(_LIB_PATH):
+        _compile(_LIB_PATH, [])
+    if force or not os.path.exists(_LIB_OMP_PATH):
+        _compile(_LIB_OMP_PATH, ["-fopenmp"])
     return _LIB_PATH
 
 
-_lib = None
+_libs = {}
+_threads = False
+
+
+def use_threads(enable):
+    """Route the calls of this module to the OpenMP build (True) or the
+    serial one (False); returns the previous setting."""
+    global _threads
+    prev = _threads
+    _threads = bool(enable)
+    return prev
+
+
+class threads:
+    """Context manager: the OpenMP build inside the block."""
+
+    def __init__(self, enable=True):
+        self.enable = enable
+
+    def __enter__(self):
+        self.prev = use_threads(self.enable)
+        return self
+
+    def __exit__(self, *exc):
+        use_threads(self.prev)
+        return False
 
 
 def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-            build()
-        L = ctypes.CDLL(_LIB_PATH)
+    key = _threads
+    if key not in _libs:
+        path = _LIB_OMP_PATH if key else _LIB_PATH
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+            _compile(path, ["-fopenmp"] if key else [])
+        L = ctypes.CDLL(path)
         P = ctypes.c_void_p
         i64, i32, f64, u32 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_uint32
         L.orc_hilbert.restype = ctypes.c_uint64
@@ -96,8 +130,33 @@ def lib():
         L.orc_refine.argtypes = [i64, P, P, P, ctypes.c_int, f64, f64, ctypes.c_int, ctypes.c_int, P, P, i64, P, P, P]
         L.orc_step_subcycled.restype = f64
         L.orc_step_subcycled.argtypes = [i64, P, P, P, P, P, f64, f64]
-        _lib = L
-    return _lib
+        L.orc_oct_face_states.restype = None
+        L.orc_oct_face_states.argtypes = [i64, P, P, P, P, i64, f64, f64, P]
+        L.orc_threads.restype = ctypes.c_int
+        L.orc_threads.argtypes = []
+        L.orc_floor_counts.restype = None
+        L.orc_floor_counts.argtypes = [P]
+        L.orc_floor_reset.restype = None
+        L.orc_floor_reset.argtypes = []
+        _libs[key] = L
+    return _libs[key]
+
+
+def nthreads():
+    """Threads the active build's parallel loops use (1 when serial)."""
+    return int(lib().orc_threads())
+
+
+def floor_counts():
+    """Floor activations since the last floor_reset(): (primitive density,
+    primitive pressure, face-state density, face-state pressure)."""
+    out = np.zeros(4, dtype=np.int64)
+    lib().orc_floor_counts(_p(out))
+    return tuple(int(v) for v in out)
+
+
+def floor_reset():
+    lib().orc_floor_reset()
 
 
 def _p(a):
@@ -289,6 +348,16 @@ class Tree:
         m = m.value
         self.last_crit = crit
         return flags, new_ijkl[:m].copy(), new_u[:8 * m].copy()
+
+    def face_states(self, u, o, dt, gamma):
+        """Face states of oct o's update with time step dt:
+        [axis][side][z][y][x][var] over tile coordinates -2..3 (the inner
+        4^3 written; side 0 the cell's low face, 1 its high face)."""
+        set_ghost_mode(self.ghost)
+        out = np.zeros((3, 2, 6, 6, 6, 5))
+        lib().orc_oct_face_states(self.n, _p(self.ijkl), _p(self.nbr27), _p(self.son_mask), _p(_c(u, np.float64)),
+                                  int(o), float(dt), float(gamma), _p(out))
+        return out
 
     def tile(self, u, o):
         """The 6x6x6 tile of oct o, [z][y][x][var] for tile coordinates -2..3."""

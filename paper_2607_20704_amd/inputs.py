@@ -498,3 +498,26 @@ def deep_amr(base=7, lmax=12, nclump=2000, seed=20705, sigma_a=None, nsteps=10, 
     u = fill_split_cells(ijkl, u)
     return Workload("deep_amr_l%d_l%d" % (base, lmax), ijkl, u, gam, 0.8, PERIODIC, nsteps,
                     {"sigma_a": sig, "nclump": nclump, "seed": seed, "mean_rho": mean})
+
+
+def floor_stress(seed=20711, level_base=3, lmax=5, bc=OUTFLOW):
+    """A state that drives every density and pressure floor: a refined
+    outflow box expanding from its centre (velocity 6 (x - 1/2), density 1)
+    at a near-vacuum pressure of 1e-6, with 20 cells emptied (density,
+    momentum 0, energy 2.5e-6) and 20 cells whose energy is cut to 0.3 of its
+    value, below their kinetic energy; gamma 1.4."""
+    t = sphere_tree(level_base, lmax, (0.4, 0.55, 0.5), 0.22, bc)
+    cen, _ = cell_centres(t)
+    cen = cen.reshape(-1, 3)
+    d = cen - 0.5
+    rho = np.ones(len(cen))
+    vel = 6.0 * d
+    u = conserved(rho, vel[:, 0], vel[:, 1], vel[:, 2], np.full(len(cen), 1e-6), 1.4).reshape(-1, 5)
+    rng = np.random.default_rng(seed)
+    empty = rng.choice(len(u), 20, replace=False)
+    u[empty, 0:4] = 0.0
+    u[empty, 4] = 2.5e-6
+    cut = rng.choice(len(u), 20, replace=False)
+    u[cut, 4] = 0.3 * u[cut, 4]
+    u = fill_split_cells(t, u)
+    return Workload("floor_stress", t, u, 1.4, 0.8, bc, 5, {"seed": seed})

@@ -16,8 +16,19 @@
  * - Every call returns an rg_status.  Calls never abort, throw or print.  On
  *   an argument error nothing is enqueued and the outputs are untouched.
  *   rg_last_error_detail() returns a thread-local text for the last failure.
- * - Errors found on the device (duplicate key, ungraded tree, full table)
- *   are recorded in the hash workspace header and reported by rg_check().
+ * - Errors found on the device (duplicate key, ungraded tree, full table,
+ *   non-finite state, a flux owed to a coarse cell with no buffer) are
+ *   recorded in the hash workspace header of the tree the call works on
+ *   (rg_step, rg_step_subcycled, rg_batch_*; rg_hash_build and the
+ *   neighbour build) and reported by rg_check(d_ws).  Calls given no
+ *   workspace (rg_hydro_step_level, rg_cfl_dt, rg_cfl_dt_corrected outside
+ *   a step) record them in the library's own error word on the current
+ *   device, reported and cleared by rg_check(NULL).
+ * - Non-finite states: every CFL reduction also watches the cells it reads
+ *   for a NaN or infinite density, energy or signal speed |u|+|v|+|w|+3c.
+ *   On one it writes the time step 0 -- no finite state gives 0 and no later
+ *   limit can raise it, so later updates change no finite cell -- and
+ *   records RG_ENONFINITE.
  * - Results are deterministic: identical inputs give identical bits.  There
  *   are no floating-point atomics on the update path.
  *
@@ -61,7 +72,7 @@
 extern "C" {
 #endif
 
-#define RG_ABI_VERSION 9
+#define RG_ABI_VERSION 10
 #define RG_MAX_LEVEL 21
 #define RG_NBR_OUTSIDE INT32_MIN
 #define RG_RHO_MIN 1e-10
@@ -73,7 +84,7 @@ typedef enum rg_status {
     RG_EFULL = 2,        /* hash workspace too small for the keys */
     RG_EDUPKEY = 3,      /* a key was inserted twice */
     RG_EUNGRADED = 4,    /* a missing neighbour has no coarse cell under it */
-    RG_ENONFINITE = 5,   /* reserved: non-finite state detected */
+    RG_ENONFINITE = 5,   /* a NaN or infinite state met by a time-step reduction */
     RG_EHIP = 6,         /* a HIP runtime call failed (text in the detail) */
     RG_ENOTSUP = 7       /* unsupported device or configuration */
 } rg_status;
@@ -173,7 +184,9 @@ rg_status rg_hash_lookup(const void *d_ws, const uint64_t *d_q, int64_t m, int32
 
 /* Synchronises `stream` and returns the first device-side error recorded in
  * the workspace since the last rg_hash_build (RG_OK if none); *h_bad_index
- * receives the offending key or oct index (or -1). */
+ * receives the offending key or oct index (or -1).  With d_ws NULL it
+ * returns, and clears, the library's own error word of the current device
+ * (errors of calls that were given no workspace). */
 rg_status rg_check(const void *d_ws, int64_t *h_bad_index, void *stream);
 
 /* FNV-1a-64 of the 8 little-endian bytes of `key`, computed on the host with
@@ -270,7 +283,9 @@ size_t rg_corr_workspace_bytes(int64_t n_octs);
  *     +/- (1/8) ((G00 + G10) + (G01 + G11)), into
  *     d_corr[30 * (o - corr_base) + 5 * side + var] (side = 2 * axis +
  *     high); d_corr may be NULL only if no oct in the range has a coarse
- *     neighbour;
+ *     neighbour: an oct that has one is reported as RG_EINVAL (index: the
+ *     oct) in the error word (rg_check(NULL), or the tree's workspace
+ *     inside rg_step), its owed fluxes being lost;
  *   - if d_dt_next is not NULL (device double, set to +inf by the caller
  *     before the first level of a step), folds into it with a 64-bit
  *     atomicMin the CFL limit cfl dx / (|u|+|v|+|w|+3c) of the new state of
@@ -297,7 +312,9 @@ rg_status rg_apply_coarse_corrections(double *d_unew, const double *d_corr, int6
                                       const int32_t *d_nbr27, int64_t oct_begin, int64_t oct_end, void *stream);
 
 /* Upload (Table 1 "hydro - upload"): for octs [oct_begin, oct_end) of one
- * level, u[father_cell[o]] = 0.125 * (((c0+c1)+(c2+c3))+((c4+c5)+(c6+c7))). */
+ * level, u[father_cell[o]] = 0.125 * (((c0+c1)+(c2+c3))+((c4+c5)+(c6+c7))).
+ * Octs without a father cell (father_cell -1: the coarsest level) are
+ * skipped. */
 rg_status rg_restrict_level(double *d_u, const int32_t *d_father_cell, int64_t oct_begin, int64_t oct_end,
                             void *stream);
 

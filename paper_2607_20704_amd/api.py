@@ -410,9 +410,11 @@ class DeviceTree:
     def capture_subcycled(self, u, gamma, cfl, nsteps=1, form=RG_FP64, tune=None):
         """A captured HIP graph of `nsteps` subcycled coarse steps advancing
         u in place (for trees small enough that launching the level
-        recursion costs more than the work).  Returns (graph, dts); each
-        graph.replay() runs the steps and writes dts[s] (coarse step s's
-        time steps).  The tree must not change while the graph is used."""
+        recursion costs more than the work).  Returns a CapturedSteps that
+        owns the graph together with every buffer the graph reads or writes
+        (u, the scratch state, the flux accumulator, dts); each replay() runs
+        the steps and writes dts[s] (coarse step s's time steps).  The tree
+        must not change while the graph is used."""
         nlev = self.lmax - self.lmin + 2
         dts = torch.empty((nsteps, nlev), dtype=torch.float64, device="cuda")
         scratch = torch.empty_like(u)
@@ -425,8 +427,7 @@ class DeviceTree:
             for k in range(nsteps):
                 self.step_subcycled(u, gamma, cfl, form, False, dts[k], tune, scratch)
         torch.cuda.current_stream().wait_stream(side)
-        self._graph_buffers = (scratch,)
-        return g, dts
+        return CapturedSteps(g, dts, (u, scratch, getattr(self, "acc", None), self))
 
     def run_subcycled(self, u, gamma, cfl, nsteps, form=RG_FP64, rebuild=False, tune=None):
         """nsteps coarse subcycled steps on a copy of u; returns (state, dts)
@@ -439,6 +440,20 @@ class DeviceTree:
 
 
 # ---------------------------------------------------------------- multigrid
+
+class CapturedSteps:
+    """A captured graph and the device buffers it uses: the buffers live as
+    long as this object, so a replay never writes memory the allocator has
+    handed out again."""
+
+    def __init__(self, graph, dts, buffers):
+        self.graph = graph
+        self.dts = dts
+        self._buffers = buffers
+
+    def replay(self):
+        self.graph.replay()
+
 
 class Multigrid:
     """Multigrid Poisson V-cycles (rg_mg_vcycles) on a periodic unigrid of

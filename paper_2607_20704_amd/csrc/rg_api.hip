@@ -7,6 +7,7 @@
 // restriction from the finest level down.
 #include <cstdarg>
 #include <cstring>
+#include <mutex>
 
 #include "rg_internal.hpp"
 
@@ -33,6 +34,68 @@ rg_status launch_status(const char *what)
 {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(RG_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return RG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// device-side error sink of calls that have no hash workspace
+// ---------------------------------------------------------------------------
+
+namespace {
+// one per device; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device
+__device__ HashHeader g_err_sink;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_sink_mu;
+HashHeader *g_sink_addr[kMaxDevices] = {};
+thread_local HashHeader *tl_sink = nullptr;
+}  // namespace
+
+HashHeader *err_sink()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_sink_mu);
+    if (!g_sink_addr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_err_sink)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_sink_addr[dev] = static_cast<HashHeader *>(p);
+    }
+    return g_sink_addr[dev];
+}
+
+HashHeader *current_sink() { return tl_sink ? tl_sink : err_sink(); }
+
+SinkScope::SinkScope(void *d_hash_ws) : prev(tl_sink)
+{
+    if (d_hash_ws) tl_sink = static_cast<HashHeader *>(d_hash_ws);
+}
+
+SinkScope::~SinkScope() { tl_sink = prev; }
+
+// reads and clears the library's own error word (rg_check with no workspace)
+rg_status check_sink(int64_t *h_bad_index, hipStream_t s)
+{
+    HashHeader *d = err_sink();
+    if (!d) return fail(RG_EHIP, "rg_check: no error word on this device");
+    HashHeader h;
+    hipError_t e = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(RG_EHIP, "rg_check: %s", hipGetErrorString(e));
+    if (h.err) {
+        HashHeader z;
+        memset(&z, 0, sizeof(z));
+        e = hipMemcpyAsync(d, &z, sizeof(z), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return fail(RG_EHIP, "rg_check: %s", hipGetErrorString(e));
+    }
+    if (h_bad_index) *h_bad_index = h.err ? h.bad : -1;
+    if (h.err) return fail(static_cast<rg_status>(h.err), "device reported %s at index %lld",
+                           rg_status_string(h.err), static_cast<long long>(h.bad));
     return RG_OK;
 }
 
@@ -113,6 +176,7 @@ rg_status rg_step(const rg_tree *t, const double *d_uold, double *d_unew, double
     RG_REQUIRE(gamma > 1 && cfl > 0, "bad gamma or cfl");
     RG_REQUIRE(t->ghost == RG_GHOST_INJECT || t->ghost == RG_GHOST_LINEAR, "bad ghost mode %d", t->ghost);
     hipStream_t s = as_stream(stream);
+    const SinkScope sink(t->d_hash_ws);
     const unsigned prep = flags & (RG_STEP_REBUILD | RG_STEP_REKEY);
     if (prep) RG_TRY(rg_prepare_tree(t, prep, stream));
     const bool chain = (flags & RG_STEP_CHAIN_DT) != 0;

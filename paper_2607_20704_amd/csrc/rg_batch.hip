@@ -90,6 +90,7 @@ __global__ __launch_bounds__(kT) void k_batch_dt(const BTree *__restrict__ trees
         const BTree &T = trees[I.tree];
         const double *u = T.u[parity];
         double best = __longlong_as_double(0x7ff0000000000000ll);
+        double nf = 0.0;
         for (int64_t cell = I.first + threadIdx.x; cell < I.first + I.count; cell += kT) {
             const int64_t o = cell >> 3;
             const int c = static_cast<int>(cell & 7);
@@ -105,7 +106,9 @@ __global__ __launch_bounds__(kT) void k_batch_dt(const BTree *__restrict__ trees
             const double sp = ((fabs(W[1]) + fabs(W[2])) + fabs(W[3])) + 3.0 * cs;
             const double cd = T.cfl * (dx / sp);
             if (cd < best) best = cd;
+            track_finite(nf, sp, U);
         }
+        best = nonfinite_limit(best, nf);
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
             double o = __shfl_xor(best, off, 64);
@@ -116,7 +119,7 @@ __global__ __launch_bounds__(kT) void k_batch_dt(const BTree *__restrict__ trees
         if (threadIdx.x == 0) {
             double m = s_min[0];
             for (int k = 1; k < kT / 64; ++k) m = s_min[k] < m ? s_min[k] : m;
-            fold_min(reinterpret_cast<unsigned long long *>(dt + I.tree), m);
+            fold_min(reinterpret_cast<unsigned long long *>(dt + I.tree), m, T.hdr);
         }
         __syncthreads();
     }
@@ -167,6 +170,7 @@ __global__ __launch_bounds__(BT, sizeof(R) == 8 ? 2 : 4) void k_batch_bricks(con
         a.outflow = T.bc == RG_BC_OUTFLOW;
         a.cfl = T.cfl;
         a.dt_next = reinterpret_cast<unsigned long long *>(dt_next + I.tree);
+        a.hdr = T.hdr;
         brick_body<R, sizeof(R) == 8>(a, T.list[I.first], I.first, S);
         __syncthreads();
     }
@@ -203,6 +207,7 @@ __global__ __launch_bounds__(kT) void k_batch_octs(const BTree *__restrict__ tre
         a.gamma = T.gamma;
         a.cfl = T.cfl;
         a.dt_next = reinterpret_cast<unsigned long long *>(dt_next + I.tree);
+        a.hdr = T.hdr;
         hydro_group<R, G, kT, GH>(a, I.first, static_cast<int>(I.count), S);
         __syncthreads();
     }
@@ -239,6 +244,7 @@ __global__ __launch_bounds__(kT) void k_batch_groups(const BTree *__restrict__ t
         a.gamma = T.gamma;
         a.cfl = T.cfl;
         a.dt_next = reinterpret_cast<unsigned long long *>(dt_next + I.tree);
+        a.hdr = T.hdr;
         hydro_sib<R, kT, GH>(a, T.father, T.list[I.first], S);
         __syncthreads();
     }
@@ -278,6 +284,7 @@ __global__ __launch_bounds__(kT) void k_batch_corr_dt(const BTree *__restrict__ 
         const BTree &T = trees[I.tree];
         const double *u = T.u[parity ^ 1];
         double best = __longlong_as_double(0x7ff0000000000000ll);
+        double nf = 0.0;
         for (int64_t k = threadIdx.x; k < I.count * 6; k += kT) {
             const int64_t o = I.first + k / 6;
             const int side = static_cast<int>(k % 6);
@@ -298,7 +305,9 @@ __global__ __launch_bounds__(kT) void k_batch_corr_dt(const BTree *__restrict__ 
             const double sp = ((fabs(W[1]) + fabs(W[2])) + fabs(W[3])) + 3.0 * cs;
             const double cd = T.cfl * (dx / sp);
             if (cd < best) best = cd;
+            track_finite(nf, sp, U);
         }
+        best = nonfinite_limit(best, nf);
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
             double o = __shfl_xor(best, off, 64);
@@ -309,7 +318,7 @@ __global__ __launch_bounds__(kT) void k_batch_corr_dt(const BTree *__restrict__ 
         if (threadIdx.x == 0) {
             double m = s_min[0];
             for (int k = 1; k < kT / 64; ++k) m = s_min[k] < m ? s_min[k] : m;
-            fold_min(reinterpret_cast<unsigned long long *>(dt_next + I.tree), m);
+            fold_min(reinterpret_cast<unsigned long long *>(dt_next + I.tree), m, T.hdr);
         }
         __syncthreads();
     }

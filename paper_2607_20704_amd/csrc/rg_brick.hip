@@ -69,6 +69,7 @@ rg_status hydro_bricks(const double *uold, double *unew, const int32_t *nbr27, c
     a.outflow = outflow;
     a.cfl = cfl;
     a.dt_next = reinterpret_cast<unsigned long long *>(dt_next);
+    a.hdr = current_sink();
     const unsigned grid = static_cast<unsigned>(8 * ((nbricks + 7) / 8));
     if (form == RG_FP64) {
         if (waves == 0 || waves == 2)

@@ -31,6 +31,7 @@ struct BrickArgs {
     int outflow;               // clamp positions outside the domain (zero gradient)
     double cfl;
     unsigned long long *dt_next;   // if set: CFL limit of the new state folded in (bits of a positive double)
+    HashHeader *hdr;               // device-side errors (non-finite state)
 };
 
 // Face states, written by the reconstruction; each is read by exactly one
@@ -75,6 +76,7 @@ template <typename R, int NB = 1> struct BrickSmem {
     R hw[3][4 * BC][NV];            // primitive variables of the reconstructed ghost ring, planes r-1, r, r+1
     uint8_t split[NB][PW * PW];     // split flags of the current plane's cells
     double red[8];                  // block minimum of the fused CFL limit, one per wave
+    int32_t any_son;                // some slot oct in reach has a split cell
     // mixed form with one buffer: each column's partial update of the
     // previous plane (its own slot, no sharing), kept here rather than in
     // registers
@@ -93,13 +95,15 @@ __device__ __forceinline__ int slot_index(int sa, int sb, int sc) { return (sa +
 // Source of the cell at brick-relative position (x, y, z): its global cell
 // id, and whether it is a split cell.  Outside the domain (outflow) the
 // position takes the nearest cell inside (zero gradient) and counts as not
-// split; a missing same-level oct gives its coarse cell (injection).
-template <typename R, int NB>
+// split; a missing same-level oct gives its coarse cell (injection).  GEN =
+// false: the brick has no split cell in reach and no position outside the
+// domain (checked once per brick), so neither is looked at.
+template <bool GEN, typename R, int NB>
 __device__ __forceinline__ int64_t source_cell(const BrickSmem<R, NB> &S, const Geom &g, int x, int y, int z,
                                                bool &split)
 {
     bool clamped = false;
-    if (g.outflow) {
+    if (GEN && g.outflow) {
         const int gx = g.cx0 + x, gy = g.cy0 + y, gz = g.cz0 + z;
         if (gx < 0) { x = -g.cx0; clamped = true; }
         if (gx >= g.ncell) { x = g.ncell - 1 - g.cx0; clamped = true; }
@@ -111,7 +115,7 @@ __device__ __forceinline__ int64_t source_cell(const BrickSmem<R, NB> &S, const 
     const int bit = (x & 1) + 2 * (y & 1) + 4 * (z & 1);
     const int si = slot_index(x >> 1, y >> 1, z >> 1);
     int32_t e = S.slot[si];
-    split = !clamped && ((S.son[si] >> bit) & 1u);
+    split = GEN && !clamped && ((S.son[si] >> bit) & 1u);
     if (e == RG_NBR_OUTSIDE) e = S.slot[slot_index(0, 0, 0)];   // unreachable for a consistent list
     return e >= 0 ? 8 * int64_t(e) + bit : (-1 - int64_t(e));
 }
@@ -122,12 +126,14 @@ __device__ __forceinline__ void load_u(const double *__restrict__ u, int64_t cel
     for (int v = 0; v < NV; ++v) U[v] = u[NV * cell + v];
 }
 
-template <typename R> __device__ __forceinline__ void to_prim(const double *U, double gamma, R *W)
+// primitive variables in R; returns 1 / rho in double
+template <typename R> __device__ __forceinline__ double to_prim(const double *U, double gamma, R *W)
 {
     double w[NV];
-    prim64(U, gamma, w);
+    const double inv = prim64(U, gamma, w);
 #pragma unroll
     for (int v = 0; v < NV; ++v) W[v] = static_cast<R>(w[v]);
+    return inv;
 }
 
 template <typename R> __device__ __forceinline__ void copy5(R *d, const R *s)
@@ -155,13 +161,48 @@ __device__ __forceinline__ void ring_pos(int kind, int lane, int &x, int &y)
     else { x = k; y = hi; }
 }
 
-// hllc flux of one face, zeroed when it touches a split cell
-template <typename R>
+// Face fluxes in the LDS buffer: the mixed form keeps F in float; FP64
+// stores G = F dt/dx once per face (the same product both cells would form)
+template <typename R> __device__ __forceinline__ void store_flux(R *dst, const R *F, double r)
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) dst[v] = sizeof(R) == 8 ? static_cast<R>(static_cast<double>(F[v]) * r) : F[v];
+}
+
+template <typename R> __device__ __forceinline__ double flux_G(R f, double r)
+{
+    return sizeof(R) == 8 ? static_cast<double>(f) : static_cast<double>(f) * r;
+}
+
+// hllc flux of one face, zeroed when it touches a split cell (GEN only)
+template <bool GEN, typename R>
 __device__ __forceinline__ void face_F(const R *L, const R *Rt, int dir, R gamma, R g1, bool zero, R *F)
 {
     hllc<R>(L, Rt, dir, gamma, g1, F);
+    if constexpr (GEN) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) F[v] = zero ? R(0) : F[v];
+        for (int v = 0; v < NV; ++v) F[v] = zero ? R(0) : F[v];
+    }
+}
+
+// G = F dt/dx of the z face, zeroed when it touches a split cell (GEN only)
+template <bool GEN, typename R>
+__device__ __forceinline__ void face_G(const R *L, const R *Rt, R gamma, R g1, double r, bool zero, double *G)
+{
+    R F[NV];
+    hllc<R>(L, Rt, 2, gamma, g1, F);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) G[v] = (GEN && zero) ? 0.0 : static_cast<double>(F[v]) * r;
+}
+
+// signal speed |u| + |v| + |w| + 3c of a new conserved state, for the CFL
+// limit cfl dx / speed
+__device__ __forceinline__ double signal_speed(const double *U, double gamma)
+{
+    double Wn[NV];
+    prim64(U, gamma, Wn);
+    const double cs = sqrt((gamma * Wn[4]) / Wn[0]);
+    return ((fabs(Wn[1]) + fabs(Wn[2])) + fabs(Wn[3])) + 3.0 * cs;
 }
 
 // One brick (first oct `base`) by one workgroup of BT threads, each owning
@@ -175,6 +216,15 @@ __device__ __forceinline__ void face_F(const R *L, const R *Rt, int dir, R gamma
 // KU: keep each column's conserved state of the current plane in registers
 // until the update instead of reading it again (10 more registers, one
 // 40-byte read per cell less).
+//
+// GEN: the brick has a split cell within reach of its stencil, or an
+// outflow wall within two cells; otherwise (GEN = false, decided once per
+// brick) the sweep skips the split flags, the zeroed fluxes, the leaf tests
+// of the folded time step and the clamping at walls.  Both give the same
+// bits where both apply.
+template <typename R, bool KU, int NB, bool GEN>
+__device__ __forceinline__ void brick_sweep(const BrickArgs &a, int64_t b, const Geom &g, BrickSmem<R, NB> &S);
+
 template <typename R, bool KU = false, int NB = 1>
 __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int64_t b, BrickSmem<R, NB> &S)
 {
@@ -186,6 +236,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
         key_coords(a.keys[base + k], i, j, kk, l);
         S.slot[slot_index(i & 7, j & 7, kk & 7)] = static_cast<int32_t>(base + k);
     }
+    if (tid == 0) S.any_son = 0;
     Geom g;
     {
         int32_t i, j, kk, l;
@@ -211,11 +262,25 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
             const int32_t o = S.slot[slot_index(ca, cb, cc)];
             e = a.nbr27[27 * int64_t(o) + (sa - ca + 1) + 3 * (sb - cb + 1) + 9 * (sc - cc + 1)];
         }
-        S.son[s] = e >= 0 ? static_cast<uint8_t>(a.son[e]) : 0;
+        const uint8_t m = e >= 0 ? static_cast<uint8_t>(a.son[e]) : 0;
+        S.son[s] = m;
+        if (m) S.any_son = 1;
         if (out) S.slot[s] = e;
     }
     __syncthreads();
+    const bool wall = g.outflow && (g.cx0 == 0 || g.cy0 == 0 || g.cz0 == 0 || g.cx0 + BC == g.ncell ||
+                                    g.cy0 + BC == g.ncell || g.cz0 + BC == g.ncell);
+    const bool gen = S.any_son != 0 || wall;
+    if (gen)
+        brick_sweep<R, KU, NB, true>(a, b, g, S);
+    else
+        brick_sweep<R, KU, NB, false>(a, b, g, S);
+}
 
+template <typename R, bool KU, int NB, bool GEN>
+__device__ __forceinline__ void brick_sweep(const BrickArgs &a, int64_t b, const Geom &g, BrickSmem<R, NB> &S)
+{
+    const int tid = threadIdx.x;
     const double r = *a.dt / a.dx;
     const R h = static_cast<R>(0.5 * r);
     const R gam = static_cast<R>(a.gamma);
@@ -243,20 +308,25 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
     // of plane rz-1 decide whether the cell written next is a leaf that no
     // coarse-fine correction will change
     bool sp_prev2 = false, nxy_prev = false, nxy_cur = false;
-    double dt_min = __longlong_as_double(0x7ff0000000000000ll);
+    // fused CFL limit: cfl dx / max speed equals the minimum of cfl dx /
+    // speed over the cells, bit for bit (both roundings are monotone), so
+    // only the largest signal speed is kept
+    double sp_max = 0.0;
+    double nfs = 0.0;   // non-finite tracking of the folded limits
+    double inv0 = 0.0;  // FP64: 1 / rho of the own column's plane rz (the predictor's)
     {
         double U[NV];
         bool sdummy;
         sp_cur = false;
         {
-            load_u(a.uold, source_cell(S, g, x, y, -2, sdummy), U);
+            load_u(a.uold, source_cell<GEN>(S, g, x, y, -2, sdummy), U);
             to_prim(U, a.gamma, Wm);
-            load_u(a.uold, source_cell(S, g, x, y, -1, sp_cur), U);
-            to_prim(U, a.gamma, W0);
+            load_u(a.uold, source_cell<GEN>(S, g, x, y, -1, sp_cur), U);
+            inv0 = to_prim(U, a.gamma, W0);
             if constexpr (KU) copy5(Uc, U);
         }
         if (do_face) {
-            load_u(a.uold, source_cell(S, g, hx, hy, -1, sdummy), U);
+            load_u(a.uold, source_cell<GEN>(S, g, hx, hy, -1, sdummy), U);
             R Wh[NV];
             to_prim(U, a.gamma, Wh);
             copy5(S.hw[2][lane], Wh);
@@ -275,8 +345,8 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
     double Upf[NV];
     if constexpr (PF) {
         bool sdummy;
-        if (do_face) load_u(a.uold, source_cell(S, g, hx, hy, 0, sdummy), Upf);
-        if (ring_role) load_u(a.uold, source_cell(S, g, rx, ry, 0, sdummy), Upf);
+        if (do_face) load_u(a.uold, source_cell<GEN>(S, g, hx, hy, 0, sdummy), Upf);
+        if (ring_role) load_u(a.uold, source_cell<GEN>(S, g, rx, ry, 0, sdummy), Upf);
     }
     // DB (NB = 2): planes alternate between two face buffers and split-flag
     // planes, so the fluxes of plane rz are read -- and plane rz is updated --
@@ -305,7 +375,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
         uint8_t *spl = S.split[fb];
         double Un[NV];                               // conserved variables of plane rz+1, own column
         sp_next = false;
-        load_u(a.uold, source_cell(S, g, x, y, rz + 1, sp_next), Un);
+        load_u(a.uold, source_cell<GEN>(S, g, x, y, rz + 1, sp_next), Un);
         // 1. the reconstructed ghost ring: primitive variables of plane rz+1
         bool hsplit = false;
         if (do_face) {
@@ -314,34 +384,34 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
                 bool sdummy;
                 if constexpr (PF) {
                     to_prim(Upf, a.gamma, Wh);
-                    if (rz + 2 <= BC) load_u(a.uold, source_cell(S, g, hx, hy, rz + 2, sdummy), Upf);
+                    if (rz + 2 <= BC) load_u(a.uold, source_cell<GEN>(S, g, hx, hy, rz + 2, sdummy), Upf);
                 } else {
                     double U[NV];
-                    load_u(a.uold, source_cell(S, g, hx, hy, rz + 1, sdummy), U);
+                    load_u(a.uold, source_cell<GEN>(S, g, hx, hy, rz + 1, sdummy), U);
                     to_prim(U, a.gamma, Wh);
                 }
                 copy5(S.hw[(rz + 4) % 3][lane], Wh);
             }
-            (void)source_cell(S, g, hx, hy, rz, hsplit);
+            (void)source_cell<GEN>(S, g, hx, hy, rz, hsplit);
         }
         // 2. plane rz into LDS: W and split flags
         {
             copy5(S.w[(x + 2) + PW * (y + 2)], W0);
-            spl[(x + 2) + PW * (y + 2)] = sp_cur;
+            if constexpr (GEN) spl[(x + 2) + PW * (y + 2)] = sp_cur;
         }
         if (do_face) {
             copy5(S.w[(hx + 2) + PW * (hy + 2)], S.hw[(rz + 3) % 3][lane]);
-            spl[(hx + 2) + PW * (hy + 2)] = hsplit;
+            if constexpr (GEN) spl[(hx + 2) + PW * (hy + 2)] = hsplit;
         }
         if (ring_role && inner) {
             R Wr[NV];
             bool sdummy;
             if constexpr (PF) {
                 to_prim(Upf, a.gamma, Wr);
-                if (rz + 1 < BC) load_u(a.uold, source_cell(S, g, rx, ry, rz + 1, sdummy), Upf);
+                if (rz + 1 < BC) load_u(a.uold, source_cell<GEN>(S, g, rx, ry, rz + 1, sdummy), Upf);
             } else {
                 double U[NV];
-                load_u(a.uold, source_cell(S, g, rx, ry, rz, sdummy), U);
+                load_u(a.uold, source_cell<GEN>(S, g, rx, ry, rz, sdummy), U);
                 to_prim(U, a.gamma, Wr);
             }
             copy5(S.w[(rx + 2) + PW * (ry + 2)], Wr);
@@ -362,12 +432,16 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
         }
         R sxm[NV], sym[NV];
         double gz[NV];
+        double invp;
         {
-            to_prim(Un, a.gamma, Wp);
+            invp = to_prim(Un, a.gamma, Wp);
             R dW[3][NV], Wq[NV], st[NV], szm[NV];
             const int c = (x + 2) + PW * (y + 2);
-            nxy_cur = spl[c - 1] || spl[c + 1] || spl[c - PW] || spl[c + PW];
-            reconstruct<R>(W0, S.w[c - 1], S.w[c + 1], S.w[c - PW], S.w[c + PW], Wm, Wp, h, gam, dW, Wq);
+            nxy_cur = GEN && (spl[c - 1] || spl[c + 1] || spl[c - PW] || spl[c + PW]);
+            if constexpr (sizeof(R) == 8)
+                reconstruct<R>(W0, S.w[c - 1], S.w[c + 1], S.w[c - PW], S.w[c + PW], Wm, Wp, h, gam, R(inv0), dW, Wq);
+            else
+                reconstruct<R>(W0, S.w[c - 1], S.w[c + 1], S.w[c - PW], S.w[c + PW], Wm, Wp, h, gam, dW, Wq);
             if (inner) {
                 face_state<R>(Wq, dW[0], true, st);
                 copy5(FB.st.sxp[x + 1][y], st);
@@ -377,7 +451,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
                 face_state<R>(Wq, dW[1], false, sym);
             }
             face_state<R>(Wq, dW[2], false, szm);
-            if (rz >= 0) face_flux<R>(zp_prev, szm, 2, gam, g1, r, sp_prev || sp_cur, gz);
+            if (rz >= 0) face_G<GEN, R>(zp_prev, szm, gam, g1, r, sp_prev || sp_cur, gz);
             face_state<R>(Wq, dW[2], true, zp_prev);
         }
         // DB: plane rz-1 is complete: its x/y fluxes have been in the other
@@ -391,28 +465,25 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
                     copy5(Ucur, Ucp);
                 } else {
                     bool sdummy;
-                    load_u(a.uold, source_cell(S, g, x, y, rz - 1, sdummy), Ucur);
+                    load_u(a.uold, source_cell<GEN>(S, g, x, y, rz - 1, sdummy), Ucur);
                 }
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
-                    const double gxm = static_cast<double>(PB.fl.fx[x][y][v]) * r;
-                    const double gxp = static_cast<double>(PB.fl.fx[x + 1][y][v]) * r;
-                    const double gym = static_cast<double>(PB.fl.fy[y][x][v]) * r;
-                    const double gyp = static_cast<double>(PB.fl.fy[y + 1][x][v]) * r;
+                    const double gxm = flux_G(PB.fl.fx[x][y][v], r);
+                    const double gxp = flux_G(PB.fl.fx[x + 1][y][v], r);
+                    const double gym = flux_G(PB.fl.fy[y][x][v], r);
+                    const double gyp = flux_G(PB.fl.fy[y + 1][x][v], r);
                     const double acc = (Ucur[v] + (gxm - gxp)) + (gym - gyp);
                     out[v] = acc + (gz_prev[v] - gz[v]);
                 }
                 bool sdummy;
-                const int64_t cell = source_cell(S, g, x, y, rz - 1, sdummy);
+                const int64_t cell = source_cell<GEN>(S, g, x, y, rz - 1, sdummy);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) a.unew[NV * cell + v] = out[v];
                 if (a.dt_next && !sp_prev && !(nxy_prev || sp_prev2 || sp_cur)) {
-                    double Wn[NV];
-                    prim64(out, a.gamma, Wn);
-                    const double cs = sqrt((a.gamma * Wn[4]) / Wn[0]);
-                    const double sp = ((fabs(Wn[1]) + fabs(Wn[2])) + fabs(Wn[3])) + 3.0 * cs;
-                    const double cd = a.cfl * (a.dx / sp);
-                    dt_min = cd < dt_min ? cd : dt_min;
+                    const double sp = signal_speed(out, a.gamma);
+                    sp_max = sp > sp_max ? sp : sp_max;
+                    track_finite(nfs, sp, out);
                 }
             }
         }
@@ -424,20 +495,20 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
         if (inner) {
             R F[NV];
             {
-                face_F<R>(FB.st.sxp[x][y], sxm, 0, gam, g1, spl[(x + 1) + PW * (y + 2)] || sp_cur, F);
-                copy5(FB.fl.fx[x][y], F);
-                face_F<R>(FB.st.syp[y][x], sym, 1, gam, g1, spl[(x + 2) + PW * (y + 1)] || sp_cur, F);
-                copy5(FB.fl.fy[y][x], F);
+                face_F<GEN, R>(FB.st.sxp[x][y], sxm, 0, gam, g1, GEN && (spl[(x + 1) + PW * (y + 2)] || sp_cur), F);
+                store_flux(FB.fl.fx[x][y], F, r);
+                face_F<GEN, R>(FB.st.syp[y][x], sym, 1, gam, g1, GEN && (spl[(x + 2) + PW * (y + 1)] || sp_cur), F);
+                store_flux(FB.fl.fy[y][x], F, r);
             }
             if (extra_faces) {
                 if (lane < BC) {
-                    const bool z2 = spl[(BC + 1) + PW * (hk + 2)] || spl[(BC + 2) + PW * (hk + 2)];
-                    face_F<R>(FB.st.sxp[BC][hk], FB.st.sxm_hi[hk], 0, gam, g1, z2, F);
-                    copy5(FB.fl.fx[BC][hk], F);
+                    const bool z2 = GEN && (spl[(BC + 1) + PW * (hk + 2)] || spl[(BC + 2) + PW * (hk + 2)]);
+                    face_F<GEN, R>(FB.st.sxp[BC][hk], FB.st.sxm_hi[hk], 0, gam, g1, z2, F);
+                    store_flux(FB.fl.fx[BC][hk], F, r);
                 } else {
-                    const bool z2 = spl[(hk + 2) + PW * (BC + 1)] || spl[(hk + 2) + PW * (BC + 2)];
-                    face_F<R>(FB.st.syp[BC][hk], FB.st.sym_hi[hk], 1, gam, g1, z2, F);
-                    copy5(FB.fl.fy[BC][hk], F);
+                    const bool z2 = GEN && (spl[(hk + 2) + PW * (BC + 1)] || spl[(hk + 2) + PW * (BC + 2)]);
+                    face_F<GEN, R>(FB.st.syp[BC][hk], FB.st.sym_hi[hk], 1, gam, g1, z2, F);
+                    store_flux(FB.fl.fy[BC][hk], F, r);
                 }
             }
         }
@@ -451,16 +522,13 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
             for (int v = 0; v < NV; ++v)
                 out[v] = (ACC_LDS ? S.acc[ACC_LDS ? tid : 0][v] : acc_prev[v]) + (gz_prev[v] - gz[v]);
             bool sdummy;
-            const int64_t cell = source_cell(S, g, x, y, rz - 1, sdummy);
+            const int64_t cell = source_cell<GEN>(S, g, x, y, rz - 1, sdummy);
 #pragma unroll
             for (int v = 0; v < NV; ++v) a.unew[NV * cell + v] = out[v];
             if (a.dt_next && !sp_prev && !(nxy_prev || sp_prev2 || sp_cur)) {
-                double Wn[NV];
-                prim64(out, a.gamma, Wn);
-                const double cs = sqrt((a.gamma * Wn[4]) / Wn[0]);
-                const double sp = ((fabs(Wn[1]) + fabs(Wn[2])) + fabs(Wn[3])) + 3.0 * cs;
-                const double cd = a.cfl * (a.dx / sp);
-                dt_min = cd < dt_min ? cd : dt_min;
+                const double sp = signal_speed(out, a.gamma);
+                sp_max = sp > sp_max ? sp : sp_max;
+                track_finite(nfs, sp, out);
             }
         }
         if (!DB && inner) {
@@ -469,14 +537,14 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
                 copy5(Ucur, Uc);
             } else {
                 bool sdummy;
-                load_u(a.uold, source_cell(S, g, x, y, rz, sdummy), Ucur);
+                load_u(a.uold, source_cell<GEN>(S, g, x, y, rz, sdummy), Ucur);
             }
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const double gxm = static_cast<double>(FB.fl.fx[x][y][v]) * r;
-                const double gxp = static_cast<double>(FB.fl.fx[x + 1][y][v]) * r;
-                const double gym = static_cast<double>(FB.fl.fy[y][x][v]) * r;
-                const double gyp = static_cast<double>(FB.fl.fy[y + 1][x][v]) * r;
+                const double gxm = flux_G(FB.fl.fx[x][y][v], r);
+                const double gxp = flux_G(FB.fl.fx[x + 1][y][v], r);
+                const double gym = flux_G(FB.fl.fy[y][x][v], r);
+                const double gyp = flux_G(FB.fl.fy[y + 1][x][v], r);
                 const double acc = (Ucur[v] + (gxm - gxp)) + (gym - gyp);
                 if constexpr (ACC_LDS)
                     S.acc[tid][v] = acc;
@@ -492,6 +560,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
                 Wm[v] = W0[v];
                 W0[v] = Wp[v];
             }
+            inv0 = invp;
             if constexpr (KU) {
                 if constexpr (DB) copy5(Ucp, Uc);
                 copy5(Uc, Un);
@@ -503,6 +572,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
         nxy_prev = nxy_cur;
     }
     if (a.dt_next) {
+        double dt_min = nonfinite_limit(a.cfl * (a.dx / sp_max), nfs);
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
             const double o = __shfl_xor(dt_min, off, 64);
@@ -513,7 +583,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
         if (tid == 0) {
             double m = S.red[0];
             for (int k = 1; k < BT / 64; ++k) m = S.red[k] < m ? S.red[k] : m;
-            fold_min(a.dt_next, m);
+            fold_min(a.dt_next, m, a.hdr);
         }
     }
 }

@@ -56,6 +56,7 @@ struct DtArgs {
     double gamma, cfl;
     int64_t n_cell;
     unsigned long long *dt_bits;
+    HashHeader *hdr;   // device-side errors (non-finite state)
     int sub;   // subcycled: each limit scaled by 2^(l - lmin), the ratio of the coarse step to level l's
 };
 
@@ -65,6 +66,7 @@ __global__ void k_set_u64(unsigned long long *p, unsigned long long v) { *p = v;
 __global__ __launch_bounds__(256) void k_cfl_dt(DtArgs a)
 {
     double best = __longlong_as_double(0x7ff0000000000000ll);   // +inf
+    double nf = 0.0;
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     for (int64_t cell = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; cell < a.n_cell; cell += stride) {
         const int64_t o = cell >> 3;
@@ -84,7 +86,9 @@ __global__ __launch_bounds__(256) void k_cfl_dt(DtArgs a)
         // constant is monotone
         const double cd = a.cfl * d;
         if (cd < best) best = cd;
+        track_finite(nf, sp, U);
     }
+    best = nonfinite_limit(best, nf);
     // wavefront minimum, then across the block's waves, then one atomic
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -98,7 +102,7 @@ __global__ __launch_bounds__(256) void k_cfl_dt(DtArgs a)
     if (threadIdx.x == 0) {
         double m = s_min[0];
         for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = s_min[k] < m ? s_min[k] : m;
-        fold_min(a.dt_bits, m);
+        fold_min(a.dt_bits, m, a.hdr);
     }
 }
 
@@ -126,6 +130,7 @@ __global__ __launch_bounds__(256) void k_cfl_dt_corrected(DtArgs a, const int32_
                                                           int64_t oe)
 {
     double best = __longlong_as_double(0x7ff0000000000000ll);
+    double nf = 0.0;
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < (oe - ob) * 6; t += stride) {
         const int64_t o = ob + t / 6;
@@ -146,7 +151,9 @@ __global__ __launch_bounds__(256) void k_cfl_dt_corrected(DtArgs a, const int32_
         const double sp = ((fabs(W[1]) + fabs(W[2])) + fabs(W[3])) + 3.0 * cs;
         const double cd = a.cfl * (dx / sp);
         if (cd < best) best = cd;
+        track_finite(nf, sp, U);
     }
+    best = nonfinite_limit(best, nf);
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         double o = __shfl_xor(best, off, 64);
@@ -159,7 +166,7 @@ __global__ __launch_bounds__(256) void k_cfl_dt_corrected(DtArgs a, const int32_
     if (threadIdx.x == 0) {
         double m = s_min[0];
         for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = s_min[k] < m ? s_min[k] : m;
-        fold_min(a.dt_bits, m);
+        fold_min(a.dt_bits, m, a.hdr);
     }
 }
 
@@ -171,9 +178,11 @@ __global__ void k_restrict(const double *src, double *dst, const int32_t *__rest
     const int64_t o = ob + t / NV;
     const int v = static_cast<int>(t % NV);
     if (o >= oe) return;
+    const int32_t f = father[o];
+    if (f < 0) return;   // no father cell (coarsest level): nothing to restrict into
     const double *c = src + 8 * NV * o + v;
     const double sum = ((c[0] + c[5]) + (c[10] + c[15])) + ((c[20] + c[25]) + (c[30] + c[35]));
-    dst[NV * int64_t(father[o]) + v] = 0.125 * sum;
+    dst[NV * int64_t(f) + v] = 0.125 * sum;
 }
 
 // ---------------------------------------------------------------------------
@@ -247,6 +256,7 @@ LevelArgs level_args(const double *uold, double *unew, const int32_t *nbr27, con
     a.gamma = gamma;
     a.cfl = cfl;
     a.dt_next = reinterpret_cast<unsigned long long *>(dt_next);
+    a.hdr = current_sink();
     return a;
 }
 
@@ -331,6 +341,7 @@ rg_status cfl_dt_pass(const double *d_u, const uint32_t *d_son_mask, const int64
     a.n_cell = 8 * n_oct;
     a.sub = sub;
     a.dt_bits = reinterpret_cast<unsigned long long *>(d_dt);
+    a.hdr = current_sink();
     hipStream_t s = as_stream(stream);
     k_set_u64<<<1, 1, 0, s>>>(a.dt_bits, 0x7ff0000000000000ull);
     RG_TRY(launch_status("rg_cfl_dt init"));
@@ -381,6 +392,7 @@ rg_status rg_hydro_step_level(double dx, const double *d_dt, double gamma, const
     a.gamma = gamma;
     a.cfl = cfl;
     a.dt_next = reinterpret_cast<unsigned long long *>(d_dt_next);
+    a.hdr = current_sink();
     return hydro_level(a, form, tune, as_stream(stream));
 }
 
@@ -437,6 +449,7 @@ rg_status rg_cfl_dt_corrected(const double *d_u, const int32_t *d_nbr27, const i
     a.n_cell = 0;
     a.sub = 0;
     a.dt_bits = reinterpret_cast<unsigned long long *>(d_dt);
+    a.hdr = current_sink();
     const int64_t ob = h_level_begin[lmin + 1], oe = h_level_begin[lmax + 1];
     if (oe <= ob) return RG_OK;
     const unsigned blocks = grid_for((oe - ob) * 6, 256);

@@ -37,18 +37,43 @@ rg_status launch_status(const char *what);
 
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+struct HashHeader;
+__device__ inline void flag_error(HashHeader *hdr, int code, int64_t bad);
+
 // Folds a limit m into *p, the bits of a positive double (+inf at first):
 // positive doubles order like their bit patterns, so a 64-bit atomic minimum
 // gives the exact minimum in any order.  The stored value is read first and
 // the atomic skipped when m cannot lower it -- the value only decreases, so a
 // stale read is never below it -- which spares one atomic per workgroup on a
-// single address.  m = +inf or NaN folds nothing.
-__device__ __forceinline__ void fold_min(unsigned long long *p, double m)
+// single address.  m = +inf folds nothing.  A negative m marks a non-finite
+// state (see nonfinite_limit): the time step becomes 0, which no finite
+// state gives and no later fold can raise, and RG_ENONFINITE is recorded in
+// hdr (if not null).
+__device__ __forceinline__ void fold_min(unsigned long long *p, double m, HashHeader *hdr)
 {
+    if (m < 0.0) {
+        atomicMin(p, 0ull);
+        flag_error(hdr, RG_ENONFINITE, -1);
+        return;
+    }
     if (!(m < __longlong_as_double(0x7ff0000000000000ll))) return;
     const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(m));
     if (b < *reinterpret_cast<volatile unsigned long long *>(p)) atomicMin(p, b);
 }
+
+// Non-finite tracking beside a running minimum of CFL limits: nf starts at
+// 0 and takes nf + 0 * (sp + (rho + E)) for every cell, with sp its signal
+// speed; it stays 0 while every state is finite and is NaN from the first
+// NaN or infinite value on.  (The speed alone is not enough: the density
+// and pressure floors turn a NaN density or energy into the floor value.)
+__device__ __forceinline__ void track_finite(double &nf, double sp, const double *U)
+{
+    nf = __builtin_fma(sp + (U[0] + U[4]), 0.0, nf);
+}
+
+// The running minimum to reduce: -1 (the non-finite mark of fold_min) when
+// the thread met a non-finite speed
+__device__ __forceinline__ double nonfinite_limit(double best, double nf) { return nf == nf ? best : -1.0; }
 
 inline bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
@@ -305,8 +330,20 @@ inline HashView hash_view(void *ws, uint64_t cap)
 
 __device__ inline void flag_error(HashHeader *hdr, int code, int64_t bad)
 {
-    if (atomicCAS(&hdr->err, 0, code) == 0) hdr->bad = bad;
+    if (hdr && atomicCAS(&hdr->err, 0, code) == 0) hdr->bad = bad;
 }
+
+// Where device-side errors of a call go: the header of the tree's hash
+// workspace inside rg_step, rg_step_subcycled and rg_batch_create (a
+// SinkScope names it), else the library's own per-device error word,
+// which rg_check(NULL, ...) reads and clears.  Host side.
+HashHeader *err_sink();
+HashHeader *current_sink();
+struct SinkScope {
+    explicit SinkScope(void *d_hash_ws);
+    ~SinkScope();
+    HashHeader *prev;
+};
 
 __device__ inline int32_t hash_probe(const uint64_t *keys, const int32_t *vals, uint64_t mask, uint64_t key)
 {

@@ -25,8 +25,9 @@ template <> struct Math<float> {
     static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 };
 
-// conservative -> primitive in double, floors applied
-__device__ __forceinline__ void prim64(const double *U, double gamma, double *W)
+// conservative -> primitive in double, floors applied; returns 1 / rho
+// (of the floored density), which the predictor needs again
+__device__ __forceinline__ double prim64(const double *U, double gamma, double *W)
 {
     double rho = fmax(U[0], RG_RHO_MIN);
     double inv = 1.0 / rho;
@@ -41,28 +42,44 @@ __device__ __forceinline__ void prim64(const double *U, double gamma, double *W)
     W[2] = v;
     W[3] = w;
     W[4] = p;
+    return inv;
 }
 
-// zero unless a and b have the same strict sign, else the one of smaller
-// magnitude (written as copysign(min(|a|, |b|), a) under the sign test)
-template <typename R> __device__ __forceinline__ R minmod(R a, R b)
+// Minmod of two undivided differences: zero unless a and b have the same
+// strict sign, else the one of smaller magnitude.  Written as the median of
+// (a, b, 0), which is exactly that value for every finite pair (only the
+// sign of a zero result can differ): one v_med3 in float, four min/max in
+// double, and no branches or lane-mask logic.
+template <typename R> __device__ __forceinline__ R minmod(R a, R b);
+
+template <> __device__ __forceinline__ float minmod<float>(float a, float b)
 {
-    const bool same = (a > R(0) && b > R(0)) || (a < R(0) && b < R(0));
-    return same ? copysign(fmin(fabs(a), fabs(b)), a) : R(0);
+    return __builtin_amdgcn_fmed3f(a, b, 0.0f);
 }
 
-// Hancock half step W' = W - h sum_d A_d(W) dW_d (primitive Euler equations)
+template <> __device__ __forceinline__ double minmod<double>(double a, double b)
+{
+    return fmax(fmin(a, b), fmin(fmax(a, b), 0.0));
+}
+
+// Hancock half step W' = W - h sum_d A_d(W) dW_d (primitive Euler equations),
+// inv = 1 / rho
 template <typename R>
-__device__ __forceinline__ void predict(const R *W, const R (*dW)[NV], R h, R gamma, R *Wp)
+__device__ __forceinline__ void predict(const R *W, const R (*dW)[NV], R h, R gamma, R inv, R *Wp)
 {
     const R rho = W[0], u = W[1], v = W[2], w = W[3], p = W[4];
-    const R inv = Math<R>::div(R(1), rho);
     const R div = (dW[0][1] + dW[1][2]) + dW[2][3];
     Wp[0] = rho - h * (((u * dW[0][0] + v * dW[1][0]) + w * dW[2][0]) + rho * div);
     Wp[1] = u - h * (((u * dW[0][1] + v * dW[1][1]) + w * dW[2][1]) + dW[0][4] * inv);
     Wp[2] = v - h * (((u * dW[0][2] + v * dW[1][2]) + w * dW[2][2]) + dW[1][4] * inv);
     Wp[3] = w - h * (((u * dW[0][3] + v * dW[1][3]) + w * dW[2][3]) + dW[2][4] * inv);
     Wp[4] = p - h * (((u * dW[0][4] + v * dW[1][4]) + w * dW[2][4]) + (gamma * p) * div);
+}
+
+template <typename R>
+__device__ __forceinline__ void predict(const R *W, const R (*dW)[NV], R h, R gamma, R *Wp)
+{
+    predict<R>(W, dW, h, gamma, Math<R>::div(R(1), W[0]), Wp);
 }
 
 // HLLC across a face normal to axis `dir`: Davis wave speeds, contact speed
@@ -87,8 +104,21 @@ __device__ __forceinline__ void hllc(const R *WL, const R *WR, int dir, R gamma,
     const R cr = Math<R>::sqrt_(Math<R>::div(gamma * r4, r0));
     const R sl = fmin(ul - cl, ur - cr);
     const R sr = fmax(ul + cl, ur + cr);
-    const R ml = l0 * (ul - sl);
-    const R mr = r0 * (sr - ur);
+    // u_L - S_L and S_R - u_R.  In float they are formed without the
+    // cancellation of ul - sl, which in a cold flow (c below |u| / 2^24, as
+    // where the pressure floor acts) rounds both to zero and makes the
+    // division below infinite; algebraically the same values.  The double
+    // instance keeps the reference's expressions (bit-equal results).
+    R wl, wr;
+    if constexpr (sizeof(R) == 4) {
+        wl = fmax(cl, (ul - ur) + cr);
+        wr = fmax((ul - ur) + cl, cr);
+    } else {
+        wl = ul - sl;
+        wr = sr - ur;
+    }
+    const R ml = l0 * wl;
+    const R mr = r0 * wr;
     const R inv = Math<R>::div(R(1), ml + mr);
     const R sstar = ((mr * ur + ml * ul) + (l4 - r4)) * inv;
     const R pstar = ((mr * l4 + ml * r4) + ml * mr * (ul - ur)) * inv;
@@ -100,8 +130,10 @@ __device__ __forceinline__ void hllc(const R *WL, const R *WR, int dir, R gamma,
     const R s = useL ? sl : sr;
     const R E = p * g1 + R(0.5) * rho * q;
     const R d = Math<R>::div(R(1), s - sstar);
-    const R rs = outer ? rho : rho * (s - un) * d;
-    const R es = outer ? E : (((s - un) * E - p * un) + pstar * sstar) * d;
+    // s - un = -(u_L - S_L) on the left, S_R - u_R on the right
+    const R su = sizeof(R) == 4 ? (useL ? -wl : wr) : s - un;
+    const R rs = outer ? rho : rho * su * d;
+    const R es = outer ? E : ((su * E - p * un) + pstar * sstar) * d;
     const R ss = outer ? un : sstar;
     const R ps = outer ? p : pstar;
     const R m = rs * ss;
@@ -117,11 +149,10 @@ __device__ __forceinline__ void hllc(const R *WL, const R *WR, int dir, R gamma,
 
 namespace rg {
 
-// minmod slopes along x, y, z of primitive cell W0 from its six neighbours,
-// then the Hancock half step W'
+// minmod slopes along x, y, z of primitive cell W0 from its six neighbours
 template <typename R>
-__device__ __forceinline__ void reconstruct(const R *w0, const R *wxm, const R *wxp, const R *wym, const R *wyp,
-                                            const R *wzm, const R *wzp, R h, R gamma, R (*dW)[NV], R *Wp)
+__device__ __forceinline__ void slopes(const R *w0, const R *wxm, const R *wxp, const R *wym, const R *wyp,
+                                       const R *wzm, const R *wzp, R (*dW)[NV])
 {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -129,7 +160,24 @@ __device__ __forceinline__ void reconstruct(const R *w0, const R *wxm, const R *
         dW[1][v] = minmod<R>(w0[v] - wym[v], wyp[v] - w0[v]);
         dW[2][v] = minmod<R>(w0[v] - wzm[v], wzp[v] - w0[v]);
     }
+}
+
+// slopes, then the Hancock half step W'
+template <typename R>
+__device__ __forceinline__ void reconstruct(const R *w0, const R *wxm, const R *wxp, const R *wym, const R *wyp,
+                                            const R *wzm, const R *wzp, R h, R gamma, R (*dW)[NV], R *Wp)
+{
+    slopes<R>(w0, wxm, wxp, wym, wyp, wzm, wzp, dW);
     predict<R>(w0, dW, h, gamma, Wp);
+}
+
+// the same with 1 / rho of W0 given (bit-identical: the same quotient)
+template <typename R>
+__device__ __forceinline__ void reconstruct(const R *w0, const R *wxm, const R *wxp, const R *wym, const R *wyp,
+                                            const R *wzm, const R *wzp, R h, R gamma, R inv, R (*dW)[NV], R *Wp)
+{
+    slopes<R>(w0, wxm, wxp, wym, wyp, wzm, wzp, dW);
+    predict<R>(w0, dW, h, gamma, inv, Wp);
 }
 
 // face state on the high (W' + dW/2) or low (W' - dW/2) side of a cell along

@@ -124,6 +124,7 @@ struct LevelArgs {
     double gamma;
     double cfl;
     unsigned long long *dt_next;   // if set: CFL limit of the new state folded in (bits of a positive double)
+    HashHeader *hdr;      // device-side errors: non-finite state, fluxes owed to a coarse cell with no buffer
 };
 
 // Values of the fine position at sub-cell (sx, sy, sz) of coarse cell C:
@@ -346,8 +347,18 @@ __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, i
         S.u[g][cidx][v] = un;
     }
 
-    // E: flux owed to coarse neighbours
-    if (a.corr) {
+    // E: flux owed to coarse neighbours.  Without a buffer there must be
+    // none: a coarse face neighbour is then reported (its flux is lost).
+    if (!a.corr) {
+        for (int it = tid; it < G * 6; it += NT) {
+            const int g = it / 6, side = it - 6 * g;
+            if (g >= count) continue;
+            const int ax = side >> 1, hi = side & 1;
+            const int e = S.nb[g][nslot(ax == 0 ? (hi ? 1 : -1) : 0, ax == 1 ? (hi ? 1 : -1) : 0,
+                                        ax == 2 ? (hi ? 1 : -1) : 0)];
+            if (e < 0 && e != RG_NBR_OUTSIDE) flag_error(a.hdr, RG_EINVAL, S.oct[g]);
+        }
+    } else {
         for (int it = tid; it < G * 6 * NV; it += NT) {
             int g = it / (6 * NV), k = it - 6 * NV * g;
             if (g >= count) continue;
@@ -371,6 +382,7 @@ __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, i
     if (a.dt_next) {
         __syncthreads();
         double best = __longlong_as_double(0x7ff0000000000000ll);
+        double nf = 0.0;
         for (int it = tid; it < G * 8; it += NT) {
             const int g = it >> 3, cidx = it & 7;
             if (g >= count) continue;
@@ -395,7 +407,9 @@ __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, i
             const double sp = ((fabs(W[1]) + fabs(W[2])) + fabs(W[3])) + 3.0 * cs;
             const double cd = a.cfl * (a.dx / sp);
             best = cd < best ? cd : best;
+            track_finite(nf, sp, S.u[g][cidx]);
         }
+        best = nonfinite_limit(best, nf);
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
             const double o = __shfl_xor(best, off, 64);
@@ -406,7 +420,7 @@ __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, i
         if (tid == 0) {
             double m = S.red[0];
             for (int k = 1; k < NT / 64; ++k) m = S.red[k] < m ? S.red[k] : m;
-            fold_min(a.dt_next, m);
+            fold_min(a.dt_next, m, a.hdr);
         }
     }
 }

@@ -292,8 +292,17 @@ __device__ __forceinline__ void hydro_sib(const LevelArgs &a, const int32_t *__r
         S.u[own][v] = un;
     }
 
-    // E: flux owed to coarse neighbours across the group's outer faces
-    if (a.corr) {
+    // E: flux owed to coarse neighbours across the group's outer faces;
+    // without a buffer there must be none (a coarse neighbour is reported)
+    if (!a.corr) {
+        for (int it = tid; it < 8 * 6; it += NT) {
+            const int sib = it / 6, side = it - 6 * sib;
+            const int ax = side >> 1, hi = side & 1;
+            if (((sib >> ax) & 1) != hi) continue;
+            const int e = S.nb[sib][side_slot(ax, hi)];
+            if (e < 0 && e != RG_NBR_OUTSIDE) flag_error(a.hdr, RG_EINVAL, S.oct[sib]);
+        }
+    } else {
         for (int it = tid; it < 8 * 6 * NV; it += NT) {
             const int sib = it / (6 * NV), k = it - 6 * NV * sib;
             const int side = k / NV, v = k - NV * side;
@@ -318,6 +327,7 @@ __device__ __forceinline__ void hydro_sib(const LevelArgs &a, const int32_t *__r
     if (a.dt_next) {
         __syncthreads();
         double best = __longlong_as_double(0x7ff0000000000000ll);
+        double nf = 0.0;
         for (int it = tid; it < 64; it += NT) {
             const int x = it & 3, y = (it >> 2) & 3, z = it >> 4;
             const int bit0 = (x & 1) + 2 * (y & 1) + 4 * (z & 1);
@@ -340,7 +350,9 @@ __device__ __forceinline__ void hydro_sib(const LevelArgs &a, const int32_t *__r
             const double sp = ((fabs(W[1]) + fabs(W[2])) + fabs(W[3])) + 3.0 * cs;
             const double cd = a.cfl * (a.dx / sp);
             best = cd < best ? cd : best;
+            track_finite(nf, sp, S.u[it]);
         }
+        best = nonfinite_limit(best, nf);
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
             const double o = __shfl_xor(best, off, 64);
@@ -351,7 +363,7 @@ __device__ __forceinline__ void hydro_sib(const LevelArgs &a, const int32_t *__r
         if (tid == 0) {
             double m = S.red[0];
             for (int k = 1; k < NT / 64; ++k) m = S.red[k] < m ? S.red[k] : m;
-            fold_min(a.dt_next, m);
+            fold_min(a.dt_next, m, a.hdr);
         }
     }
 }

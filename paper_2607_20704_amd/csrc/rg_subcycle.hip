@@ -106,6 +106,7 @@ rg_status rg_step_subcycled(const rg_tree *t, double *d_u, double *d_scratch, do
     RG_REQUIRE(form == RG_FP64 || form == RG_MIXED, "bad form %d", form);
     RG_REQUIRE(gamma > 1 && cfl > 0, "bad gamma or cfl");
     hipStream_t s = as_stream(stream);
+    const SinkScope sink(t->d_hash_ws);
     if (flags) RG_TRY(rg_prepare_tree(t, flags, stream));
     RG_TRY(cfl_dt_pass(d_u, t->d_son_mask, t->level_begin, t->lmin, t->lmax, gamma, cfl, d_dt, 1, stream));
     k_level_dts<<<1, 64, 0, s>>>(d_dt, t->lmax - t->lmin + 1);

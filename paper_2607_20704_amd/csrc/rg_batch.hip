@@ -102,7 +102,7 @@ __global__ __launch_bounds__(kT) void k_batch_dt(const BTree *__restrict__ trees
 #pragma unroll
             for (int v = 0; v < NV; ++v) U[v] = u[NV * cell + v];
             prim64(U, T.gamma, W);
-            const double cs = sqrt((T.gamma * W[4]) / W[0]);
+            const double cs = sqrt_pos(div_pos(T.gamma * W[4], W[0]));
             const double sp = ((fabs(W[1]) + fabs(W[2])) + fabs(W[3])) + 3.0 * cs;
             const double cd = T.cfl * (dx / sp);
             if (cd < best) best = cd;
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(kT) void k_batch_corr_dt(const BTree *__restrict__ 
 #pragma unroll
             for (int v = 0; v < NV; ++v) U[v] = u[NV * C + v];
             prim64(U, T.gamma, W);
-            const double cs = sqrt((T.gamma * W[4]) / W[0]);
+            const double cs = sqrt_pos(div_pos(T.gamma * W[4], W[0]));
             const double sp = ((fabs(W[1]) + fabs(W[2])) + fabs(W[3])) + 3.0 * cs;
             const double cd = T.cfl * (dx / sp);
             if (cd < best) best = cd;

@@ -201,7 +201,7 @@ __device__ __forceinline__ double signal_speed(const double *U, double gamma)
 {
     double Wn[NV];
     prim64(U, gamma, Wn);
-    const double cs = sqrt((gamma * Wn[4]) / Wn[0]);
+    const double cs = sqrt_pos(div_pos(gamma * Wn[4], Wn[0]));
     return ((fabs(Wn[1]) + fabs(Wn[2])) + fabs(Wn[3])) + 3.0 * cs;
 }
 

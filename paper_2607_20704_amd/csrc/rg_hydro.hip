@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void k_cfl_dt(DtArgs a)
 #pragma unroll
         for (int v = 0; v < NV; ++v) U[v] = a.u[NV * cell + v];
         prim64(U, a.gamma, W);
-        const double cs = sqrt((a.gamma * W[4]) / W[0]);
+        const double cs = sqrt_pos(div_pos(a.gamma * W[4], W[0]));
         const double sp = ((fabs(W[1]) + fabs(W[2])) + fabs(W[3])) + 3.0 * cs;
         const double d = a.sub ? ldexp(dx / sp, l - a.lmin) : dx / sp;
         // cfl * min(d) == min(cfl * d): rounding a product by a positive
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void k_cfl_dt_corrected(DtArgs a, const int32_
 #pragma unroll
         for (int v = 0; v < NV; ++v) U[v] = a.u[NV * C + v];
         prim64(U, a.gamma, W);
-        const double cs = sqrt((a.gamma * W[4]) / W[0]);
+        const double cs = sqrt_pos(div_pos(a.gamma * W[4], W[0]));
         const double sp = ((fabs(W[1]) + fabs(W[2])) + fabs(W[3])) + 3.0 * cs;
         const double cd = a.cfl * (dx / sp);
         if (cd < best) best = cd;

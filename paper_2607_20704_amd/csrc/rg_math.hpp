@@ -15,9 +15,53 @@ constexpr int NV = 5;
 
 template <typename R> struct Math;
 
+// Quotient and square root of positive normal doubles, correctly rounded.
+// The general IEEE sequences first rescale operands whose exponents are
+// extreme (near overflow, underflow or denormals) and afterwards patch the
+// special values (zero, infinity, NaN); the operands of this update (density
+// >= 1e-10, pressure >= 1e-20, signal speeds and mass fluxes of physical
+// states) never need either, so only the arithmetic core is kept:
+//   a / b: reciprocal estimate refined by two Newton-Raphson steps
+//          y <- y + y (1 - b y), then q = a y and Markstein's correction
+//          q <- q + y (a - b q) (P. Markstein, IBM J. Res. Dev. 34, 1990),
+//          which with fused multiply-adds gives the correctly rounded
+//          quotient;
+//   sqrt:  reciprocal square root estimate y, then the coupled iteration of
+//          g ~ sqrt(x) and h ~ 1/(2 sqrt(x)) (Goldschmidt): r = 1/2 - h g,
+//          g <- g + g r, h <- h + h r, followed by two corrections
+//          g <- g + h (x - g g).
+// For such operands both give the same bits as a / b and sqrt(x); outside
+// that range they stay within a few units in the last place (never used
+// there).
+__device__ __forceinline__ double div_pos(double a, double b)
+{
+    double y = __builtin_amdgcn_rcp(b);
+    double e = __builtin_fma(-b, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-b, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    const double q = a * y;
+    const double rem = __builtin_fma(-b, q, a);
+    return __builtin_fma(rem, y, q);
+}
+
+__device__ __forceinline__ double sqrt_pos(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y;
+    double h = 0.5 * y;
+    const double r = __builtin_fma(-h, g, 0.5);
+    g = __builtin_fma(g, r, g);
+    h = __builtin_fma(h, r, h);
+    double d = __builtin_fma(-g, g, x);
+    g = __builtin_fma(d, h, g);
+    d = __builtin_fma(-g, g, x);
+    return __builtin_fma(d, h, g);
+}
+
 template <> struct Math<double> {
-    static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
-    static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+    static __device__ __forceinline__ double sqrt_(double x) { return sqrt_pos(x); }
+    static __device__ __forceinline__ double div(double a, double b) { return div_pos(a, b); }
 };
 
 template <> struct Math<float> {
@@ -30,7 +74,7 @@ template <> struct Math<float> {
 __device__ __forceinline__ double prim64(const double *U, double gamma, double *W)
 {
     double rho = fmax(U[0], RG_RHO_MIN);
-    double inv = 1.0 / rho;
+    double inv = div_pos(1.0, rho);
     double u = U[1] * inv;
     double v = U[2] * inv;
     double w = U[3] * inv;

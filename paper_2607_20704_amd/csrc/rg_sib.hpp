@@ -346,7 +346,7 @@ __device__ __forceinline__ void hydro_sib(const LevelArgs &a, const int32_t *__r
             if (touch) continue;
             double W[NV];
             prim64(S.u[it], a.gamma, W);
-            const double cs = sqrt((a.gamma * W[4]) / W[0]);
+            const double cs = sqrt_pos(div_pos(a.gamma * W[4], W[0]));
             const double sp = ((fabs(W[1]) + fabs(W[2])) + fabs(W[3])) + 3.0 * cs;
             const double cd = a.cfl * (a.dx / sp);
             best = cd < best ? cd : best;

@@ -394,7 +394,7 @@ def time_dynamic(api, inputs):
     for _ in range(2):
         D.step_subcycled(u, w.gamma, w.cfl)
     _, eager_ms = wall(lambda: [D.step_subcycled(u, w.gamma, w.cfl) for _ in range(nrep)])
-    g, _ = D.capture_subcycled(u, w.gamma, w.cfl)
+    g = D.capture_subcycled(u, w.gamma, w.cfl)
     g.replay()
     _, graph_ms = wall(lambda: [g.replay() for _ in range(nrep)])
     ups = sum(2 ** (l - D.lmin) * 8 * int(D.level_begin[l + 1] - D.level_begin[l]) for l in range(D.lmin, D.lmax + 1))

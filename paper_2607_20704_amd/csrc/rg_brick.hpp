@@ -34,34 +34,60 @@ struct BrickArgs {
     HashHeader *hdr;               // device-side errors (non-finite state)
 };
 
+// LDS holds every 5-variable quantity as five planes, one per variable
+// (structure of arrays), so that the 64 lanes of a wave, which own
+// consecutive cells of a row, read and write consecutive 8-byte words:
+// with 40-byte cell records (array of structures) lane i's word sits 10
+// dwords after lane i-1's and the accesses of a wave collide in the banks.
+constexpr int FXN = BC * (BC + 1);   // x faces: row y, face x (x = 0..16 -> faces -1|0 .. 15|16)
+constexpr int FYN = (BC + 1) * BC;   // y faces: face y (y = 0..16), column x
+
 // Face states, written by the reconstruction; each is read by exactly one
 // thread in the flux pass, which then overwrites it with the flux of that
 // face, so states and fluxes share the storage without a barrier.
-template <typename R> union BrickFaces {
-    struct {
-        R sxp[BC + 1][BC][NV];  // [x][y]: x+ state of cell x-1 (x = 0..16 -> cells -1..15)
-        R syp[BC + 1][BC][NV];  // [y][x]: y+ state of cell y-1
-        R sxm_hi[BC][NV];       // x- state of the ghost cell x = 16
-        R sym_hi[BC][NV];
-    } st;
-    struct {                    // fluxes F (zero on faces touching split cells)
-        R fx[BC + 1][BC][NV];   // [x][y]: face (x-1 | x), in place of sxp[x][y]
-        R fy[BC + 1][BC][NV];   // [y][x]: face (y-1 | y), in place of syp[y][x]
-    } fl;
-    R row[2 * (BC + 1) * BC + 2 * BC][NV];   // the face states as one list of rows (st's layout)
+//   fx[v][y * (BC + 1) + x]: face (x-1 | x) of row y: the x+ state of cell
+//     x-1, then the face's flux;
+//   fy[v][y * BC + x]: face (y-1 | y) of column x: the y+ state of cell y-1,
+//     then the flux;
+//   sxm_hi[v][y], sym_hi[v][x]: the x- / y- states of the ghost cells x = 16
+//     (row y) and y = 16 (column x).
+template <typename R> struct BrickFaces {
+    R fx[NV][FXN];
+    R fy[NV][FYN];
+    R sxm_hi[NV][BC];
+    R sym_hi[NV][BC];
 };
-static_assert(sizeof(BrickFaces<double>) == sizeof(double) * (2 * (BC + 1) * BC + 2 * BC) * NV,
-              "the row list spans the face states");
+static_assert(sizeof(BrickFaces<double>) == sizeof(double) * NV * (FXN + FYN + 2 * BC), "packed face planes");
 
-// Row of the face state that ghost-ring lane (side q, position k) writes:
-// q = 0 sxp[0][k], 1 sxm_hi[k], 2 syp[0][k], 3 sym_hi[k].  Plain arithmetic:
-// a pointer chosen per lane through branches (one pointer per side) was
-// compiled wrongly for the two-buffer layout -- the lanes of the last side
-// stored through the pointer of the third.
-__host__ __device__ __forceinline__ int ring_row(int q, int k)
+template <typename R, int N> __device__ __forceinline__ void lds_get(R *d, const R (&a)[NV][N], int i)
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) d[v] = a[v][i];
+}
+
+template <typename R, int N> __device__ __forceinline__ void lds_put(R (&a)[NV][N], int i, const R *src)
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) a[v][i] = src[v];
+}
+
+// The face state that ghost-ring lane (side q, position k) writes: q = 0 the
+// x+ state of cell x = -1 in row k (fx, face 0), 1 the x- state of ghost
+// x = 16 (sxm_hi), 2 the y+ state of cell y = -1 in column k (fy, face 0),
+// 3 the y- state of ghost y = 16 (sym_hi).  Element v sits at flat index
+// base + v * stride of the buffer, computed with plain arithmetic: a pointer
+// chosen per lane through branches (one pointer per side) was compiled
+// wrongly once (the lanes of the last side stored through the pointer of
+// the third).
+template <typename R> __device__ __forceinline__ void ring_put(BrickFaces<R> &F, int q, int k, const R *src)
 {
     const int hi = q & 1, ax = q >> 1;
-    return k + hi * (2 * (BC + 1) * BC + ax * BC) + (1 - hi) * ax * ((BC + 1) * BC);
+    const int base = (1 - hi) * ((1 - ax) * (BC + 1) * k + ax * (NV * FXN + k)) +
+                     hi * (NV * (FXN + FYN) + ax * NV * BC + k);
+    const int stride = (1 - hi) * FXN + hi * BC;
+    R *flat = &F.fx[0][0];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) flat[base + v * stride] = src[v];
 }
 
 // NB = 2: two face buffers and two split-flag planes (planes of even and odd
@@ -72,15 +98,15 @@ template <typename R, int NB = 1> struct BrickSmem {
     BrickFaces<R> u_[NB];           // face states and fluxes (NB = 2: planes of even / odd z)
     int32_t slot[HS * HS * HS];     // oct slots -1..8 around the brick: oct index inside, neighbour entry outside
     uint8_t son[HS * HS * HS];      // son mask of same-level slot octs, 0 otherwise
-    R w[PW * PW][NV];               // primitive variables of the current plane
-    R hw[3][4 * BC][NV];            // primitive variables of the reconstructed ghost ring, planes r-1, r, r+1
+    R w[NV][PW * PW];               // primitive variables of the current plane
+    R hw[3][NV][4 * BC];            // primitive variables of the reconstructed ghost ring, planes r-1, r, r+1
     uint8_t split[NB][PW * PW];     // split flags of the current plane's cells
     double red[8];                  // block minimum of the fused CFL limit, one per wave
     int32_t any_son;                // some slot oct in reach has a split cell
     // mixed form with one buffer: each column's partial update of the
     // previous plane (its own slot, no sharing), kept here rather than in
     // registers
-    double acc[(sizeof(R) == 4 && NB == 1) ? BT : 1][NV];
+    double acc[NV][(sizeof(R) == 4 && NB == 1) ? BT : 1];
 };
 
 struct Geom {
@@ -98,9 +124,8 @@ __device__ __forceinline__ int slot_index(int sa, int sb, int sc) { return (sa +
 // split; a missing same-level oct gives its coarse cell (injection).  GEN =
 // false: the brick has no split cell in reach and no position outside the
 // domain (checked once per brick), so neither is looked at.
-template <bool GEN, typename R, int NB>
-__device__ __forceinline__ int64_t source_cell(const BrickSmem<R, NB> &S, const Geom &g, int x, int y, int z,
-                                               bool &split)
+template <bool GEN, typename SM>
+__device__ __forceinline__ int64_t source_cell(const SM &S, const Geom &g, int x, int y, int z, bool &split)
 {
     bool clamped = false;
     if (GEN && g.outflow) {
@@ -163,15 +188,27 @@ __device__ __forceinline__ void ring_pos(int kind, int lane, int &x, int &y)
 
 // Face fluxes in the LDS buffer: the mixed form keeps F in float; FP64
 // stores G = F dt/dx once per face (the same product both cells would form)
-template <typename R> __device__ __forceinline__ void store_flux(R *dst, const R *F, double r)
+template <typename R, int N>
+__device__ __forceinline__ void store_flux(R (&a)[NV][N], int i, const R *F, double r)
 {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) dst[v] = sizeof(R) == 8 ? static_cast<R>(static_cast<double>(F[v]) * r) : F[v];
+    for (int v = 0; v < NV; ++v) a[v][i] = sizeof(R) == 8 ? static_cast<R>(static_cast<double>(F[v]) * r) : F[v];
 }
 
 template <typename R> __device__ __forceinline__ double flux_G(R f, double r)
 {
     return sizeof(R) == 8 ? static_cast<double>(f) : static_cast<double>(f) * r;
+}
+
+// the 5-variable value at index i of a plane set, in registers
+template <typename R, int N> struct Ld5 {
+    R v[NV];
+    __device__ __forceinline__ Ld5(const R (&a)[NV][N], int i) { lds_get(v, a, i); }
+};
+
+template <typename R, int N> __device__ __forceinline__ Ld5<R, N> ld5(const R (&a)[NV][N], int i)
+{
+    return Ld5<R, N>(a, i);
 }
 
 // hllc flux of one face, zeroed when it touches a split cell (GEN only)
@@ -225,19 +262,18 @@ __device__ __forceinline__ double signal_speed(const double *U, double gamma)
 template <typename R, bool KU, int NB, bool GEN>
 __device__ __forceinline__ void brick_sweep(const BrickArgs &a, int64_t b, const Geom &g, BrickSmem<R, NB> &S);
 
-template <typename R, bool KU = false, int NB = 1>
-__device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int64_t b, BrickSmem<R, NB> &S)
+// Slot table and geometry of the brick whose first oct is `base`, built by
+// NT threads; returns GEN (see brick_sweep) for the brick.
+template <int NT, typename SM>
+__device__ __forceinline__ bool brick_setup(const BrickArgs &a, int64_t base, SM &S, Geom &g)
 {
     const int tid = threadIdx.x;
-
-    // ---- brick geometry and slot table
-    for (int k = tid; k < BO * BO * BO; k += BT) {
+    for (int k = tid; k < BO * BO * BO; k += NT) {
         int32_t i, j, kk, l;
         key_coords(a.keys[base + k], i, j, kk, l);
         S.slot[slot_index(i & 7, j & 7, kk & 7)] = static_cast<int32_t>(base + k);
     }
     if (tid == 0) S.any_son = 0;
-    Geom g;
     {
         int32_t i, j, kk, l;
         key_coords(a.keys[base], i, j, kk, l);
@@ -248,7 +284,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
         g.outflow = a.outflow;
     }
     __syncthreads();
-    for (int s = tid; s < HS * HS * HS; s += BT) {
+    for (int s = tid; s < HS * HS * HS; s += NT) {
         const int sa = s % HS - 1, sb = (s / HS) % HS - 1, sc = s / (HS * HS) - 1;
         const int out = (sa < 0 || sa >= BO) + (sb < 0 || sb >= BO) + (sc < 0 || sc >= BO);
         int32_t e = RG_NBR_OUTSIDE;
@@ -270,8 +306,14 @@ __device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int
     __syncthreads();
     const bool wall = g.outflow && (g.cx0 == 0 || g.cy0 == 0 || g.cz0 == 0 || g.cx0 + BC == g.ncell ||
                                     g.cy0 + BC == g.ncell || g.cz0 + BC == g.ncell);
-    const bool gen = S.any_son != 0 || wall;
-    if (gen)
+    return S.any_son != 0 || wall;
+}
+
+template <typename R, bool KU = false, int NB = 1>
+__device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int64_t b, BrickSmem<R, NB> &S)
+{
+    Geom g;
+    if (brick_setup<BT>(a, base, S, g))
         brick_sweep<R, KU, NB, true>(a, b, g, S);
     else
         brick_sweep<R, KU, NB, false>(a, b, g, S);
@@ -329,7 +371,7 @@ __device__ __forceinline__ void brick_sweep(const BrickArgs &a, int64_t b, const
             load_u(a.uold, source_cell<GEN>(S, g, hx, hy, -1, sdummy), U);
             R Wh[NV];
             to_prim(U, a.gamma, Wh);
-            copy5(S.hw[2][lane], Wh);
+            lds_put(S.hw[2], lane, Wh);
         }
     }
     // FP64: ghost-ring cells are loaded one plane ahead of their use, so that
@@ -390,17 +432,17 @@ __device__ __forceinline__ void brick_sweep(const BrickArgs &a, int64_t b, const
                     load_u(a.uold, source_cell<GEN>(S, g, hx, hy, rz + 1, sdummy), U);
                     to_prim(U, a.gamma, Wh);
                 }
-                copy5(S.hw[(rz + 4) % 3][lane], Wh);
+                lds_put(S.hw[(rz + 4) % 3], lane, Wh);
             }
             (void)source_cell<GEN>(S, g, hx, hy, rz, hsplit);
         }
         // 2. plane rz into LDS: W and split flags
         {
-            copy5(S.w[(x + 2) + PW * (y + 2)], W0);
+            lds_put(S.w, (x + 2) + PW * (y + 2), W0);
             if constexpr (GEN) spl[(x + 2) + PW * (y + 2)] = sp_cur;
         }
         if (do_face) {
-            copy5(S.w[(hx + 2) + PW * (hy + 2)], S.hw[(rz + 3) % 3][lane]);
+            lds_put(S.w, (hx + 2) + PW * (hy + 2), ld5(S.hw[(rz + 3) % 3], lane).v);
             if constexpr (GEN) spl[(hx + 2) + PW * (hy + 2)] = hsplit;
         }
         if (ring_role && inner) {
@@ -414,7 +456,7 @@ __device__ __forceinline__ void brick_sweep(const BrickArgs &a, int64_t b, const
                 load_u(a.uold, source_cell<GEN>(S, g, rx, ry, rz, sdummy), U);
                 to_prim(U, a.gamma, Wr);
             }
-            copy5(S.w[(rx + 2) + PW * (ry + 2)], Wr);
+            lds_put(S.w, (rx + 2) + PW * (ry + 2), Wr);
         }
         __syncthreads();
 
@@ -423,12 +465,13 @@ __device__ __forceinline__ void brick_sweep(const BrickArgs &a, int64_t b, const
         if (do_face && inner) {
             R dW[3][NV], Wq[NV], st[NV];
             const int c = (hx + 2) + PW * (hy + 2);
-            reconstruct<R>(S.hw[(rz + 3) % 3][lane], S.w[c - 1], S.w[c + 1], S.w[c - PW], S.w[c + PW],
-                           S.hw[(rz + 2) % 3][lane], S.hw[(rz + 4) % 3][lane], h, gam, dW, Wq);
+            reconstruct<R>(ld5(S.hw[(rz + 3) % 3], lane).v, ld5(S.w, c - 1).v, ld5(S.w, c + 1).v, ld5(S.w, c - PW).v,
+                           ld5(S.w, c + PW).v, ld5(S.hw[(rz + 2) % 3], lane).v, ld5(S.hw[(rz + 4) % 3], lane).v, h,
+                           gam, dW, Wq);
             // x = -1 / y = -1 feed their high-side state to face (-1|0), x = 16
             // / y = 16 their low-side state to face (15|16)
             face_state<R>(Wq, hq < 2 ? dW[0] : dW[1], (hq & 1) == 0, st);
-            copy5(FB.row[ring_row(hq, hk)], st);
+            ring_put(FB, hq, hk, st);
         }
         R sxm[NV], sym[NV];
         double gz[NV];
@@ -439,14 +482,16 @@ __device__ __forceinline__ void brick_sweep(const BrickArgs &a, int64_t b, const
             const int c = (x + 2) + PW * (y + 2);
             nxy_cur = GEN && (spl[c - 1] || spl[c + 1] || spl[c - PW] || spl[c + PW]);
             if constexpr (sizeof(R) == 8)
-                reconstruct<R>(W0, S.w[c - 1], S.w[c + 1], S.w[c - PW], S.w[c + PW], Wm, Wp, h, gam, R(inv0), dW, Wq);
+                reconstruct<R>(W0, ld5(S.w, c - 1).v, ld5(S.w, c + 1).v, ld5(S.w, c - PW).v, ld5(S.w, c + PW).v, Wm,
+                               Wp, h, gam, R(inv0), dW, Wq);
             else
-                reconstruct<R>(W0, S.w[c - 1], S.w[c + 1], S.w[c - PW], S.w[c + PW], Wm, Wp, h, gam, dW, Wq);
+                reconstruct<R>(W0, ld5(S.w, c - 1).v, ld5(S.w, c + 1).v, ld5(S.w, c - PW).v, ld5(S.w, c + PW).v, Wm,
+                               Wp, h, gam, dW, Wq);
             if (inner) {
                 face_state<R>(Wq, dW[0], true, st);
-                copy5(FB.st.sxp[x + 1][y], st);
+                lds_put(FB.fx, y * (BC + 1) + x + 1, st);
                 face_state<R>(Wq, dW[1], true, st);
-                copy5(FB.st.syp[y + 1][x], st);
+                lds_put(FB.fy, (y + 1) * BC + x, st);
                 face_state<R>(Wq, dW[0], false, sxm);
                 face_state<R>(Wq, dW[1], false, sym);
             }
@@ -469,10 +514,10 @@ __device__ __forceinline__ void brick_sweep(const BrickArgs &a, int64_t b, const
                 }
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
-                    const double gxm = flux_G(PB.fl.fx[x][y][v], r);
-                    const double gxp = flux_G(PB.fl.fx[x + 1][y][v], r);
-                    const double gym = flux_G(PB.fl.fy[y][x][v], r);
-                    const double gyp = flux_G(PB.fl.fy[y + 1][x][v], r);
+                    const double gxm = flux_G(PB.fx[v][y * (BC + 1) + x], r);
+                    const double gxp = flux_G(PB.fx[v][y * (BC + 1) + x + 1], r);
+                    const double gym = flux_G(PB.fy[v][y * BC + x], r);
+                    const double gyp = flux_G(PB.fy[v][(y + 1) * BC + x], r);
                     const double acc = (Ucur[v] + (gxm - gxp)) + (gym - gyp);
                     out[v] = acc + (gz_prev[v] - gz[v]);
                 }
@@ -495,20 +540,20 @@ __device__ __forceinline__ void brick_sweep(const BrickArgs &a, int64_t b, const
         if (inner) {
             R F[NV];
             {
-                face_F<GEN, R>(FB.st.sxp[x][y], sxm, 0, gam, g1, GEN && (spl[(x + 1) + PW * (y + 2)] || sp_cur), F);
-                store_flux(FB.fl.fx[x][y], F, r);
-                face_F<GEN, R>(FB.st.syp[y][x], sym, 1, gam, g1, GEN && (spl[(x + 2) + PW * (y + 1)] || sp_cur), F);
-                store_flux(FB.fl.fy[y][x], F, r);
+                face_F<GEN, R>(ld5(FB.fx, y * (BC + 1) + x).v, sxm, 0, gam, g1, GEN && (spl[(x + 1) + PW * (y + 2)] || sp_cur), F);
+                store_flux(FB.fx, y * (BC + 1) + x, F, r);
+                face_F<GEN, R>(ld5(FB.fy, y * BC + x).v, sym, 1, gam, g1, GEN && (spl[(x + 2) + PW * (y + 1)] || sp_cur), F);
+                store_flux(FB.fy, y * BC + x, F, r);
             }
             if (extra_faces) {
                 if (lane < BC) {
                     const bool z2 = GEN && (spl[(BC + 1) + PW * (hk + 2)] || spl[(BC + 2) + PW * (hk + 2)]);
-                    face_F<GEN, R>(FB.st.sxp[BC][hk], FB.st.sxm_hi[hk], 0, gam, g1, z2, F);
-                    store_flux(FB.fl.fx[BC][hk], F, r);
+                    face_F<GEN, R>(ld5(FB.fx, hk * (BC + 1) + BC).v, ld5(FB.sxm_hi, hk).v, 0, gam, g1, z2, F);
+                    store_flux(FB.fx, hk * (BC + 1) + BC, F, r);
                 } else {
                     const bool z2 = GEN && (spl[(hk + 2) + PW * (BC + 1)] || spl[(hk + 2) + PW * (BC + 2)]);
-                    face_F<GEN, R>(FB.st.syp[BC][hk], FB.st.sym_hi[hk], 1, gam, g1, z2, F);
-                    store_flux(FB.fl.fy[BC][hk], F, r);
+                    face_F<GEN, R>(ld5(FB.fy, BC * BC + hk).v, ld5(FB.sym_hi, hk).v, 1, gam, g1, z2, F);
+                    store_flux(FB.fy, BC * BC + hk, F, r);
                 }
             }
         }
@@ -520,7 +565,7 @@ __device__ __forceinline__ void brick_sweep(const BrickArgs &a, int64_t b, const
             double out[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v)
-                out[v] = (ACC_LDS ? S.acc[ACC_LDS ? tid : 0][v] : acc_prev[v]) + (gz_prev[v] - gz[v]);
+                out[v] = (ACC_LDS ? S.acc[v][ACC_LDS ? tid : 0] : acc_prev[v]) + (gz_prev[v] - gz[v]);
             bool sdummy;
             const int64_t cell = source_cell<GEN>(S, g, x, y, rz - 1, sdummy);
 #pragma unroll
@@ -541,13 +586,13 @@ __device__ __forceinline__ void brick_sweep(const BrickArgs &a, int64_t b, const
             }
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const double gxm = flux_G(FB.fl.fx[x][y][v], r);
-                const double gxp = flux_G(FB.fl.fx[x + 1][y][v], r);
-                const double gym = flux_G(FB.fl.fy[y][x][v], r);
-                const double gyp = flux_G(FB.fl.fy[y + 1][x][v], r);
+                const double gxm = flux_G(FB.fx[v][y * (BC + 1) + x], r);
+                const double gxp = flux_G(FB.fx[v][y * (BC + 1) + x + 1], r);
+                const double gym = flux_G(FB.fy[v][y * BC + x], r);
+                const double gyp = flux_G(FB.fy[v][(y + 1) * BC + x], r);
                 const double acc = (Ucur[v] + (gxm - gxp)) + (gym - gyp);
                 if constexpr (ACC_LDS)
-                    S.acc[tid][v] = acc;
+                    S.acc[v][tid] = acc;
                 else
                     acc_prev[v] = acc;
             }

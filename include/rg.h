@@ -221,7 +221,7 @@ typedef struct rg_tuning {
     int32_t persistent;       /* batched form: 1 = persistent grids looping over the work list,
                                  0 = one workgroup per work item */
     int32_t brick_waves;      /* brick kernel register budget: waves per SIMD it is compiled for
-                                 (FP64: 2 or 3, mixed: 3 or 4; 0 = default: 2 for FP64, 4 mixed) */
+                                 (FP64: 2 or 3, mixed: 3 or 4; 0 = default: 2 for FP64, 3 mixed) */
     int32_t no_groups;        /* 1: scheduled updates leave complete sibling groups to the per-oct kernel */
     int32_t group_threads;    /* sibling-group kernel workgroup size: 256, 320 or 384 (0 = default) */
     int32_t reserved[1];

@@ -29,9 +29,9 @@ namespace {
 
 // W: waves per SIMD the register allocation is sized for (the compiler
 // spills beyond it); KU: see brick_body.  FP64 keeps the state in registers
-// at two waves; the mixed form at four waves reads it again instead (with
-// KU it would spill), at three it keeps it.  Every variant gives the same
-// bits.
+// at two waves; the mixed form keeps it at three (the default: no second
+// read of uold, fewer bricks sharing an XCD's L2) or reads it again at four
+// (with KU it would spill).  Every variant gives the same bits.
 template <typename R, int W, bool KU>
 __global__ __launch_bounds__(BT, W) void k_hydro_brick(BrickArgs a)
 {
@@ -79,9 +79,9 @@ rg_status hydro_bricks(const double *uold, double *unew, const int32_t *nbr27, c
         else
             return fail(RG_ENOTSUP, "no FP64 brick kernel for %d waves per SIMD", waves);
     } else {
-        if (waves == 0 || waves == 4)
+        if (waves == 4)
             k_hydro_brick<float, 4, false><<<grid, BT, 0, s>>>(a);
-        else if (waves == 3)
+        else if (waves == 0 || waves == 3)
             k_hydro_brick<float, 3, true><<<grid, BT, 0, s>>>(a);
         else
             return fail(RG_ENOTSUP, "no mixed brick kernel for %d waves per SIMD", waves);

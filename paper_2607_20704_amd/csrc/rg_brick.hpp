@@ -59,18 +59,6 @@ template <typename R> struct BrickFaces {
 };
 static_assert(sizeof(BrickFaces<double>) == sizeof(double) * NV * (FXN + FYN + 2 * BC), "packed face planes");
 
-template <typename R, int N> __device__ __forceinline__ void lds_get(R *d, const R (&a)[NV][N], int i)
-{
-#pragma unroll
-    for (int v = 0; v < NV; ++v) d[v] = a[v][i];
-}
-
-template <typename R, int N> __device__ __forceinline__ void lds_put(R (&a)[NV][N], int i, const R *src)
-{
-#pragma unroll
-    for (int v = 0; v < NV; ++v) a[v][i] = src[v];
-}
-
 // The face state that ghost-ring lane (side q, position k) writes: q = 0 the
 // x+ state of cell x = -1 in row k (fx, face 0), 1 the x- state of ghost
 // x = 16 (sxm_hi), 2 the y+ state of cell y = -1 in column k (fy, face 0),
@@ -198,17 +186,6 @@ __device__ __forceinline__ void store_flux(R (&a)[NV][N], int i, const R *F, dou
 template <typename R> __device__ __forceinline__ double flux_G(R f, double r)
 {
     return sizeof(R) == 8 ? static_cast<double>(f) : static_cast<double>(f) * r;
-}
-
-// the 5-variable value at index i of a plane set, in registers
-template <typename R, int N> struct Ld5 {
-    R v[NV];
-    __device__ __forceinline__ Ld5(const R (&a)[NV][N], int i) { lds_get(v, a, i); }
-};
-
-template <typename R, int N> __device__ __forceinline__ Ld5<R, N> ld5(const R (&a)[NV][N], int i)
-{
-    return Ld5<R, N>(a, i);
 }
 
 // hllc flux of one face, zeroed when it touches a split cell (GEN only)

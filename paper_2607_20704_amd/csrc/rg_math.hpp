@@ -234,6 +234,33 @@ template <typename R> __device__ __forceinline__ void face_state(const R *Wp, co
     st[4] = fmax(st[4], R(RG_P_MIN));
 }
 
+// LDS planes: a 5-variable quantity of many cells or faces stored as five
+// planes a[v][i] (one per variable), so that the lanes of a wave, which
+// handle consecutive i, touch consecutive words (40-byte records would put
+// the words of neighbouring lanes 10 dwords apart and collide in the banks).
+template <typename R, int N> __device__ __forceinline__ void lds_get(R *d, const R (&a)[NV][N], int i)
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) d[v] = a[v][i];
+}
+
+template <typename R, int N> __device__ __forceinline__ void lds_put(R (&a)[NV][N], int i, const R *src)
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) a[v][i] = src[v];
+}
+
+// the 5-variable value at index i of a plane set, in registers
+template <typename R, int N> struct Ld5 {
+    R v[NV];
+    __device__ __forceinline__ Ld5(const R (&a)[NV][N], int i) { lds_get(v, a, i); }
+};
+
+template <typename R, int N> __device__ __forceinline__ Ld5<R, N> ld5(const R (&a)[NV][N], int i)
+{
+    return Ld5<R, N>(a, i);
+}
+
 // G = F dt/dx in double, or zero on a face touching a split cell
 template <typename R> __device__ __forceinline__ void face_flux(const R *L, const R *Rt, int dir, R gamma, R g1,
                                                                 double r, bool zero, double *G)

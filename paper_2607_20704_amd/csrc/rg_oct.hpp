@@ -180,10 +180,10 @@ template <typename R, int G> struct Smem {
     // the stencil's primitives are dead once the face states exist (phase
     // B), before the fluxes are written (phase C): one LDS region serves both
     union {
-        R w[G][80][NV];         // primitive variables of the stencil cells
+        R w[G][NV][80];         // primitive variables of the stencil cells (planes, lds_get)
         double g[G][36][NV];    // G = F dt/dx per face
     };
-    R fs[G][36][2][NV];         // face states: [face][0] left of the face, [1] right
+    R fs[G][2][NV][36];         // face states: [0] left of the face, [1] right (planes)
     double red[8];              // block minimum of the fused CFL limit (one per wave)
 };
 
@@ -260,7 +260,7 @@ __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, i
         }
         prim64(U, a.gamma, W);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) S.w[g][wc][v] = static_cast<R>(W[v]);
+        for (int v = 0; v < NV; ++v) S.w[g][v][wc] = static_cast<R>(W[v]);
         if (wc < 8) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) S.u[g][wc][v] = U[v];
@@ -275,10 +275,10 @@ __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, i
         const uint64_t code = c_tab.rcode[rc];
         const int x = static_cast<int>((code >> 49) & 7) - 2, y = static_cast<int>((code >> 52) & 7) - 2,
                   z = static_cast<int>((code >> 55) & 7) - 2;
-        const R *w0 = S.w[g][code & 127];
         R dW[3][NV], Wp[NV];
-        reconstruct<R>(w0, S.w[g][(code >> 7) & 127], S.w[g][(code >> 14) & 127], S.w[g][(code >> 21) & 127],
-                       S.w[g][(code >> 28) & 127], S.w[g][(code >> 35) & 127], S.w[g][(code >> 42) & 127], h,
+        reconstruct<R>(ld5(S.w[g], code & 127).v, ld5(S.w[g], (code >> 7) & 127).v, ld5(S.w[g], (code >> 14) & 127).v,
+                       ld5(S.w[g], (code >> 21) & 127).v, ld5(S.w[g], (code >> 28) & 127).v,
+                       ld5(S.w[g], (code >> 35) & 127).v, ld5(S.w[g], (code >> 42) & 127).v, h,
                        gam, dW, Wp);
         const int p[3] = {x, y, z};
 #pragma unroll
@@ -293,9 +293,7 @@ __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, i
                 if (c < 0 || c > 2) continue;
                 R st[NV];
                 face_state<R>(Wp, dW[ax], side != 0, st);
-                R *dst = S.fs[g][face_id(ax, c, p[t1], p[t2])][side ? 0 : 1];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) dst[v] = st[v];
+                lds_put(S.fs[g][side ? 0 : 1], face_id(ax, c, p[t1], p[t2]), st);
             }
         }
     }
@@ -307,11 +305,8 @@ __device__ __forceinline__ void hydro_group(const LevelArgs &a, int64_t first, i
         if (g >= count) continue;
         const int ax = f / 12, c = (f / 4) % 3, t1 = f & 1, t2 = (f >> 1) & 1;
         R L[NV], Rr[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            L[v] = S.fs[g][f][0][v];
-            Rr[v] = S.fs[g][f][1][v];
-        }
+        lds_get(L, S.fs[g][0], f);
+        lds_get(Rr, S.fs[g][1], f);
         // split test for the two cells: position c-1 and c along the axis
         bool zero = false;
 #pragma unroll

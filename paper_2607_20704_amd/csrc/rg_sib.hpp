@@ -121,10 +121,10 @@ template <typename R> struct SibSmem {
     uint32_t sm[32];
     double u[64][NV];           // uold, then unew, of the own cells (x + 4y + 16z)
     union {
-        R w[kSibW][NV];         // primitive variables of the stencil cells
+        R w[NV][kSibW];         // primitive variables of the stencil cells (planes, lds_get)
         double g[kSibF][NV];    // G = F dt/dx per face
     };
-    R fs[kSibF][2][NV];         // face states: [0] left of the face, [1] right
+    R fs[2][NV][kSibF];         // face states: [0] left of the face, [1] right (planes)
     double red[8];
 };
 
@@ -215,7 +215,7 @@ __device__ __forceinline__ void hydro_sib(const LevelArgs &a, const int32_t *__r
         }
         prim64(U, a.gamma, W);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) S.w[it][v] = static_cast<R>(W[v]);
+        for (int v = 0; v < NV; ++v) S.w[v][it] = static_cast<R>(W[v]);
         if (it < 64) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) S.u[it][v] = U[v];
@@ -229,8 +229,9 @@ __device__ __forceinline__ void hydro_sib(const LevelArgs &a, const int32_t *__r
         const int x = static_cast<int>((code >> 54) & 7) - 2, y = static_cast<int>((code >> 57) & 7) - 2,
                   z = static_cast<int>((code >> 60) & 7) - 2;
         R dW[3][NV], Wp[NV];
-        reconstruct<R>(S.w[it], S.w[code & 511], S.w[(code >> 9) & 511], S.w[(code >> 18) & 511],
-                       S.w[(code >> 27) & 511], S.w[(code >> 36) & 511], S.w[(code >> 45) & 511], h, gam, dW, Wp);
+        reconstruct<R>(ld5(S.w, it).v, ld5(S.w, code & 511).v, ld5(S.w, (code >> 9) & 511).v,
+                       ld5(S.w, (code >> 18) & 511).v, ld5(S.w, (code >> 27) & 511).v, ld5(S.w, (code >> 36) & 511).v,
+                       ld5(S.w, (code >> 45) & 511).v, h, gam, dW, Wp);
         const int p[3] = {x, y, z};
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
@@ -243,9 +244,7 @@ __device__ __forceinline__ void hydro_sib(const LevelArgs &a, const int32_t *__r
                 if (c < 0 || c > 4) continue;
                 R st[NV];
                 face_state<R>(Wp, dW[ax], side != 0, st);
-                R *dst = S.fs[sib_face(ax, c, p[t1], p[t2])][side ? 0 : 1];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) dst[v] = st[v];
+                lds_put(S.fs[side ? 0 : 1], sib_face(ax, c, p[t1], p[t2]), st);
             }
         }
     }
@@ -255,11 +254,8 @@ __device__ __forceinline__ void hydro_sib(const LevelArgs &a, const int32_t *__r
     for (int f = tid; f < kSibF; f += NT) {
         const int ax = f / 80, c = (f / 16) % 5, t1 = f & 3, t2 = (f >> 2) & 3;
         R L[NV], Rr[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            L[v] = S.fs[f][0][v];
-            Rr[v] = S.fs[f][1][v];
-        }
+        lds_get(L, S.fs[0], f);
+        lds_get(Rr, S.fs[1], f);
         bool zero = false;
 #pragma unroll
         for (int k = 0; k < 2; ++k) {

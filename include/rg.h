@@ -72,7 +72,7 @@
 extern "C" {
 #endif
 
-#define RG_ABI_VERSION 10
+#define RG_ABI_VERSION 11
 #define RG_MAX_LEVEL 21
 #define RG_NBR_OUTSIDE INT32_MIN
 #define RG_RHO_MIN 1e-10
@@ -178,6 +178,26 @@ size_t rg_hash_workspace_bytes(int64_t n_keys);
  * be non-zero and unique; violations are flagged in the header (rg_check).
  * Slot positions depend on insertion order; only lookups are defined. */
 rg_status rg_hash_build(const uint64_t *d_keys, int64_t n, void *d_ws, size_t ws_bytes, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * build as rg_hash_build, same table, same lookups, with the build's scratch
+ * taken from a static device array of the library instead of the caller's
+ * workspace.  d_table (256-byte aligned, caller-owned) receives only the
+ * table: the 256-byte header and the slots, at least
+ * ((256 + capacity * 12 + 255) / 256) * 256 bytes, capacity being the power of
+ * two >= max(2n, 16); a buffer of rg_hash_workspace_bytes(n) bytes also
+ * fits.  The result is read by rg_hash_lookup, rg_check and
+ * rg_build_neighbours like a workspace rg_hash_build filled.
+ * Limits: n <= 4,194,304 keys (RG_EINVAL above, before any launch); a table
+ * smaller than the above is RG_EFULL.  The static array (about 40 MiB) is
+ * held by every device that runs this call, from its first call until the
+ * process ends.  Calls allocate nothing (no hipMalloc, hipFree or allocating
+ * library routine) and need no clearing between them: every call writes each
+ * scratch word before it reads it.  All calls on one device share that
+ * device's array: calls that overlap in time on one device (on different
+ * streams, or from different threads) race and give undefined tables. */
+rg_status rg_hash_build_noalloc(const uint64_t *d_keys, int64_t n, void *d_table, size_t table_bytes, void *stream);
 
 /* The paper's hash_get: d_idx[i] = index of key d_q[i], or -1 if absent. */
 rg_status rg_hash_lookup(const void *d_ws, const uint64_t *d_q, int64_t m, int32_t *d_idx, void *stream);

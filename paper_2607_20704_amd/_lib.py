@@ -73,6 +73,7 @@ SIGNATURES = {
     "rg_permute_rows": (st, [P, P, i64, ctypes.c_int, P, P]),
     "rg_hash_workspace_bytes": (sz, [i64]),
     "rg_hash_build": (st, [P, i64, P, sz, P]),
+    "rg_hash_build_noalloc": (st, [P, i64, P, sz, P]),
     "rg_hash_lookup": (st, [P, P, i64, P, P]),
     "rg_check": (st, [P, ctypes.POINTER(i64), P]),
     "rg_fnv1a64": (u64, [u64]),

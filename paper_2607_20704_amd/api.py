@@ -115,6 +115,13 @@ def hash_build(keys, ws=None):
     return ws
 
 
+def hash_build_noalloc(keys, table):
+    """Builds the hash table of `keys` into the caller's `table` (uint8,
+    256-byte aligned) with the library's static scratch: no allocation."""
+    check(L.lib().rg_hash_build_noalloc(_ptr(keys), keys.shape[0], _ptr(table), table.numel(), _stream()))
+    return table
+
+
 def hash_lookup(ws, q):
     out = torch.empty(q.shape[0], dtype=torch.int32, device="cuda")
     check(L.lib().rg_hash_lookup(_ptr(ws), _ptr(q), q.shape[0], _ptr(out), _stream()))

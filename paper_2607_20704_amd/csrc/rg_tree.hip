@@ -10,6 +10,8 @@
 // 64-bit CAS, so the key itself is the CAS target).
 #include <hipcub/hipcub.hpp>
 
+#include <mutex>
+
 #include "rg_internal.hpp"
 #include "rg_nbr.hpp"
 
@@ -147,15 +149,14 @@ int seg_log_for(uint64_t cap)
 
 size_t table_bytes(uint64_t cap) { return align256(sizeof(HashHeader) + cap * (sizeof(uint64_t) + sizeof(int32_t))); }
 
-// scratch of the build, placed after the table
-SegBuild seg_build_layout(void *ws, int64_t n, uint64_t cap)
+// scratch of the build at p (256-byte aligned)
+SegBuild seg_build_layout_at(char *p, int64_t n, uint64_t cap)
 {
     SegBuild b;
     b.seg_log = seg_log_for(cap);
     b.bits = log2_ceil(cap) - b.seg_log;
     b.nseg = int64_t(1) << b.bits;
     b.nblk = n > 0 ? (n + kBucketChunk - 1) / kBucketChunk : 1;
-    char *p = static_cast<char *>(ws) + table_bytes(cap);
     const size_t nb = align256(static_cast<size_t>(n) * sizeof(uint32_t));
     b.idx = reinterpret_cast<uint32_t *>(p);
     p += nb;
@@ -168,6 +169,12 @@ SegBuild seg_build_layout(void *ws, int64_t n, uint64_t cap)
     b.seg_tot = b.seg_end + b.nseg;
     b.ovf_count = b.seg_tot + b.nseg;
     return b;
+}
+
+// scratch of the build, placed after the table in the caller's workspace
+SegBuild seg_build_layout(void *ws, int64_t n, uint64_t cap)
+{
+    return seg_build_layout_at(static_cast<char *>(ws) + table_bytes(cap), n, cap);
 }
 
 size_t seg_build_bytes(int64_t n, uint64_t cap)
@@ -413,6 +420,78 @@ rg_status fill_u64(uint64_t *d, int64_t n, uint64_t v, hipStream_t s)
     return launch_status("fill_u64");
 }
 
+namespace {
+
+// Builds the table at d_table (header + slots) from the keys, with the
+// build's scratch (bucketing, overflow lists) at b.
+rg_status hash_build_into(const uint64_t *d_keys, int64_t n, void *d_table, const SegBuild &b, hipStream_t s)
+{
+    const uint64_t cap = hash_capacity(n);
+    HashView h = hash_view(d_table, cap);
+    const size_t cnt_bytes = static_cast<size_t>(b.nseg) * sizeof(uint32_t);
+    RG_REQUIRE(cnt_bytes <= 64 * 1024, "table too large for the bucketed build (%lld segments)", (long long)b.nseg);
+    const unsigned nblk = static_cast<unsigned>(b.nblk);
+    k_bucket_count<<<nblk, kBucketThreads, cnt_bytes, s>>>(d_keys, n, h.mask, b.seg_log, b.nseg, b.hist, h.hdr, cap,
+                                                b.ovf_count);
+    RG_TRY(launch_status("rg_hash_build count"));
+    k_bucket_scan_seg<<<static_cast<unsigned>(b.nseg), 256, 0, s>>>(b.hist, b.nblk, b.seg_tot);
+    RG_TRY(launch_status("rg_hash_build scan"));
+    k_bucket_scan_tot<<<1, 1024, 0, s>>>(b.seg_tot, b.nseg, b.seg_begin, b.seg_end);
+    RG_TRY(launch_status("rg_hash_build bounds"));
+    if (n > 0) {
+        k_bucket_scatter<<<nblk, kBucketThreads, cnt_bytes, s>>>(d_keys, n, h.mask, b.seg_log, b.nseg, b.hist, b.seg_begin,
+                                                      b.idx);
+        RG_TRY(launch_status("rg_hash_build scatter"));
+    }
+    const uint32_t *idx = b.idx;
+    k_seg_build<<<static_cast<unsigned>(b.nseg), 256, 0, s>>>(d_keys, b.seg_begin, b.seg_end, idx, h.hdr, h.keys,
+                                                              h.vals, h.mask, b.seg_log, b.ovf_count, b.ovf);
+    RG_TRY(launch_status("rg_hash_build segments"));
+    k_seg_overflow<<<64, 256, 0, s>>>(d_keys, b.ovf_count, b.ovf, h.hdr, h.keys, h.vals, h.mask);
+    return launch_status("rg_hash_build overflow");
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of rg_hash_build_noalloc: a file-scope device array, one per
+// device (each device that loads the library holds its own copy at its own
+// address until the process ends).  Host code never uses the array's name as
+// an address: the first call on a device, with that device current, asks
+// for the device address with hipGetSymbolAddress and keeps it per device.
+// Sized for the largest table the entry point accepts (kNoAllocMaxKeys keys:
+// capacity 2^23 slots, 2048 segments of 4096 slots, 1024 chunks of 4096
+// keys): key-index and overflow lists of 16 MiB each, per-chunk counts of
+// 8 MiB, per-segment bounds.  The build writes every word it later reads
+// (its first kernel clears the overflow counter), so no call depends on
+// what the previous one left; calls that overlap on one device race.
+// ---------------------------------------------------------------------------
+constexpr int64_t kNoAllocMaxKeys = int64_t(1) << 22;
+constexpr size_t kNoAllocScratchBytes = 2 * (size_t(kNoAllocMaxKeys) * 4) + size_t(2048) * 1024 * 4 +
+                                        ((size_t(3 * 2048 + 64) * 4 + 255) & ~size_t(255));
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kScratchDevices] = {};
+
+rg_status noalloc_scratch(char *&out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(RG_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kScratchDevices) return fail(RG_ENOTSUP, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return fail(RG_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<char *>(p);
+    }
+    out = g_scratch_ptr[dev];
+    return RG_OK;
+}
+
+}  // namespace
+
 }  // namespace rg
 
 using namespace rg;
@@ -534,30 +613,25 @@ rg_status rg_hash_build(const uint64_t *d_keys, int64_t n, void *d_ws, size_t ws
     const uint64_t cap = hash_capacity(n);
     if (ws_bytes < rg_hash_workspace_bytes(n))
         return fail(RG_EFULL, "hash workspace holds %zu bytes, %zu needed", ws_bytes, rg_hash_workspace_bytes(n));
-    HashView h = hash_view(d_ws, cap);
-    hipStream_t s = as_stream(stream);
-    SegBuild b = seg_build_layout(d_ws, n, cap);
-    const size_t cnt_bytes = static_cast<size_t>(b.nseg) * sizeof(uint32_t);
-    RG_REQUIRE(cnt_bytes <= 64 * 1024, "table too large for the bucketed build (%lld segments)", (long long)b.nseg);
-    const unsigned nblk = static_cast<unsigned>(b.nblk);
-    k_bucket_count<<<nblk, kBucketThreads, cnt_bytes, s>>>(d_keys, n, h.mask, b.seg_log, b.nseg, b.hist, h.hdr, cap,
-                                                b.ovf_count);
-    RG_TRY(launch_status("rg_hash_build count"));
-    k_bucket_scan_seg<<<static_cast<unsigned>(b.nseg), 256, 0, s>>>(b.hist, b.nblk, b.seg_tot);
-    RG_TRY(launch_status("rg_hash_build scan"));
-    k_bucket_scan_tot<<<1, 1024, 0, s>>>(b.seg_tot, b.nseg, b.seg_begin, b.seg_end);
-    RG_TRY(launch_status("rg_hash_build bounds"));
-    if (n > 0) {
-        k_bucket_scatter<<<nblk, kBucketThreads, cnt_bytes, s>>>(d_keys, n, h.mask, b.seg_log, b.nseg, b.hist, b.seg_begin,
-                                                      b.idx);
-        RG_TRY(launch_status("rg_hash_build scatter"));
-    }
-    const uint32_t *idx = b.idx;
-    k_seg_build<<<static_cast<unsigned>(b.nseg), 256, 0, s>>>(d_keys, b.seg_begin, b.seg_end, idx, h.hdr, h.keys,
-                                                              h.vals, h.mask, b.seg_log, b.ovf_count, b.ovf);
-    RG_TRY(launch_status("rg_hash_build segments"));
-    k_seg_overflow<<<64, 256, 0, s>>>(d_keys, b.ovf_count, b.ovf, h.hdr, h.keys, h.vals, h.mask);
-    return launch_status("rg_hash_build overflow");
+    return hash_build_into(d_keys, n, d_ws, seg_build_layout(d_ws, n, cap), as_stream(stream));
+}
+
+rg_status rg_hash_build_noalloc(const uint64_t *d_keys, int64_t n, void *d_table, size_t table_bytes_given,
+                                void *stream)
+{
+    RG_REQUIRE(n >= 0 && n <= kNoAllocMaxKeys, "n = %lld: the build without allocation takes at most %lld keys",
+               static_cast<long long>(n), static_cast<long long>(kNoAllocMaxKeys));
+    RG_REQUIRE(d_table && (n == 0 || d_keys), "null pointer");
+    RG_REQUIRE(aligned(d_table, 256), "table must be 256-byte aligned");
+    const uint64_t cap = hash_capacity(n);
+    if (table_bytes_given < table_bytes(cap))
+        return fail(RG_EFULL, "hash table holds %zu bytes, %zu needed", table_bytes_given, table_bytes(cap));
+    const size_t need = seg_build_bytes(n, cap);
+    RG_REQUIRE(need <= kNoAllocScratchBytes, "build scratch of %zu bytes exceeds the static %zu", need,
+               kNoAllocScratchBytes);
+    char *scratch_ptr = nullptr;
+    RG_TRY(noalloc_scratch(scratch_ptr));
+    return hash_build_into(d_keys, n, d_table, seg_build_layout_at(scratch_ptr, n, cap), as_stream(stream));
 }
 
 // The capacity is recorded in the header on the device; host callers pass the

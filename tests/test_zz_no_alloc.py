@@ -1,0 +1,126 @@
+"""The hash build that allocates nothing (rg_hash_build_noalloc: the build's
+scratch is a static device array of the library) against rg_hash_build, the
+entry point it is a variant of, through the C ABI.
+
+Two calls in a row on the one static array, the second with fewer keys: the
+largest input it takes (4,194,304 keys), then a refined tree.  Each table is
+written over a buffer filled with junk, and must give the same lookups
+(present and absent keys) as rg_hash_build's, the same error word, and, for
+the tree, the same neighbour lists (also the oracle's).  The second call
+changes the device's free memory by nothing.  Sizes beyond the limit and
+tables too small are refused on the host."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import say
+from oracle import oracle as O
+from paper_2607_20704_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+MAX_KEYS = 1 << 22
+
+
+def _table_bytes(n):
+    cap = 16
+    while cap < 2 * n:
+        cap <<= 1
+    return (256 + cap * 12 + 255) // 256 * 256
+
+
+def _dev(keys):
+    return torch.as_tensor(np.ascontiguousarray(keys).astype(np.int64)).cuda().view(torch.uint64)
+
+
+def _junk_table(n):
+    return torch.full((_table_bytes(n),), 0xA5, dtype=torch.uint8, device="cuda")
+
+
+def _children(ijkl):
+    return O.keys(np.concatenate([2 * ijkl[:, :3], ijkl[:, 3:] + 1], 1).astype(np.int32))
+
+
+def _same_lookups(api, table, ws, queries):
+    for q in queries:
+        got = api.hash_lookup(table, q).cpu().numpy()
+        ref = api.hash_lookup(ws, q).cpu().numpy()
+        assert np.array_equal(got, ref)
+
+
+def test_noalloc_build_two_calls():
+    from paper_2607_20704_amd import api
+    from paper_2607_20704_amd import _lib as L
+
+    # call 1: the largest input, a random set of level-9 octs
+    rng = np.random.default_rng(20704)
+    flat = rng.choice(256 ** 3, size=MAX_KEYS, replace=False)
+    ijkl = np.stack([flat % 256, flat // 256 % 256, flat // 65536, np.full(MAX_KEYS, 9)], 1).astype(np.int32)
+    keys_np = O.keys(ijkl)
+    keys = _dev(keys_np)
+    absent = _dev(np.concatenate([_children(ijkl[:100000]), [0]]))
+    say("no-alloc hash build, call 1: %d keys" % MAX_KEYS)
+    table = _junk_table(MAX_KEYS)
+    api.hash_build_noalloc(keys, table)
+    ws = api.hash_build(keys)
+    assert api.check_ws(table) == (L.RG_OK, -1)
+    assert api.check_ws(ws) == (L.RG_OK, -1)
+    idx = api.hash_lookup(table, keys).cpu().numpy()
+    assert np.array_equal(idx, np.arange(MAX_KEYS))
+    _same_lookups(api, table, ws, [keys, absent])
+    del table, ws, keys, absent
+
+    # call 2: fewer keys, a refined tree, on the same static scratch
+    w = I.sedov_amr()
+    T = O.Tree(w.ijkl, w.bc)
+    keys = _dev(T.keys)
+    absent = _dev(np.concatenate([_children(w.ijkl[-2000:]), [0]]))
+    say("no-alloc hash build, call 2: %d keys" % T.n)
+    table = _junk_table(T.n)
+    ws = api.hash_build(keys)
+    lists = [torch.empty((T.n, 27), dtype=torch.int32, device="cuda"),
+             torch.empty(T.n, dtype=torch.int32, device="cuda"),
+             torch.empty(T.n, dtype=torch.int32, device="cuda")]
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    api.hash_build_noalloc(keys, table)
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    assert free1 == free0
+    assert api.check_ws(table) == (L.RG_OK, -1)
+    assert np.array_equal(api.hash_lookup(table, keys).cpu().numpy(), np.arange(T.n))
+    _same_lookups(api, table, ws, [keys, absent])
+    lmin = int(w.ijkl[:, 3].min())
+    got = api.build_neighbours(table, keys, lmin, w.bc, *lists)
+    got = [g.cpu().numpy() for g in got]
+    ref = [r.cpu().numpy() for r in api.build_neighbours(ws, keys, lmin, w.bc)]
+    for g, r in zip(got, ref):
+        assert np.array_equal(g, r)
+    assert np.array_equal(got[0], T.nbr27)
+    assert np.array_equal(got[1], T.father_cell)
+
+
+def test_noalloc_build_edges():
+    from paper_2607_20704_amd import api
+    from paper_2607_20704_amd import _lib as L
+    hk = O.keys(I.uniform_tree(3)).astype(np.int64)
+    # no keys: an empty table, every lookup absent
+    table = _junk_table(0)
+    api.hash_build_noalloc(_dev(hk[:0]), table)
+    assert api.check_ws(table) == (L.RG_OK, -1)
+    assert np.all(api.hash_lookup(table, _dev(hk)).cpu().numpy() == -1)
+    # a duplicate key is flagged in the table's header as by rg_hash_build
+    dup = _dev(np.concatenate([hk[:100], hk[:1]]))
+    table = _junk_table(101)
+    api.hash_build_noalloc(dup, table)
+    st, bad = api.check_ws(table)
+    assert st == L.RG_EDUPKEY and bad in (0, 100)
+    # refused before any launch: too many keys, table too small
+    k = _dev(hk[:8])
+    with pytest.raises(L.RgError) as e:
+        L.check(L.lib().rg_hash_build_noalloc(api._ptr(k), MAX_KEYS + 1, api._ptr(table), table.numel(), None))
+    assert e.value.status == L.RG_EINVAL
+    small = torch.empty(_table_bytes(8) - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(L.RgError) as e:
+        api.hash_build_noalloc(k, small)
+    assert e.value.status == L.RG_EFULL

@@ -8,16 +8,22 @@ FNV hash rebuild from the keys, neighbour lists, CFL dt, the hydro update of
 every level, coarse-fine correction and restriction (the last two are empty
 on a single level).  Re-keying (key encode, radix sort, level ranges; needed
 only when the tree changes) is timed separately as "rekey_ms".  Inputs are
-resident in HBM before the timed region starts.
+resident in HBM before the timed region starts.  Each figure is the median
+of 5 repetitions of exactly --steps steps.
 
 Prints one JSON line.  `value` is FP64 cell-updates/s; the mixed form
-(FP32 reconstruction/HLLC, FP64 state) is reported under "mixed".  Two more
-workloads are reported beside it: "batched" (64 seeded boxes of uneven size
-and depth, 20 steps in one graph launch, against the same boxes stepped one
-at a time) and "deep_amr" (clumpy gas on a base-7 tree refined to level 12,
-about 28 M cells, with the mixed form's L1 error against FP64).  The kernel
+(FP32 reconstruction/HLLC, FP64 state) is reported under "mixed".  Beside
+it: "sedov_amr" (global steps of the Sedov blast on its graded AMR tree,
+both forms), "batched" (64 seeded boxes of uneven size and depth, 20 steps
+in one graph launch, against the same boxes stepped one at a time),
+"deep_amr" (clumpy gas on a base-7 tree refined to level 12, about 28 M
+cells), "mg_poisson" and "dynamic" (refinement on the device).  The kernel
 variants are chosen by the autotuner before timing (they give identical
-bits).
+bits).  "cpu_baseline" times the oracle on the host (its OpenMP build on
+every core and its serial build) and "parity" compares the device's state
+after the same steps, in the timed launch shape, with the oracle's: FP64
+within 1e-12 per cell, the mixed form within an L1 of 1e-5 per field.  A
+mismatch prints the line with a null value and exits non-zero.
 """
 import argparse
 import hashlib
@@ -32,6 +38,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "hydro cell-updates/s on 1 MI355X, FP64 vs mixed FP32; % of HBM roofline"
 HBM_PEAK_GBS = 8000.0
+REPS = 5
 # algorithmic bytes per cell-update of the hydro kernel: read uold (40 B),
 # write unew (40 B), the 27-entry int32 neighbour list over 8 cells (13.5 B)
 ALG_BYTES_PER_CELL = 93.5
@@ -69,14 +76,22 @@ def measured_traffic(form):
     return float(m.group(1)) if m else None
 
 
-def time_form(D, u0, w, form, steps, warmup, api, tune=None):
-    """Timed steps on tree D.  The time step of each step is folded into the
-    previous step's update (cells no correction touches) and the corrected
-    coarse cells' pass, as rg_step does with RG_STEP_CHAIN_DT; the first one
-    comes from the separate CFL pass, outside the timed region."""
+def _median(xs):
+    ys = sorted(xs)
+    n = len(ys)
+    return ys[n // 2] if n % 2 else 0.5 * (ys[n // 2 - 1] + ys[n // 2])
+
+
+def time_form(D, u0, w, form, steps, warmup, api, tune=None, reps=5):
+    """Timed steps on tree D: `reps` repetitions of exactly `steps` steps,
+    each bracketed by device synchronisations; the median repetition is
+    reported.  The time step of each step is folded into the previous
+    step's update (cells no correction touches) and the corrected coarse
+    cells' pass, as rg_step does with RG_STEP_CHAIN_DT; the first one comes
+    from the separate CFL pass, outside the timed region."""
     import torch
     a, b = u0.clone(), torch.empty_like(u0)
-    n = warmup + 3 * steps + 1
+    n = warmup + 2 * reps * steps + 1
     dts = torch.empty(n, dtype=torch.float64, device="cuda")
     api.cfl_dt(a, D.son_mask, D.level_begin, D.lmin, D.lmax, w.gamma, w.cfl, dts[0:1])
     # each step rebuilds the FNV hash and the neighbour lists from the keys;
@@ -104,35 +119,42 @@ def time_form(D, u0, w, form, steps, warmup, api, tune=None):
                 api.restrict_level(b, D.father_cell, int(D.level_begin[l]), int(D.level_begin[l + 1]))
         k[0] = s + 1
 
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
     for _ in range(warmup):
         one_step(a, b)
         a, b = b, a
-    torch.cuda.synchronize()
-    h0 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    h1 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    start.record()
-    for i in range(steps):
-        one_step(a, b, h0[i], h1[i])
-        a, b = b, a
-    end.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = start.elapsed_time(end) / steps
-    hydro_ms = sum(x.elapsed_time(y) for x, y in zip(h0, h1)) / steps
+    rep_ms, rep_hydro, rep_wall = [], [], []
+    for _ in range(reps):
+        h0 = [ev() for _ in range(steps)]
+        h1 = [ev() for _ in range(steps)]
+        start, end = ev(), ev()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        start.record()
+        for i in range(steps):
+            one_step(a, b, h0[i], h1[i])
+            a, b = b, a
+        end.record()
+        torch.cuda.synchronize()
+        rep_wall.append(1e3 * (time.perf_counter() - t0) / steps)
+        rep_ms.append(start.elapsed_time(end) / steps)
+        rep_hydro.append(sum(x.elapsed_time(y) for x, y in zip(h0, h1)) / steps)
     # hydro-only steps (dt + update with prebuilt lists), for the paper's
     # "Godunov solver only" comparison
-    s2, e2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    s2.record()
-    for i in range(steps):
-        one_step(a, b, prepare=False)
-        a, b = b, a
-    e2.record()
-    torch.cuda.synchronize()
-    hydro_only_ms = s2.elapsed_time(e2) / steps
-    s3, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rep_only = []
+    for _ in range(reps):
+        s2, e2 = ev(), ev()
+        torch.cuda.synchronize()
+        s2.record()
+        for i in range(steps):
+            one_step(a, b, prepare=False)
+            a, b = b, a
+        e2.record()
+        torch.cuda.synchronize()
+        rep_only.append(s2.elapsed_time(e2) / steps)
+    s3, e3 = ev(), ev()
     s3.record()
     for i in range(steps):
         D.prepare(api.L.RG_STEP_REKEY)
@@ -143,8 +165,19 @@ def time_form(D, u0, w, form, steps, warmup, api, tune=None):
     check = api.cfl_dt(a, D.son_mask, D.level_begin, D.lmin, D.lmax, w.gamma, w.cfl)
     if float(check.cpu()[0]) != float(dts[k[0]].cpu()):
         raise RuntimeError("folded time step differs from the CFL pass")
-    return {"ms_per_step": ms, "wall_ms_per_step": 1e3 * wall / steps, "hydro_kernel_ms": hydro_ms,
-            "hydro_only_ms_per_step": hydro_only_ms, "rekey_ms": rekey_ms, "state": a}
+    return {"ms_per_step": _median(rep_ms), "reps_ms_per_step": [round(x, 4) for x in rep_ms],
+            "wall_ms_per_step": _median(rep_wall), "hydro_kernel_ms": _median(rep_hydro),
+            "hydro_only_ms_per_step": _median(rep_only), "rekey_ms": rekey_ms, "state": a}
+
+
+def device_check_run(D, u0, w, form, nsteps, tune):
+    """`nsteps` steps from the initial state in the timed launch shape (hash
+    and lists rebuilt every step, each dt folded into the previous update),
+    for the parity re-check against the oracle; host copies."""
+    import torch
+    u, dts = D.run(u0, w.gamma, w.cfl, nsteps, form=form, rebuild=True, tune=tune, chain=True)
+    torch.cuda.synchronize()
+    return u.cpu().numpy(), dts.cpu().numpy()
 
 
 def time_batched(forms, nsteps, reps, api, inputs, autotune):
@@ -211,7 +244,7 @@ def deep_workload(inputs):
     return _DEEP["w"]
 
 
-def time_deep_amr(forms, nsteps, api, inputs, autotune=None):
+def time_deep_amr(forms, nsteps, api, inputs, autotune=None, check_steps=0):
     """The clumpy-gas deep tree (base 7 up to level 12, about 28 M cells):
     `nsteps` whole steps per form (dt folded into the previous step's
     update as in the main workload, every level, corrections,
@@ -238,7 +271,7 @@ def time_deep_amr(forms, nsteps, api, inputs, autotune=None):
            "schedule": {str(l): {"bricks": c[0], "per_oct": c[1], "sibling_groups": c[2]} for l, c in D.schedule_counts().items()}}
     updates_sub = sum(2 ** (l - D.lmin) * 8 * int(D.level_begin[l + 1] - D.level_begin[l])
                       for l in range(D.lmin, D.lmax + 1))
-    states = {}
+    states, device = {}, {}
     for f in forms:
         form = api.RG_FP64 if f == "fp64" else api.RG_MIXED
         tune = autotune.tune_tree(D, u0, w.gamma, form)[0] if autotune else None
@@ -253,6 +286,8 @@ def time_deep_amr(forms, nsteps, api, inputs, autotune=None):
         states[f] = u
         out[f] = {"cell_updates_per_s": cells / (ms * 1e-3), "ms_per_step": round(ms, 4),
                   "tune": list(tune) if tune else None}
+        if check_steps:
+            device[f] = device_check_run(D, u0, w, form, check_steps, tune)
         global_dt = float(dts.mean())
         # the same steps with the sibling groups left to the per-oct kernel
         base = list(tune[:5]) if tune else [4, 256, 0, 0, 0]
@@ -304,7 +339,39 @@ def time_deep_amr(forms, nsteps, api, inputs, autotune=None):
         l1 = [float(num[0] / den[0])] + [float(num[v] / rho_den) for v in (1, 2, 3)] + [float(num[4] / den[4])]
         out["mixed"]["l1_vs_fp64_after_%d_steps" % nsteps] = l1
         out["mixed"]["l1_note"] = "momenta start at rest: their L1 is relative to the density norm"
-    return out
+    return out, device
+
+
+def time_sedov(forms, steps, warmup, api, inputs, autotune=None, check_steps=0):
+    """The Sedov blast on its graded AMR tree (base level 6, refined to level
+    8 inside r < 0.15 of the centre): whole global steps per form, timed like
+    the main workload (hash and lists rebuilt, dt folded, corrections,
+    corrected cells' dt, restriction; median of 5 repetitions).  Returns the
+    report, the workload and, with check_steps, each form's state after
+    that many steps from the initial state (host copies)."""
+    w = inputs.sedov_amr()
+    D = api.DeviceTree(w.ijkl, w.bc)
+    u0 = D.to_key_order(w.u)
+    cells = 8 * D.n
+    out = {"workload": "Sedov blast: base level 6 (64^3) refined to level 8 inside r < 0.15 of the centre, rho 1, "
+                       "p 1e-5, E 1 in the central cell, gamma 1.4, periodic, CFL 0.8; %d global steps" % steps,
+           "octs": D.n, "cells": cells, "levels": [D.lmin, D.lmax],
+           "octs_per_level": {str(l): int(D.level_begin[l + 1] - D.level_begin[l]) for l in range(D.lmin, D.lmax + 1)},
+           "schedule": {str(l): {"bricks": c[0], "per_oct": c[1], "sibling_groups": c[2]}
+                        for l, c in D.schedule_counts().items()}}
+    device = {}
+    for f in forms:
+        form = api.RG_FP64 if f == "fp64" else api.RG_MIXED
+        tune = autotune.tune_tree(D, u0, w.gamma, form)[0] if autotune else None
+        r = time_form(D, u0, w, form, steps, warmup, api, tune)
+        out[f] = {"cell_updates_per_s": cells / (r["ms_per_step"] * 1e-3), "ms_per_step": round(r["ms_per_step"], 4),
+                  "reps_ms_per_step": r["reps_ms_per_step"],
+                  "hydro_only_cell_updates_per_s": cells / (r["hydro_only_ms_per_step"] * 1e-3),
+                  "hydro_kernels_ms_per_step": round(r["hydro_kernel_ms"], 4),
+                  "tune": list(tune) if tune else None}
+        if check_steps:
+            device[f] = device_check_run(D, u0, w, form, check_steps, tune)
+    return out, w, device
 
 
 def time_dynamic(api, inputs):
@@ -462,33 +529,122 @@ def copy_ceiling(torch, mib=1024, reps=5):
     return 2 * n * 8 / (best * 1e-3) / 1e9
 
 
-def cpu_baseline(w, sample_octs):
-    """The oracle, as it stands, on the host: its hydro update (tile,
-    reconstruction, Riemann, update) of the first `sample_octs` octs in key
-    order, with its own neighbour lists."""
+FP64_BAR = 1e-12
+MIXED_L1_BAR = 1e-5
+
+
+def _parity_ratio(got, ref):
+    """Worst per-cell ratio of the FP64 bar: |d| / |ref| for density and
+    energy, |d| / max|ref| for each momentum component (<= 1e-12 passes)."""
+    import numpy as np
+    d = np.abs(got - ref)
+    worst = 0.0
+    for v in range(5):
+        scale = np.abs(ref[:, v]) if v in (0, 4) else np.full(len(ref), np.abs(ref[:, v]).max())
+        ok = scale > 0
+        r = np.where(ok, d[:, v] / np.where(ok, scale, 1.0), np.where(d[:, v] > 0, np.inf, 0.0))
+        worst = max(worst, float(r.max()))
+    return worst
+
+
+def _mixed_l1(got, ref, T):
+    """Per conserved field: sum V |x - x_ref| / sum V |x_ref| over leaf cells;
+    momenta against the larger of their own norm and the density norm (a
+    field that starts at rest has no norm of its own)."""
+    import numpy as np
+    leaf = (((T.son_mask[:, None] >> np.arange(8)[None, :]) & 1) == 0).reshape(-1)
+    vol = np.repeat((0.5 ** T.ijkl[:, 3].astype(np.float64)) ** 3, 8) * leaf
+    num = (vol[:, None] * np.abs(got - ref)).sum(0)
+    den = (vol[:, None] * np.abs(ref)).sum(0)
+    den[1:4] = np.maximum(den[1:4], den[0])
+    return [float(x) for x in num / den]
+
+
+def cpu_baseline(cases, sample_octs):
+    """The oracle, as it stands, on the host, and the in-run parity re-check.
+
+    cases: name -> (workload, omp_steps, serial, device) with serial either
+    ("steps", n) (whole steps of the serial oracle) or ("octs", ob, oe) (the
+    serial oracle's hydro update of octs [ob, oe), with the first step's
+    dt), and device a dict form -> (state, dts) of the device after
+    omp_steps steps from the same initial state.  Per case the OpenMP build
+    of the oracle runs omp_steps whole steps on every host core; its state
+    is the expected value of the device's, FP64 per cell within 1e-12 (and
+    the time steps), the mixed form's L1 per field within 1e-5."""
     import numpy as np
 
     from oracle import oracle as O
-    T = O.Tree(w.ijkl, w.bc)
-    u = T.permute_cells(w.u)
-    dt = T.cfl_dt(u, w.gamma, w.cfl)
-    unew = np.zeros_like(u)
-    corr = np.zeros(1)
-    n = min(sample_octs, T.n)
-    t0 = time.perf_counter()
-    O.hydro_octs(T.ijkl, T.nbr27, T.son_mask, 0, n, u, unew, corr, dt, w.gamma)
-    sec = time.perf_counter() - t0
     model = None
     try:
         with open("/proc/cpuinfo") as f:
             model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
     except OSError:
         pass
-    return {"value": 8 * n / sec, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+    configs, parity, ok = {}, {}, True
+    for name, (w, omp_steps, serial, device) in cases.items():
+        log("oracle: %s" % name)
+        T = O.Tree(w.ijkl, w.bc)
+        u = T.permute_cells(w.u)
+        cells = 8 * T.n
+        ref = u.copy()
+        with O.threads():
+            threads = O.nthreads()
+            t0 = time.perf_counter()
+            ref_dts = T.run(ref, w.gamma, w.cfl, omp_steps)
+            sec = time.perf_counter() - t0
+        c = {"octs": T.n, "cells": cells,
+             "omp": {"value": cells * omp_steps / sec, "cores": threads, "steps": omp_steps, "seconds": round(sec, 2)}}
+        if serial[0] == "steps":
+            x = u.copy()
+            t0 = time.perf_counter()
+            T.run(x, w.gamma, w.cfl, serial[1])
+            sec1 = time.perf_counter() - t0
+            c["serial"] = {"value": cells * serial[1] / sec1, "cores": 1, "steps": serial[1],
+                           "seconds": round(sec1, 2)}
+        else:
+            ob, oe = serial[1], min(serial[2], T.n)
+            unew = np.zeros_like(u)
+            corr = np.zeros(1)
+            t0 = time.perf_counter()
+            O.hydro_octs(T.ijkl, T.nbr27, T.son_mask, ob, oe, u, unew, corr, float(ref_dts[0]), w.gamma)
+            sec1 = time.perf_counter() - t0
+            c["serial"] = {"value": 8 * (oe - ob) / sec1, "cores": 1, "octs": [ob, oe],
+                           "what": "hydro update of octs [%d, %d) (first step's dt)" % (ob, oe),
+                           "seconds": round(sec1, 2)}
+        configs[name] = c
+        p = {"steps": omp_steps}
+        if "fp64" in device:
+            got, dts = device["fp64"]
+            p["fp64_worst_ratio"] = _parity_ratio(got, ref)
+            p["fp64_dt_worst_rel"] = float(np.max(np.abs(dts - ref_dts) / ref_dts))
+            good = p["fp64_worst_ratio"] <= FP64_BAR and p["fp64_dt_worst_rel"] <= FP64_BAR
+            p["fp64_ok"] = bool(good)
+            ok = ok and good
+        if "mixed" in device:
+            got, _ = device["mixed"]
+            p["mixed_l1"] = _mixed_l1(got, ref, T)
+            good = max(p["mixed_l1"]) <= MIXED_L1_BAR
+            p["mixed_ok"] = bool(good)
+            ok = ok and good
+        parity[name] = p
+        log("  oracle %d threads %.1f s, serial %.1f s; parity %s" % (threads, sec, sec1, p))
+        del T, u, ref
+    hname = "random256" if "random256" in configs else next(iter(configs))
+    head = configs[hname]
+    what = "the same 256^3 box" if hname == "random256" else "the %s workload" % hname
+    base = {"value": head["omp"]["value"], "unit": "cell-updates/s", "cores": head["omp"]["cores"], "kind": "oracle",
             "host_cpus": len(os.sched_getaffinity(0)), "cpu_model": model,
-            "sample": "hydro update (stencil, MUSCL-Hancock, HLLC, update) of the first %d octs (%d cells, a "
-                      "Hilbert-contiguous %s of the box) of the same 256^3 state; serial FP64, %.1f s"
-                      % (n, 8 * n, "half" if 2 * n == T.n else "part", sec)}
+            "sample": "%d whole step(s) of %s (CFL dt, neighbour lists prebuilt, hydro update of every oct, "
+                      "corrections, restriction) by the oracle's OpenMP build on %d threads, %.1f s"
+                      % (head["omp"]["steps"], what, head["omp"]["cores"], head["omp"]["seconds"]),
+            "serial": {"value": head["serial"]["value"], "cores": 1,
+                       "sample": "%s of %s, serial FP64 oracle, %.1f s"
+                                 % (head["serial"].get("what", "%d whole step(s)" % head["serial"].get("steps", 0)),
+                                    what, head["serial"]["seconds"])},
+            "configs": configs}
+    return base, {"ok": bool(ok), "fp64_bar": FP64_BAR, "mixed_l1_bar": MIXED_L1_BAR, "cases": parity,
+                  "note": "device state after the same steps from the same initial state, in the timed launch shape "
+                          "(hash and lists rebuilt, dt folded), against the oracle's OpenMP build"}
 
 
 def main():
@@ -498,12 +654,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-octs", type=int, default=1 << 20)
+    ap.add_argument("--cpu-sample-octs", type=int, default=1 << 19,
+                    help="octs of the 256^3 box in the serial oracle's timed update")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-box batched workload")
     ap.add_argument("--no-tune", action="store_true", help="library default kernels instead of autotuned ones")
     ap.add_argument("--no-deep-amr", action="store_true", help="skip the clumpy-gas deep-AMR workload")
     ap.add_argument("--no-dynamic", action="store_true", help="skip the refinement (dynamic tree) measurements")
     ap.add_argument("--no-mg", action="store_true", help="skip the multigrid Poisson measurement")
+    ap.add_argument("--no-sedov", action="store_true", help="skip the Sedov AMR global-step workload")
     ap.add_argument("--leg", choices=["all", "deep_amr", "dynamic", "mg_poisson"], default="all",
                     help="run one workload only and print its JSON (for profiling it); 'all' is the benchmark line")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -519,7 +677,7 @@ def main():
     torch.cuda.set_device(0)
     if args.leg != "all":
         forms = [f.strip() for f in args.forms.split(",") if f.strip()]
-        leg = (time_deep_amr(forms, 10, api, inputs, None if args.no_tune else autotune) if args.leg == "deep_amr" else
+        leg = (time_deep_amr(forms, 10, api, inputs, None if args.no_tune else autotune)[0] if args.leg == "deep_amr" else
                time_dynamic(api, inputs) if args.leg == "dynamic" else time_mg(api))
         print(json.dumps({args.leg: leg}), flush=True)
         return
@@ -550,7 +708,7 @@ def main():
             for c, t in sorted(times.items(), key=lambda kv: kv[1]):
                 log("    %-24s %.4f ms" % (c, t))
         log("timing form %s: %d warmup + %d steps" % (f, args.warmup, args.steps))
-        res[f] = time_form(D, u0, w, form, args.steps, args.warmup, api, tune)
+        res[f] = time_form(D, u0, w, form, args.steps, args.warmup, api, tune, REPS)
         res[f]["tune"] = list(tune) if tune else None
         log("  %.3f ms/step, hydro kernel %.3f ms" % (res[f]["ms_per_step"], res[f]["hydro_kernel_ms"]))
 
@@ -594,7 +752,31 @@ def main():
     if "fp64" in res and "mixed" in res:
         a, b = res["fp64"]["state"], res["mixed"]["state"]
         l1 = ((a - b).abs().sum(0) / a.abs().sum(0).clamp_min(1e-300)).cpu().numpy()
-        out["mixed"]["l1_vs_fp64_after_%d_steps" % (2 * args.steps + args.warmup)] = [float(x) for x in l1]
+        out["mixed"]["l1_vs_fp64_after_%d_steps" % (2 * REPS * args.steps + args.warmup)] = [float(x) for x in l1]
+    out["reps"] = REPS
+    out["reps_ms_per_step"] = res[primary]["reps_ms_per_step"]
+    # the parity re-check: states after a few steps from the initial state, in
+    # the timed launch shape, compared with the oracle in the CPU leg below
+    cases = {}
+    if not args.no_cpu_baseline:
+        log("parity re-check runs: 256^3 box, 1 step")
+        dev = {f: device_check_run(D, u0, w, api.RG_FP64 if f == "fp64" else api.RG_MIXED, 1, res[f]["tune"])
+               for f in forms}
+        cases["random256"] = (w, 1, ("octs", 0, args.cpu_sample_octs), dev)
+        log("parity re-check runs: Sod tube, 20 steps")
+        ws = inputs.sod_uniform()
+        Ds = api.DeviceTree(ws.ijkl, ws.bc)
+        cases["sod_l5"] = (ws, 20, ("steps", 20),
+                           {"fp64": device_check_run(Ds, Ds.to_key_order(ws.u), ws, api.RG_FP64, 20, None)})
+        del Ds
+    if not args.no_sedov:
+        log("Sedov AMR global steps")
+        out["sedov_amr"], wsd, dev = time_sedov(forms, args.steps, args.warmup, api, inputs,
+                                                None if args.no_tune else autotune,
+                                                0 if args.no_cpu_baseline else 20)
+        if dev:
+            cases["sedov_amr"] = (wsd, 20, ("steps", 2), dev)
+        torch.cuda.empty_cache()
     if not args.no_batched:
         log("batched workload")
         del res
@@ -603,7 +785,10 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_deep_amr:
         log("deep-AMR workload: generating")
-        out["deep_amr"] = time_deep_amr(forms, 10, api, inputs, None if args.no_tune else autotune)
+        out["deep_amr"], dev = time_deep_amr(forms, 10, api, inputs, None if args.no_tune else autotune,
+                                             0 if args.no_cpu_baseline else 1)
+        if dev:
+            cases["deep_amr"] = (deep_workload(inputs), 1, ("octs", 0, 1 << 17), dev)
         torch.cuda.empty_cache()
     if not args.no_mg:
         log("multigrid Poisson V-cycles")
@@ -614,8 +799,14 @@ def main():
         out["dynamic"] = time_dynamic(api, inputs)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        log("oracle CPU baseline on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_octs)
+        log("oracle on the host: timings and the parity re-check")
+        order = ["sod_l5", "sedov_amr", "random256", "deep_amr"]
+        out["cpu_baseline"], out["parity"] = cpu_baseline({k: cases[k] for k in order if k in cases},
+                                                          args.cpu_sample_octs)
+        if not out["parity"]["ok"]:
+            out["value"] = None
+            print(json.dumps(out), flush=True)
+            sys.exit("the device state differs from the oracle's beyond the stated bars")
     print(json.dumps(out), flush=True)
 
 

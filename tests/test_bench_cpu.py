@@ -57,3 +57,34 @@ def test_digest_ignores_comments(tmp_path, monkeypatch):
     assert b.kernel_source_digest() == d0
     p.write_text(p.read_text() + "static int unused_marker = 1;\n")
     assert b.kernel_source_digest() != d0
+
+
+def test_parity_recheck_accepts_the_oracle_and_rejects_a_change():
+    """The bench's in-run re-check: a device state equal to the oracle's
+    passes, one cell off by 1e-10 (relative) fails the FP64 bar, and an L1
+    error above 1e-5 fails the mixed bar."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_2607_20704_amd import inputs as I
+    b = load_bench()
+    w = I.sod_uniform()
+    T = O.Tree(w.ijkl, w.bc)
+    ref = T.permute_cells(w.u)
+    dts = T.run(ref, w.gamma, w.cfl, 2)
+    cases = {"sod_l5": (w, 2, ("steps", 1), {"fp64": (ref.copy(), dts.copy()), "mixed": (ref.copy(), dts.copy())})}
+    base, par = b.cpu_baseline(cases, 0)
+    assert par["ok"] and par["cases"]["sod_l5"]["fp64_worst_ratio"] == 0.0
+    assert base["kind"] == "oracle" and base["cores"] >= 1 and base["serial"]["cores"] == 1
+    assert base["value"] > 0 and base["serial"]["value"] > 0
+    bad = ref.copy()
+    bad[1000, 0] *= 1 + 1e-10
+    cases["sod_l5"] = (w, 2, ("steps", 1), {"fp64": (bad, dts.copy())})
+    _, par = b.cpu_baseline(cases, 0)
+    assert not par["ok"] and not par["cases"]["sod_l5"]["fp64_ok"]
+    off = ref.copy()
+    off[:, 4] *= 1 + 1e-4
+    cases["sod_l5"] = (w, 2, ("steps", 1), {"mixed": (off, dts.copy())})
+    _, par = b.cpu_baseline(cases, 0)
+    assert not par["ok"] and not par["cases"]["sod_l5"]["mixed_ok"]
+    assert np.isclose(par["cases"]["sod_l5"]["mixed_l1"][4], 1e-4, rtol=1e-6)

@@ -1240,3 +1240,263 @@ void orc_mg_residual(int L, const double *phi, const double *f, double *r)
 void orc_mg_prolong_add(int Lc, const double *e, double *phi) { mg_prolong_add(e, phi, 1 << Lc); }
 
 void orc_mg_smooth(int L, double *phi, const double *f, int sweeps) { mg_smooth(phi, f, 1 << L, ldexp(1.0, -L), sweeps); }
+
+/* ------------------------------------------------------------------------
+ * The self-gravity solver on one level of an AMR tree (Sec. 5: the
+ * potential is built level by level with V-cycles; red-black Gauss-Seidel
+ * whose diagonal is adjusted in cells cut by the level's boundary, located
+ * with a signed-distance-like mask; residuals restricted by the mean of 8
+ * children; corrections prolongated with weights 27, 9, 3, 1 over 64).
+ *
+ * Readings taken here (the paper names the operations, not these details):
+ * - Level L's unknowns are the potential of every cell of its octs (the
+ *   domain).  The equation is the 7-point Lap phi = f.  A face neighbour
+ *   outside the domain lies in a leaf of level L-1; its value is fixed
+ *   (Dirichlet data): the trilinear interpolation of level L-1's potential
+ *   at its centre, with the prolongation's weights.  Level L-1 is solved
+ *   first and is not changed by level L.  A complete periodic level (the
+ *   coarsest) has no such neighbour.
+ * - The coarse levels of level L's V-cycle are levels L-1 .. lcoarse,
+ *   holding the cells whose descendants reach the domain.  mask = +1 on a
+ *   domain cell and -1 on any other level-L position; on a coarser level,
+ *   the mean of the 8 children's masks.  A cell with mask > 0 is inside.
+ * - On a coarse level the correction e obeys Lap e = (restricted residual)
+ *   with e = 0 on the boundary, placed between an inside cell i and an
+ *   outside neighbour j where the mask changes sign, at the fraction
+ *   theta = m_i / (m_i - m_j) of the way; e_j is replaced by the linear
+ *   extrapolation e_i (1 - 1/theta).  With s the sum of the inside
+ *   neighbours and d the sum of (1/theta - 1) = (m_i - m_j) / m_i - 1 over
+ *   the outside ones (faces in the order x-, x+, y-, y+, z-, z+), a
+ *   Gauss-Seidel update is e_i = (s - h^2 f_i) / (6 + d) and the residual is
+ *   f_i - (s - (6 + d) e_i) / h^2.  Cells with mask <= 0 keep e = 0 and
+ *   residual 0.  On a complete level these reduce to the periodic solver's
+ *   expressions, value for value.
+ * - The fine level's Gauss-Seidel update and residual use the six
+ *   neighbour values (domain cells or Dirichlet data) summed as the
+ *   periodic solver does.  Cells outside the domain keep residual 0, so the
+ *   restriction averages zeros there.
+ * Grids are dense, [z][y][x], N_m = 2^m cells per side, periodic. */
+
+static double amr_ghost(const double *phic, int Nc, int i, int j, int k)
+{
+    const int I = (i + 2 * Nc) % (2 * Nc) >> 1, J = (j + 2 * Nc) % (2 * Nc) >> 1, K = (k + 2 * Nc) % (2 * Nc) >> 1;
+    const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
+    const double w = ((((((27.0 * MG_AT(phic, Nc, I, J, K) + 9.0 * MG_AT(phic, Nc, I + sx, J, K)) +
+                          9.0 * MG_AT(phic, Nc, I, J + sy, K)) + 9.0 * MG_AT(phic, Nc, I, J, K + sz)) +
+                        3.0 * MG_AT(phic, Nc, I + sx, J + sy, K)) + 3.0 * MG_AT(phic, Nc, I + sx, J, K + sz)) +
+                      3.0 * MG_AT(phic, Nc, I, J + sy, K + sz)) + MG_AT(phic, Nc, I + sx, J + sy, K + sz);
+    return 0.015625 * w;
+}
+
+/* value of the fine-level neighbour (i, j, k): the domain cell's potential
+ * or the Dirichlet datum */
+static double amr_fine_value(const double *phi, const double *mask, const double *phic, int N, int i, int j, int k)
+{
+    if (MG_AT(mask, N, i, j, k) > 0.0) return MG_AT(phi, N, i, j, k);
+    return amr_ghost(phic, N / 2, i, j, k);
+}
+
+static double amr_fine_sum6(const double *phi, const double *mask, const double *phic, int N, int i, int j, int k)
+{
+    return ((((amr_fine_value(phi, mask, phic, N, i - 1, j, k) + amr_fine_value(phi, mask, phic, N, i + 1, j, k)) +
+              amr_fine_value(phi, mask, phic, N, i, j - 1, k)) + amr_fine_value(phi, mask, phic, N, i, j + 1, k)) +
+            amr_fine_value(phi, mask, phic, N, i, j, k - 1)) + amr_fine_value(phi, mask, phic, N, i, j, k + 1);
+}
+
+/* inside-neighbour sum s and diagonal excess d of a coarse cell */
+static void amr_coarse_terms(const double *e, const double *mask, int N, int i, int j, int k, double *s_out,
+                             double *d_out)
+{
+    const int di[6] = {-1, 1, 0, 0, 0, 0}, dj[6] = {0, 0, -1, 1, 0, 0}, dk[6] = {0, 0, 0, 0, -1, 1};
+    const double mi = MG_AT(mask, N, i, j, k);
+    double s = 0.0, d = 0.0;
+    for (int f = 0; f < 6; ++f) {
+        const double mj = MG_AT(mask, N, i + di[f], j + dj[f], k + dk[f]);
+        if (mj > 0.0)
+            s = s + MG_AT(e, N, i + di[f], j + dj[f], k + dk[f]);
+        else
+            d = d + ((mi - mj) / mi - 1.0);
+    }
+    *s_out = s;
+    *d_out = d;
+}
+
+static void amr_smooth(int fine, double *phi, const double *f, const double *mask, const double *phic, int N, double h,
+                       int sweeps)
+{
+    const double h2 = h * h;
+    for (int sw = 0; sw < sweeps; ++sw)
+        for (int colour = 0; colour < 2; ++colour)
+            for (int k = 0; k < N; ++k)
+                for (int j = 0; j < N; ++j)
+                    for (int i = 0; i < N; ++i) {
+                        if (((i + j + k) & 1) != colour || !(MG_AT(mask, N, i, j, k) > 0.0)) continue;
+                        if (fine) {
+                            MG_AT(phi, N, i, j, k) =
+                                (amr_fine_sum6(phi, mask, phic, N, i, j, k) - h2 * MG_AT(f, N, i, j, k)) / 6.0;
+                        } else {
+                            double s, d;
+                            amr_coarse_terms(phi, mask, N, i, j, k, &s, &d);
+                            MG_AT(phi, N, i, j, k) = (s - h2 * MG_AT(f, N, i, j, k)) / (6.0 + d);
+                        }
+                    }
+}
+
+static void amr_residual(int fine, const double *phi, const double *f, double *r, const double *mask,
+                         const double *phic, int N, double h)
+{
+    const double h2 = h * h;
+    for (int k = 0; k < N; ++k)
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) {
+                if (!(MG_AT(mask, N, i, j, k) > 0.0)) {
+                    MG_AT(r, N, i, j, k) = 0.0;
+                    continue;
+                }
+                double lap;
+                if (fine) {
+                    lap = (amr_fine_sum6(phi, mask, phic, N, i, j, k) - 6.0 * MG_AT(phi, N, i, j, k)) / h2;
+                } else {
+                    double s, d;
+                    amr_coarse_terms(phi, mask, N, i, j, k, &s, &d);
+                    lap = (s - (6.0 + d) * MG_AT(phi, N, i, j, k)) / h2;
+                }
+                MG_AT(r, N, i, j, k) = MG_AT(f, N, i, j, k) - lap;
+            }
+}
+
+/* phi += prolongated correction, on inside cells only */
+static void amr_prolong_add(const double *e, double *phi, const double *mask, int Nc)
+{
+    const int N = 2 * Nc;
+    for (int k = 0; k < N; ++k)
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) {
+                if (!(MG_AT(mask, N, i, j, k) > 0.0)) continue;
+                const int I = i >> 1, J = j >> 1, K = k >> 1;
+                const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
+                const double w = ((((((27.0 * MG_AT(e, Nc, I, J, K) + 9.0 * MG_AT(e, Nc, I + sx, J, K)) +
+                                      9.0 * MG_AT(e, Nc, I, J + sy, K)) + 9.0 * MG_AT(e, Nc, I, J, K + sz)) +
+                                    3.0 * MG_AT(e, Nc, I + sx, J + sy, K)) + 3.0 * MG_AT(e, Nc, I + sx, J, K + sz)) +
+                                  3.0 * MG_AT(e, Nc, I, J + sy, K + sz)) + MG_AT(e, Nc, I + sx, J + sy, K + sz);
+                MG_AT(phi, N, i, j, k) = MG_AT(phi, N, i, j, k) + 0.015625 * w;
+            }
+}
+
+typedef struct {
+    int L, lcoarse, nu1, nu2, ncoarse;
+    double *phi[ORC_MAX_LEVEL + 1], *f[ORC_MAX_LEVEL + 1], *r[ORC_MAX_LEVEL + 1], *mask[ORC_MAX_LEVEL + 1];
+    const double *phic;
+} AmrMg;
+
+static void amr_vcycle(AmrMg *g, int l)
+{
+    const int N = 1 << l, fine = l == g->L;
+    const double h = ldexp(1.0, -l);
+    if (l == g->lcoarse) {
+        amr_smooth(fine, g->phi[l], g->f[l], g->mask[l], g->phic, N, h, g->ncoarse);
+        return;
+    }
+    amr_smooth(fine, g->phi[l], g->f[l], g->mask[l], g->phic, N, h, g->nu1);
+    amr_residual(fine, g->phi[l], g->f[l], g->r[l], g->mask[l], g->phic, N, h);
+    mg_restrict(g->r[l], g->f[l - 1], N / 2);
+    const size_t nc = (size_t)(N / 2) * (N / 2) * (N / 2);
+    for (size_t q = 0; q < nc; ++q) g->phi[l - 1][q] = 0.0;
+    amr_vcycle(g, l - 1);
+    amr_prolong_add(g->phi[l - 1], g->phi[l], g->mask[l], N / 2);
+    amr_smooth(fine, g->phi[l], g->f[l], g->mask[l], g->phic, N, h, g->nu2);
+}
+
+/* ncycles V-cycles on level L.  inside[N^3] (N = 2^L) marks the domain
+ * cells; phic[(N/2)^3] holds level L-1's potential (read only where a
+ * Dirichlet datum needs it; may be NULL when no domain cell has an outside
+ * neighbour); phi_io and f_in are dense over level L (only domain cells
+ * are read and written).  res[c] = root mean square of the domain cells'
+ * residual after cycle c (may be NULL).  With lcoarse == L the cycle is
+ * ncoarse sweeps. */
+void orc_mg_amr_vcycles(int L, int lcoarse, int nu1, int nu2, int ncoarse, int ncycles, const uint8_t *inside,
+                        const double *phic, double *phi_io, const double *f_in, double *res)
+{
+    AmrMg g;
+    g.L = L;
+    g.lcoarse = lcoarse;
+    g.nu1 = nu1;
+    g.nu2 = nu2;
+    g.ncoarse = ncoarse;
+    g.phic = phic;
+    for (int l = lcoarse; l <= L; ++l) {
+        const size_t n = (size_t)1 << (3 * l);
+        g.phi[l] = (double *)calloc(n, sizeof(double));
+        g.f[l] = (double *)calloc(n, sizeof(double));
+        g.r[l] = (double *)calloc(n, sizeof(double));
+        g.mask[l] = (double *)calloc(n, sizeof(double));
+    }
+    const size_t n = (size_t)1 << (3 * L);
+    size_t ndom = 0;
+    for (size_t q = 0; q < n; ++q) {
+        g.mask[L][q] = inside[q] ? 1.0 : -1.0;
+        ndom += inside[q] ? 1 : 0;
+        g.phi[L][q] = inside[q] ? phi_io[q] : 0.0;
+        g.f[L][q] = inside[q] ? f_in[q] : 0.0;
+    }
+    for (int l = L - 1; l >= lcoarse; --l) mg_restrict(g.mask[l + 1], g.mask[l], 1 << l);
+    for (int c = 0; c < ncycles; ++c) {
+        amr_vcycle(&g, L);
+        if (res) {
+            amr_residual(1, g.phi[L], g.f[L], g.r[L], g.mask[L], phic, 1 << L, ldexp(1.0, -L));
+            double s = 0.0;
+            for (size_t q = 0; q < n; ++q) s += g.r[L][q] * g.r[L][q];
+            res[c] = ndom ? sqrt(s / (double)ndom) : 0.0;
+        }
+    }
+    for (size_t q = 0; q < n; ++q)
+        if (inside[q]) phi_io[q] = g.phi[L][q];
+    for (int l = lcoarse; l <= L; ++l) {
+        free(g.phi[l]);
+        free(g.f[l]);
+        free(g.r[l]);
+        free(g.mask[l]);
+    }
+}
+
+/* the fine level's residual alone (domain cells; 0 elsewhere) */
+void orc_mg_amr_residual(int L, const uint8_t *inside, const double *phic, const double *phi, const double *f,
+                         double *r)
+{
+    const size_t n = (size_t)1 << (3 * L);
+    double *mask = (double *)malloc(n * sizeof(double));
+    for (size_t q = 0; q < n; ++q) mask[q] = inside[q] ? 1.0 : -1.0;
+    amr_residual(1, phi, f, r, mask, phic, 1 << L, ldexp(1.0, -L));
+    free(mask);
+}
+
+/* the masks of every level lcoarse .. L, dense, concatenated coarse first */
+void orc_mg_amr_masks(int L, int lcoarse, const uint8_t *inside, double *out)
+{
+    double *m[ORC_MAX_LEVEL + 1];
+    for (int l = lcoarse; l <= L; ++l) m[l] = (double *)malloc(((size_t)1 << (3 * l)) * sizeof(double));
+    const size_t n = (size_t)1 << (3 * L);
+    for (size_t q = 0; q < n; ++q) m[L][q] = inside[q] ? 1.0 : -1.0;
+    for (int l = L - 1; l >= lcoarse; --l) mg_restrict(m[l + 1], m[l], 1 << l);
+    size_t off = 0;
+    for (int l = lcoarse; l <= L; ++l) {
+        const size_t nl = (size_t)1 << (3 * l);
+        memcpy(out + off, m[l], nl * sizeof(double));
+        off += nl;
+        free(m[l]);
+    }
+}
+
+/* For the pins: the coarse problem of level L's V-cycle on level m alone,
+ * Lap e = f with e = 0 on the boundary the masks place, by `sweeps`
+ * Gauss-Seidel sweeps from e (in/out); f and e dense over level m. */
+void orc_mg_amr_coarse_sweeps(int L, int m, const uint8_t *inside, const double *f, double *e, int sweeps)
+{
+    double *mk[ORC_MAX_LEVEL + 1];
+    for (int l = m; l <= L; ++l) mk[l] = (double *)malloc(((size_t)1 << (3 * l)) * sizeof(double));
+    const size_t n = (size_t)1 << (3 * L);
+    for (size_t q = 0; q < n; ++q) mk[L][q] = inside[q] ? 1.0 : -1.0;
+    for (int l = L - 1; l >= m; --l) mg_restrict(mk[l + 1], mk[l], 1 << l);
+    amr_smooth(0, e, f, mk[m], NULL, 1 << m, ldexp(1.0, -m), sweeps);
+    for (int l = m; l <= L; ++l) free(mk[l]);
+}

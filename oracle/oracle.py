@@ -126,6 +126,14 @@ def lib():
         L.orc_mg_prolong_add.argtypes = [ctypes.c_int, P, P]
         L.orc_mg_smooth.restype = None
         L.orc_mg_smooth.argtypes = [ctypes.c_int, P, P, ctypes.c_int]
+        L.orc_mg_amr_vcycles.restype = None
+        L.orc_mg_amr_vcycles.argtypes = [ctypes.c_int] * 6 + [P, P, P, P, P]
+        L.orc_mg_amr_residual.restype = None
+        L.orc_mg_amr_residual.argtypes = [ctypes.c_int, P, P, P, P, P]
+        L.orc_mg_amr_coarse_sweeps.restype = None
+        L.orc_mg_amr_coarse_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int]
+        L.orc_mg_amr_masks.restype = None
+        L.orc_mg_amr_masks.argtypes = [ctypes.c_int, ctypes.c_int, P, P]
         L.orc_refine.restype = ctypes.c_int
         L.orc_refine.argtypes = [i64, P, P, P, ctypes.c_int, f64, f64, ctypes.c_int, ctypes.c_int, P, P, i64, P, P, P]
         L.orc_step_subcycled.restype = f64
@@ -404,3 +412,120 @@ def mg_smooth(phi, f, sweeps):
     f = np.ascontiguousarray(f, dtype=np.float64)
     lib().orc_mg_smooth(int(round(np.log2(phi.shape[0]))), _p(phi), _p(f), int(sweeps))
     return phi
+
+
+# ------------------------------------------------- multigrid on an AMR tree
+
+def _level_cells(T, level):
+    """Dense [z][y][x] indices (flat, N = 2^level) of the cells of level
+    `level`'s octs, in key order (cell c = x + 2y + 4z of each oct)."""
+    ob, oe = T.level_begin[level], T.level_begin[level + 1]
+    ijk = T.ijkl[ob:oe, :3].astype(np.int64)
+    N = 1 << level
+    q = np.arange(8)
+    x = 2 * ijk[:, 0:1] + (q & 1)
+    y = 2 * ijk[:, 1:2] + ((q >> 1) & 1)
+    z = 2 * ijk[:, 2:3] + (q >> 2)
+    return ((z * N + y) * N + x).reshape(-1), 8 * ob, 8 * oe
+
+
+def _dense_level(T, level, values, fill):
+    N = 1 << level
+    d = np.full(N ** 3, fill, dtype=np.float64)
+    idx, cb, ce = _level_cells(T, level)
+    d[idx] = values[cb:ce]
+    return d
+
+
+def mg_amr_level(T, phi, f, level, ncycles, lcoarse=1, nu1=2, nu2=2, ncoarse=50):
+    """V-cycles for Lap phi = f on the cells of level `level` of tree T
+    (periodic), the coarser level's potential giving the Dirichlet data at
+    the level's boundary.  phi and f are per-cell arrays in key order (8
+    per oct); phi's entries on level `level` are updated in place (the
+    others are read only).  Returns the RMS residual of the level's cells
+    after each cycle.  Dense grids: for levels up to about 8."""
+    assert T.bc == PERIODIC
+    assert phi.dtype == np.float64 and phi.flags.c_contiguous and phi.shape == (8 * T.n,)
+    N = 1 << level
+    idx, cb, ce = _level_cells(T, level)
+    inside = np.zeros(N ** 3, np.uint8)
+    inside[idx] = 1
+    dphi = np.zeros(N ** 3)
+    dphi[idx] = phi[cb:ce]
+    df = np.zeros(N ** 3)
+    df[idx] = f[cb:ce]
+    phic = _dense_level(T, level - 1, phi, np.nan) if level > T.lmin else None
+    res = np.zeros(ncycles)
+    lib().orc_mg_amr_vcycles(int(level), int(lcoarse), int(nu1), int(nu2), int(ncoarse), int(ncycles), _p(inside),
+                             None if phic is None else _p(phic), _p(dphi), _p(df), _p(res))
+    phi[cb:ce] = dphi[idx]
+    return res
+
+
+def mg_amr_residual(T, phi, f, level):
+    """Residual f - Lap phi of the cells of level `level` (key order)."""
+    N = 1 << level
+    idx, cb, ce = _level_cells(T, level)
+    inside = np.zeros(N ** 3, np.uint8)
+    inside[idx] = 1
+    dphi = np.zeros(N ** 3)
+    dphi[idx] = phi[cb:ce]
+    df = np.zeros(N ** 3)
+    df[idx] = f[cb:ce]
+    phic = _dense_level(T, level - 1, phi, np.nan) if level > T.lmin else None
+    r = np.zeros(N ** 3)
+    lib().orc_mg_amr_residual(int(level), _p(inside), None if phic is None else _p(phic), _p(dphi), _p(df), _p(r))
+    return r[idx]
+
+
+def mg_amr_masks(T, level, lcoarse=1):
+    """The masks of levels lcoarse .. level of level `level`'s V-cycle,
+    dense, as a dict level -> [N][N][N]."""
+    N = 1 << level
+    idx, _, _ = _level_cells(T, level)
+    inside = np.zeros(N ** 3, np.uint8)
+    inside[idx] = 1
+    total = sum(1 << (3 * l) for l in range(lcoarse, level + 1))
+    out = np.zeros(total)
+    lib().orc_mg_amr_masks(int(level), int(lcoarse), _p(inside), _p(out))
+    masks, off = {}, 0
+    for l in range(lcoarse, level + 1):
+        n = 1 << l
+        masks[l] = out[off:off + n ** 3].reshape(n, n, n)
+        off += n ** 3
+    return masks
+
+
+def mg_amr_solve(T, f, ncycles, lcoarse=1, nu1=2, nu2=2, ncoarse=50, phi=None):
+    """The potential of every level, coarsest first: `ncycles` V-cycles per
+    level (f on the coarsest level must have zero mean).  Returns (phi,
+    {level: RMS residual after each cycle})."""
+    phi = np.zeros(8 * T.n) if phi is None else np.ascontiguousarray(phi, dtype=np.float64).copy()
+    res = {}
+    for l in range(T.lmin, T.lmax + 1):
+        res[l] = mg_amr_level(T, phi, f, l, ncycles, lcoarse, nu1, nu2, ncoarse)
+    return phi, res
+
+
+def mg_amr_coarse_sweeps(inside, m, f, e, sweeps):
+    """Gauss-Seidel sweeps of the coarse problem on level m of a V-cycle
+    whose finest level's domain is the dense bool grid `inside` (2^L per
+    side): Lap e = f, e = 0 on the boundary placed by the masks.  f and e
+    are dense over level m; returns the new e."""
+    inside = np.ascontiguousarray(inside, dtype=np.uint8).reshape(-1)
+    L = int(round(np.log2(round(len(inside) ** (1.0 / 3.0)))))
+    assert len(inside) == 1 << (3 * L)
+    e = np.ascontiguousarray(e, dtype=np.float64).reshape(-1).copy()
+    f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
+    lib().orc_mg_amr_coarse_sweeps(int(L), int(m), _p(inside), _p(f), _p(e), int(sweeps))
+    return e
+
+
+def mg_amr_masks_dense(inside, m):
+    """The mask of level m for the dense bool domain grid `inside`."""
+    inside = np.ascontiguousarray(inside, dtype=np.uint8).reshape(-1)
+    L = int(round(np.log2(round(len(inside) ** (1.0 / 3.0)))))
+    total = sum(1 << (3 * l) for l in range(m, L + 1))
+    out = np.zeros(total)
+    lib().orc_mg_amr_masks(int(L), int(m), _p(inside), _p(out))
+    return out[:1 << (3 * m)]

@@ -72,7 +72,7 @@
 extern "C" {
 #endif
 
-#define RG_ABI_VERSION 11
+#define RG_ABI_VERSION 12
 #define RG_MAX_LEVEL 21
 #define RG_NBR_OUTSIDE INT32_MIN
 #define RG_RHO_MIN 1e-10
@@ -546,6 +546,66 @@ rg_status rg_mg_vcycles(const rg_tree *t, double *d_phi, double *d_f, double *d_
 /* r = f - Lap phi on one complete periodic level of t (as in a V-cycle). */
 rg_status rg_mg_residual(const rg_tree *t, const double *d_phi, const double *d_f, double *d_r, int level,
                          void *stream);
+
+/* The potential on one level of an AMR tree (Sec. 5: built level by level
+ * with V-cycles; the Gauss-Seidel diagonal adjusted in cells the boundary
+ * cuts, located with a signed-distance-like mask).  Tree t: periodic, with
+ * keys and neighbour lists.  Level L's unknowns are the potentials of its
+ * octs' cells; the equation is Lap phi = f with the 7-point Laplacian and
+ * h = 2^-L.  A face neighbour outside the level lies in a level-(L-1) leaf
+ * (the tree is graded); its value is the trilinear interpolation of level
+ * L-1's potential at its centre (weights 27, 9, 3, 1 over 64 from the 8
+ * nearest level-(L-1) cells), fixed during the solve.  Level L-1 is solved
+ * before level L and is not changed by it.  On the coarsest level of a tree
+ * (complete, periodic) no neighbour is outside and f must have zero mean.
+ *
+ * The V-cycle's coarse levels m = L-1 .. lcoarse hold the ancestors of level
+ * L's octs.  mask = +1 on level L's cells; on a coarse cell the mean of its
+ * 8 children's masks (-1 for a cell without children).  A coarse cell is
+ * inside when its mask is positive.  The coarse correction e solves Lap e =
+ * (restricted residual) with e = 0 on the boundary: for an inside cell i
+ * with s the sum of its inside face neighbours and d the sum over outside
+ * ones j (absent cells count m_j = -1) of (m_i - m_j) / m_i - 1, a
+ * Gauss-Seidel update is e_i = (s - h^2 f_i) / (6 + d) and the residual
+ * f_i - (s - (6 + d) e_i) / h^2; outside cells keep e = 0 and residual 0.
+ * One V-cycle on level l: nu1 sweeps (a red pass over cells with even
+ * coordinate sum, then black), the residual, restricted to level l-1 as the
+ * mean of 8 children (summed pairwise in cell order), a correction on l-1
+ * from zero (recursively; ncoarse sweeps on lcoarse, or on L itself when
+ * lcoarse == L), added by trilinear interpolation to the inside cells (absent
+ * coarse cells count 0), then nu2 sweeps.  Faces are summed in the order x-,
+ * x+, y-, y+, z-, z+.  On a complete level the values are rg_mg_vcycles'.
+ *
+ * rg_mg_level_create builds the hierarchy of level `level` (coarse keys,
+ * their hash table, same-level neighbour lists, father links and masks) in
+ * one device allocation owned by the handle; synchronises `stream` once per
+ * coarse level.  The handle is valid while t's octs are unchanged (checked:
+ * RG_EINVAL otherwise).  Errors: RG_EINVAL for a tree that is not periodic, a
+ * level outside the tree or without octs, lcoarse outside 1..level;
+ * RG_EHIP on allocation failure (nothing is then allocated). */
+typedef struct rg_mg_level rg_mg_level;
+rg_status rg_mg_level_create(const rg_tree *t, int level, int lcoarse, rg_mg_level **out, void *stream);
+
+/* h_octs[m] (m = 0 .. RG_MAX_LEVEL) = octs of level m in the hierarchy
+ * (level L's own octs at m = L). */
+rg_status rg_mg_level_counts(const rg_mg_level *h, int64_t *h_octs);
+
+/* ncycles V-cycles on h's level.  d_phi, d_f: per-cell arrays over the whole
+ * tree (8 n_oct doubles, key order).  On entry d_phi holds level L-1's
+ * potential (read) and the initial guess on level L, which is updated in
+ * place; d_f holds the right-hand side on level L.  No other entry of either
+ * array is read or written.  Calls on one handle must not overlap (the
+ * handle holds the coarse levels' work arrays). */
+rg_status rg_mg_level_vcycles(rg_mg_level *h, const rg_tree *t, double *d_phi, const double *d_f, int nu1, int nu2,
+                              int ncoarse, int ncycles, void *stream);
+
+/* d_r (per-cell over the whole tree) = f - Lap phi on the cells of h's
+ * level, with the same boundary values; other entries are not written. */
+rg_status rg_mg_level_residual(const rg_mg_level *h, const rg_tree *t, const double *d_phi, const double *d_f,
+                               double *d_r, void *stream);
+
+/* Frees the handle and its device memory (NULL: nothing). */
+rg_status rg_mg_level_destroy(rg_mg_level *h);
 
 /* ---------------------------------------------------------------------- */
 /* Many independent trees in one graph launch                             */

@@ -97,6 +97,11 @@ SIGNATURES = {
     "rg_schedule_build_device": (st, [ctypes.POINTER(RgTree), P, i64, P, sz, ctypes.POINTER(RgSchedule), P]),
     "rg_mg_vcycles": (st, [ctypes.POINTER(RgTree), P, P, P] + [ctypes.c_int] * 6 + [P]),
     "rg_mg_residual": (st, [ctypes.POINTER(RgTree), P, P, P, ctypes.c_int, P]),
+    "rg_mg_level_create": (st, [ctypes.POINTER(RgTree), ctypes.c_int, ctypes.c_int, ctypes.POINTER(P), P]),
+    "rg_mg_level_counts": (st, [P, P]),
+    "rg_mg_level_vcycles": (st, [P, ctypes.POINTER(RgTree), P, P] + [ctypes.c_int] * 4 + [P]),
+    "rg_mg_level_residual": (st, [P, ctypes.POINTER(RgTree), P, P, P, P]),
+    "rg_mg_level_destroy": (st, [P]),
     "rg_refine_workspace_bytes": (sz, [i64]),
     "rg_refine_flags": (st, [ctypes.POINTER(RgTree), P, ctypes.POINTER(RgRefineParams), ctypes.c_int, P, P]),
     "rg_refine": (st, [ctypes.POINTER(RgTree), P, P, ctypes.POINTER(RgRefineParams), P, sz, P]),

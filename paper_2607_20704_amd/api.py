@@ -499,6 +499,63 @@ class Multigrid:
         return self.r[self.fine]
 
 
+class MgLevel:
+    """The multigrid hierarchy of one level of a periodic AMR tree
+    (rg_mg_level_create): V-cycles for Lap phi = f on the level's cells, the
+    coarser level's potential giving the boundary values.  phi and f are
+    per-cell arrays over the whole tree (8 n_oct doubles, key order)."""
+
+    def __init__(self, tree, level, lcoarse=1):
+        self.tree, self.level = tree, int(level)
+        h = ctypes.c_void_p()
+        check(L.lib().rg_mg_level_create(ctypes.byref(tree._desc), self.level, int(lcoarse), ctypes.byref(h),
+                                         _stream()))
+        self._h = h
+
+    def counts(self):
+        """{level: octs} of the hierarchy (this level's own octs included)."""
+        out = (ctypes.c_int64 * (RG_MAX_LEVEL + 1))()
+        check(L.lib().rg_mg_level_counts(self._h, out))
+        return {m: int(out[m]) for m in range(RG_MAX_LEVEL + 1) if out[m]}
+
+    def vcycles(self, phi, f, ncycles, nu1=2, nu2=2, ncoarse=50):
+        check(L.lib().rg_mg_level_vcycles(self._h, ctypes.byref(self.tree._desc), _ptr(phi), _ptr(f), int(nu1),
+                                          int(nu2), int(ncoarse), int(ncycles), _stream()))
+
+    def residual(self, phi, f, r=None):
+        """f - Lap phi on this level's cells, as a slice of a per-cell array."""
+        r = torch.zeros_like(phi) if r is None else r
+        check(L.lib().rg_mg_level_residual(self._h, ctypes.byref(self.tree._desc), _ptr(phi), _ptr(f), _ptr(r),
+                                           _stream()))
+        lb = self.tree.level_begin
+        return r[8 * int(lb[self.level]):8 * int(lb[self.level + 1])]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().rg_mg_level_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mg_solve_levels(tree, f, ncycles, nu1=2, nu2=2, ncoarse=50, lcoarse=1, phi=None, levels=None):
+    """The potential of every level of `tree`, coarsest first, `ncycles`
+    V-cycles each (f on the coarsest level must have zero mean).  Returns
+    (phi, {level: MgLevel}); the hierarchies can be reused while the tree is
+    unchanged."""
+    phi = torch.zeros_like(f) if phi is None else phi
+    levels = levels or {}
+    for l in range(tree.lmin, tree.lmax + 1):
+        if l not in levels:
+            levels[l] = MgLevel(tree, l, lcoarse)
+        levels[l].vcycles(phi, f, ncycles, nu1, nu2, ncoarse)
+    return phi, levels
+
+
 # ---------------------------------------------------------------- many trees
 
 class Batch:

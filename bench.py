@@ -510,6 +510,72 @@ def time_mg(api, level=8, ncycles=5):
             "octs_in_hierarchy": M.tree.n}
 
 
+def time_mg_amr(api, inputs, trees=("sedov", "deep"), ncycles=4, reps=5):
+    """The level-by-level multigrid on AMR trees (rg_mg_level_*): per level,
+    the hierarchy build, the time of one V-cycle (median of `reps`), the
+    level's cell-updates per second per V-cycle and the residual factor per
+    cycle over `ncycles` cycles from zero; then the whole solve (every level
+    in turn, `ncycles` cycles each).  Random right-hand side (zero mean on
+    the coarsest level), seed 20704."""
+    import numpy as np
+    import torch
+    out = {}
+    for name in trees:
+        w = inputs.sedov_amr() if name == "sedov" else deep_workload(inputs)
+        D = api.DeviceTree(w.ijkl, w.bc)
+        rng = np.random.default_rng(20704)
+        f = rng.standard_normal(8 * D.n)
+        cb, ce = 8 * int(D.level_begin[D.lmin]), 8 * int(D.level_begin[D.lmin + 1])
+        f[cb:ce] -= f[cb:ce].mean()
+        fd = torch.as_tensor(f, device="cuda")
+        phi = torch.zeros_like(fd)
+        r = torch.zeros_like(fd)
+        levels = {}
+        total_ms = 0.0
+        for l in range(D.lmin, D.lmax + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h = api.MgLevel(D, l)
+            build_ms = 1e3 * (time.perf_counter() - t0)
+            res = []
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(ncycles)]
+            for c in range(ncycles):
+                ev[c][0].record()
+                h.vcycles(phi, fd, 1)
+                ev[c][1].record()
+                rr = h.residual(phi, fd, r)
+                res.append(float(torch.sqrt((rr * rr).mean())))
+            torch.cuda.synchronize()
+            total_ms += sum(a.elapsed_time(b) for a, b in ev)
+            # timing: further cycles from the converged state (same work)
+            times = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                h.vcycles(phi, fd, 1)
+                b.record()
+                b.synchronize()
+                times.append(a.elapsed_time(b))
+            ms = _median(times)
+            cells = 8 * int(D.level_begin[l + 1] - D.level_begin[l])
+            levels[str(l)] = {"cells": cells, "hierarchy_octs": h.counts(), "build_ms": round(build_ms, 3),
+                              "ms_per_vcycle": round(ms, 4), "cell_updates_per_s_per_vcycle": cells / (ms * 1e-3),
+                              "residual_rms": res,
+                              "residual_factor_per_cycle": (res[-1] / res[0]) ** (1.0 / max(1, ncycles - 1))}
+            h.close()
+        cells_all = 8 * D.n
+        out[name] = {"workload": ("Sedov blast tree (base 6, refined to 8 inside r < 0.15)" if name == "sedov" else
+                                  "clumpy-gas deep tree (base 7 to level 12)") +
+                     ", Lap phi = f with a seeded random f, V(2,2) cycles to level 1, each level solved in turn "
+                     "with the coarser potential as boundary values",
+                     "octs": D.n, "levels": levels,
+                     "solve_ms_%d_cycles_per_level" % ncycles: round(total_ms, 3),
+                     "cell_updates_per_s_per_vcycle": cells_all * ncycles / (total_ms * 1e-3)}
+        del D, fd, phi, r
+        torch.cuda.empty_cache()
+    return out
+
+
 def copy_ceiling(torch, mib=1024, reps=5):
     """Practical HBM ceiling: GB/s (read + write) of a plain device copy of
     `mib` MiB, best of `reps`."""
@@ -662,7 +728,7 @@ def main():
     ap.add_argument("--no-dynamic", action="store_true", help="skip the refinement (dynamic tree) measurements")
     ap.add_argument("--no-mg", action="store_true", help="skip the multigrid Poisson measurement")
     ap.add_argument("--no-sedov", action="store_true", help="skip the Sedov AMR global-step workload")
-    ap.add_argument("--leg", choices=["all", "deep_amr", "dynamic", "mg_poisson"], default="all",
+    ap.add_argument("--leg", choices=["all", "deep_amr", "dynamic", "mg_poisson", "mg_amr"], default="all",
                     help="run one workload only and print its JSON (for profiling it); 'all' is the benchmark line")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (reference for HBM byte counters)")
@@ -678,7 +744,8 @@ def main():
     if args.leg != "all":
         forms = [f.strip() for f in args.forms.split(",") if f.strip()]
         leg = (time_deep_amr(forms, 10, api, inputs, None if args.no_tune else autotune)[0] if args.leg == "deep_amr" else
-               time_dynamic(api, inputs) if args.leg == "dynamic" else time_mg(api))
+               time_dynamic(api, inputs) if args.leg == "dynamic" else
+               time_mg_amr(api, inputs) if args.leg == "mg_amr" else time_mg(api))
         print(json.dumps({args.leg: leg}), flush=True)
         return
     log("generating the 256^3 random-field box")
@@ -793,6 +860,9 @@ def main():
     if not args.no_mg:
         log("multigrid Poisson V-cycles")
         out["mg_poisson"] = time_mg(api)
+        torch.cuda.empty_cache()
+        log("multigrid on the AMR trees, level by level")
+        out["mg_poisson_amr"] = time_mg_amr(api, inputs, ("sedov",) if args.no_deep_amr else ("sedov", "deep"))
         torch.cuda.empty_cache()
     if not args.no_dynamic:
         log("dynamic trees: refinement on the device")

@@ -312,7 +312,9 @@ __device__ __forceinline__ void brick_sweep(const BrickArgs &a, int64_t b, const
     const bool do_face = wave == ew;
     const bool do_outer = wave == ((ew + 1) & 3);
     const bool do_corner = wave == ((ew + 2) & 3) && lane < 4;
-    const bool extra_faces = wave == ((ew + 1) & 3) && lane < 2 * BC;   // faces x = 16 and y = 16
+    // faces x = 16 (lanes 0-15) and y = 16 (lanes 16-31), one Riemann pass,
+    // on the wave without a ghost-ring role
+    const bool extra_faces = wave == ((ew + 3) & 3) && lane < 2 * BC;
     int hx = 0, hy = 0;
     ring_pos(1, lane, hx, hy);      // face layer position of this lane
     const int hq = lane >> 4, hk = lane & 15;
@@ -478,37 +480,40 @@ __device__ __forceinline__ void brick_sweep(const BrickArgs &a, int64_t b, const
         }
         // DB: plane rz-1 is complete: its x/y fluxes have been in the other
         // buffer since the barrier above, and its upper z face was just
-        // evaluated
-        if constexpr (DB) {
-            if (rz >= 1) {
-                const BrickFaces<R> &PB = S.u_[(rz - 1) & 1];
-                double Ucur[NV], out[NV];
-                if constexpr (KU) {
-                    copy5(Ucur, Ucp);
-                } else {
+        // evaluated.
+        auto update_prev = [&]() {
+            if constexpr (DB) {
+                if (rz >= 1) {
+                    const BrickFaces<R> &PB = S.u_[(rz - 1) & 1];
+                    double Ucur[NV], out[NV];
+                    if constexpr (KU) {
+                        copy5(Ucur, Ucp);
+                    } else {
+                        bool sdummy;
+                        load_u(a.uold, source_cell<GEN>(S, g, x, y, rz - 1, sdummy), Ucur);
+                    }
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        const double gxm = flux_G(PB.fx[v][y * (BC + 1) + x], r);
+                        const double gxp = flux_G(PB.fx[v][y * (BC + 1) + x + 1], r);
+                        const double gym = flux_G(PB.fy[v][y * BC + x], r);
+                        const double gyp = flux_G(PB.fy[v][(y + 1) * BC + x], r);
+                        const double acc = (Ucur[v] + (gxm - gxp)) + (gym - gyp);
+                        out[v] = acc + (gz_prev[v] - gz[v]);
+                    }
                     bool sdummy;
-                    load_u(a.uold, source_cell<GEN>(S, g, x, y, rz - 1, sdummy), Ucur);
-                }
+                    const int64_t cell = source_cell<GEN>(S, g, x, y, rz - 1, sdummy);
 #pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    const double gxm = flux_G(PB.fx[v][y * (BC + 1) + x], r);
-                    const double gxp = flux_G(PB.fx[v][y * (BC + 1) + x + 1], r);
-                    const double gym = flux_G(PB.fy[v][y * BC + x], r);
-                    const double gyp = flux_G(PB.fy[v][(y + 1) * BC + x], r);
-                    const double acc = (Ucur[v] + (gxm - gxp)) + (gym - gyp);
-                    out[v] = acc + (gz_prev[v] - gz[v]);
-                }
-                bool sdummy;
-                const int64_t cell = source_cell<GEN>(S, g, x, y, rz - 1, sdummy);
-#pragma unroll
-                for (int v = 0; v < NV; ++v) a.unew[NV * cell + v] = out[v];
-                if (a.dt_next && !sp_prev && !(nxy_prev || sp_prev2 || sp_cur)) {
-                    const double sp = signal_speed(out, a.gamma);
-                    sp_max = sp > sp_max ? sp : sp_max;
-                    track_finite(nfs, sp, out);
+                    for (int v = 0; v < NV; ++v) a.unew[NV * cell + v] = out[v];
+                    if (a.dt_next && !sp_prev && !(nxy_prev || sp_prev2 || sp_cur)) {
+                        const double sp = signal_speed(out, a.gamma);
+                        sp_max = sp > sp_max ? sp : sp_max;
+                        track_finite(nfs, sp, out);
+                    }
                 }
             }
-        }
+        };
+        update_prev();
         __syncthreads();
 
         // 4. fluxes of the own low x and y faces, and of the x = 16 / y = 16
@@ -523,15 +528,28 @@ __device__ __forceinline__ void brick_sweep(const BrickArgs &a, int64_t b, const
                 store_flux(FB.fy, y * BC + x, F, r);
             }
             if (extra_faces) {
-                if (lane < BC) {
-                    const bool z2 = GEN && (spl[(BC + 1) + PW * (hk + 2)] || spl[(BC + 2) + PW * (hk + 2)]);
-                    face_F<GEN, R>(ld5(FB.fx, hk * (BC + 1) + BC).v, ld5(FB.sxm_hi, hk).v, 0, gam, g1, z2, F);
-                    store_flux(FB.fx, hk * (BC + 1) + BC, F, r);
-                } else {
-                    const bool z2 = GEN && (spl[(hk + 2) + PW * (BC + 1)] || spl[(hk + 2) + PW * (BC + 2)]);
-                    face_F<GEN, R>(ld5(FB.fy, BC * BC + hk).v, ld5(FB.sym_hi, hk).v, 1, gam, g1, z2, F);
-                    store_flux(FB.fy, BC * BC + hk, F, r);
+                // ex = 0: face (15|16) of row hk, left state in fx, right in
+                // sxm_hi; ex = 1: face (15|16) of column hk, fy and sym_hi;
+                // flat indices into the buffer, so that both halves run as
+                // one pass
+                const int ex = lane >> 4;
+                R *flat = &FB.fx[0][0];
+                const int lb = ex ? NV * FXN + BC * BC + hk : hk * (BC + 1) + BC;
+                const int ls = ex ? FYN : FXN;
+                const int rb = NV * (FXN + FYN) + ex * NV * BC + hk;
+                R Lf[NV], Rf[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    Lf[v] = flat[lb + v * ls];
+                    Rf[v] = flat[rb + v * BC];
                 }
+                const int s1 = ex ? (hk + 2) + PW * (BC + 1) : (BC + 1) + PW * (hk + 2);
+                const int s2 = ex ? s1 + PW : s1 + 1;
+                const bool z2 = GEN && (spl[s1] || spl[s2]);
+                face_F<GEN, R>(Lf, Rf, ex, gam, g1, z2, F);
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    flat[lb + v * ls] = sizeof(R) == 8 ? static_cast<R>(static_cast<double>(F[v]) * r) : F[v];
             }
         }
         // DB: the fluxes are read after the next iteration's first barrier

@@ -466,16 +466,20 @@ __device__ __forceinline__ void brick_sweep(const BrickArgs &a, int64_t b, const
             else
                 reconstruct<R>(W0, ld5(S.w, c - 1).v, ld5(S.w, c + 1).v, ld5(S.w, c - PW).v, ld5(S.w, c + PW).v, Wm,
                                Wp, h, gam, dW, Wq);
-            if (inner) {
-                face_state<R>(Wq, dW[0], true, st);
-                lds_put(FB.fx, y * (BC + 1) + x + 1, st);
-                face_state<R>(Wq, dW[1], true, st);
-                lds_put(FB.fy, (y + 1) * BC + x, st);
-                face_state<R>(Wq, dW[0], false, sxm);
-                face_state<R>(Wq, dW[1], false, sym);
-            }
+            // written on every plane, also rz = -1 and 16 where nobody reads
+            // them: the buffer of those planes is not in use then (plane
+            // rz-2's update, the last reader of this buffer, ended before
+            // the previous iteration's second barrier), and unconditional
+            // code keeps the values out of branch merges
+            face_state<R>(Wq, dW[0], true, st);
+            lds_put(FB.fx, y * (BC + 1) + x + 1, st);
+            face_state<R>(Wq, dW[1], true, st);
+            lds_put(FB.fy, (y + 1) * BC + x, st);
+            face_state<R>(Wq, dW[0], false, sxm);
+            face_state<R>(Wq, dW[1], false, sym);
             face_state<R>(Wq, dW[2], false, szm);
-            if (rz >= 0) face_G<GEN, R>(zp_prev, szm, gam, g1, r, sp_prev || sp_cur, gz);
+            // at rz = -1 zp_prev is not a state (the result is discarded)
+            face_G<GEN, R>(zp_prev, szm, gam, g1, r, sp_prev || sp_cur, gz);
             face_state<R>(Wq, dW[2], true, zp_prev);
         }
         // DB: plane rz-1 is complete: its x/y fluxes have been in the other

@@ -136,12 +136,9 @@ __device__ __forceinline__ void hllc(const R *WL, const R *WR, int dir, R gamma,
     // Both states are read once into registers and every choice below is a
     // choice between values: selecting or branching on pointers to the two
     // states (one may be in LDS, one private) would force the private state
-    // into scratch memory.  The kinetic terms of both sides are formed so
-    // that each loaded value has several uses.
+    // into scratch memory.
     const R l0 = WL[0], l1 = WL[1], l2 = WL[2], l3 = WL[3], l4 = WL[4];
     const R r0 = WR[0], r1 = WR[1], r2 = WR[2], r3 = WR[3], r4 = WR[4];
-    const R ql = (l1 * l1 + l2 * l2) + l3 * l3;
-    const R qr = (r1 * r1 + r2 * r2) + r3 * r3;
     const R ul = dir == 0 ? l1 : (dir == 1 ? l2 : l3);
     const R ur = dir == 0 ? r1 : (dir == 1 ? r2 : r3);
     const R cl = Math<R>::sqrt_(Math<R>::div(gamma * l4, l0));
@@ -169,8 +166,12 @@ __device__ __forceinline__ void hllc(const R *WL, const R *WR, int dir, R gamma,
 
     const bool useL = (sl > R(0)) || (sstar > R(0));
     const bool outer = useL ? (sl > R(0)) : !(sr > R(0));
-    const R rho = useL ? l0 : r0, p = useL ? l4 : r4, un = useL ? ul : ur, q = useL ? ql : qr;
+    const R rho = useL ? l0 : r0, p = useL ? l4 : r4, un = useL ? ul : ur;
     const R w1 = useL ? l1 : r1, w2 = useL ? l2 : r2, w3 = useL ? l3 : r3;
+    // the kinetic term of the chosen side only, from its selected velocities
+    // (the same expression as per side, so the same value); forming one per
+    // side let the compiler branch on the side to skip the other
+    const R q = (w1 * w1 + w2 * w2) + w3 * w3;
     const R s = useL ? sl : sr;
     const R E = p * g1 + R(0.5) * rho * q;
     const R d = Math<R>::div(R(1), s - sstar);

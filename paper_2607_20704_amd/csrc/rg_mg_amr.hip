@@ -255,6 +255,92 @@ __global__ void k_prolong_coarse(double *e, const double *__restrict__ mask, con
     e[cell] = e[cell] + prolong_value(e, nbr, father[g], c);
 }
 
+// ---------------------------------------------------------------- small levels
+//
+// The coarse levels with at most kTailOcts octs (all levels below the first
+// such level are smaller still) run their whole part of the V-cycle in one
+// workgroup: the same passes in the same order as the per-level launches,
+// separated by barriers instead of kernel boundaries, so the results are the
+// same bits.  Each of those launches (two per sweep, 100 for 50 sweeps on
+// the coarsest level) costs a few microseconds of GPU time however little
+// it does.
+
+constexpr int64_t kTailOcts = 512;
+constexpr int kTailThreads = 1024;
+
+struct TailArgs {
+    double *e, *f, *r;
+    const double *mask;
+    const int32_t *nbr, *father;
+    int64_t begin[RG_MAX_LEVEL + 2];
+    double h2[RG_MAX_LEVEL + 1];
+    int m0, lcoarse, nu1, nu2, ncoarse;
+};
+
+__device__ void tail_smooth(const TailArgs &A, int m, int sweeps)
+{
+    const int64_t gb = A.begin[m], n4 = 4 * (A.begin[m + 1] - gb);
+    for (int sw = 0; sw < sweeps; ++sw)
+        for (int colour = 0; colour < 2; ++colour) {
+            for (int64_t t = threadIdx.x; t < n4; t += blockDim.x) {
+                const int64_t g = gb + (t >> 2);
+                const int c = c_amr_colour[colour][t & 3];
+                const int64_t cell = 8 * g + c;
+                const double mi = A.mask[cell];
+                if (!(mi > 0.0)) continue;
+                double s, d;
+                coarse_terms(A.e, A.mask, A.nbr, g, c, mi, s, d);
+                A.e[cell] = (s - A.h2[m] * A.f[cell]) / (6.0 + d);
+            }
+            __syncthreads();
+        }
+}
+
+__global__ __launch_bounds__(kTailThreads) void k_vcycle_tail(TailArgs A)
+{
+    for (int m = A.m0; m > A.lcoarse; --m) {
+        tail_smooth(A, m, A.nu1);
+        const int64_t gb = A.begin[m], ge = A.begin[m + 1];
+        for (int64_t t = threadIdx.x; t < 8 * (ge - gb); t += blockDim.x) {
+            const int64_t g = gb + (t >> 3);
+            const int c = static_cast<int>(t & 7);
+            const int64_t cell = 8 * g + c;
+            const double mi = A.mask[cell];
+            if (!(mi > 0.0)) {
+                A.r[cell] = 0.0;
+                continue;
+            }
+            double s, d;
+            coarse_terms(A.e, A.mask, A.nbr, g, c, mi, s, d);
+            const double lap = (s - (6.0 + d) * A.e[cell]) / A.h2[m];
+            A.r[cell] = A.f[cell] - lap;
+        }
+        for (int64_t i = 8 * A.begin[m - 1] + threadIdx.x; i < 8 * A.begin[m]; i += blockDim.x) {
+            A.f[i] = 0.0;
+            A.e[i] = 0.0;
+        }
+        __syncthreads();
+        for (int64_t g = gb + threadIdx.x; g < ge; g += blockDim.x) {
+            const double *c = A.r + 8 * g;
+            A.f[A.father[g]] = 0.125 * (((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7])));
+        }
+        __syncthreads();
+    }
+    tail_smooth(A, A.lcoarse, A.ncoarse);
+    for (int m = A.lcoarse + 1; m <= A.m0; ++m) {
+        const int64_t gb = A.begin[m], ge = A.begin[m + 1];
+        for (int64_t t = threadIdx.x; t < 8 * (ge - gb); t += blockDim.x) {
+            const int64_t g = gb + (t >> 3);
+            const int c = static_cast<int>(t & 7);
+            const int64_t cell = 8 * g + c;
+            if (!(A.mask[cell] > 0.0)) continue;
+            A.e[cell] = A.e[cell] + prolong_value(A.e, A.nbr, A.father[g], c);
+        }
+        __syncthreads();
+        tail_smooth(A, m, A.nu2);
+    }
+}
+
 // ---------------------------------------------------------------- build
 
 __global__ void k_shift3(const uint64_t *__restrict__ in, int64_t n, uint64_t *__restrict__ out)
@@ -338,6 +424,24 @@ rg_status fill(double *p, int64_t b, int64_t e, double v, hipStream_t s)
 rg_status vcoarse(const Ctx &x, int m)
 {
     rg_mg_level *h = x.h;
+    if (h->mg_begin[m + 1] - h->mg_begin[m] <= kTailOcts) {
+        TailArgs A;
+        A.e = h->e;
+        A.f = h->f;
+        A.r = h->r;
+        A.mask = h->mask;
+        A.nbr = h->nbr;
+        A.father = h->father;
+        for (int k = 0; k <= RG_MAX_LEVEL + 1; ++k) A.begin[k] = h->mg_begin[k];
+        for (int k = 0; k <= RG_MAX_LEVEL; ++k) A.h2[k] = ldexp(1.0, -2 * k);
+        A.m0 = m;
+        A.lcoarse = h->lcoarse;
+        A.nu1 = x.nu1;
+        A.nu2 = x.nu2;
+        A.ncoarse = x.ncoarse;
+        k_vcycle_tail<<<1, kTailThreads, 0, x.s>>>(A);
+        return launch_status("level multigrid small levels");
+    }
     if (m == h->lcoarse) return coarse_smooth(x, m, x.ncoarse);
     RG_TRY(coarse_smooth(x, m, x.nu1));
     const int64_t gb = h->mg_begin[m], ge = h->mg_begin[m + 1];

@@ -44,6 +44,34 @@ __device__ __forceinline__ double sum6(const double *__restrict__ phi, const int
 // cells of one colour: even (0, 3, 5, 6) or odd (1, 2, 4, 7) coordinate sum
 __constant__ int c_colour[2][4] = {{0, 3, 5, 6}, {1, 2, 4, 7}};
 
+// Gauss-Seidel update of cell c of oct o
+__device__ __forceinline__ void smooth_cell(double *phi, const double *f, const int32_t *__restrict__ nbr27, int64_t o,
+                                            int c, double h2)
+{
+    int64_t nb[6];
+    face_cells(nbr27, o, c, nb);
+    const int64_t cell = 8 * o + c;
+    phi[cell] = (sum6(phi, nb) - h2 * f[cell]) / 6.0;
+}
+
+__device__ __forceinline__ void residual_cell(const double *phi, const double *f, double *r,
+                                              const int32_t *__restrict__ nbr27, int64_t o, int c, double h2)
+{
+    int64_t nb[6];
+    face_cells(nbr27, o, c, nb);
+    const int64_t cell = 8 * o + c;
+    const double lap = (sum6(phi, nb) - 6.0 * phi[cell]) / h2;
+    r[cell] = f[cell] - lap;
+}
+
+// coarse right-hand side at fine oct o's father cell: the mean of the 8
+// fine residuals, summed pairwise in cell order
+__device__ __forceinline__ void restrict_oct(const double *r, double *f, const int32_t *__restrict__ father, int64_t o)
+{
+    const double *c = r + 8 * o;
+    f[father[o]] = 0.125 * (((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7])));
+}
+
 // one colour pass of Gauss-Seidel over the octs [ob, oe): four cells per oct
 __global__ void k_mg_smooth(double *phi, const double *__restrict__ f, const int32_t *__restrict__ nbr27, int64_t ob,
                             int64_t oe, double h2, int colour)
@@ -51,11 +79,7 @@ __global__ void k_mg_smooth(double *phi, const double *__restrict__ f, const int
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t o = ob + (t >> 2);
     if (o >= oe) return;
-    const int c = c_colour[colour][t & 3];
-    int64_t nb[6];
-    face_cells(nbr27, o, c, nb);
-    const int64_t cell = 8 * o + c;
-    phi[cell] = (sum6(phi, nb) - h2 * f[cell]) / 6.0;
+    smooth_cell(phi, f, nbr27, o, c_colour[colour][t & 3], h2);
 }
 
 __global__ void k_mg_residual(const double *__restrict__ phi, const double *__restrict__ f, double *__restrict__ r,
@@ -64,23 +88,15 @@ __global__ void k_mg_residual(const double *__restrict__ phi, const double *__re
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t o = ob + (t >> 3);
     if (o >= oe) return;
-    const int c = static_cast<int>(t & 7);
-    int64_t nb[6];
-    face_cells(nbr27, o, c, nb);
-    const int64_t cell = 8 * o + c;
-    const double lap = (sum6(phi, nb) - 6.0 * phi[cell]) / h2;
-    r[cell] = f[cell] - lap;
+    residual_cell(phi, f, r, nbr27, o, static_cast<int>(t & 7), h2);
 }
 
-// coarse right-hand side at each fine oct's father cell: the mean of the 8
-// fine residuals, summed pairwise in cell order
 __global__ void k_mg_restrict(const double *__restrict__ r, double *__restrict__ f, const int32_t *__restrict__ father,
                               int64_t ob, int64_t oe)
 {
     const int64_t o = ob + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (o >= oe) return;
-    const double *c = r + 8 * o;
-    f[father[o]] = 0.125 * (((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7])));
+    restrict_oct(r, f, father, o);
 }
 
 __global__ void k_mg_zero(double *p, int64_t b, int64_t e)
@@ -93,13 +109,9 @@ __global__ void k_mg_zero(double *p, int64_t b, int64_t e)
 // the fine cell sits a quarter of its father cell C's width from C's centre
 // toward side s per axis; the 8 coarse cells C + {0, s_x} x {0, s_y} x {0,
 // s_z} weigh 27, 9, 3, 1 by the number of steps
-__global__ void k_mg_prolong(double *phi, const int32_t *__restrict__ nbr27, const int32_t *__restrict__ father,
-                             int64_t ob, int64_t oe)
+__device__ __forceinline__ void prolong_cell(double *phi, const int32_t *__restrict__ nbr27,
+                                             const int32_t *__restrict__ father, int64_t o, int c)
 {
-    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t o = ob + (t >> 3);
-    if (o >= oe) return;
-    const int c = static_cast<int>(t & 7);
     const int64_t C = father[o];
     const int64_t P = C >> 3;
     const int q = static_cast<int>(C & 7);
@@ -127,6 +139,64 @@ __global__ void k_mg_prolong(double *phi, const int32_t *__restrict__ nbr27, con
                       3.0 * e[6]) + e[7];
     const int64_t cell = 8 * o + c;
     phi[cell] = phi[cell] + 0.015625 * w;
+}
+
+__global__ void k_mg_prolong(double *phi, const int32_t *__restrict__ nbr27, const int32_t *__restrict__ father,
+                             int64_t ob, int64_t oe)
+{
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t o = ob + (t >> 3);
+    if (o >= oe) return;
+    prolong_cell(phi, nbr27, father, o, static_cast<int>(t & 7));
+}
+
+// The levels of at most kTailOcts octs (those below lfine's first such
+// level are smaller still) run their whole part of the V-cycle in one
+// workgroup: the same passes in the same order as the per-level launches,
+// separated by barriers, so the same bits.  Each launch (two per sweep, 100
+// for 50 sweeps on the coarsest level) costs a few microseconds of GPU time.
+constexpr int64_t kTailOcts = 512;
+constexpr int kTailThreads = 1024;
+
+struct MgTail {
+    double *phi, *f, *r;
+    const int32_t *nbr27, *father;
+    int64_t begin[RG_MAX_LEVEL + 2];
+    double h2[RG_MAX_LEVEL + 1];
+    int m0, lcoarse, nu1, nu2, ncoarse;
+};
+
+__device__ void tail_sweeps(const MgTail &A, int l, int sweeps)
+{
+    const int64_t ob = A.begin[l], n4 = 4 * (A.begin[l + 1] - ob);
+    for (int sw = 0; sw < sweeps; ++sw)
+        for (int colour = 0; colour < 2; ++colour) {
+            for (int64_t t = threadIdx.x; t < n4; t += blockDim.x)
+                smooth_cell(A.phi, A.f, A.nbr27, ob + (t >> 2), c_colour[colour][t & 3], A.h2[l]);
+            __syncthreads();
+        }
+}
+
+__global__ __launch_bounds__(kTailThreads) void k_mg_tail(MgTail A)
+{
+    for (int l = A.m0; l > A.lcoarse; --l) {
+        tail_sweeps(A, l, A.nu1);
+        const int64_t ob = A.begin[l], oe = A.begin[l + 1];
+        for (int64_t t = threadIdx.x; t < 8 * (oe - ob); t += blockDim.x)
+            residual_cell(A.phi, A.f, A.r, A.nbr27, ob + (t >> 3), static_cast<int>(t & 7), A.h2[l]);
+        __syncthreads();
+        for (int64_t o = ob + threadIdx.x; o < oe; o += blockDim.x) restrict_oct(A.r, A.f, A.father, o);
+        for (int64_t i = 8 * A.begin[l - 1] + threadIdx.x; i < 8 * A.begin[l]; i += blockDim.x) A.phi[i] = 0.0;
+        __syncthreads();
+    }
+    tail_sweeps(A, A.lcoarse, A.ncoarse);
+    for (int l = A.lcoarse + 1; l <= A.m0; ++l) {
+        const int64_t ob = A.begin[l], oe = A.begin[l + 1];
+        for (int64_t t = threadIdx.x; t < 8 * (oe - ob); t += blockDim.x)
+            prolong_cell(A.phi, A.nbr27, A.father, ob + (t >> 3), static_cast<int>(t & 7));
+        __syncthreads();
+        tail_sweeps(A, l, A.nu2);
+    }
 }
 
 struct Mg {
@@ -157,8 +227,25 @@ rg_status residual(const rg_tree *t, const double *phi, const double *f, double 
 
 rg_status vcycle(const Mg &m, int l)
 {
-    if (l == m.lcoarse) return smooth(m, l, m.ncoarse);
     const rg_tree *t = m.t;
+    if (t->level_begin[l + 1] - t->level_begin[l] <= kTailOcts) {
+        MgTail A;
+        A.phi = m.phi;
+        A.f = m.f;
+        A.r = m.r;
+        A.nbr27 = t->d_nbr27;
+        A.father = t->d_father_cell;
+        for (int k = 0; k <= RG_MAX_LEVEL + 1; ++k) A.begin[k] = t->level_begin[k];
+        for (int k = 0; k <= RG_MAX_LEVEL; ++k) A.h2[k] = ldexp(1.0, -2 * k);
+        A.m0 = l;
+        A.lcoarse = m.lcoarse;
+        A.nu1 = m.nu1;
+        A.nu2 = m.nu2;
+        A.ncoarse = m.ncoarse;
+        k_mg_tail<<<1, kTailThreads, 0, m.s>>>(A);
+        return launch_status("multigrid small levels");
+    }
+    if (l == m.lcoarse) return smooth(m, l, m.ncoarse);
     RG_TRY(smooth(m, l, m.nu1));
     RG_TRY(residual(t, m.phi, m.f, m.r, l, m.s));
     const int64_t ob = t->level_begin[l], oe = t->level_begin[l + 1];

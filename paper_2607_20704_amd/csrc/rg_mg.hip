@@ -177,8 +177,40 @@ __device__ void tail_sweeps(const MgTail &A, int l, int sweeps)
         }
 }
 
+// The coarsest level's sweeps (50 by default, each pass depending on the
+// last) with its values staged in LDS when it holds at most kLdsCells cells:
+// the same update of each cell, read from and written to LDS.
+constexpr int kLdsCells = 1024;
+
+__device__ void tail_sweeps_lds(const MgTail &A, int l, int sweeps, double *sp, double *sf)
+{
+    const int64_t ob = A.begin[l], cb = 8 * ob, n = 8 * (A.begin[l + 1] - ob);
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        sp[i] = A.phi[cb + i];
+        sf[i] = A.f[cb + i];
+    }
+    __syncthreads();
+    for (int sw = 0; sw < sweeps; ++sw)
+        for (int colour = 0; colour < 2; ++colour) {
+            for (int64_t t = threadIdx.x; t < n / 2; t += blockDim.x) {
+                const int64_t o = ob + (t >> 2);
+                const int c = c_colour[colour][t & 3];
+                int64_t nb[6];
+                face_cells(A.nbr27, o, c, nb);
+                const double s6 = ((((sp[nb[0] - cb] + sp[nb[1] - cb]) + sp[nb[2] - cb]) + sp[nb[3] - cb]) +
+                                   sp[nb[4] - cb]) + sp[nb[5] - cb];
+                const int64_t k = 8 * o + c - cb;
+                sp[k] = (s6 - A.h2[l] * sf[k]) / 6.0;
+            }
+            __syncthreads();
+        }
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) A.phi[cb + i] = sp[i];
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(kTailThreads) void k_mg_tail(MgTail A)
 {
+    __shared__ double sp[kLdsCells], sf[kLdsCells];
     for (int l = A.m0; l > A.lcoarse; --l) {
         tail_sweeps(A, l, A.nu1);
         const int64_t ob = A.begin[l], oe = A.begin[l + 1];
@@ -189,7 +221,10 @@ __global__ __launch_bounds__(kTailThreads) void k_mg_tail(MgTail A)
         for (int64_t i = 8 * A.begin[l - 1] + threadIdx.x; i < 8 * A.begin[l]; i += blockDim.x) A.phi[i] = 0.0;
         __syncthreads();
     }
-    tail_sweeps(A, A.lcoarse, A.ncoarse);
+    if (8 * (A.begin[A.lcoarse + 1] - A.begin[A.lcoarse]) <= kLdsCells)
+        tail_sweeps_lds(A, A.lcoarse, A.ncoarse, sp, sf);
+    else
+        tail_sweeps(A, A.lcoarse, A.ncoarse);
     for (int l = A.lcoarse + 1; l <= A.m0; ++l) {
         const int64_t ob = A.begin[l], oe = A.begin[l + 1];
         for (int64_t t = threadIdx.x; t < 8 * (oe - ob); t += blockDim.x)

@@ -296,8 +296,58 @@ __device__ void tail_smooth(const TailArgs &A, int m, int sweeps)
         }
 }
 
+// The coarsest level's sweeps (50 by default, each pass depending on the
+// last) with its corrections, right-hand sides and masks staged in LDS when
+// it holds at most kLdsCells cells: the same update of each cell.
+constexpr int kLdsCells = 1024;
+
+__device__ void tail_sweeps_lds(const TailArgs &A, int m, int sweeps, double *se, double *sf, double *sm)
+{
+    const int64_t gb = A.begin[m], cb = 8 * gb, n = 8 * (A.begin[m + 1] - gb);
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        se[i] = A.e[cb + i];
+        sf[i] = A.f[cb + i];
+        sm[i] = A.mask[cb + i];
+    }
+    __syncthreads();
+    for (int sw = 0; sw < sweeps; ++sw)
+        for (int colour = 0; colour < 2; ++colour) {
+            for (int64_t t = threadIdx.x; t < n / 2; t += blockDim.x) {
+                const int64_t g = gb + (t >> 2);
+                const int c = c_amr_colour[colour][t & 3];
+                const int64_t k = 8 * g + c - cb;
+                const double mi = sm[k];
+                if (!(mi > 0.0)) continue;
+                double s = 0.0, d = 0.0;
+#pragma unroll
+                for (int side = 0; side < 6; ++side) {
+                    const int ax = side >> 1, dd = (side & 1) ? 1 : -1;
+                    int p[3] = {c & 1, (c >> 1) & 1, c >> 2};
+                    p[ax] += dd;
+                    int64_t j = -1;
+                    if (p[ax] >= 0 && p[ax] <= 1) {
+                        j = 8 * g + cell_of(p);
+                    } else {
+                        const int32_t nn = A.nbr[27 * g + 13 + (ax == 0 ? dd : ax == 1 ? 3 * dd : 9 * dd)];
+                        if (nn >= 0) j = 8 * int64_t(nn) + cell_of(p);
+                    }
+                    const double mj = j >= 0 ? sm[j - cb] : -1.0;
+                    if (mj > 0.0)
+                        s = s + se[j - cb];
+                    else
+                        d = d + ((mi - mj) / mi - 1.0);
+                }
+                se[k] = (s - A.h2[m] * sf[k]) / (6.0 + d);
+            }
+            __syncthreads();
+        }
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) A.e[cb + i] = se[i];
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(kTailThreads) void k_vcycle_tail(TailArgs A)
 {
+    __shared__ double se[kLdsCells], sf[kLdsCells], sm[kLdsCells];
     for (int m = A.m0; m > A.lcoarse; --m) {
         tail_smooth(A, m, A.nu1);
         const int64_t gb = A.begin[m], ge = A.begin[m + 1];
@@ -326,7 +376,10 @@ __global__ __launch_bounds__(kTailThreads) void k_vcycle_tail(TailArgs A)
         }
         __syncthreads();
     }
-    tail_smooth(A, A.lcoarse, A.ncoarse);
+    if (8 * (A.begin[A.lcoarse + 1] - A.begin[A.lcoarse]) <= kLdsCells)
+        tail_sweeps_lds(A, A.lcoarse, A.ncoarse, se, sf, sm);
+    else
+        tail_smooth(A, A.lcoarse, A.ncoarse);
     for (int m = A.lcoarse + 1; m <= A.m0; ++m) {
         const int64_t gb = A.begin[m], ge = A.begin[m + 1];
         for (int64_t t = threadIdx.x; t < 8 * (ge - gb); t += blockDim.x) {

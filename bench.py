@@ -734,7 +734,7 @@ def main():
                     help="run one plain device copy of this size first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        sys.exit("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus)
+        sys.exit("bench.py measures one GPU: the library has no multi-GPU path (--gpus %d requested)" % args.gpus)
 
     import numpy as np
     import torch

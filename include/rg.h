@@ -165,7 +165,7 @@ rg_status rg_permute_rows(const double *d_in, const int32_t *d_perm, int64_t n_r
 
 /* Workspace for n keys: a 256-byte header, then capacity = the power of two
  * >= 2n (load factor <= 1/2) slots of uint64 keys and int32 values, then the
- * scratch of the build (about 9 n bytes). */
+ * scratch of the build (about 17 n bytes). */
 size_t rg_hash_workspace_bytes(int64_t n_keys);
 
 /* Clears the table and inserts (d_keys[i], i) for i < n: slot = FNV-1a-64
@@ -190,7 +190,7 @@ rg_status rg_hash_build(const uint64_t *d_keys, int64_t n, void *d_ws, size_t ws
  * fits.  The result is read by rg_hash_lookup, rg_check and
  * rg_build_neighbours like a workspace rg_hash_build filled.
  * Limits: n <= 4,194,304 keys (RG_EINVAL above, before any launch); a table
- * smaller than the above is RG_EFULL.  The static array (about 40 MiB) is
+ * smaller than the above is RG_EFULL.  The static array (about 72 MiB) is
  * held by every device that runs this call, from its first call until the
  * process ends.  Calls allocate nothing (no hipMalloc, hipFree or allocating
  * library routine) and need no clearing between them: every call writes each

@@ -153,7 +153,8 @@ rg_status rg_prepare_tree(const rg_tree *t, unsigned flags, void *stream)
         RG_TRY(rg_hash_build(t->d_keys, t->n_oct, t->d_hash_ws, t->hash_ws_bytes, stream));
         if (t->sched && t->sched->d_list) {
             const rg_schedule *sc = t->sched;
-            RG_TRY(neighbours_scheduled(t->d_hash_ws, t->d_keys, t->n_oct, t->lmin, t->bc,
+            RG_TRY(neighbours_scheduled(t->d_hash_ws, t->d_keys, t->n_oct, t->lmin, t->lmax,
+                                        t->level_begin[t->lmax], t->bc,
                                         sc->d_list + sc->nbr_brick_begin, sc->nbr_brick_count,
                                         sc->d_list + sc->nbr_rest_begin, sc->nbr_rest_count, t->d_nbr27,
                                         t->d_father_cell, t->d_son_mask, as_stream(stream)));

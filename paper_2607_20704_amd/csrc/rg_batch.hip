@@ -387,7 +387,8 @@ __global__ __launch_bounds__(kT) void k_batch_nbr(const BTree *__restrict__ tree
     for (int64_t it = r.begin; it < r.end; it += r.stride) {
         const Item I = items[it];
         const BTree &T = trees[I.tree];
-        const NbrTable tab{T.keys, T.hdr, T.hkeys, T.hvals, T.hmask, T.nbr27, T.father, T.son, T.lmin, T.bc};
+        const NbrTable tab{T.keys, T.hdr, T.hkeys, T.hvals, T.hmask, T.nbr27, T.father, T.son, T.lmin, T.bc,
+                           RG_MAX_LEVEL + 1};
         if (I.a == 0)
             nbr_brick_body(tab, T.list[I.first], S.brick);
         else

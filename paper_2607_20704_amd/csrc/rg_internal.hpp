@@ -348,13 +348,19 @@ struct SinkScope {
 __device__ inline int32_t hash_probe(const uint64_t *keys, const int32_t *vals, uint64_t mask, uint64_t key)
 {
     uint64_t s = fnv1a64(key) & mask;
+    int32_t found = -1;
     for (uint64_t it = 0; it <= mask; ++it) {
-        uint64_t k = keys[s];
-        if (k == key) return vals[s];
-        if (k == 0) return -1;
+        // the value is read beside the key and taken by a select ahead of the
+        // loop's exit test (a return from inside the test would let the
+        // compiler move the load behind the comparison): a probe that hits
+        // its first slot waits for one memory round trip, not two
+        const uint64_t k = keys[s];
+        const int32_t v = vals[s];
+        found = k == key ? v : found;
+        if (k == key || k == 0) break;
         s = (s + 1) & mask;
     }
-    return -1;
+    return found;
 }
 
 // insert key (index i) by linear probing with a 64-bit compare-and-swap;
@@ -388,9 +394,11 @@ __device__ inline void hash_insert_one(HashHeader *hdr, uint64_t *keys, int32_t 
 // ---------------------------------------------------------------------------
 
 rg_status fill_u32(uint32_t *d, int64_t n, uint32_t v, hipStream_t s);
-rg_status neighbours_scheduled(void *d_ws, const uint64_t *d_keys, int64_t n, int lmin, int bc, const int32_t *bricks,
-                               int64_t nbricks, const int32_t *rest, int64_t nrest, int32_t *d_nbr27,
-                               int32_t *d_father_cell, uint32_t *d_son_mask, hipStream_t s);
+// lmax: the tree's finest level; n_below_lmax: the octs before it (the ones
+// whose son masks are cleared first)
+rg_status neighbours_scheduled(void *d_ws, const uint64_t *d_keys, int64_t n, int lmin, int lmax, int64_t n_below_lmax,
+                               int bc, const int32_t *bricks, int64_t nbricks, const int32_t *rest, int64_t nrest,
+                               int32_t *d_nbr27, int32_t *d_father_cell, uint32_t *d_son_mask, hipStream_t s);
 rg_status sort_keys_bits(const uint64_t *d_keys_in, int64_t n, uint64_t *d_keys_out, int32_t *d_perm, void *d_ws,
                          size_t ws_bytes, int end_bit, hipStream_t s);
 rg_status fill_u64(uint64_t *d, int64_t n, uint64_t v, hipStream_t s);

@@ -25,6 +25,9 @@ struct NbrTable {
     int32_t *father_cell;
     uint32_t *son_mask;
     int lmin, bc;
+    // octs on this level have no children: their son masks are written as
+    // 0 here rather than cleared beforehand (RG_MAX_LEVEL + 1: none are)
+    int lmax_zero;
 };
 
 struct NbrGroup {
@@ -55,6 +58,7 @@ __device__ __forceinline__ void nbr_octs_body(const NbrTable &T, const int32_t *
             const int32_t i = grp.c[g][0], j = grp.c[g][1], k = grp.c[g][2], l = grp.c[g][3];
             if (slot == 13) {
                 T.nbr27[27 * o + 13] = static_cast<int32_t>(o);
+                if (l == T.lmax_zero) T.son_mask[o] = 0u;
                 if (l > T.lmin) {
                     int32_t f = hash_probe(T.keys, T.vals, T.mask, T.okeys[o] >> 3);
                     if (f < 0) {
@@ -113,8 +117,11 @@ __device__ __forceinline__ void nbr_octs_body(const NbrTable &T, const int32_t *
 struct NbrBrick {
     int32_t slot[10 * 10 * 10];
     int16_t pos[512];         // local position of the k-th oct in key order
+    int16_t sbase[512];       // its slot-table index less one in each direction
+    int16_t offs[27];         // slot-table offset of each of the 27 list entries
     int32_t father[64];       // father oct of each sibling group
-    int32_t cube[27];         // first oct of each complete neighbouring cube, else -1
+    int32_t cube[27];         // first oct of each neighbouring cube, else -1
+    int32_t cube_last[27];    // last oct of each neighbouring cube, else -1
 };
 
 __device__ __forceinline__ void nbr_brick_body(const NbrTable &T, int64_t base, NbrBrick &S)
@@ -130,12 +137,17 @@ __device__ __forceinline__ void nbr_brick_body(const NbrTable &T, int64_t base, 
         int32_t i, j, kk, ll;
         key_coords(T.okeys[base + k], i, j, kk, ll);
         const int p = (i & 7) + BO * (j & 7) + BO * BO * (kk & 7);
+        const int sb = (p & 7) + HS * ((p >> 3) & 7) + HS * HS * (p >> 6);
         S.pos[k] = static_cast<int16_t>(p);
-        S.slot[((p & 7) + 1) + HS * (((p >> 3) & 7) + 1) + HS * HS * ((p >> 6) + 1)] = static_cast<int32_t>(base + k);
+        S.sbase[k] = static_cast<int16_t>(sb);
+        S.slot[sb + 1 + HS + HS * HS] = static_cast<int32_t>(base + k);
     }
     const int32_t N = 1 << (l - 1);
-    if (tid < 27) {
-        const int dx = tid % 3 - 1, dy = (tid / 3) % 3 - 1, dz = tid / 9 - 1;
+    // first and last key of each neighbouring cube, looked up on two lanes
+    // at once
+    if (tid < 54) {
+        const int c = tid < 27 ? tid : tid - 27;
+        const int dx = c % 3 - 1, dy = (c / 3) % 3 - 1, dz = c / 9 - 1;
         int32_t bi = i0 + BO * dx, bj = j0 + BO * dy, bk = k0 + BO * dz;
         bool inside = true;
         if (T.bc == RG_BC_PERIODIC) {
@@ -145,14 +157,16 @@ __device__ __forceinline__ void nbr_brick_body(const NbrTable &T, int64_t base, 
         } else {
             inside = bi >= 0 && bj >= 0 && bk >= 0 && bi < N && bj < N && bk < N;
         }
-        int32_t first = -1;
+        int32_t f = -1;
         if (inside) {
             const uint64_t kb = oct_key(bi, bj, bk, l) & ~uint64_t(BO * BO * BO - 1);
-            const int32_t f = hash_probe(T.keys, T.vals, T.mask, kb);
-            if (f >= 0 && hash_probe(T.keys, T.vals, T.mask, kb + (BO * BO * BO - 1)) == f + (BO * BO * BO - 1))
-                first = f;
+            f = hash_probe(T.keys, T.vals, T.mask, tid < 27 ? kb : kb + (BO * BO * BO - 1));
         }
-        S.cube[tid] = first;
+        if (tid < 27) S.cube[c] = f;
+        else S.cube_last[c] = f;
+    } else if (tid < 54 + 27) {
+        const int e = tid - 54;
+        S.offs[e] = static_cast<int16_t>(e % 3 + HS * ((e / 3) % 3) + HS * HS * (e / 9));
     }
     __syncthreads();
     for (int sidx = tid; sidx < HS * HS * HS; sidx += 256) {
@@ -170,7 +184,9 @@ __device__ __forceinline__ void nbr_brick_body(const NbrTable &T, int64_t base, 
         const uint64_t kn = oct_key(ni, nj, nk, l);
         const int cube = (sa < 0 ? 0 : (sa >= BO ? 2 : 1)) + 3 * (sb < 0 ? 0 : (sb >= BO ? 2 : 1)) +
                          9 * (sc < 0 ? 0 : (sc >= BO ? 2 : 1));
-        const int32_t first = S.cube[cube];
+        // a cube whose first and last keys are 511 entries apart is complete
+        const int32_t f0 = S.cube[cube];
+        const int32_t first = f0 >= 0 && S.cube_last[cube] == f0 + (BO * BO * BO - 1) ? f0 : -1;
         int32_t e = first >= 0 ? first + static_cast<int32_t>(kn & uint64_t(BO * BO * BO - 1))
                                : hash_probe(T.keys, T.vals, T.mask, kn);
         if (e < 0) {
@@ -194,16 +210,29 @@ __device__ __forceinline__ void nbr_brick_body(const NbrTable &T, int64_t base, 
         S.father[tid] = f;
     }
     __syncthreads();
-    for (int q = tid; q < 27 * BO * BO * BO; q += 256) {
-        const int k = q / 27, e = q - 27 * k;
-        const int p = S.pos[k];
-        const int a = (p & 7) + e % 3, bb = ((p >> 3) & 7) + (e / 3) % 3, c = (p >> 6) + e / 9;
-        T.nbr27[27 * base + q] = S.slot[a + HS * bb + HS * HS * c];
+    // list entry q = 27 k + e of the brick for q = tid + 256 i: (k, e) is
+    // stepped rather than divided out (256 = 9 * 27 + 13), and the entry's
+    // slot is its oct's base index plus the offset of e
+    static_assert(27 * BO * BO * BO % 256 == 0, "whole passes of the workgroup over the brick's list");
+    {
+        int k = tid / 27, e = tid - 27 * (tid / 27);
+        int32_t *dst = T.nbr27 + 27 * base + tid;
+#pragma unroll 6
+        for (int i = 0; i < 27 * BO * BO * BO / 256; ++i) {
+            __builtin_nontemporal_store(S.slot[S.sbase[k] + S.offs[e]], dst + 256 * i);
+            k += 9;
+            e += 13;
+            if (e >= 27) {
+                e -= 27;
+                ++k;
+            }
+        }
     }
     for (int k = tid; k < BO * BO * BO; k += 256) {
         const int p = S.pos[k];
         const int32_t f = S.father[k >> 3];
         T.father_cell[base + k] = f < 0 ? -1 : 8 * f + ((p & 1) + 2 * ((p >> 3) & 1) + 4 * ((p >> 6) & 1));
+        if (l == T.lmax_zero) T.son_mask[base + k] = 0u;
     }
 }
 

@@ -358,8 +358,8 @@ rg_status rg_refine(rg_tree *t, const double *d_u, double *d_u_new, const rg_ref
     int64_t nb = 0, nr = 0;
     RG_TRY(nbr_lists_device(t->d_keys, m, t->level_begin, t->lmin, t->lmax, static_cast<char *>(d_ws) + core,
                             ws_bytes - core, &lst, &nb, &nr, s));
-    return neighbours_scheduled(t->d_hash_ws, t->d_keys, m, t->lmin, t->bc, lst, nb, lst + nb, nr, t->d_nbr27,
-                                t->d_father_cell, t->d_son_mask, s);
+    return neighbours_scheduled(t->d_hash_ws, t->d_keys, m, t->lmin, t->lmax, t->level_begin[t->lmax], t->bc, lst,
+                                nb, lst + nb, nr, t->d_nbr27, t->d_father_cell, t->d_son_mask, s);
 }
 
 }  // extern "C"

@@ -117,9 +117,12 @@ __global__ void k_hash_insert(const uint64_t *__restrict__ in, int64_t n, HashHe
 
 constexpr int kSegLog = 12;
 constexpr int kSegMax = 1 << kSegLog;
+constexpr int kSegThreads = 512;   // threads of k_seg_build (48 KB of LDS: 3 workgroups per CU)
+constexpr int kSegKpt = 6;         // its segment entries per thread per pass
 
 struct SegBuild {
-    uint32_t *idx;                                   // [n] key indices, bucketed by segment
+    uint64_t *bkeys;                                 // [n] the keys, bucketed by segment
+    uint32_t *idx;                                   // [n] their indices, in the same order
     uint32_t *hist;                                  // [nseg][nblk] per-chunk counts, then offsets
     uint32_t *seg_begin, *seg_end, *seg_tot;         // [nseg] each
     uint32_t *ovf_count;                             // [64] (first used)
@@ -131,6 +134,32 @@ struct SegBuild {
 // keys per bucketing workgroup
 constexpr int kBucketChunk = 4096;
 constexpr int kBucketThreads = 1024;   // per chunk: four keys per thread
+constexpr int kBucketKpt = kBucketChunk / kBucketThreads;
+
+// The chunk of a bucketing workgroup.  Workgroup w runs on XCD w % 8; each
+// XCD takes a contiguous range of chunks, so that the runs which
+// neighbouring chunks write side by side in every segment's range (and in
+// the count matrix) meet in one L2 and leave it as whole lines.  The grid is
+// 8 ceil(nblk / 8) workgroups; those past the last chunk return at once.
+__device__ __forceinline__ int64_t bucket_chunk(int64_t nblk)
+{
+    const int64_t per = (nblk + 7) / 8;
+    return static_cast<int64_t>(blockIdx.x % 8) * per + blockIdx.x / 8;
+}
+
+inline unsigned bucket_grid(int64_t nblk) { return static_cast<unsigned>(8 * ((nblk + 7) / 8)); }
+
+// the keys of chunk blk that this thread handles (0 past the end), loaded
+// together so that the thread waits for memory once, not once per key
+__device__ __forceinline__ void chunk_keys(const uint64_t *__restrict__ keys, int64_t n, int64_t blk,
+                                           uint64_t (&kk)[kBucketKpt])
+{
+#pragma unroll
+    for (int j = 0; j < kBucketKpt; ++j) {
+        const int64_t i = blk * kBucketChunk + threadIdx.x + kBucketThreads * j;
+        kk[j] = i < n ? keys[i] : 0ull;
+    }
+}
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -158,6 +187,8 @@ SegBuild seg_build_layout_at(char *p, int64_t n, uint64_t cap)
     b.nseg = int64_t(1) << b.bits;
     b.nblk = n > 0 ? (n + kBucketChunk - 1) / kBucketChunk : 1;
     const size_t nb = align256(static_cast<size_t>(n) * sizeof(uint32_t));
+    b.bkeys = reinterpret_cast<uint64_t *>(p);
+    p += align256(static_cast<size_t>(n) * sizeof(uint64_t));
     b.idx = reinterpret_cast<uint32_t *>(p);
     p += nb;
     b.ovf = reinterpret_cast<uint32_t *>(p);
@@ -184,17 +215,20 @@ size_t seg_build_bytes(int64_t n, uint64_t cap)
     const int64_t nseg = int64_t(1) << bits;
     const int64_t nblk = nn > 0 ? (nn + kBucketChunk - 1) / kBucketChunk : 1;
     const size_t nb = align256(static_cast<size_t>(nn) * sizeof(uint32_t));
-    return 2 * nb + align256(static_cast<size_t>(nseg * nblk) * sizeof(uint32_t)) +
+    return align256(static_cast<size_t>(nn) * sizeof(uint64_t)) + 2 * nb +
+           align256(static_cast<size_t>(nseg * nblk) * sizeof(uint32_t)) +
            align256(static_cast<size_t>(3 * nseg + 64) * sizeof(uint32_t));
 }
 
 // per chunk of kBucketChunk keys: how many fall in each segment
 __global__ __launch_bounds__(kBucketThreads) void k_bucket_count(const uint64_t *__restrict__ keys, int64_t n, uint64_t mask,
-                                                      int seg_log, int64_t nseg, uint32_t *__restrict__ hist,
-                                                      HashHeader *hdr, uint64_t cap, uint32_t *ovf_count)
+                                                      int seg_log, int64_t nseg, int64_t nblk,
+                                                      uint32_t *__restrict__ hist, HashHeader *hdr, uint64_t cap,
+                                                      uint32_t *ovf_count)
 {
     extern __shared__ uint32_t cnt[];
-    const int64_t blk = blockIdx.x, nblk = gridDim.x;
+    const int64_t blk = bucket_chunk(nblk);
+    if (blk >= nblk) return;
     if (blk == 0 && threadIdx.x == 0) {
         hdr->cap = cap;
         hdr->n = n;
@@ -203,10 +237,12 @@ __global__ __launch_bounds__(kBucketThreads) void k_bucket_count(const uint64_t 
         *ovf_count = 0;
     }
     for (int64_t s = threadIdx.x; s < nseg; s += blockDim.x) cnt[s] = 0;
+    uint64_t kk[kBucketKpt];
+    chunk_keys(keys, n, blk, kk);
     __syncthreads();
-    const int64_t b0 = blk * kBucketChunk, b1 = b0 + kBucketChunk < n ? b0 + kBucketChunk : n;
-    for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x)
-        atomicAdd(&cnt[(fnv1a64(keys[i]) & mask) >> seg_log], 1u);
+#pragma unroll
+    for (int j = 0; j < kBucketKpt; ++j)
+        if (blk * kBucketChunk + threadIdx.x + kBucketThreads * j < n) atomicAdd(&cnt[(fnv1a64(kk[j]) & mask) >> seg_log], 1u);
     __syncthreads();
     for (int64_t s = threadIdx.x; s < nseg; s += blockDim.x) hist[s * nblk + blk] = cnt[s];
 }
@@ -266,24 +302,35 @@ __global__ __launch_bounds__(1024) void k_bucket_scan_tot(const uint32_t *__rest
     }
 }
 
-// key indices into their segment's range (order inside a segment is free)
+// keys and their indices into their segment's range (order inside a segment
+// is free).  The keys travel with the indices: the segment build then reads
+// both contiguously instead of gathering each key through its index (keys of
+// one segment lie about a chunk apart, one cache line per 8-byte key).
 __global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(const uint64_t *__restrict__ keys, int64_t n, uint64_t mask,
-                                                        int seg_log, int64_t nseg, const uint32_t *__restrict__ hist,
+                                                        int seg_log, int64_t nseg, int64_t nblk,
+                                                        const uint32_t *__restrict__ hist,
                                                         const uint32_t *__restrict__ seg_begin,
-                                                        uint32_t *__restrict__ idx)
+                                                        uint64_t *__restrict__ bkeys, uint32_t *__restrict__ idx)
 {
     extern __shared__ uint32_t cur[];
-    const int64_t blk = blockIdx.x, nblk = gridDim.x;
+    const int64_t blk = bucket_chunk(nblk);
+    if (blk >= nblk) return;
+    uint64_t kk[kBucketKpt];
+    chunk_keys(keys, n, blk, kk);
     for (int64_t s = threadIdx.x; s < nseg; s += blockDim.x) cur[s] = seg_begin[s] + hist[s * nblk + blk];
     __syncthreads();
-    const int64_t b0 = blk * kBucketChunk, b1 = b0 + kBucketChunk < n ? b0 + kBucketChunk : n;
-    for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
-        const uint32_t pos = atomicAdd(&cur[(fnv1a64(keys[i]) & mask) >> seg_log], 1u);
-        idx[pos] = static_cast<uint32_t>(i);
+#pragma unroll
+    for (int j = 0; j < kBucketKpt; ++j) {
+        const int64_t i = blk * kBucketChunk + threadIdx.x + kBucketThreads * j;
+        if (i < n) {
+            const uint32_t pos = atomicAdd(&cur[(fnv1a64(kk[j]) & mask) >> seg_log], 1u);
+            bkeys[pos] = kk[j];
+            idx[pos] = static_cast<uint32_t>(i);
+        }
     }
 }
 
-__global__ __launch_bounds__(256) void k_seg_build(const uint64_t *__restrict__ keys,
+__global__ __launch_bounds__(kSegThreads) void k_seg_build(const uint64_t *__restrict__ bkeys,
                                                    const uint32_t *__restrict__ seg_begin,
                                                    const uint32_t *__restrict__ seg_end,
                                                    const uint32_t *__restrict__ idx, HashHeader *hdr,
@@ -300,29 +347,50 @@ __global__ __launch_bounds__(256) void k_seg_build(const uint64_t *__restrict__ 
     }
     __syncthreads();
     const uint64_t base = static_cast<uint64_t>(s) << seg_log;
-    for (uint32_t e = seg_begin[s] + threadIdx.x; e < seg_end[s]; e += blockDim.x) {
-        const uint32_t i = idx[e];
-        const uint64_t key = keys[i];
-        if (key == 0) {
-            flag_error(hdr, RG_EINVAL, i);
-            continue;
+    const uint32_t e_begin = seg_begin[s], e_end = seg_end[s];
+    // kSegKpt entries per thread per pass, their keys and indices loaded
+    // together, so that a thread waits for memory once per pass rather than
+    // once per key (a segment holds about 2048 keys at the table's load
+    // factor: one pass)
+    for (uint32_t e0 = e_begin; e0 < e_end; e0 += kSegThreads * kSegKpt) {
+        uint32_t ii[kSegKpt];
+        uint64_t kk[kSegKpt];
+        // the loads are unconditional (past the segment's end they repeat its
+        // last entry, which exists inside this loop): loads in branches are
+        // each waited for before the next one is issued
+#pragma unroll
+        for (int j = 0; j < kSegKpt; ++j) {
+            const uint32_t e = e0 + threadIdx.x + kSegThreads * j;
+            const uint32_t ec = e < e_end ? e : e_end - 1;
+            ii[j] = idx[ec];
+            kk[j] = bkeys[ec];
         }
-        int local = static_cast<int>((fnv1a64(key) & mask) - base);
-        bool placed = false;
-        for (; local < seg; ++local) {
-            const unsigned long long prev = atomicCAS(&lk[local], 0ull, static_cast<unsigned long long>(key));
-            if (prev == 0ull) {
-                lv[local] = static_cast<int32_t>(i);
-                placed = true;
-                break;
+#pragma unroll
+        for (int j = 0; j < kSegKpt; ++j) {
+            if (e0 + threadIdx.x + kSegThreads * j >= e_end) continue;
+            const uint32_t i = ii[j];
+            const uint64_t key = kk[j];
+            if (key == 0) {
+                flag_error(hdr, RG_EINVAL, i);
+                continue;
             }
-            if (prev == key) {
-                flag_error(hdr, RG_EDUPKEY, i);
-                placed = true;
-                break;
+            int local = static_cast<int>((fnv1a64(key) & mask) - base);
+            bool placed = false;
+            for (; local < seg; ++local) {
+                const unsigned long long prev = atomicCAS(&lk[local], 0ull, static_cast<unsigned long long>(key));
+                if (prev == 0ull) {
+                    lv[local] = static_cast<int32_t>(i);
+                    placed = true;
+                    break;
+                }
+                if (prev == key) {
+                    flag_error(hdr, RG_EDUPKEY, i);
+                    placed = true;
+                    break;
+                }
             }
+            if (!placed) ovf[atomicAdd(ovf_count, 1u)] = i;
         }
-        if (!placed) ovf[atomicAdd(ovf_count, 1u)] = i;
     }
     __syncthreads();
     for (int j = threadIdx.x; j < seg; j += blockDim.x) {
@@ -354,7 +422,7 @@ __global__ void k_hash_lookup(const uint64_t *__restrict__ keys, const int32_t *
 
 // `list` (optional) maps positions 0..n-1 to oct indices
 __global__ __launch_bounds__(256) void k_neighbours(const uint64_t *__restrict__ okeys, const int32_t *__restrict__ list,
-                                                    int64_t n, int lmin, int bc, HashHeader *hdr,
+                                                    int64_t n, int lmin, int bc, int lmax_zero, HashHeader *hdr,
                                                     const uint64_t *__restrict__ keys, const int32_t *__restrict__ vals,
                                                     uint64_t mask, int32_t *__restrict__ nbr27,
                                                     int32_t *__restrict__ father_cell, uint32_t *__restrict__ son_mask)
@@ -362,13 +430,13 @@ __global__ __launch_bounds__(256) void k_neighbours(const uint64_t *__restrict__
     __shared__ NbrGroup grp;
     const int64_t first = int64_t(blockIdx.x) * kNbrOcts;
     const int64_t left = n - first;
-    const NbrTable tab{okeys, hdr, keys, vals, mask, nbr27, father_cell, son_mask, lmin, bc};
+    const NbrTable tab{okeys, hdr, keys, vals, mask, nbr27, father_cell, son_mask, lmin, bc, lmax_zero};
     nbr_octs_body(tab, list, first, left < kNbrOcts ? static_cast<int>(left) : kNbrOcts, grp);
 }
 
 __global__ __launch_bounds__(256) void k_neighbours_brick(const uint64_t *__restrict__ okeys,
                                                           const int32_t *__restrict__ bricks, int64_t nbricks,
-                                                          int lmin, int bc, HashHeader *hdr,
+                                                          int lmin, int bc, int lmax_zero, HashHeader *hdr,
                                                           const uint64_t *__restrict__ keys,
                                                           const int32_t *__restrict__ vals, uint64_t mask,
                                                           int32_t *__restrict__ nbr27,
@@ -379,28 +447,34 @@ __global__ __launch_bounds__(256) void k_neighbours_brick(const uint64_t *__rest
     const int64_t per_xcd = (nbricks + 7) / 8;
     const int64_t b = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (b >= nbricks) return;
-    const NbrTable tab{okeys, hdr, keys, vals, mask, nbr27, father_cell, son_mask, lmin, bc};
+    const NbrTable tab{okeys, hdr, keys, vals, mask, nbr27, father_cell, son_mask, lmin, bc, lmax_zero};
     nbr_brick_body(tab, bricks[b], nb);
 }
 
 }  // namespace
 
-rg_status neighbours_scheduled(void *d_ws, const uint64_t *d_keys, int64_t n, int lmin, int bc, const int32_t *bricks,
-                               int64_t nbricks, const int32_t *rest, int64_t nrest, int32_t *d_nbr27,
-                               int32_t *d_father_cell, uint32_t *d_son_mask, hipStream_t s)
+rg_status neighbours_scheduled(void *d_ws, const uint64_t *d_keys, int64_t n, int lmin, int lmax, int64_t n_below_lmax,
+                               int bc, const int32_t *bricks, int64_t nbricks, const int32_t *rest, int64_t nrest,
+                               int32_t *d_nbr27, int32_t *d_father_cell, uint32_t *d_son_mask, hipStream_t s)
 {
     const uint64_t cap = hash_capacity(n);
     HashView h = hash_view(d_ws, cap);
-    RG_TRY(fill_u32(d_son_mask, n, 0u, s));
+    // only the octs below the finest level can be fathers: their masks are
+    // cleared before the children set bits in them; the kernels write the
+    // finest level's masks (no children) themselves
+    RG_REQUIRE(n_below_lmax >= 0 && n_below_lmax <= n, "bad level range");
+    RG_TRY(fill_u32(d_son_mask, n_below_lmax, 0u, s));
     if (nbricks > 0) {
         k_neighbours_brick<<<static_cast<unsigned>(8 * ((nbricks + 7) / 8)), 256, 0, s>>>(
-            d_keys, bricks, nbricks, lmin, bc, h.hdr, h.keys, h.vals, h.mask, d_nbr27, d_father_cell, d_son_mask);
+            d_keys, bricks, nbricks, lmin, bc, lmax, h.hdr, h.keys, h.vals, h.mask, d_nbr27, d_father_cell,
+            d_son_mask);
         RG_TRY(launch_status("brick neighbours"));
     }
     if (nrest > 0) {
         const int64_t blocks = (nrest + kNbrOcts - 1) / kNbrOcts;
-        k_neighbours<<<static_cast<unsigned>(blocks), 256, 0, s>>>(d_keys, rest, nrest, lmin, bc, h.hdr, h.keys,
-                                                                   h.vals, h.mask, d_nbr27, d_father_cell, d_son_mask);
+        k_neighbours<<<static_cast<unsigned>(blocks), 256, 0, s>>>(d_keys, rest, nrest, lmin, bc, lmax, h.hdr,
+                                                                   h.keys, h.vals, h.mask, d_nbr27, d_father_cell,
+                                                                   d_son_mask);
         RG_TRY(launch_status("neighbours"));
     }
     return RG_OK;
@@ -430,21 +504,20 @@ rg_status hash_build_into(const uint64_t *d_keys, int64_t n, void *d_table, cons
     HashView h = hash_view(d_table, cap);
     const size_t cnt_bytes = static_cast<size_t>(b.nseg) * sizeof(uint32_t);
     RG_REQUIRE(cnt_bytes <= 64 * 1024, "table too large for the bucketed build (%lld segments)", (long long)b.nseg);
-    const unsigned nblk = static_cast<unsigned>(b.nblk);
-    k_bucket_count<<<nblk, kBucketThreads, cnt_bytes, s>>>(d_keys, n, h.mask, b.seg_log, b.nseg, b.hist, h.hdr, cap,
-                                                b.ovf_count);
+    k_bucket_count<<<bucket_grid(b.nblk), kBucketThreads, cnt_bytes, s>>>(d_keys, n, h.mask, b.seg_log, b.nseg, b.nblk,
+                                                                         b.hist, h.hdr, cap, b.ovf_count);
     RG_TRY(launch_status("rg_hash_build count"));
     k_bucket_scan_seg<<<static_cast<unsigned>(b.nseg), 256, 0, s>>>(b.hist, b.nblk, b.seg_tot);
     RG_TRY(launch_status("rg_hash_build scan"));
     k_bucket_scan_tot<<<1, 1024, 0, s>>>(b.seg_tot, b.nseg, b.seg_begin, b.seg_end);
     RG_TRY(launch_status("rg_hash_build bounds"));
     if (n > 0) {
-        k_bucket_scatter<<<nblk, kBucketThreads, cnt_bytes, s>>>(d_keys, n, h.mask, b.seg_log, b.nseg, b.hist, b.seg_begin,
-                                                      b.idx);
+        k_bucket_scatter<<<bucket_grid(b.nblk), kBucketThreads, cnt_bytes, s>>>(
+            d_keys, n, h.mask, b.seg_log, b.nseg, b.nblk, b.hist, b.seg_begin, b.bkeys, b.idx);
         RG_TRY(launch_status("rg_hash_build scatter"));
     }
     const uint32_t *idx = b.idx;
-    k_seg_build<<<static_cast<unsigned>(b.nseg), 256, 0, s>>>(d_keys, b.seg_begin, b.seg_end, idx, h.hdr, h.keys,
+    k_seg_build<<<static_cast<unsigned>(b.nseg), kSegThreads, 0, s>>>(b.bkeys, b.seg_begin, b.seg_end, idx, h.hdr, h.keys,
                                                               h.vals, h.mask, b.seg_log, b.ovf_count, b.ovf);
     RG_TRY(launch_status("rg_hash_build segments"));
     k_seg_overflow<<<64, 256, 0, s>>>(d_keys, b.ovf_count, b.ovf, h.hdr, h.keys, h.vals, h.mask);
@@ -459,13 +532,14 @@ rg_status hash_build_into(const uint64_t *d_keys, int64_t n, void *d_table, cons
 // for the device address with hipGetSymbolAddress and keeps it per device.
 // Sized for the largest table the entry point accepts (kNoAllocMaxKeys keys:
 // capacity 2^23 slots, 2048 segments of 4096 slots, 1024 chunks of 4096
-// keys): key-index and overflow lists of 16 MiB each, per-chunk counts of
-// 8 MiB, per-segment bounds.  The build writes every word it later reads
+// keys): the bucketed keys (32 MiB), key-index and overflow lists of 16 MiB
+// each, per-chunk counts of 8 MiB, per-segment bounds.  The build writes every word it later reads
 // (its first kernel clears the overflow counter), so no call depends on
 // what the previous one left; calls that overlap on one device race.
 // ---------------------------------------------------------------------------
 constexpr int64_t kNoAllocMaxKeys = int64_t(1) << 22;
-constexpr size_t kNoAllocScratchBytes = 2 * (size_t(kNoAllocMaxKeys) * 4) + size_t(2048) * 1024 * 4 +
+constexpr size_t kNoAllocScratchBytes = size_t(kNoAllocMaxKeys) * 8 + 2 * (size_t(kNoAllocMaxKeys) * 4) +
+                                        size_t(2048) * 1024 * 4 +
                                         ((size_t(3 * 2048 + 64) * 4 + 255) & ~size_t(255));
 static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
 
@@ -687,7 +761,8 @@ rg_status rg_build_neighbours(void *d_ws, const uint64_t *d_keys, int64_t n, int
     hipStream_t s = as_stream(stream);
     RG_TRY(fill_u32(d_son_mask, n, 0u, s));
     const int64_t blocks = (n + kNbrOcts - 1) / kNbrOcts;
-    k_neighbours<<<static_cast<unsigned>(blocks), 256, 0, s>>>(d_keys, nullptr, n, lmin, bc, h.hdr, h.keys, h.vals,
+    k_neighbours<<<static_cast<unsigned>(blocks), 256, 0, s>>>(d_keys, nullptr, n, lmin, bc, RG_MAX_LEVEL + 1, h.hdr,
+                                                               h.keys, h.vals,
                                                                h.mask, d_nbr27, d_father_cell, d_son_mask);
     return launch_status("rg_build_neighbours");
 }

@@ -243,13 +243,14 @@ def test_multigrid_argument_errors_without_a_device():
 def test_workspace_sizes():
     lib = L.lib()
     # the table (256-byte header, capacity = power of two >= 2n slots of 12
-    # bytes) followed by the scratch of the segmented build (two int32 arrays
-    # of n entries, the per-chunk segment counts, the segment bounds)
+    # bytes) followed by the scratch of the segmented build (the bucketed
+    # keys, two int32 arrays of n entries, the per-chunk segment counts, the
+    # segment bounds)
     def table(cap):
         return (256 + cap * 12 + 255) // 256 * 256
     for n, cap in ((0, 16), (4096, 8192), (4097, 16384), (1 << 21, 1 << 22)):
         b = lib.rg_hash_workspace_bytes(n)
-        assert b >= table(cap) + 2 * 4 * n, (n, b)
+        assert b >= table(cap) + 16 * n, (n, b)
         assert b % 256 == 0
-        assert b < table(cap) + 2 * 4 * n + 2 * n + 64 * 1024, (n, b)
+        assert b < table(cap) + 16 * n + 2 * n + 64 * 1024, (n, b)
     assert lib.rg_corr_workspace_bytes(10) == 2400

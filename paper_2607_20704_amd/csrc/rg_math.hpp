@@ -59,14 +59,21 @@ __device__ __forceinline__ double sqrt_pos(double x)
     return __builtin_fma(d, h, g);
 }
 
+// madd(a, b, c) = a b + c: in double the product and the sum are rounded
+// separately, exactly as the expression a * b + c (the library is built
+// without contraction), so every double expression written with it keeps
+// its bits; in float (the mixed form's reconstruction and Riemann solver) it
+// is one fused multiply-add, one rounding and one instruction.
 template <> struct Math<double> {
     static __device__ __forceinline__ double sqrt_(double x) { return sqrt_pos(x); }
     static __device__ __forceinline__ double div(double a, double b) { return div_pos(a, b); }
+    static __device__ __forceinline__ double madd(double a, double b, double c) { return a * b + c; }
 };
 
 template <> struct Math<float> {
     static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+    static __device__ __forceinline__ float madd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 };
 
 // conservative -> primitive in double, floors applied; returns 1 / rho
@@ -113,11 +120,17 @@ __device__ __forceinline__ void predict(const R *W, const R (*dW)[NV], R h, R ga
 {
     const R rho = W[0], u = W[1], v = W[2], w = W[3], p = W[4];
     const R div = (dW[0][1] + dW[1][2]) + dW[2][3];
-    Wp[0] = rho - h * (((u * dW[0][0] + v * dW[1][0]) + w * dW[2][0]) + rho * div);
-    Wp[1] = u - h * (((u * dW[0][1] + v * dW[1][1]) + w * dW[2][1]) + dW[0][4] * inv);
-    Wp[2] = v - h * (((u * dW[0][2] + v * dW[1][2]) + w * dW[2][2]) + dW[1][4] * inv);
-    Wp[3] = w - h * (((u * dW[0][3] + v * dW[1][3]) + w * dW[2][3]) + dW[2][4] * inv);
-    Wp[4] = p - h * (((u * dW[0][4] + v * dW[1][4]) + w * dW[2][4]) + (gamma * p) * div);
+    // W'_k = W_k - h ((((u dW_x + v dW_y) + w dW_z) + s_k), the products and
+    // sums in that order (each madd adds its product to the running sum)
+    auto step = [&](int k, R base, R s) {
+        const R t = Math<R>::madd(w, dW[2][k], Math<R>::madd(u, dW[0][k], v * dW[1][k]));
+        return Math<R>::madd(-h, t + s, base);
+    };
+    Wp[0] = step(0, rho, rho * div);
+    Wp[1] = step(1, u, dW[0][4] * inv);
+    Wp[2] = step(2, v, dW[1][4] * inv);
+    Wp[3] = step(3, w, dW[2][4] * inv);
+    Wp[4] = step(4, p, (gamma * p) * div);
 }
 
 template <typename R>
@@ -161,8 +174,10 @@ __device__ __forceinline__ void hllc(const R *WL, const R *WR, int dir, R gamma,
     const R ml = l0 * wl;
     const R mr = r0 * wr;
     const R inv = Math<R>::div(R(1), ml + mr);
-    const R sstar = ((mr * ur + ml * ul) + (l4 - r4)) * inv;
-    const R pstar = ((mr * l4 + ml * r4) + ml * mr * (ul - ur)) * inv;
+    // ((mr ur + ml ul) + (pL - pR)) / (ml + mr) and
+    // ((mr pL + ml pR) + ml mr (uL - uR)) / (ml + mr)
+    const R sstar = (Math<R>::madd(mr, ur, ml * ul) + (l4 - r4)) * inv;
+    const R pstar = Math<R>::madd(ml * mr, ul - ur, Math<R>::madd(mr, l4, ml * r4)) * inv;
 
     const bool useL = (sl > R(0)) || (sstar > R(0));
     const bool outer = useL ? (sl > R(0)) : !(sr > R(0));
@@ -171,21 +186,22 @@ __device__ __forceinline__ void hllc(const R *WL, const R *WR, int dir, R gamma,
     // the kinetic term of the chosen side only, from its selected velocities
     // (the same expression as per side, so the same value); forming one per
     // side let the compiler branch on the side to skip the other
-    const R q = (w1 * w1 + w2 * w2) + w3 * w3;
+    const R q = Math<R>::madd(w3, w3, Math<R>::madd(w1, w1, w2 * w2));
     const R s = useL ? sl : sr;
-    const R E = p * g1 + R(0.5) * rho * q;
+    const R E = Math<R>::madd(p, g1, (R(0.5) * rho) * q);
     const R d = Math<R>::div(R(1), s - sstar);
     // s - un = -(u_L - S_L) on the left, S_R - u_R on the right
     const R su = sizeof(R) == 4 ? (useL ? -wl : wr) : s - un;
     const R rs = outer ? rho : rho * su * d;
-    const R es = outer ? E : ((su * E - p * un) + pstar * sstar) * d;
+    const R es = outer ? E : Math<R>::madd(pstar, sstar, Math<R>::madd(su, E, -(p * un))) * d;
     const R ss = outer ? un : sstar;
     const R ps = outer ? p : pstar;
     const R m = rs * ss;
     F[0] = m;
-    F[1] = dir == 0 ? (m * ss + ps) : (m * w1);
-    F[2] = dir == 1 ? (m * ss + ps) : (m * w2);
-    F[3] = dir == 2 ? (m * ss + ps) : (m * w3);
+    const R mp = Math<R>::madd(m, ss, ps);
+    F[1] = dir == 0 ? mp : (m * w1);
+    F[2] = dir == 1 ? mp : (m * w2);
+    F[3] = dir == 2 ? mp : (m * w3);
     F[4] = (es + ps) * ss;
 }
 
@@ -230,7 +246,7 @@ __device__ __forceinline__ void reconstruct(const R *w0, const R *wxm, const R *
 template <typename R> __device__ __forceinline__ void face_state(const R *Wp, const R *dWa, bool high, R *st)
 {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) st[v] = high ? (Wp[v] + R(0.5) * dWa[v]) : (Wp[v] - R(0.5) * dWa[v]);
+    for (int v = 0; v < NV; ++v) st[v] = Math<R>::madd(high ? R(0.5) : R(-0.5), dWa[v], Wp[v]);
     st[0] = fmax(st[0], R(RG_RHO_MIN));
     st[4] = fmax(st[4], R(RG_P_MIN));
 }

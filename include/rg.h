@@ -72,7 +72,7 @@
 extern "C" {
 #endif
 
-#define RG_ABI_VERSION 12
+#define RG_ABI_VERSION 13
 #define RG_MAX_LEVEL 21
 #define RG_NBR_OUTSIDE INT32_MIN
 #define RG_RHO_MIN 1e-10
@@ -244,7 +244,8 @@ typedef struct rg_tuning {
                                  (FP64: 2 or 3, mixed: 3 or 4; 0 = default: 2 for FP64, 3 mixed) */
     int32_t no_groups;        /* 1: scheduled updates leave complete sibling groups to the per-oct kernel */
     int32_t group_threads;    /* sibling-group kernel workgroup size: 256, 320 or 384 (0 = default) */
-    int32_t reserved[1];
+    int32_t no_pairs;         /* 1: a complete periodic finest level's bricks one by one, not two
+                                 stacked along z per workgroup (the same bits either way) */
 } rg_tuning;
 
 /* Kernel schedule of a tree.  A brick is a Hilbert-aligned cube of 8x8x8

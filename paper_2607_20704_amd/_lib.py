@@ -28,7 +28,7 @@ st = ctypes.c_int
 
 class RgTuning(ctypes.Structure):
     _fields_ = [("octs_per_group", i32), ("threads", i32), ("no_bricks", i32), ("persistent", i32),
-                ("brick_waves", i32), ("no_groups", i32), ("group_threads", i32), ("reserved", i32 * 1)]
+                ("brick_waves", i32), ("no_groups", i32), ("group_threads", i32), ("no_pairs", i32)]
 
 
 class RgSchedule(ctypes.Structure):

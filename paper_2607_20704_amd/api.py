@@ -31,7 +31,7 @@ def _ptr(t):
 
 def _tuning(tune):
     """tune: None or (octs_per_group, threads[, no_bricks[, persistent[, brick_waves[, no_groups[,
-    group_threads]]]]])."""
+    group_threads[, no_pairs]]]]]])."""
     if tune is None:
         return None
     t = RgTuning()
@@ -41,6 +41,7 @@ def _tuning(tune):
     t.brick_waves = int(tune[4]) if len(tune) > 4 else 0
     t.no_groups = int(tune[5]) if len(tune) > 5 else 0
     t.group_threads = int(tune[6]) if len(tune) > 6 else 0
+    t.no_pairs = int(tune[7]) if len(tune) > 7 else 0
     return ctypes.byref(t)
 
 

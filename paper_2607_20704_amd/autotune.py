@@ -20,10 +20,12 @@ import torch
 from . import api
 
 # (octs_per_group, threads, no_bricks, persistent, brick_waves, no_groups,
-# group_threads): per-oct workgroup shapes, bricks off, sibling groups off
-# or on other workgroup sizes, and the brick kernel's register budgets
+# group_threads, no_pairs): per-oct workgroup shapes, bricks off, sibling
+# groups off or on other workgroup sizes, bricks one by one where they could
+# go in pairs, and the brick kernel's register budgets
 TREE_CANDIDATES = [(4, 256, 0, 0, 0), (2, 128, 0, 0, 0), (8, 256, 0, 0, 0), (7, 256, 0, 0, 0), (3, 128, 0, 0, 0),
-                   (4, 256, 1, 0, 0), (4, 256, 0, 0, 0, 1, 0), (4, 256, 0, 0, 0, 0, 256), (4, 256, 0, 0, 0, 0, 384)]
+                   (4, 256, 1, 0, 0), (4, 256, 0, 0, 0, 1, 0), (4, 256, 0, 0, 0, 0, 256), (4, 256, 0, 0, 0, 0, 384),
+                   (4, 256, 0, 0, 0, 0, 0, 1)]
 BRICK_WAVES = {api.RG_FP64: (2, 3), api.RG_MIXED: (3, 4)}
 
 

@@ -82,10 +82,13 @@ template <typename R> __device__ __forceinline__ void ring_put(BrickFaces<R> &F,
 // z), which saves one barrier per plane (see brick_body) for 23 KB more LDS
 // in FP64 -- free at two workgroups per CU, which the FP64 kernel's registers
 // allow anyway; NB = 1 for variants that fit more workgroups.
-template <typename R, int NB = 1> struct BrickSmem {
+// NZ = 2: two bricks stacked along z swept as one column of 32 planes (the
+// slot table then spans octs -1..16 in z).
+template <typename R, int NB = 1, int NZ = 1> struct BrickSmem {
     BrickFaces<R> u_[NB];           // face states and fluxes (NB = 2: planes of even / odd z)
-    int32_t slot[HS * HS * HS];     // oct slots -1..8 around the brick: oct index inside, neighbour entry outside
-    uint8_t son[HS * HS * HS];      // son mask of same-level slot octs, 0 otherwise
+    int32_t slot[HS * HS * (BO * NZ + 2)];   // oct slots -1..8 (z: -1..8 NZ) around the brick(s): oct
+                                             // index inside, neighbour entry outside
+    uint8_t son[HS * HS * (BO * NZ + 2)];    // son mask of same-level slot octs, 0 otherwise
     R w[NV][PW * PW];               // primitive variables of the current plane
     R hw[3][NV][4 * BC];            // primitive variables of the reconstructed ghost ring, planes r-1, r, r+1
     uint8_t split[NB][PW * PW];     // split flags of the current plane's cells
@@ -236,19 +239,23 @@ __device__ __forceinline__ double signal_speed(const double *U, double gamma)
 // brick) the sweep skips the split flags, the zeroed fluxes, the leaf tests
 // of the folded time step and the clamping at walls.  Both give the same
 // bits where both apply.
-template <typename R, bool KU, int NB, bool GEN>
-__device__ __forceinline__ void brick_sweep(const BrickArgs &a, int64_t b, const Geom &g, BrickSmem<R, NB> &S);
+template <typename R, bool KU, int NB, bool GEN, int NZ>
+__device__ __forceinline__ void brick_sweep(const BrickArgs &a, int64_t b, const Geom &g, BrickSmem<R, NB, NZ> &S);
 
-// Slot table and geometry of the brick whose first oct is `base`, built by
-// NT threads; returns GEN (see brick_sweep) for the brick.
-template <int NT, typename SM>
-__device__ __forceinline__ bool brick_setup(const BrickArgs &a, int64_t base, SM &S, Geom &g)
+// Slot table and geometry of the brick whose first oct is `base` (NZ = 2:
+// and of the brick directly above it, first oct `base2`), built by NT
+// threads; returns GEN (see brick_sweep) for the brick(s).
+template <int NT, int NZ, typename SM>
+__device__ __forceinline__ bool brick_setup(const BrickArgs &a, int64_t base, int64_t base2, SM &S, Geom &g)
 {
+    constexpr int ZO = BO * NZ;   // octs along z
     const int tid = threadIdx.x;
-    for (int k = tid; k < BO * BO * BO; k += NT) {
+    for (int k = tid; k < NZ * BO * BO * BO; k += NT) {
+        const bool upper = k >= BO * BO * BO;
+        const int64_t o = upper ? base2 + (k - BO * BO * BO) : base + k;
         int32_t i, j, kk, l;
-        key_coords(a.keys[base + k], i, j, kk, l);
-        S.slot[slot_index(i & 7, j & 7, kk & 7)] = static_cast<int32_t>(base + k);
+        key_coords(a.keys[o], i, j, kk, l);
+        S.slot[slot_index(i & 7, j & 7, (kk & 7) + (upper ? BO : 0))] = static_cast<int32_t>(o);
     }
     if (tid == 0) S.any_son = 0;
     {
@@ -261,9 +268,9 @@ __device__ __forceinline__ bool brick_setup(const BrickArgs &a, int64_t base, SM
         g.outflow = a.outflow;
     }
     __syncthreads();
-    for (int s = tid; s < HS * HS * HS; s += NT) {
+    for (int s = tid; s < HS * HS * (ZO + 2); s += NT) {
         const int sa = s % HS - 1, sb = (s / HS) % HS - 1, sc = s / (HS * HS) - 1;
-        const int out = (sa < 0 || sa >= BO) + (sb < 0 || sb >= BO) + (sc < 0 || sc >= BO);
+        const int out = (sa < 0 || sa >= BO) + (sb < 0 || sb >= BO) + (sc < 0 || sc >= ZO);
         int32_t e = RG_NBR_OUTSIDE;
         if (out == 0) {
             e = S.slot[s];
@@ -271,7 +278,7 @@ __device__ __forceinline__ bool brick_setup(const BrickArgs &a, int64_t base, SM
             // the nearest brick oct and its neighbour entry towards this slot
             const int ca = sa < 0 ? 0 : (sa >= BO ? BO - 1 : sa);
             const int cb = sb < 0 ? 0 : (sb >= BO ? BO - 1 : sb);
-            const int cc = sc < 0 ? 0 : (sc >= BO ? BO - 1 : sc);
+            const int cc = sc < 0 ? 0 : (sc >= ZO ? ZO - 1 : sc);
             const int32_t o = S.slot[slot_index(ca, cb, cc)];
             e = a.nbr27[27 * int64_t(o) + (sa - ca + 1) + 3 * (sb - cb + 1) + 9 * (sc - cc + 1)];
         }
@@ -282,23 +289,25 @@ __device__ __forceinline__ bool brick_setup(const BrickArgs &a, int64_t base, SM
     }
     __syncthreads();
     const bool wall = g.outflow && (g.cx0 == 0 || g.cy0 == 0 || g.cz0 == 0 || g.cx0 + BC == g.ncell ||
-                                    g.cy0 + BC == g.ncell || g.cz0 + BC == g.ncell);
+                                    g.cy0 + BC == g.ncell || g.cz0 + NZ * BC == g.ncell);
     return S.any_son != 0 || wall;
 }
 
-template <typename R, bool KU = false, int NB = 1>
-__device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int64_t b, BrickSmem<R, NB> &S)
+template <typename R, bool KU = false, int NB = 1, int NZ = 1>
+__device__ __forceinline__ void brick_body(const BrickArgs &a, int64_t base, int64_t b, BrickSmem<R, NB, NZ> &S,
+                                           int64_t base2 = -1)
 {
     Geom g;
-    if (brick_setup<BT>(a, base, S, g))
-        brick_sweep<R, KU, NB, true>(a, b, g, S);
+    if (brick_setup<BT, NZ>(a, base, base2, S, g))
+        brick_sweep<R, KU, NB, true, NZ>(a, b, g, S);
     else
-        brick_sweep<R, KU, NB, false>(a, b, g, S);
+        brick_sweep<R, KU, NB, false, NZ>(a, b, g, S);
 }
 
-template <typename R, bool KU, int NB, bool GEN>
-__device__ __forceinline__ void brick_sweep(const BrickArgs &a, int64_t b, const Geom &g, BrickSmem<R, NB> &S)
+template <typename R, bool KU, int NB, bool GEN, int NZ>
+__device__ __forceinline__ void brick_sweep(const BrickArgs &a, int64_t b, const Geom &g, BrickSmem<R, NB, NZ> &S)
 {
+    constexpr int ZC = NZ * BC;   // planes swept
     const int tid = threadIdx.x;
     const double r = *a.dt / a.dx;
     const R h = static_cast<R>(0.5 * r);
@@ -389,8 +398,8 @@ __device__ __forceinline__ void brick_sweep(const BrickArgs &a, int64_t b, const
         zp_prev[v] = R(0);
     }
 
-    for (int rz = -1; rz <= BC; ++rz) {
-        const bool inner = rz >= 0 && rz < BC;      // plane with x/y faces
+    for (int rz = -1; rz <= ZC; ++rz) {
+        const bool inner = rz >= 0 && rz < ZC;      // plane with x/y faces
         const int fb = DB ? (rz & 1) : 0;           // this plane's face buffer and split flags
         BrickFaces<R> &FB = S.u_[fb];
         uint8_t *spl = S.split[fb];
@@ -400,12 +409,12 @@ __device__ __forceinline__ void brick_sweep(const BrickArgs &a, int64_t b, const
         // 1. the reconstructed ghost ring: primitive variables of plane rz+1
         bool hsplit = false;
         if (do_face) {
-            if (rz + 1 <= BC) {
+            if (rz + 1 <= ZC) {
                 R Wh[NV];
                 bool sdummy;
                 if constexpr (PF) {
                     to_prim(Upf, a.gamma, Wh);
-                    if (rz + 2 <= BC) load_u(a.uold, source_cell<GEN>(S, g, hx, hy, rz + 2, sdummy), Upf);
+                    if (rz + 2 <= ZC) load_u(a.uold, source_cell<GEN>(S, g, hx, hy, rz + 2, sdummy), Upf);
                 } else {
                     double U[NV];
                     load_u(a.uold, source_cell<GEN>(S, g, hx, hy, rz + 1, sdummy), U);
@@ -429,7 +438,7 @@ __device__ __forceinline__ void brick_sweep(const BrickArgs &a, int64_t b, const
             bool sdummy;
             if constexpr (PF) {
                 to_prim(Upf, a.gamma, Wr);
-                if (rz + 1 < BC) load_u(a.uold, source_cell<GEN>(S, g, rx, ry, rz + 1, sdummy), Upf);
+                if (rz + 1 < ZC) load_u(a.uold, source_cell<GEN>(S, g, rx, ry, rz + 1, sdummy), Upf);
             } else {
                 double U[NV];
                 load_u(a.uold, source_cell<GEN>(S, g, rx, ry, rz, sdummy), U);

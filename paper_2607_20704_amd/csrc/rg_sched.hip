@@ -24,7 +24,8 @@ rg_status hydro_groups_list(const double *uold, double *unew, const int32_t *nbr
                             int corr_mode, int ghost, const double *ucoarse2);
 rg_status hydro_bricks(const double *uold, double *unew, const int32_t *nbr27, const uint32_t *son,
                        const uint64_t *keys, const int32_t *bricks, int64_t nbricks, const double *dt, double dx,
-                       double gamma, int outflow, int form, double cfl, double *dt_next, int waves, hipStream_t s);
+                       double gamma, int outflow, int form, double cfl, double *dt_next, int waves, hipStream_t s,
+                       int64_t pair_first, int pair_level);
 }  // namespace rg
 
 using namespace rg;
@@ -55,9 +56,15 @@ rg_status hydro_tree_level(const rg_tree *t, const rg_schedule *sc, int level, c
     double *corr = level > t->lmin ? d_corr : nullptr;
     const bool bricks = sc && !(tune && tune->no_bricks);
     if (bricks) {
+        // a complete periodic level without split cells (the finest, with
+        // every oct in a brick): its bricks go two by two along z
+        const int64_t nl = t->level_begin[level + 1] - t->level_begin[level];
+        const bool pairs = !(tune && tune->no_pairs) && level >= 5 && level == t->lmax &&
+                           t->bc == RG_BC_PERIODIC && nl == (int64_t(1) << (3 * (level - 1))) &&
+                           sc->brick_count[level] * 512 == nl;
         RG_TRY(hydro_bricks(d_uold, d_unew, t->d_nbr27, t->d_son_mask, t->d_keys, sc->d_list + sc->brick_begin[level],
                             sc->brick_count[level], d_dt, dx, gamma, t->bc == RG_BC_OUTFLOW, form, cfl, d_dt_next,
-                            tune ? tune->brick_waves : 0, s));
+                            tune ? tune->brick_waves : 0, s, t->level_begin[level], pairs ? level : -1));
         if (tune && tune->no_groups) {
             RG_TRY(hydro_level_list(d_uold, d_unew, t->d_nbr27, t->d_son_mask, sc->d_list + sc->rest_begin[level],
                                     sc->rest_count[level], corr, corr_base, d_dt, dx, gamma, form, tune, cfl,

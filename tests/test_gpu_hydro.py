@@ -197,6 +197,8 @@ BRICK_CASES = [
     ("sod_l5_outflow", lambda: (I.uniform_tree(5), I.OUTFLOW, lambda t: (I.sod_state(t, 1.4), 1.4))),
     ("random_l5_periodic", lambda: (I.uniform_tree(5), I.PERIODIC,
                                     lambda t: (I.grid_to_tree_state(t, 5, I.random_fields_grid(32, 31), 5 / 3), 5 / 3))),
+    ("random_l6_periodic", lambda: (I.uniform_tree(6), I.PERIODIC,
+                                    lambda t: (I.grid_to_tree_state(t, 6, I.random_fields_grid(64, 33), 5 / 3), 5 / 3))),
     ("sedov_l4_l6", lambda: (I.sedov_amr(base=4, lmax=6).ijkl, I.PERIODIC, lambda t: (I.sedov_state(t, 1.4), 1.4))),
     ("sphere_5_6_outflow", lambda: (I.sphere_tree(5, 6, (0.3, 0.6, 0.55), 0.2, I.OUTFLOW), I.OUTFLOW,
                                     lambda t: (I.grid_to_tree_state(t, 5, I.random_fields_grid(32, 32), 5 / 3), 5 / 3))),
@@ -207,7 +209,9 @@ BRICK_CASES = [
 @pytest.mark.parametrize("case", BRICK_CASES, ids=[c[0] for c in BRICK_CASES])
 def test_brick_schedule_bit_identical(case, form):
     """The brick kernel (complete 8^3-oct bricks, plane sweep) and the per-oct
-    kernel give the same bits; FP64 also matches the oracle."""
+    kernel give the same bits; FP64 also matches the oracle.  On the complete
+    periodic levels the bricks go two by two along z by default; one by one
+    they give the same bits."""
     name, mk = case
     ijkl, bc, state = mk()
     u_in, gam = state(ijkl)
@@ -226,8 +230,10 @@ def test_brick_schedule_bit_identical(case, form):
     for waves in ((2, 3) if form == 0 else (3, 4)):
         c = run_device(D, u0, gam, 0.8, 5, form, tune=(4, 256, 0, 0, waves))[0]
         assert np.array_equal(a, c), waves
-    # sibling groups left to the per-oct kernel, or on other workgroup sizes
-    for t in ((4, 256, 0, 0, 0, 1), (4, 256, 0, 0, 0, 0, 256), (4, 256, 0, 0, 0, 0, 384)):
+    # sibling groups left to the per-oct kernel, or on other workgroup sizes;
+    # bricks one by one instead of in pairs (where pairs apply)
+    for t in ((4, 256, 0, 0, 0, 1), (4, 256, 0, 0, 0, 0, 256), (4, 256, 0, 0, 0, 0, 384),
+              (4, 256, 0, 0, 0, 0, 0, 1)):
         c = run_device(D, u0, gam, 0.8, 5, form, tune=t)[0]
         assert np.array_equal(a, c), t
     if form == 0:
@@ -238,7 +244,7 @@ def test_brick_schedule_bit_identical(case, form):
         assert worst <= 1e-12
 
 
-@pytest.mark.parametrize("case", BRICK_CASES[2:], ids=[c[0] for c in BRICK_CASES[2:]])
+@pytest.mark.parametrize("case", BRICK_CASES[3:], ids=[c[0] for c in BRICK_CASES[3:]])
 def test_sibling_group_lists(case):
     """Per level above lmin, the group list holds exactly the octs outside
     bricks whose key ends in 0 (binary 000) and whose 7 following keys are
@@ -265,7 +271,7 @@ def test_sibling_group_lists(case):
     assert total > 0
 
 
-@pytest.mark.parametrize("case", BRICK_CASES[2:], ids=[c[0] for c in BRICK_CASES[2:]])
+@pytest.mark.parametrize("case", BRICK_CASES[3:], ids=[c[0] for c in BRICK_CASES[3:]])
 def test_border_lists_and_unscheduled_corrections(case):
     """The schedule's per-level border lists (octs with a coarse cell across
     a face, which the scheduled step corrects from) equal a brute-force scan
